@@ -1,0 +1,203 @@
+"""DG spatial residual R(u) = M^-1 L(u) of Eq. 13, written out densely.
+
+Discretisation (Sec. 3.1): for element e with test function phi_p,
+
+  L_e[p] =   sum_q w_q |J| grad phi_p(x_q) . (F - G)(Q_q, grad Q_q)          (volume)
+           - sum_faces sum_i w^G_i |J^G| phi_p(x_i) Hhat^n_i                 (Riemann + IP)
+           + sum_faces sum_i w^G_i |J^G| grad phi_p(x_i) . Shat_i           (symmetric IP term)
+
+with Q = B u (Eq. 9), Hhat^n = Fhat^n - Ghat^n and the IP fluxes of
+physics.ip_face_fluxes.  Each interior face is visited once and contributes
+to the test functions on both of its sides (the sum over element
+boundaries of Eq. 12 would otherwise count it twice).  The penalty is
+beta_p = (P+1)^2 / h with h = min(|Omega_e|, |Omega_e'|) / |Gamma_f|, the
+element width normal to the face on a Cartesian grid (the paper does not
+define h).  Traces are evaluated directly at the face quadrature points
+(equal to interpolation from the volume points on affine elements).
+
+Elements are affine boxes: x = origin + (xi + 1) h / 2, so d/dx_j =
+(2/h_j) d/dxi_j, |J| = prod(h)/2^d and |J^Gamma| is the product of the
+tangential half-widths.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+
+from .basis import ref_element
+from .physics import Gas, euler_flux, viscous_flux, face_flux_own
+
+
+@dataclasses.dataclass
+class Disc:
+    """A DG discretisation on a structured mesh of affine boxes."""
+    gas: Gas
+    dim: int
+    P: int
+    nq: int
+    elem_origin: np.ndarray
+    elem_h: np.ndarray
+    face_nbr: np.ndarray
+    bc: Optional[Callable] = None   # boundary ghost-state hook (unused on periodic grids)
+
+    def __post_init__(self):
+        self.ref = ref_element(self.dim, self.P, self.nq)
+        self.nv = self.dim + 2
+        self.n_elem = self.elem_h.shape[0]
+        self.detJ = np.prod(self.elem_h / 2.0, axis=1)            # [E]
+        self.dxi = 2.0 / self.elem_h                                # [E, d] dxi_j/dx_j
+        self.vol = np.prod(self.elem_h, axis=1)
+        ref = self.ref
+        # mass matrix M_e = B^T diag(w |J|) B   (Eq. 13)
+        self.M = np.einsum('qm,q,qn->mn', ref.B, ref.W, ref.B)[None] * self.detJ[:, None, None]
+
+    @property
+    def shape(self):
+        return (self.n_elem, self.nv, self.ref.nm)
+
+    def face_det(self, e, axis):
+        h = self.elem_h[e]
+        return np.prod(np.delete(h, axis, axis=-1) / 2.0, axis=-1)
+
+    def beta_p(self, eL, eR, axis):
+        area = np.prod(np.delete(self.elem_h[eL], axis, axis=-1), axis=-1)
+        hf = np.minimum(self.vol[eL], self.vol[eR]) / area
+        return (self.P + 1) ** 2 / hf
+
+    # -- element-level evaluations ------------------------------------------------
+    def vol_values(self, u):
+        """Q[e, q, v] and grad Q[e, q, j, v] at the volume points."""
+        ref = self.ref
+        Q = np.einsum('qm,evm->eqv', ref.B, u)
+        G = np.stack([np.einsum('qm,evm->eqv', ref.D[j], u) * self.dxi[:, j, None, None]
+                      for j in range(self.dim)], axis=2)
+        return Q, G
+
+    def trace(self, u, elems, f):
+        """Trace value [k, p, v] and broken gradient [k, p, j, v] of the
+        elements `elems` at the points of their face f."""
+        ref = self.ref
+        ue = u[elems]
+        Q = np.einsum('pm,evm->epv', ref.BF[f], ue)
+        G = np.stack([np.einsum('pm,evm->epv', ref.DF[f][j], ue) * self.dxi[elems, j, None, None]
+                      for j in range(self.dim)], axis=2)
+        return Q, G
+
+    def interior_faces(self, axis):
+        """Interior faces normal to `axis` as (left elems, right elems): the
+        left element meets the face with its side 1, the right one with
+        side 0."""
+        eL = np.arange(self.n_elem)
+        eR = self.face_nbr[:, 2 * axis + 1]
+        keep = eR >= 0
+        return eL[keep], eR[keep]
+
+    # -- the residual -------------------------------------------------------------
+    def L(self, u):
+        """L(u) of Eq. 16 (the right-hand side before M^-1)."""
+        gas, ref, d = self.gas, self.ref, self.dim
+        u = np.asarray(u)
+        Q, gQ = self.vol_values(u)
+        H = euler_flux(gas, Q) - viscous_flux(gas, Q, gQ)                  # [e, q, j, v]
+        wq = ref.W[None, :] * self.detJ[:, None]                             # [e, q]
+        L = np.zeros(u.shape, dtype=np.result_type(u, np.float64))
+        for j in range(d):
+            L += np.einsum('qm,eqv->evm', ref.D[j],
+                           H[:, :, j, :] * (wq * self.dxi[:, j, None])[:, :, None])
+        for axis in range(d):
+            eL, eR = self.interior_faces(axis)
+            fL, fR = 2 * axis + 1, 2 * axis
+            QL, gL = self.trace(u, eL, fL)
+            QR, gR = self.trace(u, eR, fR)
+            n = np.zeros(QL.shape[:-1] + (d,))
+            n[..., axis] = 1.0
+            beta = np.broadcast_to(self.beta_p(eL, eR, axis)[:, None], QL.shape[:-1])
+            Hn, S = face_flux_own(gas, QL, QR, gL, gR, n, beta)
+            wf = ref.WF[None, :] * self.face_det(eL, axis)[:, None]         # [k, p]
+            contribL = -np.einsum('pm,kpv->kvm', ref.BF[fL], Hn * wf[..., None])
+            contribR = np.einsum('pm,kpv->kvm', ref.BF[fR], Hn * wf[..., None])
+            for j in range(d):
+                Sw = S[:, :, j, :] * wf[..., None]
+                contribL += np.einsum('pm,kpv->kvm', ref.DF[fL][j], Sw) * self.dxi[eL, j, None, None]
+                contribR += np.einsum('pm,kpv->kvm', ref.DF[fR][j], Sw) * self.dxi[eR, j, None, None]
+            np.add.at(L, eL, contribL)
+            np.add.at(L, eR, contribR)
+        if np.any(self.face_nbr < 0):
+            if self.bc is None:
+                raise ValueError("mesh has boundary faces but no boundary condition")
+            L += self.bc(self, u)
+        return L
+
+    def apply_Minv(self, L):
+        """Solve M_e x = L_e for every element and variable."""
+        return np.linalg.solve(self.M[:, None, :, :], L[..., None])[..., 0]
+
+    def residual(self, u):
+        """R(u) = M^-1 L(u)."""
+        return self.apply_Minv(self.L(u))
+
+    def stage_residual(self, u, S, dt_a):
+        """N(u) = u - S - dt a^mm M^-1 L(u)   (Eq. 20)."""
+        return u - S - dt_a * self.residual(u)
+
+    # -- initial conditions -------------------------------------------------------
+    def points(self):
+        """Physical coordinates of the volume quadrature points [e, q, j]."""
+        return self.elem_origin[:, None, :] + (self.ref.xi[None] + 1.0) * 0.5 * self.elem_h[:, None, :]
+
+    def project(self, fn):
+        """L2 projection of a pointwise field fn(x[..., d]) -> [..., nv]."""
+        vals = fn(self.points())
+        wq = self.ref.W[None, :] * self.detJ[:, None]
+        rhs = np.einsum('qm,eqv->evm', self.ref.B, vals * wq[..., None])
+        return self.apply_Minv(rhs)
+
+
+def make_disc(cfg, mesh, **gas_overrides) -> Disc:
+    kw = dict(gamma=cfg.gamma, Pr=cfg.Pr, Re=cfg.Re, Ma=cfg.Ma, visc_law=cfg.visc_law,
+              T_ref_K=cfg.T_ref_K, flux_mode=cfg.flux_mode, riemann=cfg.riemann)
+    kw.update(gas_overrides)
+    return Disc(gas=Gas(**kw), dim=mesh.dim, P=cfg.P, nq=cfg.nq, elem_origin=mesh.elem_origin,
+                elem_h=mesh.elem_h, face_nbr=mesh.face_nbr)
+
+
+def conserved_from_primitive(gamma, rho, vel, p):
+    """U = (rho, rho u, p/(gamma-1) + rho |u|^2 / 2)."""
+    E = p / (gamma - 1.0) + 0.5 * rho * np.sum(vel * vel, axis=-1)
+    return np.concatenate([rho[..., None], rho[..., None] * vel, E[..., None]], axis=-1)
+
+
+def taylor_green(gas: Gas, dim: int):
+    """Taylor-Green vortex field at T = 1 (rho = p / p_inf) with
+    p_inf = 1/(gamma Ma^2).  2D: u = sin x cos y, v = -cos x sin y,
+    p = p_inf + (cos 2x + cos 2y)/4.  3D: u = sin x cos y cos z,
+    v = -cos x sin y cos z, w = 0, p = p_inf + (cos 2x + cos 2y)(cos 2z + 2)/16."""
+    pinf = 1.0 / (gas.gamma * gas.Ma ** 2)
+
+    def fn(x):
+        if dim == 2:
+            X, Y = x[..., 0], x[..., 1]
+            vel = np.stack([np.sin(X) * np.cos(Y), -np.cos(X) * np.sin(Y)], axis=-1)
+            p = pinf + (np.cos(2 * X) + np.cos(2 * Y)) / 4.0
+        else:
+            X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+            vel = np.stack([np.sin(X) * np.cos(Y) * np.cos(Z), -np.cos(X) * np.sin(Y) * np.cos(Z),
+                            0.0 * X], axis=-1)
+            p = pinf + (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0) / 16.0
+        rho = p / pinf
+        return conserved_from_primitive(gas.gamma, rho, vel, p)
+    return fn
+
+
+def initial_state(disc: Disc, noise: np.ndarray, noise_amp: float):
+    """Taylor-Green field, L2-projected, plus noise_amp * sigma_v * noise on
+    every modal coefficient with sigma = (1, 1, .., 1, E_ref) and
+    E_ref = p_inf/(gamma-1) + 1/2."""
+    gas = disc.gas
+    u = disc.project(taylor_green(gas, disc.dim))
+    pinf = 1.0 / (gas.gamma * gas.Ma ** 2)
+    sigma = np.ones(disc.nv)
+    sigma[-1] = pinf / (gas.gamma - 1.0) + 0.5
+    return u + noise_amp * sigma[None, :, None] * noise

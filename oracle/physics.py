@@ -1,0 +1,221 @@
+"""Compressible Navier-Stokes fluxes (Sec. 2, Eq. 1-6) and face fluxes.
+
+States have shape [..., nv] with nv = d + 2 conserved variables
+(rho, rho u_1..rho u_d, E); gradients have shape [..., d, nv] with the
+derivative direction first; flux tensors have shape [..., d, nv] with the
+flux direction first.  Every function accepts complex arrays so that
+complex-step derivatives can be taken (|x| is then x*sign(Re x)).
+
+Readings of the paper used here:
+  * the stress tensor of Sec. 2 carries the Kronecker delta on its
+    2/3 mu div(u) term (Stokes hypothesis; the symbol is missing in print);
+  * E is the total energy per unit volume, E = p/(gamma-1) + rho|u|^2/2;
+  * Sutherland's law needs a reference temperature in kelvin, which the
+    paper does not give: visc_law=1 uses Gas.T_ref_K (default 288.15 K);
+    visc_law=0 (default) uses the constant mu = 1/Re;
+  * the Riemann solver is not named for the test cases: Roe's flux without
+    entropy fix is the default, local Lax-Friedrichs the alternative.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Gas:
+    gamma: float = 1.4
+    Pr: float = 0.72
+    Re: float = 100.0
+    Ma: float = 0.1
+    visc_law: int = 0       # 0 constant, 1 Sutherland
+    T_ref_K: float = 288.15
+    flux_mode: int = 0      # 0 Navier-Stokes, 1 Euler, 2 scalar diffusion test
+    riemann: int = 0        # 0 Roe, 1 local Lax-Friedrichs
+
+
+def cabs(x):
+    """|x| that keeps the complex-step derivative: x * sign(Re x)."""
+    if np.iscomplexobj(x):
+        return x * np.sign(x.real)
+    return np.abs(x)
+
+
+def primitives(gas: Gas, U):
+    d = U.shape[-1] - 2
+    rho = U[..., 0]
+    vel = U[..., 1:1 + d] / rho[..., None]
+    E = U[..., d + 1]
+    p = (gas.gamma - 1.0) * (E - 0.5 * rho * np.sum(vel * vel, axis=-1))
+    return rho, vel, E, p
+
+
+def temperature(gas: Gas, U):
+    """Equation of state p = rho T / (gamma Ma^2)."""
+    rho, vel, E, p = primitives(gas, U)
+    return gas.gamma * gas.Ma ** 2 * p / rho
+
+
+def viscosity(gas: Gas, U):
+    if gas.visc_law == 0:
+        return np.full(U.shape[:-1], 1.0 / gas.Re, dtype=U.dtype)
+    T = temperature(gas, U)
+    s = 110.0 / gas.T_ref_K
+    return T ** 1.5 / gas.Re * (1.0 + s) / (T + s)
+
+
+def euler_flux(gas: Gas, U):
+    """F_i of Eq. 2, returned as F[..., i, v]."""
+    d = U.shape[-1] - 2
+    F = np.zeros(U.shape[:-1] + (d, d + 2), dtype=U.dtype)
+    if gas.flux_mode == 2:
+        return F
+    rho, vel, E, p = primitives(gas, U)
+    for i in range(d):
+        F[..., i, 0] = rho * vel[..., i]
+        for c in range(d):
+            F[..., i, 1 + c] = rho * vel[..., i] * vel[..., c] + (p if c == i else 0.0)
+        F[..., i, d + 1] = vel[..., i] * (E + p)
+    return F
+
+
+def viscous_flux(gas: Gas, U, gradU):
+    """G_i of Eq. 2 from the conserved state and its gradient, returned as
+    G[..., i, v].  Velocity and temperature gradients follow from the chain
+    rule; G is linear in gradU for a fixed U (Eq. 11)."""
+    d = U.shape[-1] - 2
+    G = np.zeros(U.shape[:-1] + (d, d + 2), dtype=np.result_type(U, gradU))
+    if gas.flux_mode == 1:
+        return G
+    if gas.flux_mode == 2:
+        return gradU / gas.Re + 0.0 * G
+    rho, vel, E, p = primitives(gas, U)
+    mu = viscosity(gas, U)
+    grho = gradU[..., :, 0]                     # [..., j]
+    gvel = (gradU[..., :, 1:1 + d] - vel[..., None, :] * grho[..., :, None]) / rho[..., None, None]
+    # gvel[..., j, c] = d u_c / d x_j
+    div = sum(gvel[..., c, c] for c in range(d))
+    gE = gradU[..., :, d + 1]
+    # d(e)/dx_j with e = E/rho - |u|^2/2 ; T = gamma Ma^2 (gamma-1) e
+    ge = (gE - (E / rho)[..., None] * grho) / rho[..., None] \
+        - np.sum(vel[..., None, :] * gvel, axis=-1)
+    # -q_j = mu/(Ma^2 Pr (gamma-1)) dT/dx_j = mu gamma / Pr * de/dx_j
+    kappa = mu * gas.gamma / gas.Pr
+    for i in range(d):
+        for c in range(d):
+            tau = mu * (gvel[..., c, i] + gvel[..., i, c])
+            if c == i:
+                tau = tau - (2.0 / 3.0) * mu * div
+            G[..., i, 1 + c] = tau
+        G[..., i, d + 1] = sum(vel[..., c] * G[..., i, 1 + c] for c in range(d)) + kappa * ge[..., i]
+    return G
+
+
+def normal_flux(Fdir, n):
+    """n . F for F[..., i, v] and n[..., i]."""
+    return np.einsum('...iv,...i->...v', Fdir, n)
+
+
+def roe_flux(gas: Gas, UL, UR, n):
+    """Roe's approximate Riemann flux F^n(UL, UR, n), n the unit normal
+    pointing from L to R, without entropy fix."""
+    d = UL.shape[-1] - 2
+    g = gas.gamma
+    rL, vL, EL, pL = primitives(gas, UL)
+    rR, vR, ER, pR = primitives(gas, UR)
+    HL = (EL + pL) / rL
+    HR = (ER + pR) / rR
+    sL, sR = np.sqrt(rL), np.sqrt(rR)
+    rt = sL * sR
+    vt = (sL[..., None] * vL + sR[..., None] * vR) / (sL + sR)[..., None]
+    Ht = (sL * HL + sR * HR) / (sL + sR)
+    q2 = np.sum(vt * vt, axis=-1)
+    c2 = (g - 1.0) * (Ht - 0.5 * q2)
+    ct = np.sqrt(c2)
+    unt = np.sum(vt * n, axis=-1)
+    dr = rR - rL
+    dp = pR - pL
+    dv = vR - vL
+    dun = np.sum(dv * n, axis=-1)
+    a1 = (dp - rt * ct * dun) / (2.0 * c2)
+    a5 = (dp + rt * ct * dun) / (2.0 * c2)
+    a2 = dr - dp / c2
+    l1, l2, l5 = cabs(unt - ct), cabs(unt), cabs(unt + ct)
+    diss = np.zeros(UL.shape, dtype=np.result_type(UL, UR))
+    # acoustic waves
+    for lam, a, sgn in ((l1, a1, -1.0), (l5, a5, 1.0)):
+        coef = lam * a
+        diss[..., 0] += coef
+        diss[..., 1:1 + d] += coef[..., None] * (vt + sgn * ct[..., None] * n)
+        diss[..., d + 1] += coef * (Ht + sgn * unt * ct)
+    # entropy and shear waves (eigenvalue u.n)
+    shear = dv - dun[..., None] * n
+    diss[..., 0] += l2 * a2
+    diss[..., 1:1 + d] += l2[..., None] * (a2[..., None] * vt + rt[..., None] * shear)
+    diss[..., d + 1] += l2 * (a2 * 0.5 * q2 + rt * (np.sum(vt * dv, axis=-1) - unt * dun))
+    FL = normal_flux(euler_flux(gas, UL), n)
+    FR = normal_flux(euler_flux(gas, UR), n)
+    return 0.5 * (FL + FR) - 0.5 * diss
+
+
+def llf_flux(gas: Gas, UL, UR, n):
+    rL, vL, EL, pL = primitives(gas, UL)
+    rR, vR, ER, pR = primitives(gas, UR)
+    cL = np.sqrt(gas.gamma * pL / rL)
+    cR = np.sqrt(gas.gamma * pR / rR)
+    lL = cabs(np.sum(vL * n, axis=-1)) + cL
+    lR = cabs(np.sum(vR * n, axis=-1)) + cR
+    if np.iscomplexobj(lL) or np.iscomplexobj(lR):
+        lam = np.where(lL.real >= lR.real, lL, lR)
+    else:
+        lam = np.maximum(lL, lR)
+    FL = normal_flux(euler_flux(gas, UL), n)
+    FR = normal_flux(euler_flux(gas, UR), n)
+    return 0.5 * (FL + FR) - 0.5 * lam[..., None] * (UR - UL)
+
+
+def riemann_flux(gas: Gas, UL, UR, n):
+    if gas.flux_mode == 2:
+        return np.zeros(np.broadcast_shapes(UL.shape, UR.shape), dtype=np.result_type(UL, UR))
+    if gas.riemann == 0:
+        return roe_flux(gas, UL, UR, n)
+    return llf_flux(gas, UL, UR, n)
+
+
+def ip_face_fluxes(gas: Gas, Uo, Un, go, gn, n, beta_p):
+    """Interior-penalty face fluxes seen from the side 'o' (own), with n the
+    outward normal of that side, Uo/Un the own/neighbour traces and go/gn
+    their broken gradients ([..., d, nv]).
+
+    Returns (Ghat_n, S) with
+      Ghat_n = n . G(Ubar, {grad U}) - beta_p n . G(Ubar, dU (x) n)
+      S[..., j, v] = 1/2 n . G(Ubar, dU (x) e_j)
+    where Ubar = (Uo+Un)/2 and dU = Uo - Un.  This is Eq. 12 read with the
+    penalty term dissipative (the printed '+' makes the operator
+    anti-dissipative) and with the average of the test-function gradient
+    carrying its 1/2, the form for which beta_s = 1 gives a symmetric,
+    adjoint-consistent operator (the property Eq. 12 is stated to have);
+    the symmetric term then enters the residual with a plus sign.
+    """
+    d = Uo.shape[-1] - 2
+    Ubar = 0.5 * (Uo + Un)
+    dU = Uo - Un
+    gavg = 0.5 * (go + gn)
+    Gn = normal_flux(viscous_flux(gas, Ubar, gavg), n)
+    jump = n[..., :, None] * dU[..., None, :]           # [..., i, v] = dU_v n_i
+    Gn = Gn - beta_p[..., None] * normal_flux(viscous_flux(gas, Ubar, jump), n)
+    S = np.zeros(Uo.shape[:-1] + (d, d + 2), dtype=np.result_type(Uo, Un, go, gn))
+    for j in range(d):
+        e = np.zeros(Uo.shape[:-1] + (d, d + 2), dtype=S.dtype)
+        e[..., j, :] = dU
+        S[..., j, :] = 0.5 * normal_flux(viscous_flux(gas, Ubar, e), n)
+    return Gn, S
+
+
+def face_flux_own(gas: Gas, Uo, Un, go, gn, n, beta_p):
+    """Total numerical normal flux H^n = F^n - G^n seen from the own side
+    (outward normal n), and the symmetric flux S."""
+    F = riemann_flux(gas, Uo, Un, n)
+    Gn, S = ip_face_fluxes(gas, Uo, Un, go, gn, n, beta_p)
+    return F - Gn, S
