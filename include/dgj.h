@@ -1,0 +1,172 @@
+/*
+ * dgj: implicit discontinuous-Galerkin compressible Navier-Stokes hot path
+ * on AMD MI355X (gfx950).  C ABI.
+ *
+ * Method: arxiv 2002.04222, "Implicit high-order discontinuous Galerkin
+ * compressible flow solver" (Nektar++).  The library evaluates
+ *   R(u) = M^-1 L(u)                               (Sec. 3.1, Eq. 13)
+ *   N(u) = u - S - dt a M^-1 L(u)                  (Sec. 3.2, Eq. 20)
+ *   J v ~ (N(u + eps v) - N(u)) / eps              (Sec. 4.2.2, Eq. 25-26)
+ *   P^-1 q by block-relaxed Jacobi BRJ(J)          (Sec. 4.2.2, Eq. 27-31)
+ * and advances u by SDIRK steps with Newton (Eq. 21-23) and restarted
+ * right-preconditioned GMRES (Eq. 24).
+ *
+ * Conventions for every entry point below:
+ *  - Array arguments are DEVICE pointers (on the device current when the
+ *    context was created) to caller-owned, contiguous FP64 buffers, unless
+ *    the parameter description says "host".  The library never frees them.
+ *  - State layout is [element][variable][mode]: variables
+ *    (rho, rho u_1..rho u_d, E); modes of the orthonormal tensor Legendre
+ *    basis phi_i(xi) = sqrt((2i+1)/2) P_i(xi) on [-1,1]^d, mode index
+ *    i + n (j + n k), x fastest, n = P + 1.  n_unknowns = n_elem (d+2) n^d.
+ *  - Elements are affine boxes; faces are f = 2*axis + side (side 0 at
+ *    xi_axis = -1).  face_nbr[e][f] is the element across face f, which
+ *    meets it with its face 2*axis + (1 - side), face points aligned.
+ *  - Work is enqueued on the context's stream.  Entry points that need a
+ *    scalar on the host (norms for eps, chi and the GMRES Hessenberg
+ *    entries) synchronise that stream; the rest are asynchronous.
+ *  - Every int-returning function returns DGJ_OK or a negative status; the
+ *    message of the last failure is available from dgj_last_error().
+ *    Inputs are not modified on failure except where stated.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef DGJ_H
+#define DGJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DGJ_OK = 0,
+  DGJ_EINVAL = -1,       /* bad argument */
+  DGJ_EHIP = -2,         /* HIP runtime error */
+  DGJ_ENOMEM = -3,       /* device allocation failed */
+  DGJ_ENOTCONV = -4,     /* Newton budget exhausted */
+  DGJ_ENAN = -5,         /* non-finite norm met */
+  DGJ_ESINGULAR = -6,    /* zero pivot in a preconditioner block */
+  DGJ_EUNSUPPORTED = -7  /* combination of sizes or options not built */
+};
+
+enum { DGJ_SDIRK2 = 2, DGJ_SDIRK3 = 3 };
+enum { DGJ_PC_F64 = 0, DGJ_PC_F32 = 1, DGJ_PC_BF16 = 2 };
+
+typedef struct dgj_ctx dgj_ctx;
+
+/* Mesh of affine boxes (host arrays, copied by dgj_create). */
+typedef struct {
+  int32_t dim;                /* 2 or 3 */
+  int32_t P;                  /* polynomial order per direction */
+  int32_t nq;                 /* Gauss points per direction (P+2 built) */
+  int64_t n_elem;
+  const double *elem_origin;  /* host [n_elem][dim] lower corner */
+  const double *elem_h;       /* host [n_elem][dim] edge lengths */
+  const int32_t *face_nbr;    /* host [n_elem][2*dim]; all >= 0 (periodic grids) */
+} dgj_mesh;
+
+/* Non-dimensional gas and flux options (Sec. 2). */
+typedef struct {
+  double gamma, Pr, Re, Ma;
+  double T_ref_K;             /* Sutherland reference temperature, kelvin */
+  int32_t visc_law;           /* 0 constant mu = 1/Re, 1 Sutherland */
+  int32_t flux_mode;          /* 0 Navier-Stokes, 1 Euler, 2 scalar diffusion test */
+  int32_t riemann;            /* 0 Roe, 1 local Lax-Friedrichs */
+} dgj_phys;
+
+/* Implicit solver options (Sec. 3.2, Sec. 4.2.2). */
+typedef struct {
+  int32_t scheme;             /* DGJ_SDIRK2 or DGJ_SDIRK3 (Appendix A) */
+  double newton_rtol;         /* alpha of Eq. 23 */
+  int32_t newton_max;
+  int32_t gmres_restart;      /* 30 in the paper; 1..60 */
+  double gmres_rtol;          /* 5e-2 in the paper */
+  int32_t gmres_max;          /* total GMRES iterations per Newton step */
+  int32_t brj_sweeps;         /* J of Eq. 28 (7) */
+  double brj_omega;           /* omega of Eq. 28 (1) */
+  int32_t pc_precision;       /* DGJ_PC_F64 / F32 / BF16 storage of D^-1 */
+  int32_t pc_freeze;          /* steps a built preconditioner is kept (10) */
+} dgj_solver;
+
+/* Per-step statistics filled by dgj_sdirk_step. */
+typedef struct {
+  int32_t stages;
+  int32_t newton_its[4];
+  int32_t gmres_its[4][64];   /* per stage, per Newton iteration */
+  double nres[4][65];         /* ||N|| per stage before each Newton iteration and at exit */
+  int32_t pc_built;           /* 1 if this step (re)built the preconditioner */
+  int32_t residual_evals;     /* residual evaluations in the step */
+  int32_t status;
+  double t_total_ms;          /* host wall time of the step */
+  double t_pc_build_ms;       /* of which preconditioner build */
+} dgj_step_stats;
+
+/* Create a context on the current device; hip_stream may be NULL (default
+ * stream).  Copies the mesh and options; allocates the library's device
+ * workspaces (freed by dgj_destroy). */
+int dgj_create(const dgj_mesh *mesh, const dgj_phys *phys, const dgj_solver *solver, void *hip_stream,
+               dgj_ctx **out);
+void dgj_destroy(dgj_ctx *ctx);
+/* Number of FP64 unknowns of one state vector. */
+int dgj_sizes(const dgj_ctx *ctx, int64_t *n_unknowns);
+const char *dgj_last_error(const dgj_ctx *ctx);
+
+/* Initial condition: L2 projection (Sec. 3.1) of the Taylor-Green vortex
+ * at T = 1 (2D: u = sin x cos y, v = -cos x sin y, p = p_inf +
+ * (cos 2x + cos 2y)/4; 3D: u = sin x cos y cos z, v = -cos x sin y cos z,
+ * w = 0, p = p_inf + (cos 2x + cos 2y)(cos 2z + 2)/16; rho = p / p_inf,
+ * p_inf = 1/(gamma Ma^2)), plus noise_amp * sigma_v * noise on every
+ * coefficient, sigma = (1,..,1, p_inf/(gamma-1) + 1/2).  noise may be
+ * NULL.  u: output state. */
+int dgj_project_tgv(dgj_ctx *ctx, const double *noise, double noise_amp, double *u);
+
+/* R = M^-1 L(u)  (Eq. 13). */
+int dgj_residual(dgj_ctx *ctx, const double *u, double *R);
+
+/* N = u - S - dt_a M^-1 L(u)  (Eq. 20), dt_a = dt a^mm. */
+int dgj_stage_residual(dgj_ctx *ctx, const double *u, const double *S, double dt_a, double *N);
+
+/* Jv = (N(u + eps v) - N_u) / eps  (Eq. 25) with N_u = N(u) stored by the
+ * caller.  eps <= 0 selects eps = ||u||_2 sqrt(2^-52) (Eq. 26; synchronises
+ * to read the norm).  u + eps v is formed on the fly, not stored. */
+int dgj_jfnk_matvec(dgj_ctx *ctx, const double *u, const double *N_u, const double *S, double dt_a,
+                    const double *v, double eps, double *Jv);
+
+/* Build the BRJ preconditioner at state u_p for dt_a (Eq. 29-31; the last
+ * two terms of Eq. 30 dropped as in the paper).  Synchronises.  Returns
+ * DGJ_ESINGULAR if a block has a zero pivot (the context then has no
+ * preconditioner). */
+int dgj_precond_build(dgj_ctx *ctx, const double *u_p, double dt_a);
+
+/* out = P^-1 q by brj_sweeps sweeps of Eq. 28 from q^0 = 0.  Requires a
+ * built preconditioner.  out must not alias q. */
+int dgj_precond_apply(dgj_ctx *ctx, const double *q, double *out);
+
+/* Copy the stored block inverses, converted to FP64, into out
+ * [n_elem][nb][nb] with nb = (d+2)(P+1)^d, row-major per element. */
+int dgj_precond_diag_inverse(dgj_ctx *ctx, double *out);
+
+/* Solve J x = b approximately by restarted right-preconditioned GMRES
+ * (MGS Arnoldi, Givens rotations, x0 = 0) with the Jacobian-free J at
+ * (u, N_u, S, dt_a) and eps as in dgj_jfnk_matvec; uses the built
+ * preconditioner if any.  *iters receives the iteration count. */
+int dgj_gmres(dgj_ctx *ctx, const double *u, const double *N_u, const double *S, double dt_a, double eps,
+              const double *b, double *x, int32_t *iters);
+
+/* Solve N(u) = 0 (Eq. 20) by Newton from the guess in u (in/out) with
+ * source S; newton_its / gmres_its (host, may be NULL, gmres_its sized
+ * newton_max) receive the iteration counts.  Uses the built preconditioner
+ * if any. */
+int dgj_newton(dgj_ctx *ctx, const double *S, double dt_a, double *u, int32_t *newton_its, int32_t *gmres_its);
+
+/* One SDIRK step of size dt on u (in/out) (Eq. 17-23).  (Re)builds the
+ * preconditioner at the incoming u when none is held, when it is
+ * pc_freeze steps old, or when dt a^mm changed.  stats may be NULL.  On
+ * DGJ_ENOTCONV / DGJ_ENAN u is left unchanged and stats tell where. */
+int dgj_sdirk_step(dgj_ctx *ctx, double *u, double dt, dgj_step_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

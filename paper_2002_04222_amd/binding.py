@@ -1,0 +1,201 @@
+"""ctypes binding of the dgj C ABI (include/dgj.h).  Argument marshalling
+only: device arrays are torch tensors on the context's device, passed by
+data pointer."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libdgj.so")
+
+DGJ_OK = 0
+DGJ_SDIRK2, DGJ_SDIRK3 = 2, 3
+DGJ_PC_F64, DGJ_PC_F32, DGJ_PC_BF16 = 0, 1, 2
+STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOTCONV", -5: "ENAN", -6: "ESINGULAR",
+          -7: "EUNSUPPORTED"}
+
+
+class DgjError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dgj status {code} ({STATUS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("P", C.c_int32), ("nq", C.c_int32), ("n_elem", C.c_int64),
+                ("elem_origin", C.POINTER(C.c_double)), ("elem_h", C.POINTER(C.c_double)),
+                ("face_nbr", C.POINTER(C.c_int32))]
+
+
+class Phys(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("Pr", C.c_double), ("Re", C.c_double), ("Ma", C.c_double),
+                ("T_ref_K", C.c_double), ("visc_law", C.c_int32), ("flux_mode", C.c_int32),
+                ("riemann", C.c_int32)]
+
+
+class Solver(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("newton_rtol", C.c_double), ("newton_max", C.c_int32),
+                ("gmres_restart", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_max", C.c_int32),
+                ("brj_sweeps", C.c_int32), ("brj_omega", C.c_double), ("pc_precision", C.c_int32),
+                ("pc_freeze", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("stages", C.c_int32), ("newton_its", C.c_int32 * 4), ("gmres_its", (C.c_int32 * 64) * 4),
+                ("nres", (C.c_double * 65) * 4), ("pc_built", C.c_int32), ("residual_evals", C.c_int32),
+                ("status", C.c_int32), ("t_total_ms", C.c_double), ("t_pc_build_ms", C.c_double)]
+
+    def to_dict(self):
+        s = self.stages
+        return {
+            "stages": s,
+            "newton_its": [self.newton_its[m] for m in range(s)],
+            "gmres_its": [[self.gmres_its[m][i] for i in range(self.newton_its[m])] for m in range(s)],
+            "nres": [[self.nres[m][i] for i in range(self.newton_its[m] + 1)] for m in range(s)],
+            "pc_built": self.pc_built, "residual_evals": self.residual_evals, "status": self.status,
+            "t_total_ms": self.t_total_ms, "t_pc_build_ms": self.t_pc_build_ms,
+        }
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"dgj HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    vp, dp, i64p, i32p = C.c_void_p, C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+    sig = {
+        "dgj_create": ([C.POINTER(Mesh), C.POINTER(Phys), C.POINTER(Solver), vp, C.POINTER(vp)], C.c_int),
+        "dgj_destroy": ([vp], None),
+        "dgj_sizes": ([vp, i64p], C.c_int),
+        "dgj_last_error": ([vp], C.c_char_p),
+        "dgj_project_tgv": ([vp, vp, dp, vp], C.c_int),
+        "dgj_residual": ([vp, vp, vp], C.c_int),
+        "dgj_stage_residual": ([vp, vp, vp, dp, vp], C.c_int),
+        "dgj_jfnk_matvec": ([vp, vp, vp, vp, dp, vp, dp, vp], C.c_int),
+        "dgj_precond_build": ([vp, vp, dp], C.c_int),
+        "dgj_precond_apply": ([vp, vp, vp], C.c_int),
+        "dgj_precond_diag_inverse": ([vp, vp], C.c_int),
+        "dgj_gmres": ([vp, vp, vp, vp, dp, dp, vp, vp, i32p], C.c_int),
+        "dgj_newton": ([vp, vp, dp, vp, i32p, i32p], C.c_int),
+        "dgj_sdirk_step": ([vp, vp, dp, C.POINTER(StepStats)], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype.__repr__() != "torch.float64" or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
+SCHEMES = {"sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3}
+PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
+
+
+class Context:
+    """A dgj context for one mesh and set of options (see include/dgj.h)."""
+
+    def __init__(self, mesh, cfg, stream=None, **over):
+        import torch
+        self.lib = load_library()
+        self.dim, self.P, self.nq = mesh.dim, cfg.P, cfg.nq
+        self.n_elem = mesh.n_elem
+        self._keep = [np.ascontiguousarray(mesh.elem_origin, dtype=np.float64),
+                      np.ascontiguousarray(mesh.elem_h, dtype=np.float64),
+                      np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)]
+        m = Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem,
+                 self._keep[0].ctypes.data_as(C.POINTER(C.c_double)),
+                 self._keep[1].ctypes.data_as(C.POINTER(C.c_double)),
+                 self._keep[2].ctypes.data_as(C.POINTER(C.c_int32)))
+        g = lambda k: over.get(k, getattr(cfg, k))
+        ph = Phys(g("gamma"), g("Pr"), g("Re"), g("Ma"), g("T_ref_K"), g("visc_law"), g("flux_mode"), g("riemann"))
+        sv = Solver(SCHEMES[g("scheme")], g("newton_rtol"), g("newton_max"), g("gmres_restart"), g("gmres_rtol"),
+                    g("gmres_max"), g("brj_sweeps"), g("brj_omega"), PRECISIONS[g("pc_precision")], g("pc_freeze"))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = self.lib.dgj_create(C.byref(m), C.byref(ph), C.byref(sv), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != DGJ_OK:
+            raise DgjError(rc, "dgj_create failed")
+        self.h = h
+        n = C.c_int64()
+        self._check(self.lib.dgj_sizes(self.h, C.byref(n)))
+        self.n_unknowns = n.value
+        self.shape = (mesh.n_elem, mesh.dim + 2, (cfg.P + 1) ** mesh.dim)
+
+    def _check(self, rc):
+        if rc != DGJ_OK:
+            raise DgjError(rc, self.lib.dgj_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dgj_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self):
+        import torch
+        return torch.empty(self.shape, dtype=torch.float64, device="cuda")
+
+    def project_tgv(self, noise, amp, u):
+        self._check(self.lib.dgj_project_tgv(self.h, _ptr(noise), float(amp), _ptr(u)))
+
+    def residual(self, u, R):
+        self._check(self.lib.dgj_residual(self.h, _ptr(u), _ptr(R)))
+
+    def stage_residual(self, u, S, dt_a, N):
+        self._check(self.lib.dgj_stage_residual(self.h, _ptr(u), _ptr(S), float(dt_a), _ptr(N)))
+
+    def jfnk_matvec(self, u, N_u, S, dt_a, v, eps, Jv):
+        self._check(self.lib.dgj_jfnk_matvec(self.h, _ptr(u), _ptr(N_u), _ptr(S), float(dt_a), _ptr(v),
+                                             float(eps), _ptr(Jv)))
+
+    def precond_build(self, u_p, dt_a):
+        self._check(self.lib.dgj_precond_build(self.h, _ptr(u_p), float(dt_a)))
+
+    def precond_apply(self, q, out):
+        self._check(self.lib.dgj_precond_apply(self.h, _ptr(q), _ptr(out)))
+
+    def precond_diag_inverse(self, out):
+        self._check(self.lib.dgj_precond_diag_inverse(self.h, _ptr(out)))
+
+    def gmres(self, u, N_u, S, dt_a, eps, b, x):
+        it = C.c_int32()
+        self._check(self.lib.dgj_gmres(self.h, _ptr(u), _ptr(N_u), _ptr(S), float(dt_a), float(eps), _ptr(b),
+                                       _ptr(x), C.byref(it)))
+        return it.value
+
+    def newton(self, S, dt_a, u, newton_max=64):
+        nit = C.c_int32()
+        git = (C.c_int32 * max(64, newton_max))()
+        self._check(self.lib.dgj_newton(self.h, _ptr(S), float(dt_a), _ptr(u), C.byref(nit), git))
+        return nit.value, [git[i] for i in range(nit.value)]
+
+    def sdirk_step(self, u, dt):
+        st = StepStats()
+        rc = self.lib.dgj_sdirk_step(self.h, _ptr(u), float(dt), C.byref(st))
+        if rc != DGJ_OK:
+            raise DgjError(rc, self.lib.dgj_last_error(self.h).decode())
+        return st.to_dict()

@@ -1,0 +1,1040 @@
+// Host runtime of the dgj library: context, basis tables, kernel dispatch,
+// deterministic vector reductions, and the GMRES / Newton / SDIRK drivers of
+// arxiv 2002.04222 (Sec. 3.2, Sec. 4.2.2).
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dgj.h"
+#include "dgj_kernels.h"
+#include "dgj_precond.h"
+
+using namespace dgj;
+
+namespace {
+
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+const double EPS_HAT = std::ldexp(1.0, -52);
+
+// ---------------------------------------------------------------- basis tables (host)
+// Gauss-Legendre nodes/weights by Newton iteration on P_n, and the
+// orthonormal Legendre functions phi_i = sqrt((2i+1)/2) P_i with their
+// derivatives from the three-term recurrence.
+void legendre_all(int P, double x, std::vector<double>& v, std::vector<double>& d) {
+  // P_0 = 1, P_1 = x, i P_i = (2i-1) x P_{i-1} - (i-1) P_{i-2};
+  // P_i' = P_{i-2}' + (2i-1) P_{i-1}
+  std::vector<double> p(P + 1), dp(P + 1);
+  p[0] = 1.0;
+  dp[0] = 0.0;
+  if (P >= 1) { p[1] = x; dp[1] = 1.0; }
+  for (int i = 2; i <= P; ++i) {
+    p[i] = ((2.0 * i - 1.0) * x * p[i - 1] - (i - 1.0) * p[i - 2]) / i;
+    dp[i] = dp[i - 2] + (2.0 * i - 1.0) * p[i - 1];
+  }
+  v.assign(P + 1, 0.0);
+  d.assign(P + 1, 0.0);
+  for (int i = 0; i <= P; ++i) {
+    const double c = std::sqrt((2.0 * i + 1.0) / 2.0);
+    v[i] = c * p[i];
+    d[i] = c * dp[i];
+  }
+}
+
+// P_n(z) and P_{n-1}(z)
+static void leg_pair(int n, double z, double& pn, double& pm) {
+  double p0 = 1.0, p1 = z;
+  if (n == 0) { pn = 1.0; pm = 0.0; return; }
+  for (int j = 2; j <= n; ++j) {
+    double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pm = p0;
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < n; ++k) {
+    double z = std::cos(pi * (k + 0.75) / (n + 0.5));
+    double pn, pm, dp;
+    for (int it = 0; it < 100; ++it) {
+      leg_pair(n, z, pn, pm);
+      dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) <= 1e-16) break;
+    }
+    leg_pair(n, z, pn, pm);
+    dp = n * (z * pn - pm) / (z * z - 1.0);
+    x[n - 1 - k] = z;
+    w[n - 1 - k] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+std::vector<double> build_tables(int P, int Q) {
+  const int N = P + 1;
+  std::vector<double> x, w, v, d;
+  gauss_legendre(Q, x, w);
+  std::vector<double> t(2 * Q * N + Q + 4 * N);
+  for (int q = 0; q < Q; ++q) {
+    legendre_all(P, x[q], v, d);
+    for (int n = 0; n < N; ++n) { t[q * N + n] = v[n]; t[Q * N + q * N + n] = d[n]; }
+    t[2 * Q * N + q] = w[q];
+  }
+  for (int s = 0; s < 2; ++s) {
+    legendre_all(P, s == 0 ? -1.0 : 1.0, v, d);
+    for (int n = 0; n < N; ++n) {
+      t[2 * Q * N + Q + s * N + n] = v[n];
+      t[2 * Q * N + Q + 2 * N + s * N + n] = d[n];
+    }
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------- vector kernels
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  }
+  return s;
+}
+
+__global__ void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y, long n, double* part) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// final fixed-order sum of the partials; op 0: out = sum, 1: out = sqrt(sum)
+__global__ void k_reduce_final(const double* __restrict__ part, int np, double* out, int op) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = op == 1 ? sqrt(s) : s;
+}
+
+// per-variable sums of squares of a state: part[b][v]
+__global__ void k_varsq_partial(const double* __restrict__ u, long n_elem, int nv, int nm, double* part) {
+  __shared__ double red[16];
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    long total = n_elem * nm;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+      long e = i / nm, m = i % nm;
+      double x = u[(e * nv + v) * nm + m];
+      s += x * x;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x * nv + v] = s;
+    __syncthreads();
+  }
+}
+
+// y += sgn * alpha[0] * x
+__global__ void k_axpy_dev(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ alpha,
+                           double sgn, long n) {
+  const double a = sgn * alpha[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] += a * x[i];
+}
+// y = 0 (a plain fill kernel, so the solver loop holds no memset nodes)
+__global__ void k_zero(double* __restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = 0.0;
+}
+// y = x / h[0]
+__global__ void k_div_dev(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ h, long n) {
+  const double hv = h[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = x[i] / hv;
+}
+// y = a x + b y
+__global__ void k_axpby(double* __restrict__ y, double a, const double* __restrict__ x, double b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+// y = x + a z   (z may equal nullptr -> copy)
+__global__ void k_add_scaled(double* __restrict__ y, const double* __restrict__ x, double a, const double* __restrict__ z,
+                             long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = z ? x[i] + a * z[i] : x[i];
+}
+// y = (x - z) / a
+__global__ void k_sub_div(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ z, double a,
+                          long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (x[i] - z[i]) / a;
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ x, __hip_bfloat16* __restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = __float2bfloat16(x[i]);
+}
+template <typename T>
+__global__ void k_dinv_export(const T* __restrict__ Dinv, int nb, long n_elem, double* __restrict__ out) {
+  // out row-major [e][row][col] from column-major [e][col][row]
+  long total = n_elem * (long)nb * nb;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    long e = i / ((long)nb * nb);
+    long rc = i % ((long)nb * nb);
+    int row = rc / nb, col = rc % nb;
+    out[i] = (double)to_f<T>(Dinv[(e * nb + col) * (long)nb + row]);
+  }
+}
+template <>
+__global__ void k_dinv_export<double>(const double* __restrict__ Dinv, int nb, long n_elem, double* __restrict__ out) {
+  long total = n_elem * (long)nb * nb;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    long e = i / ((long)nb * nb);
+    long rc = i % ((long)nb * nb);
+    int row = rc / nb, col = rc % nb;
+    out[i] = Dinv[(e * nb + col) * (long)nb + row];
+  }
+}
+
+// Taylor-Green projection: u[e][v][m] = sum_q w_q phi_m(xi_q) f_v(x_q) (+ noise)
+template <int D, int N, int Q>
+__global__ void k_project_tgv(const double* __restrict__ origin, const double* __restrict__ geo,
+                              const double* __restrict__ tables, Phys ph, long n_elem, const double* __restrict__ noise,
+                              double amp, double* __restrict__ u) {
+  using S = Shape<D, N, Q>;
+  constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_elem * NM) return;
+  const long e = gid / NM;
+  const int m = gid % NM;
+  const double* B = tables;
+  const double* w = tables + 2 * Q * N;
+  int mi[3] = {0, 0, 0};
+  split<D, N>(m, mi);
+  const double pinf = 1.0 / (ph.gamma * ph.Ma * ph.Ma);
+  double acc[NV];
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    int aq[3] = {0, 0, 0};
+    int r = q;
+    for (int k = 0; k < D; ++k) { aq[k] = r % Q; r /= Q; }
+    double x[3] = {0, 0, 0}, wq = 1.0, phi = 1.0;
+    for (int k = 0; k < D; ++k) {
+      // xi from phi_1 / sqrt(3/2)
+      double xi = B[aq[k] * N + 1] / std::sqrt(1.5);
+      x[k] = origin[e * D + k] + (xi + 1.0) / geo[e * S::GEO + k];  // h/2 = 1/dxi
+      wq *= w[aq[k]];
+      phi *= B[aq[k] * N + mi[k]];
+    }
+    double vel[3] = {0, 0, 0}, p;
+    if (D == 2) {
+      vel[0] = sin(x[0]) * cos(x[1]);
+      vel[1] = -cos(x[0]) * sin(x[1]);
+      p = pinf + (cos(2 * x[0]) + cos(2 * x[1])) / 4.0;
+    } else {
+      vel[0] = sin(x[0]) * cos(x[1]) * cos(x[2]);
+      vel[1] = -cos(x[0]) * sin(x[1]) * cos(x[2]);
+      vel[2] = 0.0;
+      p = pinf + (cos(2 * x[0]) + cos(2 * x[1])) * (cos(2 * x[2]) + 2.0) / 16.0;
+    }
+    double rho = p / pinf;
+    double ke = 0.0;
+    for (int c = 0; c < D; ++c) ke += vel[c] * vel[c];
+    double U[NV];
+    U[0] = rho;
+    for (int c = 0; c < D; ++c) U[1 + c] = rho * vel[c];
+    U[D + 1] = p / (ph.gamma - 1.0) + 0.5 * rho * ke;
+    for (int v = 0; v < NV; ++v) acc[v] += wq * phi * U[v];
+  }
+  for (int v = 0; v < NV; ++v) {
+    double val = acc[v];
+    if (noise) {
+      double sig = (v == NV - 1) ? pinf / (ph.gamma - 1.0) + 0.5 : 1.0;
+      val += amp * sig * noise[(e * NV + v) * NM + m];
+    }
+    u[(e * NV + v) * NM + m] = val;
+  }
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) throw HipError{_e, #x};   \
+  } while (0)
+
+struct Status {
+  int code;
+  std::string msg;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+struct dgj_ctx {
+  int dim = 0, P = 0, nq = 0, N = 0, NV = 0, NM = 0, NB = 0;
+  long n_elem = 0, n = 0;
+  Phys ph{};
+  dgj_solver sv{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  // geometry
+  double* d_geo = nullptr;
+  double* d_beta = nullptr;
+  int* d_nbr = nullptr;
+  double* d_origin = nullptr;
+  double* d_tab = nullptr;
+  // reductions
+  double* d_part = nullptr;    // [RED_BLOCKS * 8]
+  double* d_scal = nullptr;    // scalars [64]
+  double* h_scal = nullptr;    // pinned host mirror
+  // solver workspaces
+  std::vector<double*> V;      // restart+1 Krylov vectors
+  double *d_z = nullptr, *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr;
+  double *d_ubar = nullptr, *d_N = nullptr, *d_S = nullptr, *d_b = nullptr, *d_x = nullptr, *d_un = nullptr;
+  double* d_E[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *d_pa = nullptr, *d_pb = nullptr;   // BRJ ping-pong
+  // preconditioner
+  bool pc_ready = false;
+  int pc_age = 0;
+  double pc_dta = 0.0;
+  int pc_prec = 0;
+  void* d_Dinv = nullptr;      // double / float / bf16
+  void* d_Jp = nullptr;        // double / float
+  double* d_chi = nullptr;
+  int* d_status = nullptr;
+  int residual_evals = 0;
+};
+
+namespace {
+
+long grid_for(long n, int bs = 256) {
+  long g = (n + bs - 1) / bs;
+  return std::min<long>(std::max<long>(g, 1), 4096);
+}
+
+void set_err(dgj_ctx* c, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+}
+
+template <typename F>
+int guarded(dgj_ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const HipError& h) {
+    set_err(c, "HIP error %s in %s", hipGetErrorString(h.e), h.what);
+    return h.e == hipErrorOutOfMemory ? DGJ_ENOMEM : DGJ_EHIP;
+  } catch (const Status& s) {
+    if (c) c->err = s.msg;
+    return s.code;
+  }
+}
+
+[[noreturn]] void fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Status{code, buf};
+}
+
+// ---------------------------------------------------------------- dispatch
+#define DGJ_FOR_SHAPES(X) \
+  X(2, 2, 3) X(2, 3, 4) X(2, 4, 5) X(2, 5, 6) X(2, 6, 7) X(3, 2, 3) X(3, 3, 4) X(3, 4, 5) X(3, 5, 6)
+
+template <int D, int N, int Q>
+constexpr int res_threads() { return D == 2 ? 64 : 128; }
+template <int D, int N, int Q>
+constexpr int sweep_threads() {
+  constexpr int nb = Shape<D, N, Q>::NB;
+  return nb <= 64 ? 64 : (nb <= 128 ? 128 : (nb <= 256 ? 256 : (nb <= 512 ? 512 : 1024)));
+}
+
+bool shape_supported(int D, int N, int Q) {
+#define X(d, n, q) if (D == d && N == n && Q == q) return true;
+  DGJ_FOR_SHAPES(X)
+#undef X
+  return false;
+}
+
+template <int D, int N, int Q>
+void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
+  constexpr int NT = res_threads<D, N, Q>();
+  hipLaunchKernelGGL((k_residual<D, N, Q, NT>), dim3(c->n_elem), dim3(NT), 0, c->stream, a);
+}
+
+void launch_residual(dgj_ctx* c, const ResArgs& a) {
+#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { launch_residual_t<d, n, q>(c, a); return; }
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "unsupported shape");
+}
+
+ResArgs res_args(dgj_ctx* c) {
+  ResArgs a{};
+  a.nbr = c->d_nbr;
+  a.geo = c->d_geo;
+  a.beta = c->d_beta;
+  a.tables = c->d_tab;
+  a.ph = c->ph;
+  a.n_elem = c->n_elem;
+  return a;
+}
+
+void residual(dgj_ctx* c, const double* u, double* R) {
+  ResArgs a = res_args(c);
+  a.in = StateIn{u, nullptr, 0.0};
+  a.out = R;
+  a.mode = RES_R;
+  launch_residual(c, a);
+  c->residual_evals++;
+}
+void stage_residual(dgj_ctx* c, const double* u, const double* S, double dt_a, double* Nout) {
+  ResArgs a = res_args(c);
+  a.in = StateIn{u, nullptr, 0.0};
+  a.S = S;
+  a.dt_a = dt_a;
+  a.out = Nout;
+  a.mode = RES_N;
+  launch_residual(c, a);
+  c->residual_evals++;
+}
+void matvec(dgj_ctx* c, const double* u, const double* Nu, const double* S, double dt_a, const double* v, double eps,
+            double* Jv) {
+  ResArgs a = res_args(c);
+  a.in = StateIn{u, v, eps};
+  a.S = S;
+  a.Nu = Nu;
+  a.dt_a = dt_a;
+  a.out = Jv;
+  a.mode = RES_JV;
+  launch_residual(c, a);
+  c->residual_evals++;
+}
+
+// ---------------------------------------------------------------- reductions
+void dot_dev(dgj_ctx* c, const double* x, const double* y, double* slot, int op) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, x, y, c->n, c->d_part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c->stream, c->d_part, RED_BLOCKS, slot, op);
+}
+double fetch(dgj_ctx* c, const double* slot) {
+  HIPCHK(hipMemcpyAsync(c->h_scal, slot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return c->h_scal[0];
+}
+double norm(dgj_ctx* c, const double* x) {
+  dot_dev(c, x, x, c->d_scal + 63, 1);
+  return fetch(c, c->d_scal + 63);
+}
+void axpby(dgj_ctx* c, double* y, double a, const double* x, double b) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(c->n)), dim3(256), 0, c->stream, y, a, x, b, c->n);
+}
+void copy(dgj_ctx* c, double* y, const double* x) {
+  HIPCHK(hipMemcpyAsync(y, x, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+}
+
+// ---------------------------------------------------------------- preconditioner
+template <int D, int N, int Q, typename T, typename TJ>
+void sweep_t(dgj_ctx* c, const double* q, const double* qold, double* out, double dt_a, int first) {
+  constexpr int NT = sweep_threads<D, N, Q>();
+  hipLaunchKernelGGL((k_brj_sweep<D, N, Q, NT, T, TJ>), dim3(c->n_elem), dim3(NT), 0, c->stream, q, qold, out,
+                     (const T*)c->d_Dinv, (const TJ*)c->d_Jp, c->d_nbr, c->d_geo, c->d_tab, dt_a, c->sv.brj_omega,
+                     first, c->n_elem);
+}
+
+template <int D, int N, int Q>
+void sweep_shape(dgj_ctx* c, const double* q, const double* qold, double* out, double dt_a, int first) {
+  if (c->pc_prec == DGJ_PC_F64) sweep_t<D, N, Q, double, double>(c, q, qold, out, dt_a, first);
+  else if (c->pc_prec == DGJ_PC_F32) sweep_t<D, N, Q, float, float>(c, q, qold, out, dt_a, first);
+  else sweep_t<D, N, Q, __hip_bfloat16, float>(c, q, qold, out, dt_a, first);
+}
+
+void precond_apply(dgj_ctx* c, const double* q, double* out) {
+  const int J = std::max(1, c->sv.brj_sweeps);
+  // ping-pong so the last sweep lands in out
+  double* bufs[2] = {c->d_pa, c->d_pb};
+  const double* prev = nullptr;
+  for (int j = 0; j < J; ++j) {
+    double* dst = (j == J - 1) ? out : bufs[j & 1];
+#define X(d, n, qq) \
+  if (c->dim == d && c->N == n && c->nq == qq) { sweep_shape<d, n, qq>(c, q, prev, dst, c->pc_dta, j == 0); } else
+    DGJ_FOR_SHAPES(X)
+#undef X
+    fail(DGJ_EUNSUPPORTED, "unsupported shape");
+    prev = dst;
+  }
+}
+
+template <int D, int N, int Q>
+void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* JmW, void* Dm) {
+  using S = Shape<D, N, Q>;
+  constexpr int NTV = 64;
+  hipLaunchKernelGGL((k_pc_volume<D, N, Q, NTV>), dim3(c->n_elem), dim3(NTV), 0, c->stream, up, c->d_geo, c->d_tab,
+                     c->ph, c->n_elem, Wt);
+  long nf = c->n_elem * S::NF * S::NQF;
+  if (c->pc_prec == DGJ_PC_F64)
+    hipLaunchKernelGGL((k_pc_face<D, N, Q, double>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
+                       c->d_geo, c->d_beta, c->d_tab, c->ph, c->n_elem, c->d_chi, JmW, (double*)c->d_Jp);
+  else
+    hipLaunchKernelGGL((k_pc_face<D, N, Q, float>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
+                       c->d_geo, c->d_beta, c->d_tab, c->ph, c->n_elem, c->d_chi, JmW, (float*)c->d_Jp);
+  constexpr int NTA = 256;
+  const long nblk = c->n_elem * S::NV * S::NV;
+  if (c->pc_prec == DGJ_PC_F64)
+    hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
+                       c->d_tab, dt_a, c->n_elem, (double*)Dm);
+  else
+    hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, float>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
+                       c->d_tab, dt_a, c->n_elem, (float*)Dm);
+}
+
+template <typename T, int KB>
+void invert(dgj_ctx* c, T* A) {
+  const int nb = c->NB;
+  int threads = ((nb + 63) / 64) * 64;
+  size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int);
+  HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(c->n_elem), dim3(threads), lds, c->stream, A, nb, c->n_elem,
+                     c->d_status);
+}
+
+void free_pc(dgj_ctx* c) {
+  if (c->d_Dinv) hipFree(c->d_Dinv);
+  if (c->d_Jp) hipFree(c->d_Jp);
+  c->d_Dinv = nullptr;
+  c->d_Jp = nullptr;
+  c->pc_ready = false;
+}
+
+void precond_build(dgj_ctx* c, const double* up, double dt_a) {
+  using clk = std::chrono::steady_clock;
+  const int prec = c->sv.pc_precision;
+  if (!c->d_Dinv || c->pc_prec != prec) {
+    free_pc(c);
+    size_t es = prec == DGJ_PC_F64 ? 8 : (prec == DGJ_PC_F32 ? 4 : 2);
+    HIPCHK(hipMalloc(&c->d_Dinv, (size_t)c->n_elem * c->NB * c->NB * es));
+    size_t js = prec == DGJ_PC_F64 ? 8 : 4;
+    HIPCHK(hipMalloc(&c->d_Jp, (size_t)c->n_elem * 2 * c->dim * (size_t)std::pow(c->nq, c->dim - 1) * c->NV * c->NV * js));
+    c->pc_prec = prec;
+  }
+  c->pc_ready = false;
+  // chi_v = ||u^(v)||_2 sqrt(eps_hat)  (Eq. 31)
+  hipLaunchKernelGGL(k_varsq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, up, c->n_elem, c->NV, c->NM,
+                     c->d_part);
+  std::vector<double> part((size_t)RED_BLOCKS * c->NV);
+  HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<double> chi(c->NV, 0.0);
+  for (int v = 0; v < c->NV; ++v) {
+    double s = 0.0;
+    for (int b = 0; b < RED_BLOCKS; ++b) s += part[(size_t)b * c->NV + v];
+    chi[v] = std::sqrt(s) * std::sqrt(EPS_HAT);
+    if (!(chi[v] > 0.0) || !std::isfinite(chi[v])) fail(DGJ_EINVAL, "precond_build: variable %d of u_p is zero or non-finite", v);
+  }
+  HIPCHK(hipMemcpyAsync(c->d_chi, chi.data(), c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const long nq_vol = (long)std::pow(c->nq, c->dim);
+  const long nqf = (long)std::pow(c->nq, c->dim - 1);
+  double *Wt = nullptr, *JmW = nullptr;
+  void* Dm = nullptr;
+  HIPCHK(hipMalloc(&Wt, (size_t)c->n_elem * nq_vol * c->dim * (c->dim + 1) * c->NV * c->NV * sizeof(double)));
+  HIPCHK(hipMalloc(&JmW, (size_t)c->n_elem * 2 * c->dim * nqf * c->NV * c->NV * sizeof(double)));
+  const size_t blk = (size_t)c->n_elem * c->NB * c->NB;
+  if (prec == DGJ_PC_F64) Dm = c->d_Dinv;
+  else if (prec == DGJ_PC_F32) Dm = c->d_Dinv;
+  else HIPCHK(hipMalloc(&Dm, blk * sizeof(float)));
+#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm); } else
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "unsupported shape");
+  if (prec == DGJ_PC_F64) invert<double, 32>(c, (double*)Dm);
+  else invert<float, 32>(c, (float*)Dm);
+  if (prec == DGJ_PC_BF16)
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const float*)Dm,
+                       (__hip_bfloat16*)c->d_Dinv, (long)blk);
+  HIPCHK(hipGetLastError());
+  std::vector<int> st(c->n_elem);
+  HIPCHK(hipMemcpyAsync(st.data(), c->d_status, c->n_elem * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  hipFree(Wt);
+  hipFree(JmW);
+  if (prec == DGJ_PC_BF16) hipFree(Dm);
+  for (long e = 0; e < c->n_elem; ++e)
+    if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
+  c->pc_ready = true;
+  c->pc_dta = dt_a;
+  c->pc_age = 0;
+}
+
+// ---------------------------------------------------------------- GMRES
+struct GmresOut {
+  int its;
+  bool converged;
+};
+
+GmresOut gmres(dgj_ctx* c, const double* u, const double* Nu, const double* S, double dt_a, double eps, const double* b,
+               double* x) {
+  const int m = std::max(1, std::min(c->sv.gmres_restart, (int)c->V.size() - 1));
+  const double rtol = c->sv.gmres_rtol;
+  const int maxit = c->sv.gmres_max;
+  auto prec = [&](const double* in, double* out) {
+    if (c->pc_ready) precond_apply(c, in, out);
+    else copy(c, out, in);
+  };
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(c->n)), dim3(256), 0, c->stream, x, c->n);
+  const double beta0 = norm(c, b);
+  if (!std::isfinite(beta0)) fail(DGJ_ENAN, "gmres: non-finite right-hand side");
+  GmresOut r{0, false};
+  if (beta0 == 0.0) { r.converged = true; return r; }
+  const double* rvec = b;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hc = [&](int i, int k) -> double& { return H[i * m + k]; };
+  while (true) {
+    const double beta = (rvec == b) ? beta0 : norm(c, rvec);
+    if (!std::isfinite(beta)) fail(DGJ_ENAN, "gmres: non-finite residual");
+    if (beta <= rtol * beta0) { r.converged = true; break; }
+    // V0 = r / beta
+    c->h_scal[0] = beta;
+    HIPCHK(hipMemcpyAsync(c->d_scal + 62, c->h_scal, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_div_dev, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->V[0], rvec, c->d_scal + 62, c->n);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kused = 0;
+    bool stop = false;
+    for (int k = 0; k < m; ++k) {
+      prec(c->V[k], c->d_z);
+      double* w = c->V[k + 1];
+      matvec(c, u, Nu, S, dt_a, c->d_z, eps, w);
+      r.its++;
+      for (int i = 0; i <= k; ++i) {
+        dot_dev(c, w, c->V[i], c->d_scal + i, 0);
+        hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(c->n)), dim3(256), 0, c->stream, w, c->V[i], c->d_scal + i, -1.0,
+                           c->n);
+      }
+      dot_dev(c, w, w, c->d_scal + k + 1, 1);
+      HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (int i = 0; i <= k + 1; ++i) Hc(i, k) = c->h_scal[i];
+      if (!std::isfinite(Hc(k + 1, k))) fail(DGJ_ENAN, "gmres: non-finite Krylov vector");
+      const bool breakdown = Hc(k + 1, k) == 0.0;
+      if (!breakdown)
+        hipLaunchKernelGGL(k_div_dev, dim3(grid_for(c->n)), dim3(256), 0, c->stream, w, w, c->d_scal + k + 1, c->n);
+      for (int i = 0; i < k; ++i) {
+        double t = cs[i] * Hc(i, k) + sn[i] * Hc(i + 1, k);
+        Hc(i + 1, k) = -sn[i] * Hc(i, k) + cs[i] * Hc(i + 1, k);
+        Hc(i, k) = t;
+      }
+      double den = std::hypot(Hc(k, k), Hc(k + 1, k));
+      cs[k] = Hc(k, k) / den;
+      sn[k] = Hc(k + 1, k) / den;
+      Hc(k, k) = den;
+      Hc(k + 1, k) = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      kused = k + 1;
+      if (std::fabs(g[k + 1]) <= rtol * beta0 || breakdown || r.its >= maxit) {
+        r.converged = std::fabs(g[k + 1]) <= rtol * beta0 || breakdown;
+        stop = true;
+        break;
+      }
+    }
+    for (int i = kused - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int j = i + 1; j < kused; ++j) s -= Hc(i, j) * y[j];
+      y[i] = s / Hc(i, i);
+    }
+    // t1 = V y ; x += P^-1 t1
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_t1, c->n);
+    for (int i = 0; i < kused; ++i) axpby(c, c->d_t1, y[i], c->V[i], 1.0);
+    prec(c->d_t1, c->d_z);
+    axpby(c, x, 1.0, c->d_z, 1.0);
+    if (r.converged || stop) break;
+    // restart: r = b - J x
+    matvec(c, u, Nu, S, dt_a, x, eps, c->d_t2);
+    hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_t2, b, -1.0, c->d_t2, c->n);
+    rvec = c->d_t2;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- Newton / SDIRK
+struct NewtonOut {
+  int its;
+  std::vector<int> gmres_its;
+  std::vector<double> nres;
+  bool converged;
+  bool nan;
+};
+
+NewtonOut newton(dgj_ctx* c, const double* S, double dt_a, double* u) {
+  NewtonOut o{0, {}, {}, true, false};
+  stage_residual(c, u, S, dt_a, c->d_N);
+  const double n0 = norm(c, c->d_N);
+  o.nres.push_back(n0);
+  if (!std::isfinite(n0)) { o.converged = false; o.nan = true; return o; }
+  double nrm = n0;
+  while (true) {
+    const double nu = norm(c, u);
+    if (nrm < c->sv.newton_rtol * n0 || nrm <= 1e-14 * nu) break;
+    if (o.its >= c->sv.newton_max) { o.converged = false; break; }
+    const double eps = nu * std::sqrt(EPS_HAT);
+    axpby(c, c->d_b, -1.0, c->d_N, 0.0);
+    GmresOut go = gmres(c, u, c->d_N, S, dt_a, eps, c->d_b, c->d_x);
+    o.gmres_its.push_back(go.its);
+    axpby(c, u, 1.0, c->d_x, 1.0);
+    stage_residual(c, u, S, dt_a, c->d_N);
+    nrm = norm(c, c->d_N);
+    o.nres.push_back(nrm);
+    o.its++;
+    if (!std::isfinite(nrm)) { o.converged = false; o.nan = true; break; }
+  }
+  return o;
+}
+
+void tableau(int scheme, double A[3][3], double b[3], int& s) {
+  std::memset(A, 0, sizeof(double) * 9);
+  if (scheme == DGJ_SDIRK2) {
+    const double lam = 1.0 - std::sqrt(2.0) / 2.0;
+    s = 2;
+    A[0][0] = lam;
+    A[1][0] = 1.0 - lam;
+    A[1][1] = lam;
+  } else if (scheme == DGJ_SDIRK3) {
+    // root of x^3 - 3x^2 + 3/2 x - 1/6 near 0.4358665 (third-order condition)
+    double lam = 0.4358665215;
+    for (int it = 0; it < 20; ++it) {
+      double f = ((lam - 3.0) * lam + 1.5) * lam - 1.0 / 6.0;
+      double df = (3.0 * lam - 6.0) * lam + 1.5;
+      lam -= f / df;
+    }
+    s = 3;
+    A[0][0] = lam;
+    A[1][0] = (1.0 - lam) / 2.0;
+    A[1][1] = lam;
+    A[2][0] = (-6.0 * lam * lam + 16.0 * lam - 1.0) / 4.0;
+    A[2][1] = (6.0 * lam * lam - 20.0 * lam + 5.0) / 4.0;
+    A[2][2] = lam;
+  } else {
+    fail(DGJ_EINVAL, "unknown scheme %d", scheme);
+  }
+  for (int i = 0; i < s; ++i) b[i] = A[s - 1][i];
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* solver, void* hip_stream, dgj_ctx** out) {
+  if (!out) return DGJ_EINVAL;
+  *out = nullptr;
+  if (!mesh || !phys || !solver) return DGJ_EINVAL;
+  dgj_ctx* c = new dgj_ctx();
+  int rc = guarded(c, [&]() -> int {
+    if (mesh->dim != 2 && mesh->dim != 3) fail(DGJ_EINVAL, "dim must be 2 or 3");
+    if (mesh->n_elem <= 0 || !mesh->elem_h || !mesh->face_nbr || !mesh->elem_origin)
+      fail(DGJ_EINVAL, "mesh arrays missing or empty mesh");
+    if (mesh->P < 1) fail(DGJ_EINVAL, "P must be >= 1");
+    if (!shape_supported(mesh->dim, mesh->P + 1, mesh->nq))
+      fail(DGJ_EUNSUPPORTED, "dim %d, P %d, nq %d not built (nq = P+2, P <= %d)", mesh->dim, mesh->P, mesh->nq,
+           mesh->dim == 2 ? 5 : 4);
+    if (solver->gmres_restart < 1 || solver->gmres_restart > 60) fail(DGJ_EINVAL, "gmres_restart must be in 1..60");
+    if (solver->scheme != DGJ_SDIRK2 && solver->scheme != DGJ_SDIRK3) fail(DGJ_EINVAL, "scheme must be SDIRK2 or SDIRK3");
+    if (solver->pc_precision < 0 || solver->pc_precision > 2) fail(DGJ_EINVAL, "bad pc_precision");
+    if (phys->flux_mode < 0 || phys->flux_mode > 2 || phys->riemann < 0 || phys->riemann > 1)
+      fail(DGJ_EINVAL, "bad flux options");
+    c->dim = mesh->dim;
+    c->P = mesh->P;
+    c->nq = mesh->nq;
+    c->N = mesh->P + 1;
+    c->NV = c->dim + 2;
+    c->NM = (int)std::pow(c->N, c->dim);
+    c->NB = c->NV * c->NM;
+    if (c->NB > 1024) fail(DGJ_EUNSUPPORTED, "block size %d > 1024", c->NB);
+    c->n_elem = mesh->n_elem;
+    c->n = c->n_elem * c->NB;
+    c->ph = Phys{phys->gamma, phys->Pr, phys->Re, phys->Ma, phys->T_ref_K, phys->visc_law, phys->flux_mode,
+                 phys->riemann};
+    c->sv = *solver;
+    c->stream = (hipStream_t)hip_stream;
+    const int D = c->dim, NF = 2 * D, GEO = 2 * D + 2;
+    const long E = c->n_elem;
+    std::vector<double> geo(E * GEO), beta(E * NF);
+    std::vector<int> nbr(mesh->face_nbr, mesh->face_nbr + E * NF);
+    for (long e = 0; e < E; ++e) {
+      const double* h = mesh->elem_h + e * D;
+      double detJ = 1.0;
+      for (int j = 0; j < D; ++j) {
+        if (!(h[j] > 0.0)) fail(DGJ_EINVAL, "element %ld has non-positive size", e);
+        geo[e * GEO + j] = 2.0 / h[j];
+        detJ *= h[j] / 2.0;
+      }
+      geo[e * GEO + D] = detJ;
+      geo[e * GEO + D + 1] = 1.0 / detJ;
+      for (int a = 0; a < D; ++a) {
+        double fd = 1.0;
+        for (int t = 0; t < D; ++t)
+          if (t != a) fd *= h[t] / 2.0;
+        geo[e * GEO + D + 2 + a] = fd;
+      }
+    }
+    for (long e = 0; e < E; ++e) {
+      for (int f = 0; f < NF; ++f) {
+        long en = nbr[e * NF + f];
+        if (en < 0 || en >= E) fail(DGJ_EUNSUPPORTED, "element %ld face %d: boundary faces are not supported", e, f);
+        const int a = f / 2;
+        long eL = (f & 1) ? e : en, eR = (f & 1) ? en : e;
+        double volL = 1.0, volR = 1.0, area = 1.0;
+        for (int j = 0; j < D; ++j) {
+          volL *= mesh->elem_h[eL * D + j];
+          volR *= mesh->elem_h[eR * D + j];
+          if (j != a) area *= mesh->elem_h[eL * D + j];
+        }
+        double hf = std::min(volL, volR) / area;
+        beta[e * NF + f] = (c->P + 1.0) * (c->P + 1.0) / hf;
+      }
+    }
+    std::vector<double> tab = build_tables(c->P, c->nq);
+    HIPCHK(hipMalloc(&c->d_geo, geo.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_beta, beta.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_nbr, nbr.size() * sizeof(int)));
+    HIPCHK(hipMalloc(&c->d_origin, E * D * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_tab, tab.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(c->d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_beta, beta.data(), beta.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_origin, mesh->elem_origin, E * D * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&c->d_part, RED_BLOCKS * 8 * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_scal, 64 * sizeof(double)));
+    HIPCHK(hipHostMalloc(&c->h_scal, 64 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipMalloc(&c->d_chi, 8 * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_status, E * sizeof(int)));
+    const size_t vb = c->n * sizeof(double);
+    c->V.assign(c->sv.gmres_restart + 1, nullptr);
+    for (auto& p : c->V) HIPCHK(hipMalloc(&p, vb));
+    double** bufs[] = {&c->d_z, &c->d_w, &c->d_t1, &c->d_t2, &c->d_ubar, &c->d_N, &c->d_S, &c->d_b, &c->d_x,
+                       &c->d_un, &c->d_E[0], &c->d_E[1], &c->d_E[2], &c->d_pa, &c->d_pb};
+    for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
+    return DGJ_OK;
+  });
+  if (rc != DGJ_OK) {
+    fprintf(stderr, "dgj_create: %s\n", c->err.c_str());
+    dgj_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return DGJ_OK;
+}
+
+void dgj_destroy(dgj_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  free_pc(c);
+  double* ptrs[] = {c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
+                    c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_E[0], c->d_E[1],
+                    c->d_E[2], c->d_E[3], c->d_pa, c->d_pb};
+  for (double* p : ptrs)
+    if (p) hipFree(p);
+  if (c->d_nbr) hipFree(c->d_nbr);
+  if (c->d_status) hipFree(c->d_status);
+  if (c->h_scal) hipHostFree(c->h_scal);
+  for (double* p : c->V)
+    if (p) hipFree(p);
+  delete c;
+}
+
+int dgj_sizes(const dgj_ctx* c, int64_t* n) {
+  if (!c || !n) return DGJ_EINVAL;
+  *n = c->n;
+  return DGJ_OK;
+}
+
+const char* dgj_last_error(const dgj_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int dgj_project_tgv(dgj_ctx* c, const double* noise, double amp, double* u) {
+  if (!c || !u) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    long total = c->n_elem * c->NM;
+#define X(d, n, q)                                                                                          \
+  if (c->dim == d && c->N == n && c->nq == q) {                                                              \
+    hipLaunchKernelGGL((k_project_tgv<d, n, q>), dim3((total + 127) / 128), dim3(128), 0, c->stream,         \
+                       c->d_origin, c->d_geo, c->d_tab, c->ph, c->n_elem, noise, amp, u);                   \
+  } else
+    DGJ_FOR_SHAPES(X)
+#undef X
+    fail(DGJ_EUNSUPPORTED, "unsupported shape");
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_residual(dgj_ctx* c, const double* u, double* R) {
+  if (!c || !u || !R) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    residual(c, u, R);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_stage_residual(dgj_ctx* c, const double* u, const double* S, double dt_a, double* Nout) {
+  if (!c || !u || !S || !Nout) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    stage_residual(c, u, S, dt_a, Nout);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_jfnk_matvec(dgj_ctx* c, const double* u, const double* Nu, const double* S, double dt_a, const double* v,
+                    double eps, double* Jv) {
+  if (!c || !u || !Nu || !S || !v || !Jv) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!(eps > 0.0)) eps = norm(c, u) * std::sqrt(EPS_HAT);
+    if (!(eps > 0.0) || !std::isfinite(eps)) fail(DGJ_ENAN, "jfnk_matvec: eps not positive and finite");
+    matvec(c, u, Nu, S, dt_a, v, eps, Jv);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_precond_build(dgj_ctx* c, const double* up, double dt_a) {
+  if (!c || !up) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    precond_build(c, up, dt_a);
+    return DGJ_OK;
+  });
+}
+
+int dgj_precond_apply(dgj_ctx* c, const double* q, double* out) {
+  if (!c || !q || !out || q == out) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!c->pc_ready) fail(DGJ_EINVAL, "precond_apply: no preconditioner built");
+    precond_apply(c, q, out);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_precond_diag_inverse(dgj_ctx* c, double* out) {
+  if (!c || !out) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!c->pc_ready) fail(DGJ_EINVAL, "no preconditioner built");
+    long total = c->n_elem * (long)c->NB * c->NB;
+    if (c->pc_prec == DGJ_PC_F64)
+      hipLaunchKernelGGL(k_dinv_export<double>, dim3(grid_for(total)), dim3(256), 0, c->stream,
+                         (const double*)c->d_Dinv, c->NB, c->n_elem, out);
+    else if (c->pc_prec == DGJ_PC_F32)
+      hipLaunchKernelGGL(k_dinv_export<float>, dim3(grid_for(total)), dim3(256), 0, c->stream,
+                         (const float*)c->d_Dinv, c->NB, c->n_elem, out);
+    else
+      hipLaunchKernelGGL(k_dinv_export<__hip_bfloat16>, dim3(grid_for(total)), dim3(256), 0, c->stream,
+                         (const __hip_bfloat16*)c->d_Dinv, c->NB, c->n_elem, out);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_gmres(dgj_ctx* c, const double* u, const double* Nu, const double* S, double dt_a, double eps,
+              const double* b, double* x, int32_t* iters) {
+  if (!c || !u || !Nu || !S || !b || !x) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!(eps > 0.0)) eps = norm(c, u) * std::sqrt(EPS_HAT);
+    GmresOut o = gmres(c, u, Nu, S, dt_a, eps, b, x);
+    if (iters) *iters = o.its;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DGJ_OK;
+  });
+}
+
+int dgj_newton(dgj_ctx* c, const double* S, double dt_a, double* u, int32_t* newton_its, int32_t* gmres_its) {
+  if (!c || !S || !u) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    NewtonOut o = newton(c, S, dt_a, u);
+    if (newton_its) *newton_its = o.its;
+    if (gmres_its)
+      for (size_t i = 0; i < o.gmres_its.size(); ++i) gmres_its[i] = o.gmres_its[i];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (o.nan) fail(DGJ_ENAN, "newton: non-finite residual norm");
+    if (!o.converged) fail(DGJ_ENOTCONV, "newton: not converged in %d iterations", o.its);
+    return DGJ_OK;
+  });
+}
+
+int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
+  if (!c || !u || !(dt > 0.0)) return DGJ_EINVAL;
+  dgj_step_stats local{};
+  dgj_step_stats* st = stats ? stats : &local;
+  std::memset(st, 0, sizeof(*st));
+  using clk = std::chrono::steady_clock;
+  auto t0 = clk::now();
+  c->residual_evals = 0;
+  int rc = guarded(c, [&]() -> int {
+    double A[3][3], b[3];
+    int s = 0;
+    tableau(c->sv.scheme, A, b, s);
+    st->stages = s;
+    const double dt_a = dt * A[0][0];
+    if (!c->pc_ready || c->pc_age >= c->sv.pc_freeze || c->pc_dta != dt_a) {
+      auto tb = clk::now();
+      precond_build(c, u, dt_a);
+      st->pc_built = 1;
+      st->t_pc_build_ms = std::chrono::duration<double, std::milli>(clk::now() - tb).count();
+    }
+    copy(c, c->d_un, u);
+    for (int m = 0; m < s; ++m) {
+      // S_m = u^n + sum_{i<m} a^mi E^i
+      copy(c, c->d_S, c->d_un);
+      for (int i = 0; i < m; ++i) axpby(c, c->d_S, A[m][i], c->d_E[i], 1.0);
+      copy(c, c->d_ubar, c->d_S);
+      NewtonOut o = newton(c, c->d_S, dt * A[m][m], c->d_ubar);
+      st->newton_its[m] = o.its;
+      for (size_t i = 0; i < o.gmres_its.size() && i < 64; ++i) st->gmres_its[m][i] = o.gmres_its[i];
+      for (size_t i = 0; i < o.nres.size() && i < 65; ++i) st->nres[m][i] = o.nres[i];
+      if (o.nan) fail(DGJ_ENAN, "stage %d: non-finite residual", m);
+      if (!o.converged) fail(DGJ_ENOTCONV, "stage %d: Newton not converged in %d iterations", m, o.its);
+      // E^m = (u^m - S_m) / a^mm
+      hipLaunchKernelGGL(k_sub_div, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_E[m], c->d_ubar, c->d_S,
+                         A[m][m], c->n);
+    }
+    // u^{n+1} = u^n + sum b^i E^i
+    copy(c, c->d_t1, c->d_un);
+    for (int i = 0; i < s; ++i) axpby(c, c->d_t1, b[i], c->d_E[i], 1.0);
+    copy(c, u, c->d_t1);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pc_age++;
+    return DGJ_OK;
+  });
+  st->status = rc;
+  st->residual_evals = c->residual_evals;
+  st->t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  return rc;
+}
+
+}  // extern "C"

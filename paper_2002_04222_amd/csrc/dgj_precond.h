@@ -1,0 +1,557 @@
+// Block-relaxed-Jacobi preconditioner BRJ(J) of arxiv 2002.04222
+// (Sec. 4.2.2, Eq. 27-31): build of the element blocks
+//   D_e = I - dt a M^-1 A_e,
+//   A_e = sum_j (D_j B)^T diag(w|J| dH_j/dQ) B + sum_ij (D_j B)^T diag(w|J| dH_j/d grad_i Q) (D_i B)
+//         - sum_f (B^G_f)^T diag(w^G |J^G| dHhat/dQ^-) B^G_f,
+// the forward-difference face flux Jacobians dHhat/dQ^+- of Eq. 31, the
+// explicit inverse of D_e by blocked Gauss-Jordan elimination with partial
+// pivoting, and the apply of Eq. 28 (diagonal GEMV with the stored inverse,
+// off-diagonal product on the fly from neighbour traces).
+//
+// Storage: Dinv[e][col][row] (column-major per element, nb = NV*NM rows) in
+// double, float or bfloat16; face Jacobians Jp[e][f][p][k][l] (unscaled) in
+// double or float.
+#pragma once
+#include "dgj_kernels.h"
+
+namespace dgj {
+
+// value of the element's trace at face point p of its face f: sum over modes
+template <int D, int N, int Q>
+__device__ __forceinline__ void trace_point(const Tab& tb, const StateIn& in, long X, const double* gX, int f,
+                                            int p, double* U, double (*gU)[D + 2]) {
+  using S = Shape<D, N, Q>;
+  constexpr int NV = S::NV, NM = S::NM;
+  const int ax = f >> 1, s = f & 1;
+  int tax[2] = {0, 0};
+  tang_axes<D>(ax, tax);
+  int bq[3] = {0, 0, 0};
+  bq[tax[0]] = p % Q;
+  if (D == 3) bq[tax[1]] = p / Q;
+  double dref[D][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    U[v] = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) dref[j][v] = 0.0;
+  }
+  for (int m = 0; m < NM; ++m) {
+    int mi[3] = {0, 0, 0};
+    split<D, N>(m, mi);
+    double val[D], der[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (k == ax) { val[k] = tb.phiE[s * N + mi[k]]; der[k] = tb.dphiE[s * N + mi[k]]; }
+      else { val[k] = tb.B[bq[k] * N + mi[k]]; der[k] = tb.Dq[bq[k] * N + mi[k]]; }
+    }
+    double phi = 1.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) phi *= val[k];
+    double dphi[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double t = 1.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) t *= (k == j) ? der[k] : val[k];
+      dphi[j] = t;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double uu = in(X * S::NB + v * NM + m);
+      U[v] += phi * uu;
+#pragma unroll
+      for (int j = 0; j < D; ++j) dref[j][v] += dphi[j] * uu;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gU[j][v] = dref[j][v] * gX[j];
+}
+
+// ---------------------------------------------------------------- volume flux Jacobians
+// Wt[e][q][j][b][k][l]: b = 0 -> dH_j,k/dQ_l at fixed gradient (exact, forward-mode
+// duals), b = 1+i -> dH_j,k/d(d_i Q_l) = -K (exact, G is linear in grad Q);
+// scaled by w_q |J| dxi_j (and dxi_i for b > 0).
+template <int D, int N, int Q, int NT>
+__global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, const double* __restrict__ geo,
+                                                  const double* __restrict__ tables, Phys ph, long n_elem,
+                                                  double* __restrict__ Wt) {
+  using S = Shape<D, N, Q>;
+  using L = ResidualLDS<D, N, Q>;
+  constexpr int NV = S::NV, NQ = S::NQ;
+  __shared__ double smem[L::TABSZ + S::NB + L::VOL];
+  const long e = blockIdx.x;
+  if (e >= n_elem) return;
+  Tab tb = load_tables<N, Q>(tables, smem);
+  double* sU = smem + L::TABSZ;
+  double* W = sU + S::NB;
+  double* sQ = W + L::V_T1 + L::V_T2;
+  for (int i = threadIdx.x; i < S::NB; i += NT) sU[i] = u[e * S::NB + i];
+  __syncthreads();
+  vol_forward<D, N, Q, NT>(tb, sU, W, sQ);
+  __syncthreads();
+  const double* g = geo + e * S::GEO;
+  constexpr int PER_Q = D * (D + 1) * NV * NV;
+  for (int q = threadIdx.x; q < NQ; q += NT) {
+    double U[NV], gU[D][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      U[v] = sQ[v * NQ + q];
+#pragma unroll
+      for (int j = 0; j < D; ++j) gU[j][v] = sQ[(1 + j) * NV * NQ + v * NQ + q] * g[j];
+    }
+    double wq = g[D];
+    {
+      int r = q;
+#pragma unroll
+      for (int k = 0; k < D; ++k) { wq *= tb.w[r % Q]; r /= Q; }
+    }
+    double* out = Wt + (e * NQ + q) * (long)PER_Q;
+    // dH/dQ via duals, one flux direction at a time to bound register use
+    Dual<NV> Ud[NV];
+#pragma unroll
+    for (int l = 0; l < NV; ++l) { Ud[l] = Dual<NV>(U[l]); Ud[l].d[l] = 1.0; }
+    {
+      Dual<NV> F[D][NV], G[D][NV];
+      euler_flux<D, Dual<NV>>(ph, Ud, F);
+      viscous_flux<D, Dual<NV>, double>(ph, Ud, gU, G);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double sc = wq * g[j];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+          for (int l = 0; l < NV; ++l)
+            out[((j * (D + 1) + 0) * NV + k) * NV + l] = (F[j][k].d[l] - G[j][k].d[l]) * sc;
+      }
+    }
+    // dH/d grad Q = -K: probe the linear viscous flux with unit gradients
+    for (int i = 0; i < D; ++i) {
+      for (int l = 0; l < NV; ++l) {
+        double E[D][NV], G[D][NV];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) E[a][v] = (a == i && v == l) ? 1.0 : 0.0;
+        viscous_flux<D, double, double>(ph, U, E, G);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          double sc = wq * g[j] * g[i];
+#pragma unroll
+          for (int k = 0; k < NV; ++k) out[((j * (D + 1) + 1 + i) * NV + k) * NV + l] = -G[j][k] * sc;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- face flux Jacobians
+// One thread per (element, face, face point): forward differences of Eq. 31
+// of the own-side numerical flux (outward normal of the element) with respect
+// to the own trace (JmW, weighted by w^G |J^G|, feeds the diagonal block) and
+// to the neighbour trace (Jp, stored for the off-diagonal product), at fixed
+// trace gradients.
+template <int D, int N, int Q, typename TJ>
+__global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ nbr, const double* __restrict__ geo,
+                          const double* __restrict__ beta, const double* __restrict__ tables, Phys ph, long n_elem,
+                          const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp) {
+  using S = Shape<D, N, Q>;
+  constexpr int NV = S::NV, NQF = S::NQF, NF = S::NF;
+  __shared__ double st[S::TAB];
+  Tab tb = load_tables<N, Q>(tables, st);
+  __syncthreads();
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_elem * NF * NQF) return;
+  const int p = gid % NQF;
+  const int f = (gid / NQF) % NF;
+  const long e = gid / (NQF * NF);
+  const long en = nbr[e * NF + f];
+  const int ax = f >> 1, s = f & 1;
+  StateIn in{u, nullptr, 0.0};
+  double Uo[NV], Un[NV], go[D][NV], gn[D][NV];
+  trace_point<D, N, Q>(tb, in, e, geo + e * S::GEO, f, p, Uo, go);
+  trace_point<D, N, Q>(tb, in, en, geo + en * S::GEO, f ^ 1, p, Un, gn);
+  double nrm[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
+  const double b = beta[e * NF + f];
+  double H0[NV], H1[NV];
+  face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H0, nullptr);
+  const double* g = geo + e * S::GEO;
+  double wf = g[D + 2 + ax];
+  {
+    int tax[2] = {0, 0};
+    tang_axes<D>(ax, tax);
+    wf *= tb.w[p % Q];
+    if (D == 3) wf *= tb.w[p / Q];
+  }
+  const long base = ((e * NF + f) * NQF + p) * NV * NV;
+  for (int l = 0; l < NV; ++l) {
+    const double chi = chi_dev[l];
+    double save = Uo[l];
+    Uo[l] = save + chi;
+    face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H1, nullptr);
+    Uo[l] = save;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) JmW[base + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
+    save = Un[l];
+    Un[l] = save + chi;
+    face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H1, nullptr);
+    Un[l] = save;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Jp[base + k * NV + l] = (TJ)((H1[k] - H0[k]) / chi);
+  }
+}
+
+// ---------------------------------------------------------------- block assembly
+// One workgroup per (element, k, l): the NM x NM sub-block A_kl of A_e, then
+// D = I - dt_a / |J| A written column-major into Dm[e][col][row].
+template <int D, int N, int Q, int NT, typename TD>
+__global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ Wt, const double* __restrict__ JmW,
+                                                     const double* __restrict__ geo, const double* __restrict__ tables,
+                                                     double dt_a, long n_elem, TD* __restrict__ Dm) {
+  using S = Shape<D, N, Q>;
+  constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF, NB = S::NB;
+  constexpr int PER_Q = D * (D + 1) * NV * NV;
+  constexpr int NO = (NM * NM + NT - 1) / NT;
+  __shared__ double st[S::TAB];
+  __shared__ double Z[NM];
+  __shared__ double wv[D + 1];
+  Tab tb = load_tables<N, Q>(tables, st);
+  const long blk = blockIdx.x;
+  const long e = blk / (NV * NV);
+  const int kl = blk % (NV * NV);
+  const int k = kl / NV, l = kl % NV;
+  if (e >= n_elem) return;
+  double acc[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+  __syncthreads();
+  const int tid = threadIdx.x;
+  for (int q = 0; q < NQ; ++q) {
+    int aq[3] = {0, 0, 0};
+    {
+      int r = q;
+#pragma unroll
+      for (int x = 0; x < D; ++x) { aq[x] = r % Q; r /= Q; }
+    }
+    const double* wq = Wt + (e * NQ + q) * (long)PER_Q;
+    for (int j = 0; j < D; ++j) {
+      if (tid <= D) wv[tid] = wq[((j * (D + 1) + tid) * NV + k) * NV + l];
+      __syncthreads();
+      for (int n = tid; n < NM; n += NT) {
+        int ni[3] = {0, 0, 0};
+        split<D, N>(n, ni);
+        double bv[D], dv[D];
+#pragma unroll
+        for (int x = 0; x < D; ++x) { bv[x] = tb.B[aq[x] * N + ni[x]]; dv[x] = tb.Dq[aq[x] * N + ni[x]]; }
+        double psi0 = 1.0;
+#pragma unroll
+        for (int x = 0; x < D; ++x) psi0 *= bv[x];
+        double z = wv[0] * psi0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          double t = 1.0;
+#pragma unroll
+          for (int x = 0; x < D; ++x) t *= (x == i) ? dv[x] : bv[x];
+          z += wv[1 + i] * t;
+        }
+        Z[n] = z;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        int oi = tid + o * NT;
+        if (oi < NM * NM) {
+          int m = oi / NM, n = oi % NM;
+          int mi[3] = {0, 0, 0};
+          split<D, N>(m, mi);
+          double t = 1.0;
+#pragma unroll
+          for (int x = 0; x < D; ++x) t *= (x == j) ? tb.Dq[aq[x] * N + mi[x]] : tb.B[aq[x] * N + mi[x]];
+          acc[o] += t * Z[n];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // own-side face term
+  for (int f = 0; f < NF; ++f) {
+    const int ax = f >> 1, s = f & 1;
+    int tax[2] = {0, 0};
+    tang_axes<D>(ax, tax);
+    for (int p = 0; p < NQF; ++p) {
+      int bq[3] = {0, 0, 0};
+      bq[tax[0]] = p % Q;
+      if (D == 3) bq[tax[1]] = p / Q;
+      const double jw = JmW[((e * NF + f) * NQF + p) * NV * NV + k * NV + l];
+      for (int n = tid; n < NM; n += NT) {
+        int ni[3] = {0, 0, 0};
+        split<D, N>(n, ni);
+        double t = 1.0;
+#pragma unroll
+        for (int x = 0; x < D; ++x) t *= (x == ax) ? tb.phiE[s * N + ni[x]] : tb.B[bq[x] * N + ni[x]];
+        Z[n] = t * jw;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        int oi = tid + o * NT;
+        if (oi < NM * NM) {
+          int m = oi / NM, n = oi % NM;
+          int mi[3] = {0, 0, 0};
+          split<D, N>(m, mi);
+          double t = 1.0;
+#pragma unroll
+          for (int x = 0; x < D; ++x) t *= (x == ax) ? tb.phiE[s * N + mi[x]] : tb.B[bq[x] * N + mi[x]];
+          acc[o] -= t * Z[n];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double sc = dt_a * geo[e * S::GEO + D + 1];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    int oi = tid + o * NT;
+    if (oi < NM * NM) {
+      int m = oi / NM, n = oi % NM;
+      int row = k * NM + m, col = l * NM + n;
+      double val = ((row == col) ? 1.0 : 0.0) - sc * acc[o];
+      Dm[(e * NB + col) * (long)NB + row] = (TD)val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- blocked Gauss-Jordan inverse
+// In-place inversion of each nb x nb block (column-major) by Gauss-Jordan
+// elimination with partial pivoting, processed in column panels of width KB
+// held in LDS: the panel is eliminated on all rows (row swaps applied to the
+// panel only), then the other columns take the panel's row swaps and the
+// rank-KB update x <- x(non-pivot rows) + Panel * x(pivot rows); finally the
+// columns are unscrambled in reverse order of the swaps.  One thread per row.
+// status[e] = 1 if a zero pivot was met.
+template <typename T, int KB>
+__global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restrict__ status) {
+  extern __shared__ unsigned char smraw[];
+  T* Pan = reinterpret_cast<T*>(smraw);                       // [nb][KB+1]
+  int* piv = reinterpret_cast<int*>(Pan + (size_t)nb * (KB + 1));
+  int* perm = piv + nb;
+  T* redv = reinterpret_cast<T*>(perm + nb);                   // [32]
+  int* redi = reinterpret_cast<int*>(redv + 32);               // [32]
+  const long e = blockIdx.x;
+  if (e >= n_elem) return;
+  T* Ae = A + e * (long)nb * nb;
+  const int r = threadIdx.x;
+  const int nw = (blockDim.x + 63) / 64;
+  const int lane = r & 63, wid = r >> 6;
+  int bad = 0;
+  for (int k0 = 0; k0 < nb; k0 += KB) {
+    const int kb = (nb - k0) < KB ? (nb - k0) : KB;
+    if (r < nb)
+      for (int c = 0; c < kb; ++c) Pan[r * (KB + 1) + c] = Ae[(long)(k0 + c) * nb + r];
+    __syncthreads();
+    for (int t = 0; t < kb; ++t) {
+      const int k = k0 + t;
+      // pivot: largest |Pan[r][t]| over rows r >= k (smallest row on ties)
+      T best = (T)-1;
+      int bi = nb;
+      if (r < nb && r >= k) { T x = Pan[r * (KB + 1) + t]; best = x < (T)0 ? -x : x; bi = r; }
+      for (int off = 32; off > 0; off >>= 1) {
+        T ob = __shfl_down(best, off, 64);
+        int oi = __shfl_down(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) { redv[wid] = best; redi[wid] = bi; }
+      __syncthreads();
+      if (r == 0) {
+        T b = redv[0];
+        int i = redi[0];
+        for (int w = 1; w < nw; ++w)
+          if (redv[w] > b || (redv[w] == b && redi[w] < i)) { b = redv[w]; i = redi[w]; }
+        piv[k] = i;
+        redi[0] = i;
+        redv[0] = b;
+      }
+      __syncthreads();
+      const int p = redi[0];
+      if (!(redv[0] > (T)0)) bad = 1;
+      // swap rows k and p of the panel
+      if (p != k && r < kb) {
+        T a0 = Pan[k * (KB + 1) + r], a1 = Pan[p * (KB + 1) + r];
+        Pan[k * (KB + 1) + r] = a1;
+        Pan[p * (KB + 1) + r] = a0;
+      }
+      __syncthreads();
+      const T pv = Pan[k * (KB + 1) + t];
+      const T pinv = bad ? (T)0 : (T)1 / pv;
+      // scale the pivot row
+      if (r < kb) {
+        T x = Pan[k * (KB + 1) + r];
+        Pan[k * (KB + 1) + r] = (r == t) ? pinv : x * pinv;
+      }
+      __syncthreads();
+      // eliminate column t from every other row
+      if (r < nb && r != k) {
+        T fct = Pan[r * (KB + 1) + t];
+        for (int c = 0; c < kb; ++c) {
+          if (c == t) continue;
+          Pan[r * (KB + 1) + c] -= fct * Pan[k * (KB + 1) + c];
+        }
+        Pan[r * (KB + 1) + t] = -fct * pinv;
+      }
+      __syncthreads();
+    }
+    // write the panel back; composed row permutation of this panel
+    if (r < nb) {
+      for (int c = 0; c < kb; ++c) Ae[(long)(k0 + c) * nb + r] = Pan[r * (KB + 1) + c];
+      perm[r] = r;
+    }
+    __syncthreads();
+    if (r == 0)
+      for (int t = 0; t < kb; ++t) {
+        int k = k0 + t, p = piv[k];
+        int tmp = perm[k]; perm[k] = perm[p]; perm[p] = tmp;
+      }
+    __syncthreads();
+    const int myperm = r < nb ? perm[r] : 0;
+    const bool pivrow = (r >= k0) && (r < k0 + kb);
+    T prow[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) prow[t] = (r < nb && t < kb) ? Pan[r * (KB + 1) + t] : (T)0;
+    for (int j = 0; j < nb; ++j) {
+      if (j >= k0 && j < k0 + kb) continue;
+      T* col = Ae + (long)j * nb;
+      T x = (r < nb) ? col[myperm] : (T)0;
+      T acc = pivrow ? (T)0 : x;
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        if (t < kb) acc += prow[t] * col[perm[k0 + t]];
+      }
+      __syncthreads();
+      if (r < nb) col[r] = acc;
+      __syncthreads();
+    }
+  }
+  // unscramble columns
+  for (int k = nb - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k && r < nb) {
+      T a0 = Ae[(long)k * nb + r], a1 = Ae[(long)p * nb + r];
+      Ae[(long)k * nb + r] = a1;
+      Ae[(long)p * nb + r] = a0;
+    }
+    __syncthreads();
+  }
+  if (r == 0) status[e] = bad;
+}
+
+// ---------------------------------------------------------------- apply
+template <typename T> __device__ __forceinline__ float to_f(T x) { return (float)x; }
+template <> __device__ __forceinline__ float to_f<__hip_bfloat16>(__hip_bfloat16 x) { return __bfloat162float(x); }
+
+template <typename T> struct AccT { using type = float; };
+template <> struct AccT<double> { using type = double; };
+
+template <typename T>
+__device__ __forceinline__ typename AccT<T>::type ld_acc(const T* p) { return (typename AccT<T>::type)to_f<T>(*p); }
+template <>
+__device__ __forceinline__ double ld_acc<double>(const double* p) { return *p; }
+
+template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { return (double)(*p); }
+
+// One BRJ sweep for element e (one workgroup, blockDim >= nb):
+//   r = q - (L+U) qold   (skipped when first),  out = omega Dinv r + (1-omega) qold.
+// (L+U) qold = -dt_a / |J| sum_f -(B^G_f)^T diag(w^G|J^G| Jp (B^G_f' qold_nbr)).
+template <int D, int N, int Q, int NT, typename T, typename TJ>
+__global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, const double* __restrict__ qold,
+                                                   double* __restrict__ out, const T* __restrict__ Dinv,
+                                                   const TJ* __restrict__ Jp, const int* __restrict__ nbr,
+                                                   const double* __restrict__ geo, const double* __restrict__ tables,
+                                                   double dt_a, double omega, int first, long n_elem) {
+  using S = Shape<D, N, Q>;
+  constexpr int NV = S::NV, NM = S::NM, NQF = S::NQF, NMF = S::NMF, NF = S::NF, NB = S::NB;
+  __shared__ double st[S::TAB];
+  __shared__ double sr[NB];
+  __shared__ double sacc[NB];
+  __shared__ double tvf[NV * NMF];
+  __shared__ double tpt[NV * NQF];
+  __shared__ double flx[NV * NQF];
+  Tab tb = load_tables<N, Q>(tables, st);
+  const long e = blockIdx.x;
+  if (e >= n_elem) return;
+  const int tid = threadIdx.x;
+  const double* g = geo + e * S::GEO;
+  for (int i = tid; i < NB; i += NT) { sr[i] = q[e * NB + i]; sacc[i] = 0.0; }
+  __syncthreads();
+  if (!first) {
+    for (int f = 0; f < NF; ++f) {
+      const int ax = f >> 1, s = f & 1;
+      const long en = nbr[e * NF + f];
+      const int sg = 1 - s;
+      int tax[2] = {0, 0};
+      tang_axes<D>(ax, tax);
+      for (int it = tid; it < NV * NMF; it += NT) {
+        int tm = it % NMF, v = it / NMF;
+        double sv = 0.0;
+#pragma unroll
+        for (int ia = 0; ia < N; ++ia) sv += tb.phiE[sg * N + ia] * qold[en * NB + v * NM + mode_of<D, N>(ax, ia, tm)];
+        tvf[it] = sv;
+      }
+      __syncthreads();
+      for (int it = tid; it < NV * NQF; it += NT) {
+        int p = it % NQF, v = it / NQF;
+        int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
+        double val = 0.0;
+        for (int tm = 0; tm < NMF; ++tm) {
+          int j0 = tm % N, j1 = (D == 3) ? tm / N : 0;
+          double bb = tb.B[b0 * N + j0] * ((D == 3) ? tb.B[b1 * N + j1] : 1.0);
+          val += bb * tvf[v * NMF + tm];
+        }
+        tpt[v * NQF + p] = val;
+      }
+      __syncthreads();
+      for (int it = tid; it < NV * NQF; it += NT) {
+        int p = it % NQF, k = it / NQF;
+        const TJ* J = Jp + ((e * NF + f) * NQF + p) * NV * NV + k * NV;
+        double sacc2 = 0.0;
+#pragma unroll
+        for (int l = 0; l < NV; ++l) sacc2 += jp_ld<TJ>(J + l) * tpt[l * NQF + p];
+        double wf = g[D + 2 + ax] * tb.w[p % Q];
+        if (D == 3) wf *= tb.w[p / Q];
+        flx[k * NQF + p] = sacc2 * wf;
+      }
+      __syncthreads();
+      for (int it = tid; it < NB; it += NT) {
+        int m = it % NM, v = it / NM;
+        int mi[3] = {0, 0, 0};
+        split<D, N>(m, mi);
+        int j0 = mi[tax[0]], j1 = (D == 3) ? mi[tax[1]] : 0;
+        double s2 = 0.0;
+        for (int p = 0; p < NQF; ++p) {
+          int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
+          double bb = tb.B[b0 * N + j0] * ((D == 3) ? tb.B[b1 * N + j1] : 1.0);
+          s2 += bb * flx[v * NQF + p];
+        }
+        sacc[it] -= tb.phiE[s * N + mi[ax]] * s2;
+      }
+      __syncthreads();
+    }
+    // r = q - (L+U) qold, (L+U) qold = -dt_a / |J| sacc
+    const double sc = dt_a * g[D + 1];
+    for (int i = tid; i < NB; i += NT) sr[i] = sr[i] + sc * sacc[i];
+    __syncthreads();
+  }
+  using A = typename AccT<T>::type;
+  const T* De = Dinv + e * (long)NB * NB;
+  for (int row = tid; row < NB; row += NT) {
+    A acc = (A)0;
+    for (int c = 0; c < NB; ++c) acc += ld_acc<T>(De + (long)c * NB + row) * (A)sr[c];
+    double res = omega * (double)acc;
+    if (!first && omega != 1.0) res += (1.0 - omega) * qold[e * NB + row];
+    out[e * NB + row] = res;
+  }
+}
+
+}  // namespace dgj
