@@ -1,0 +1,238 @@
+"""Benchmark of the implicit DG hot path on one MI355X.
+
+Workload (default): 3D Taylor-Green vortex on the periodic cube [0, 2 pi]^3,
+16^3 affine hexahedra, P = 3 (4^3 modes, 5^3 Gauss points), 5 conserved
+variables in FP64, Re 1600, Ma 0.1, SDIRK3 at CFL 20, GMRES(30) with rtol
+5e-2, BRJ(7), Newton tolerance 1e-8, preconditioner frozen for 10 steps.
+
+A timed "step" is one implicit SDIRK step (every stage: Newton, GMRES,
+Jacobian-free matvecs, BRJ sweeps); the timed region starts with a
+preconditioner build, as the first step of each freeze window does.
+
+Printed JSON line: value = DG residual DOFs/s delivered by the timed steps
+(per-variable DoF N_e (P+1)^d times residual evaluations, over the timed
+wall time), ms_per_step = implicit-step time, plus the residual kernel's own
+throughput, the dominant kernel's roofline figures and the CPU oracle
+baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--pc", default=None, help="preconditioner storage f64|f32|bf16 (default: workload's)")
+    ap.add_argument("--forms", action="store_true", help="also time the f32 and bf16 preconditioner forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, budget_s=20.0):
+    """The CPU oracle on the host cores: full residual evaluations of the
+    same workload until about budget_s seconds have passed."""
+    import numpy as np
+    import workloads as W
+    from oracle.dg import make_disc, initial_state
+    mesh = cfg.mesh()
+    disc = make_disc(cfg, mesh)
+    u0 = initial_state(disc, W.noise(disc.shape, cfg.seed), cfg.noise_amp)
+    n = 0
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    while True:
+        disc.residual(u0)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return {"value": cfg.dofs() * n / wall, "unit": "DOF/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": f"{n} full residual evaluations R(u) = M^-1 L(u) of the same workload "
+                      f"(u = projected initial state) in {wall:.1f} s wall, {cpu:.1f} s CPU; "
+                      f"host has {os.cpu_count()} logical CPUs"}
+
+
+def sweep_bytes(ctx, cfg, prec):
+    """Algorithmic HBM bytes of one BRJ sweep launch averaged over the J
+    sweeps of an apply: the stored block inverses once, the right-hand side
+    in and the result out, and for the J-1 sweeps with an off-diagonal
+    product the previous iterate and the face flux Jacobians."""
+    E = ctx.n_elem
+    nb = ctx.shape[1] * ctx.shape[2]
+    n = ctx.n_unknowns
+    sd = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    sj = 8 if prec == "f64" else 4
+    nqf = cfg.nq ** (cfg.dim - 1)
+    J = cfg.brj_sweeps
+    first = E * nb * nb * sd + 2 * n * 8
+    other = first + n * 8 + E * 2 * cfg.dim * nqf * (cfg.dim + 2) ** 2 * sj
+    return (first + (J - 1) * other) / J
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2002_04222_amd import Context
+
+    cfg = W.config(args.workload)
+    if args.pc:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, pc_precision=args.pc)
+    mesh = cfg.mesh()
+    dt = cfg.dt()
+    log(f"workload {cfg.name}: {mesh.n_elem} elements, P={cfg.P}, dt={dt:.4f}, pc={cfg.pc_precision}")
+
+    def make(prec):
+        ctx = Context(mesh, cfg, pc_precision=prec)
+        u = ctx.empty()
+        noise = torch.tensor(W.noise(ctx.shape, cfg.seed), dtype=torch.float64, device="cuda")
+        ctx.project_tgv(noise, cfg.noise_amp, u)
+        return ctx, u
+
+    ctx, u = make(cfg.pc_precision)
+    stream = torch.cuda.current_stream()
+
+    # ---- residual kernel throughput (inputs resident, back-to-back launches)
+    R = ctx.empty()
+    for _ in range(5):
+        ctx.residual(u, R)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.kernel_reps):
+        ctx.residual(u, R)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    res_ms = ev0.elapsed_time(ev1) / args.kernel_reps
+    log(f"residual kernel {res_ms:.4f} ms")
+
+    # ---- warmup steps
+    for i in range(args.warmup):
+        st = ctx.sdirk_step(u, dt)
+        log(f"warmup step {i}: newton {st['newton_its']} gmres {st['gmres_its']} {st['t_total_ms']:.1f} ms")
+
+    # ---- timed steps: a preconditioner build then K steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tb0 = time.perf_counter()
+    ctx.precond_build(u, dt * _lam(cfg.scheme))
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb0) * 1e3
+    stats = []
+    evals = 0
+    for i in range(args.steps):
+        st = ctx.sdirk_step(u, dt)
+        stats.append(st)
+        evals += st["residual_evals"]
+        log(f"step {i}: newton {st['newton_its']} gmres {st['gmres_its']} {st['t_total_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = cfg.dofs() * evals / wall
+
+    # ---- dominant kernel: BRJ sweep (block-inverse GEMV + off-diagonal product)
+    q = R.clone()
+    o = ctx.empty()
+    for _ in range(3):
+        ctx.precond_apply(q, o)
+    reps = max(5, args.kernel_reps // 5)
+    ev0.record(stream)
+    for _ in range(reps):
+        ctx.precond_apply(q, o)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sweep_ms = ev0.elapsed_time(ev1) / (reps * cfg.brj_sweeps)
+    sb = sweep_bytes(ctx, cfg, cfg.pc_precision)
+    achieved = sb / (sweep_ms * 1e-3) / 1e9
+    log(f"BRJ sweep {sweep_ms:.4f} ms, {achieved:.0f} GB/s")
+
+    out = {
+        "metric": "DG residual DOFs/s + implicit-step time, mixed/learned vs plain FP64 @1e-8",
+        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg.name, "elements": mesh.n_elem, "P": cfg.P, "nq": cfg.nq, "dim": cfg.dim,
+                   "dofs_per_var": cfg.dofs(), "unknowns": ctx.n_unknowns, "scheme": cfg.scheme,
+                   "cfl": cfg.cfl, "dt": dt, "Re": cfg.Re, "Ma": cfg.Ma, "newton_rtol": cfg.newton_rtol,
+                   "gmres": f"GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol}", "brj_sweeps": cfg.brj_sweeps,
+                   "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze},
+        "roofline": {"bound": "hbm", "kernel": "k_brj_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": sb, "avg_launch_ms": sweep_ms},
+        "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3)},
+        "pc_build_ms": build_ms,
+        "residual_evals": evals,
+        "newton_its": [s["newton_its"] for s in stats],
+        "gmres_its": [s["gmres_its"] for s in stats],
+    }
+
+    if args.forms:
+        base_u = None
+        forms = {}
+        for prec in ("f64", "f32", "bf16"):
+            c2, u2 = make(prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            its = []
+            for i in range(min(args.steps, 3)):
+                st = c2.sdirk_step(u2, dt)
+                its.append(st["newton_its"])
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / min(args.steps, 3)
+            uh = u2.cpu().numpy()
+            if base_u is None:
+                base_u = uh
+            forms[prec] = {"ms_per_step": ms, "newton_its": its,
+                           "rel_diff_vs_f64": float(np.linalg.norm(uh - base_u) / np.linalg.norm(base_u))}
+            c2.close()
+            log(f"form {prec}: {ms:.1f} ms/step")
+        for prec in forms:
+            forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+def _lam(scheme):
+    import numpy as np
+    if scheme == "sdirk2":
+        return 1.0 - np.sqrt(2.0) / 2.0
+    lam = 0.4358665215
+    for _ in range(20):
+        lam -= (((lam - 3.0) * lam + 1.5) * lam - 1.0 / 6.0) / ((3.0 * lam - 6.0) * lam + 1.5)
+    return lam
+
+
+if __name__ == "__main__":
+    main()

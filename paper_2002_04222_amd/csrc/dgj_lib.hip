@@ -184,9 +184,13 @@ __global__ void k_sub_div(double* __restrict__ y, const double* __restrict__ x, 
     y[i] = (x[i] - z[i]) / a;
 }
 
-__global__ void k_f32_to_bf16(const float* __restrict__ x, __hip_bfloat16* __restrict__ y, long n) {
+__global__ void k_f64_to_bf16(const double* __restrict__ x, __hip_bfloat16* __restrict__ y, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    y[i] = __float2bfloat16(x[i]);
+    y[i] = __float2bfloat16((float)x[i]);
+}
+__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
 }
 template <typename T>
 __global__ void k_dinv_export(const T* __restrict__ Dinv, int nb, long n_elem, double* __restrict__ out) {
@@ -504,12 +508,8 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
                        c->d_geo, c->d_beta, c->d_tab, c->ph, c->n_elem, c->d_chi, JmW, (float*)c->d_Jp);
   constexpr int NTA = 256;
   const long nblk = c->n_elem * S::NV * S::NV;
-  if (c->pc_prec == DGJ_PC_F64)
-    hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
-                       c->d_tab, dt_a, c->n_elem, (double*)Dm);
-  else
-    hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, float>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
-                       c->d_tab, dt_a, c->n_elem, (float*)Dm);
+  hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
+                     c->d_tab, dt_a, c->n_elem, (double*)Dm);
 }
 
 template <typename T, int KB>
@@ -562,18 +562,21 @@ void precond_build(dgj_ctx* c, const double* up, double dt_a) {
   void* Dm = nullptr;
   HIPCHK(hipMalloc(&Wt, (size_t)c->n_elem * nq_vol * c->dim * (c->dim + 1) * c->NV * c->NV * sizeof(double)));
   HIPCHK(hipMalloc(&JmW, (size_t)c->n_elem * 2 * c->dim * nqf * c->NV * c->NV * sizeof(double)));
+  // blocks are assembled and inverted in FP64 (LU-based inversion in double,
+  // as the paper's dgetrf/dgetri), then stored in the chosen precision
   const size_t blk = (size_t)c->n_elem * c->NB * c->NB;
   if (prec == DGJ_PC_F64) Dm = c->d_Dinv;
-  else if (prec == DGJ_PC_F32) Dm = c->d_Dinv;
-  else HIPCHK(hipMalloc(&Dm, blk * sizeof(float)));
+  else HIPCHK(hipMalloc(&Dm, blk * sizeof(double)));
 #define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm); } else
   DGJ_FOR_SHAPES(X)
 #undef X
   fail(DGJ_EUNSUPPORTED, "unsupported shape");
-  if (prec == DGJ_PC_F64) invert<double, 32>(c, (double*)Dm);
-  else invert<float, 32>(c, (float*)Dm);
-  if (prec == DGJ_PC_BF16)
-    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const float*)Dm,
+  invert<double, 32>(c, (double*)Dm);
+  if (prec == DGJ_PC_F32)
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const double*)Dm,
+                       (float*)c->d_Dinv, (long)blk);
+  else if (prec == DGJ_PC_BF16)
+    hipLaunchKernelGGL(k_f64_to_bf16, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const double*)Dm,
                        (__hip_bfloat16*)c->d_Dinv, (long)blk);
   HIPCHK(hipGetLastError());
   std::vector<int> st(c->n_elem);
@@ -581,7 +584,7 @@ void precond_build(dgj_ctx* c, const double* up, double dt_a) {
   HIPCHK(hipStreamSynchronize(c->stream));
   hipFree(Wt);
   hipFree(JmW);
-  if (prec == DGJ_PC_BF16) hipFree(Dm);
+  if (prec != DGJ_PC_F64) hipFree(Dm);
   for (long e = 0; e < c->n_elem; ++e)
     if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
   c->pc_ready = true;
@@ -1001,7 +1004,7 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
     tableau(c->sv.scheme, A, b, s);
     st->stages = s;
     const double dt_a = dt * A[0][0];
-    if (!c->pc_ready || c->pc_age >= c->sv.pc_freeze || c->pc_dta != dt_a) {
+    if (!c->pc_ready || c->pc_age >= c->sv.pc_freeze || std::fabs(c->pc_dta - dt_a) > 1e-12 * std::fabs(dt_a)) {
       auto tb = clk::now();
       precond_build(c, u, dt_a);
       st->pc_built = 1;
