@@ -16,6 +16,7 @@
 #include "../../include/dgj.h"
 #include "dgj_kernels.h"
 #include "dgj_precond.h"
+#include "dgj_residual.h"
 
 using namespace dgj;
 
@@ -98,6 +99,16 @@ std::vector<double> build_tables(int P, int Q) {
     for (int n = 0; n < N; ++n) {
       t[2 * Q * N + Q + s * N + n] = v[n];
       t[2 * Q * N + Q + 2 * N + s * N + n] = d[n];
+    }
+  }
+  // Lagrange basis of the Gauss points evaluated at xi = -1 and +1
+  for (int s = 0; s < 2; ++s) {
+    const double xe = s == 0 ? -1.0 : 1.0;
+    for (int a = 0; a < Q; ++a) {
+      double l = 1.0;
+      for (int b = 0; b < Q; ++b)
+        if (b != a) l *= (xe - x[b]) / (x[a] - x[b]);
+      t.push_back(l);
     }
   }
   return t;
@@ -306,6 +317,8 @@ struct dgj_ctx {
   int* d_nbr = nullptr;
   double* d_origin = nullptr;
   double* d_tab = nullptr;
+  std::vector<double> h_tab;   // tables + Lagrange weights, passed by value to the residual kernels
+  double *d_trace = nullptr, *d_X = nullptr, *d_Lvol = nullptr;   // residual scratch
   // reductions
   double* d_part = nullptr;    // [RED_BLOCKS * 8]
   double* d_scal = nullptr;    // scalars [64]
@@ -387,8 +400,16 @@ bool shape_supported(int D, int N, int Q) {
 
 template <int D, int N, int Q>
 void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
-  constexpr int NT = res_threads<D, N, Q>();
-  hipLaunchKernelGGL((k_residual<D, N, Q, NT>), dim3(c->n_elem), dim3(NT), 0, c->stream, a);
+  using K = ResK<D, N, Q>;
+  TabK<N, Q> tk;
+  static_assert(sizeof(TabK<N, Q>) == sizeof(double) * (2 * Q * N + Q + 4 * N + 2 * Q), "TabK layout");
+  std::memcpy(&tk, c->h_tab.data(), sizeof(tk));
+  constexpr int NTV = D == 2 ? 64 : 128;
+  constexpr int NTL = D == 2 ? 64 : 256;
+  hipLaunchKernelGGL((k_res_vol<D, N, Q, NTV>), dim3(c->n_elem), dim3(NTV), 0, c->stream, a, tk, c->d_trace, c->d_Lvol);
+  const long nf = c->n_elem * D * K::NQF;
+  hipLaunchKernelGGL((k_res_face<D, N, Q>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, a, tk, c->d_trace, c->d_X);
+  hipLaunchKernelGGL((k_res_lift<D, N, Q, NTL>), dim3(c->n_elem), dim3(NTL), 0, c->stream, a, tk, c->d_Lvol, c->d_X);
 }
 
 void launch_residual(dgj_ctx* c, const ResArgs& a) {
@@ -822,6 +843,13 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       }
     }
     std::vector<double> tab = build_tables(c->P, c->nq);
+    c->h_tab = tab;
+    {
+      const long nqf = (long)std::pow(c->nq, D - 1);
+      HIPCHK(hipMalloc(&c->d_trace, (size_t)E * NF * (D + 1) * c->NV * nqf * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_X, (size_t)E * D * (D + 1) * c->NV * nqf * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_Lvol, (size_t)E * c->NB * sizeof(double)));
+    }
     HIPCHK(hipMalloc(&c->d_geo, geo.size() * sizeof(double)));
     HIPCHK(hipMalloc(&c->d_beta, beta.size() * sizeof(double)));
     HIPCHK(hipMalloc(&c->d_nbr, nbr.size() * sizeof(int)));
@@ -859,7 +887,7 @@ void dgj_destroy(dgj_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   free_pc(c);
-  double* ptrs[] = {c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
+  double* ptrs[] = {c->d_trace, c->d_X, c->d_Lvol, c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
                     c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_E[0], c->d_E[1],
                     c->d_E[2], c->d_E[3], c->d_pa, c->d_pb};
   for (double* p : ptrs)

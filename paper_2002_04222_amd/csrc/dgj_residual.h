@@ -1,0 +1,461 @@
+// DG residual R(u) = M^-1 L(u) of arxiv 2002.04222 (Sec. 3.1, Eq. 13) as
+// three kernels:
+//   k_res_vol   per element: sum-factorised backward transform and reference
+//               gradients at the Gauss points, pointwise H_j = F_j - G_j
+//               scaled by w|J| dxi_j, transposed contraction with the
+//               derivative bases -> Lvol[e]; and the element's own face
+//               traces (value and physical gradient at every face point,
+//               by exact Lagrange interpolation from the Gauss points to
+//               xi = +-1) -> trace[e][f][c][v][p].
+//   k_res_face  one thread per face point, each interior face once, in its
+//               canonical orientation (left = the element that meets it
+//               with side 1, normal +e_axis): Roe/LLF flux and interior-
+//               penalty fluxes -> X[e][axis][k][v][p] = w^G|J^G| (Hhat, Shat_j).
+//   k_res_lift  per element: Lvol plus lifting of -phi Hhat_own + grad phi . Shat
+//               over the 2D faces, times 1/|J| (M^-1 of the orthonormal basis on
+//               affine elements), then the R / N / Jv epilogue.
+// Each face flux is computed once, so the element sums of the residual
+// cancel exactly across interior faces.  The 1D tables are passed by value
+// as kernel arguments: with the fully unrolled contractions their entries
+// are uniform across the wavefront and sit in scalar registers.
+#pragma once
+#include "dgj_kernels.h"
+
+namespace dgj {
+
+template <int N, int Q>
+struct TabK {
+  double B[Q][N];
+  double Dq[Q][N];
+  double w[Q];
+  double phiE[2][N];
+  double dphiE[2][N];
+  double lag[2][Q];   // Lagrange basis of the Gauss points at xi = -1, +1
+};
+
+template <int D, int N, int Q>
+struct ResK {
+  using S = Shape<D, N, Q>;
+  static constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NMF = S::NMF, NF = S::NF, NB = S::NB;
+  // sizes of the per-element scratch arrays
+  static constexpr int TRACE = NF * (D + 1) * NV * NQF;    // trace[e]
+  static constexpr int XF = D * (D + 1) * NV * NQF;        // X[e] (faces normal to each axis, side 1)
+  static constexpr int T1 = (D == 3) ? 2 * NV * Q * N * N : 2 * NV * Q * N;
+  static constexpr int T2 = (D == 3) ? 3 * NV * Q * Q * N : 0;
+  static constexpr int QG = (D + 1) * NV * NQ;
+};
+
+// ---------------------------------------------------------------- volume + traces
+template <int D, int N, int Q, int NT>
+__global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
+                                                double* __restrict__ Lvol) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
+  __shared__ double sU[NB];
+  __shared__ double W[K::T1 + K::T2];
+  __shared__ double sQ[K::QG];
+  const long e = blockIdx.x;
+  if (e >= a.n_elem) return;
+  const int tid = threadIdx.x;
+  const double* g = a.geo + e * K::S::GEO;
+  double dxi[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dxi[j] = g[j];
+  const double detJ = g[D];
+  for (int i = tid; i < NB; i += NT) sU[i] = a.in(e * NB + i);
+  __syncthreads();
+
+  if constexpr (D == 3) {
+    double* T1 = W;                  // [2][v][a0][i1 + N i2]
+    double* T2 = W + K::T1;          // [3][v][i2][a0 + Q a1]
+    constexpr int n1 = NV * Q * N * N, n2 = NV * N * Q * Q;
+    for (int pc = tid; pc < NV * N * N; pc += NT) {
+      const int v = pc / (N * N), r = pc % (N * N);
+      double x[N];
+#pragma unroll
+      for (int i0 = 0; i0 < N; ++i0) x[i0] = sU[v * NM + i0 + N * r];
+#pragma unroll
+      for (int a0 = 0; a0 < Q; ++a0) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i0 = 0; i0 < N; ++i0) { s0 += tk.B[a0][i0] * x[i0]; s1 += tk.Dq[a0][i0] * x[i0]; }
+        T1[(v * Q + a0) * N * N + r] = s0;
+        T1[n1 + (v * Q + a0) * N * N + r] = s1;
+      }
+    }
+    __syncthreads();
+    for (int pc = tid; pc < NV * Q * N; pc += NT) {
+      const int v = pc / (Q * N), a0 = (pc / N) % Q, i2 = pc % N;
+      double x[N], xd[N];
+#pragma unroll
+      for (int i1 = 0; i1 < N; ++i1) {
+        x[i1] = T1[(v * Q + a0) * N * N + i1 + N * i2];
+        xd[i1] = T1[n1 + (v * Q + a0) * N * N + i1 + N * i2];
+      }
+#pragma unroll
+      for (int a1 = 0; a1 < Q; ++a1) {
+        double s0 = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int i1 = 0; i1 < N; ++i1) {
+          s0 += tk.B[a1][i1] * x[i1];
+          sx += tk.B[a1][i1] * xd[i1];
+          sy += tk.Dq[a1][i1] * x[i1];
+        }
+        const int o = (v * N + i2) * Q * Q + a0 + Q * a1;
+        T2[o] = s0;
+        T2[n2 + o] = sx;
+        T2[2 * n2 + o] = sy;
+      }
+    }
+    __syncthreads();
+    for (int pc = tid; pc < NV * Q * Q; pc += NT) {
+      const int v = pc / (Q * Q), r = pc % (Q * Q);
+      double x[N], xx[N], xy[N];
+#pragma unroll
+      for (int i2 = 0; i2 < N; ++i2) {
+        const int o = (v * N + i2) * Q * Q + r;
+        x[i2] = T2[o];
+        xx[i2] = T2[n2 + o];
+        xy[i2] = T2[2 * n2 + o];
+      }
+#pragma unroll
+      for (int a2 = 0; a2 < Q; ++a2) {
+        double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int i2 = 0; i2 < N; ++i2) {
+          s0 += tk.B[a2][i2] * x[i2];
+          sx += tk.B[a2][i2] * xx[i2];
+          sy += tk.B[a2][i2] * xy[i2];
+          sz += tk.Dq[a2][i2] * x[i2];
+        }
+        const int q = r + Q * Q * a2;
+        sQ[v * NQ + q] = s0;
+        sQ[NV * NQ + v * NQ + q] = sx;
+        sQ[2 * NV * NQ + v * NQ + q] = sy;
+        sQ[3 * NV * NQ + v * NQ + q] = sz;
+      }
+    }
+  } else {
+    double* T1 = W;                  // [2][v][i1][a0]
+    constexpr int n1 = NV * N * Q;
+    for (int pc = tid; pc < NV * N; pc += NT) {
+      const int v = pc / N, i1 = pc % N;
+      double x[N];
+#pragma unroll
+      for (int i0 = 0; i0 < N; ++i0) x[i0] = sU[v * NM + i0 + N * i1];
+#pragma unroll
+      for (int a0 = 0; a0 < Q; ++a0) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i0 = 0; i0 < N; ++i0) { s0 += tk.B[a0][i0] * x[i0]; s1 += tk.Dq[a0][i0] * x[i0]; }
+        T1[(v * N + i1) * Q + a0] = s0;
+        T1[n1 + (v * N + i1) * Q + a0] = s1;
+      }
+    }
+    __syncthreads();
+    for (int pc = tid; pc < NV * Q; pc += NT) {
+      const int v = pc / Q, a0 = pc % Q;
+      double x[N], xd[N];
+#pragma unroll
+      for (int i1 = 0; i1 < N; ++i1) { x[i1] = T1[(v * N + i1) * Q + a0]; xd[i1] = T1[n1 + (v * N + i1) * Q + a0]; }
+#pragma unroll
+      for (int a1 = 0; a1 < Q; ++a1) {
+        double s0 = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int i1 = 0; i1 < N; ++i1) {
+          s0 += tk.B[a1][i1] * x[i1];
+          sx += tk.B[a1][i1] * xd[i1];
+          sy += tk.Dq[a1][i1] * x[i1];
+        }
+        const int q = a0 + Q * a1;
+        sQ[v * NQ + q] = s0;
+        sQ[NV * NQ + v * NQ + q] = sx;
+        sQ[2 * NV * NQ + v * NQ + q] = sy;
+      }
+    }
+  }
+  __syncthreads();
+
+  // own face traces: value and physical gradient at the face points
+  {
+    double* tr = trace + e * (long)K::TRACE;
+    for (int it = tid; it < K::TRACE; it += NT) {
+      const int p = it % NQF;
+      const int v = (it / NQF) % NV;
+      const int c = (it / (NQF * NV)) % (D + 1);
+      const int f = it / (NQF * NV * (D + 1));
+      const int ax = f >> 1, s = f & 1;
+      // volume point index of (a along ax, tangential p)
+      int qstride = 1, base = 0;
+      {
+        int t[2] = {0, 0};
+        tang_axes<D>(ax, t);
+        int st[3] = {1, Q, Q * Q};
+        qstride = st[ax];
+        base = (p % Q) * st[t[0]];
+        if (D == 3) base += (p / Q) * st[t[1]];
+      }
+      const double* y = sQ + c * NV * NQ + v * NQ + base;
+      double acc = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < Q; ++aa) acc += tk.lag[s][aa] * y[aa * qstride];
+      tr[it] = (c == 0) ? acc : acc * dxi[c - 1];
+    }
+  }
+  __syncthreads();   // the flux loop below overwrites the gradients read above
+
+  // pointwise volume flux, scaled by w |J| dxi_j (overwrites the gradients)
+  for (int q = tid; q < NQ; q += NT) {
+    double U[NV], gU[D][NV], F[D][NV], G[D][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      U[v] = sQ[v * NQ + q];
+#pragma unroll
+      for (int j = 0; j < D; ++j) gU[j][v] = sQ[(1 + j) * NV * NQ + v * NQ + q] * dxi[j];
+    }
+    euler_flux<D, double>(a.ph, U, F);
+    viscous_flux<D, double, double>(a.ph, U, gU, G);
+    double wq = detJ;
+    {
+      int r = q;
+#pragma unroll
+      for (int k = 0; k < D; ++k) { wq *= tk.w[r % Q]; r /= Q; }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sQ[(1 + j) * NV * NQ + v * NQ + q] = (F[j][v] - G[j][v]) * (wq * dxi[j]);
+  }
+  __syncthreads();
+
+  // transposed contraction with the derivative bases
+  double* out = Lvol + e * (long)NB;
+  if constexpr (D == 3) {
+    const double* Hx = sQ + NV * NQ;
+    const double* Hy = sQ + 2 * NV * NQ;
+    const double* Hz = sQ + 3 * NV * NQ;
+    double* U1 = W;                              // [3][v][i2][a0 + Q a1]
+    double* U2 = W + 3 * NV * N * Q * Q;         // [2][v][a0][i1 + N i2]
+    constexpr int n1 = NV * N * Q * Q, n2 = NV * Q * N * N;
+    for (int pc = tid; pc < NV * Q * Q; pc += NT) {
+      const int v = pc / (Q * Q), r = pc % (Q * Q);
+      double hx[Q], hy[Q], hz[Q];
+#pragma unroll
+      for (int a2 = 0; a2 < Q; ++a2) {
+        hx[a2] = Hx[v * NQ + r + Q * Q * a2];
+        hy[a2] = Hy[v * NQ + r + Q * Q * a2];
+        hz[a2] = Hz[v * NQ + r + Q * Q * a2];
+      }
+#pragma unroll
+      for (int i2 = 0; i2 < N; ++i2) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < Q; ++a2) {
+          sx += tk.B[a2][i2] * hx[a2];
+          sy += tk.B[a2][i2] * hy[a2];
+          sz += tk.Dq[a2][i2] * hz[a2];
+        }
+        const int o = (v * N + i2) * Q * Q + r;
+        U1[o] = sx;
+        U1[n1 + o] = sy;
+        U1[2 * n1 + o] = sz;
+      }
+    }
+    __syncthreads();
+    for (int pc = tid; pc < NV * Q * N; pc += NT) {
+      const int v = pc / (Q * N), a0 = (pc / N) % Q, i2 = pc % N;
+      double x[Q], y[Q], z[Q];
+#pragma unroll
+      for (int a1 = 0; a1 < Q; ++a1) {
+        const int o = (v * N + i2) * Q * Q + a0 + Q * a1;
+        x[a1] = U1[o];
+        y[a1] = U1[n1 + o];
+        z[a1] = U1[2 * n1 + o];
+      }
+#pragma unroll
+      for (int i1 = 0; i1 < N; ++i1) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int a1 = 0; a1 < Q; ++a1) {
+          sa += tk.B[a1][i1] * x[a1];
+          sb += tk.Dq[a1][i1] * y[a1] + tk.B[a1][i1] * z[a1];
+        }
+        const int o = (v * Q + a0) * N * N + i1 + N * i2;
+        U2[o] = sa;
+        U2[n2 + o] = sb;
+      }
+    }
+    __syncthreads();
+    for (int pc = tid; pc < NV * N * N; pc += NT) {
+      const int v = pc / (N * N), r = pc % (N * N);
+      double x[Q], y[Q];
+#pragma unroll
+      for (int a0 = 0; a0 < Q; ++a0) {
+        x[a0] = U2[(v * Q + a0) * N * N + r];
+        y[a0] = U2[n2 + (v * Q + a0) * N * N + r];
+      }
+#pragma unroll
+      for (int i0 = 0; i0 < N; ++i0) {
+        double s = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < Q; ++a0) s += tk.Dq[a0][i0] * x[a0] + tk.B[a0][i0] * y[a0];
+        out[v * NM + i0 + N * r] = s;
+      }
+    }
+  } else {
+    const double* Hx = sQ + NV * NQ;
+    const double* Hy = sQ + 2 * NV * NQ;
+    double* U1 = W;                              // [2][v][i1][a0]
+    constexpr int n1 = NV * N * Q;
+    for (int pc = tid; pc < NV * Q; pc += NT) {
+      const int v = pc / Q, a0 = pc % Q;
+      double hx[Q], hy[Q];
+#pragma unroll
+      for (int a1 = 0; a1 < Q; ++a1) { hx[a1] = Hx[v * NQ + a0 + Q * a1]; hy[a1] = Hy[v * NQ + a0 + Q * a1]; }
+#pragma unroll
+      for (int i1 = 0; i1 < N; ++i1) {
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int a1 = 0; a1 < Q; ++a1) { sx += tk.B[a1][i1] * hx[a1]; sy += tk.Dq[a1][i1] * hy[a1]; }
+        U1[(v * N + i1) * Q + a0] = sx;
+        U1[n1 + (v * N + i1) * Q + a0] = sy;
+      }
+    }
+    __syncthreads();
+    for (int pc = tid; pc < NV * N; pc += NT) {
+      const int v = pc / N, i1 = pc % N;
+      double x[Q], y[Q];
+#pragma unroll
+      for (int a0 = 0; a0 < Q; ++a0) { x[a0] = U1[(v * N + i1) * Q + a0]; y[a0] = U1[n1 + (v * N + i1) * Q + a0]; }
+#pragma unroll
+      for (int i0 = 0; i0 < N; ++i0) {
+        double s = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < Q; ++a0) s += tk.Dq[a0][i0] * x[a0] + tk.B[a0][i0] * y[a0];
+        out[v * NM + i0 + N * i1] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- face fluxes
+template <int D, int N, int Q>
+__global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, const double* __restrict__ trace,
+                                                  double* __restrict__ X) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NQF = K::NQF, NF = K::NF;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= a.n_elem * D * NQF) return;
+  const int p = gid % NQF;
+  const int ax = (gid / NQF) % D;
+  const long e = gid / (NQF * D);
+  const long en = a.nbr[e * NF + 2 * ax + 1];
+  const double* tL = trace + e * (long)K::TRACE + (2 * ax + 1) * (D + 1) * NV * NQF;
+  const double* tR = trace + en * (long)K::TRACE + (2 * ax) * (D + 1) * NV * NQF;
+  double UL[NV], UR[NV], gL[D][NV], gR[D][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    UL[v] = tL[v * NQF + p];
+    UR[v] = tR[v * NQF + p];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      gL[j][v] = tL[((1 + j) * NV + v) * NQF + p];
+      gR[j][v] = tR[((1 + j) * NV + v) * NQF + p];
+    }
+  }
+  double nrm[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? 1.0 : 0.0;
+  double H[NV], Sf[D][NV];
+  face_flux<D>(a.ph, UL, UR, gL, gR, nrm, a.beta[e * NF + 2 * ax + 1], H, Sf);
+  double wf = a.geo[e * K::S::GEO + D + 2 + ax] * tk.w[p % Q];
+  if (D == 3) wf *= tk.w[p / Q];
+  double* o = X + e * (long)K::XF + ax * (D + 1) * NV * NQF;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    o[v * NQF + p] = wf * H[v];
+#pragma unroll
+    for (int j = 0; j < D; ++j) o[((1 + j) * NV + v) * NQF + p] = wf * Sf[j][v];
+  }
+}
+
+// ---------------------------------------------------------------- lift + epilogue
+template <int D, int N, int Q, int NT>
+__global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const double* __restrict__ Lvol,
+                                                 const double* __restrict__ X) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NM = K::NM, NQF = K::NQF, NMF = K::NMF, NF = K::NF, NB = K::NB;
+  __shared__ double sA[NF * (D + 1) * NV * NQF];
+  __shared__ double sF[NF * 2 * NV * NMF];
+  const long e = blockIdx.x;
+  if (e >= a.n_elem) return;
+  const int tid = threadIdx.x;
+  const double* g = a.geo + e * K::S::GEO;
+  // face data in the element's own orientation and scaling
+  for (int it = tid; it < NF * (D + 1) * NV * NQF; it += NT) {
+    const int p = it % NQF;
+    const int v = (it / NQF) % NV;
+    const int k = (it / (NQF * NV)) % (D + 1);
+    const int f = it / (NQF * NV * (D + 1));
+    const int ax = f >> 1, s = f & 1;
+    const long src = (s == 1) ? e : (long)a.nbr[e * NF + f];
+    const double x = X[src * (long)K::XF + ((ax * (D + 1) + k) * NV + v) * NQF + p];
+    // k = 0: -Hhat_own = -(+-Hhat); k >= 1: Shat_j dxi_j
+    sA[it] = (k == 0) ? ((s == 1) ? -x : x) : x * g[k - 1];
+  }
+  __syncthreads();
+  // tangential contraction to face modes: F0 (multiplies phi(+-1)), F1 (phi'(+-1))
+  for (int it = tid; it < NF * NV * NMF; it += NT) {
+    const int tm = it % NMF;
+    const int v = (it / NMF) % NV;
+    const int f = it / (NMF * NV);
+    const int ax = f >> 1;
+    int t[2] = {0, 0};
+    tang_axes<D>(ax, t);
+    const int j0 = tm % N, j1 = (D == 3) ? tm / N : 0;
+    const double* A = sA + f * (D + 1) * NV * NQF;
+    double f0 = 0.0, f1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < NQF; ++p) {
+      const int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
+      const double B0 = tk.B[b0][j0], D0 = tk.Dq[b0][j0];
+      const double B1 = (D == 3) ? tk.B[b1][j1] : 1.0;
+      const double D1 = (D == 3) ? tk.Dq[b1][j1] : 0.0;
+      const double bb = B0 * B1;
+      f0 += bb * A[v * NQF + p] + D0 * B1 * A[((1 + t[0]) * NV + v) * NQF + p];
+      if (D == 3) f0 += B0 * D1 * A[((1 + t[1]) * NV + v) * NQF + p];
+      f1 += bb * A[((1 + ax) * NV + v) * NQF + p];
+    }
+    sF[(f * 2 + 0) * NV * NMF + v * NMF + tm] = f0;
+    sF[(f * 2 + 1) * NV * NMF + v * NMF + tm] = f1;
+  }
+  __syncthreads();
+  const double invdetJ = g[D + 1];
+  for (int i = tid; i < NB; i += NT) {
+    const int m = i % NM, v = i / NM;
+    int mi[3] = {0, 0, 0};
+    split<D, N>(m, mi);
+    double L = Lvol[e * NB + i];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int ax = f >> 1, s = f & 1;
+      int t[2] = {0, 0};
+      tang_axes<D>(ax, t);
+      const int tm = mi[t[0]] + ((D == 3) ? N * mi[t[1]] : 0);
+      L += tk.phiE[s][mi[ax]] * sF[(f * 2 + 0) * NV * NMF + v * NMF + tm] +
+           tk.dphiE[s][mi[ax]] * sF[(f * 2 + 1) * NV * NMF + v * NMF + tm];
+    }
+    const long gi = e * NB + i;
+    const double R = L * invdetJ;
+    if (a.mode == RES_R) {
+      a.out[gi] = R;
+    } else {
+      const double w = a.in(gi);
+      const double Nw = (w - a.S[gi]) - a.dt_a * R;
+      if (a.mode == RES_N) a.out[gi] = Nw;
+      else a.out[gi] = (Nw - a.Nu[gi]) / a.in.eps;
+    }
+  }
+}
+
+}  // namespace dgj

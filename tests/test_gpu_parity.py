@@ -220,3 +220,42 @@ def test_sdirk_step_parity_tgv2d_workload():
     print("tgv2d step rel err", rel, st["newton_its"], st["gmres_its"], flush=True)
     assert st["newton_its"] == [s.newton_its for s in sto]
     assert rel <= 1e-10
+
+
+def test_residual_bitwise_repeatable_and_full_workload():
+    """At the benchmark's full size (3D Taylor-Green, 16^3 hexahedra, P=3,
+    the launch configuration bench.py times): residual and Jacobian-free
+    matvec against the oracle, and two evaluations bitwise identical."""
+    _case("full workload residual + matvec, 16^3 P=3")
+    cfg = W.config(2)
+    mesh = cfg.mesh()
+    from oracle.dg import make_disc
+    disc = make_disc(cfg, mesh)
+    ctx = _ctx(cfg, mesh)
+    noise = W.noise(disc.shape, cfg.seed)
+    u = ctx.empty()
+    ctx.project_tgv(_dev(noise), cfg.noise_amp, u)
+    u0 = initial_state(disc, noise, cfg.noise_amp)
+    R1, R2 = ctx.empty(), ctx.empty()
+    ctx.residual(_dev(u0), R1)
+    ctx.residual(_dev(u0), R2)
+    r1, r2 = _host(R1), _host(R2)
+    assert np.array_equal(r1, r2)
+    Ro = disc.residual(u0)
+    # At Ma 0.1 the single terms summed into R are of size U (c+|u|)(P+1)^2 2/h
+    # with U up to the energy coefficient (c = 1/Ma), ~1e5 here, and cancel
+    # down to |R| ~ 1..100: FP64 rounding of a few such terms bounds the
+    # agreement, 1e-12 of |R_v| plus 2e-16 (one unit roundoff) of the largest term.
+    h = mesh.elem_h.min()
+    term = np.abs(u0).max() * (1.0 / cfg.Ma + 1.0) * (cfg.P + 1) ** 2 * 2.0 / h
+    for v in range(disc.nv):
+        err = np.abs(r1[:, v] - Ro[:, v]).max()
+        assert err <= 1e-12 * np.abs(Ro[:, v]).max() + 2e-16 * term, (v, err, term)
+    dt_a = cfg.dt() * 0.4358665215
+    No = disc.stage_residual(u0, u0, dt_a)
+    v = W.random_vector(mesh.n_elem, 3, cfg.P, seed=5)
+    eps = OS.jfnk_eps(u0)
+    Jv = ctx.empty()
+    ctx.jfnk_matvec(_dev(u0), _dev(No), _dev(u0), dt_a, _dev(v), eps, Jv)
+    Jo = OS.jfnk_matvec(disc, u0, No, u0, dt_a, v, eps)
+    assert np.linalg.norm(_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
