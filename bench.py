@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--forms", action="store_true", help="also time the f32 and bf16 preconditioner forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--mode", default="full", choices=["full", "sweep", "copy"],
+                    help="sweep: only build the preconditioner and apply it (for counter runs); "
+                         "copy: a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -92,6 +95,25 @@ def sweep_bytes(ctx, cfg, prec):
     return (first + (J - 1) * other) / J
 
 
+def measured_traffic(prec):
+    """HBM bytes per BRJ sweep launch from the committed counter runs, or None
+    when the sweep kernel's source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_brj_sweep_tgv3d-16c-p3_traffic.md")
+    src = os.path.join(ROOT, "paper_2002_04222_amd", "csrc", "dgj_precond.h")
+    try:
+        rec = None
+        for line in open(path):
+            if line.startswith("TRAFFIC "):
+                rec = json.loads(line[len("TRAFFIC "):])
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if rec is None or rec.get("kernel_source_sha256_16") != h:
+            return None
+        return rec.get(prec)
+    except OSError:
+        return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,8 +140,25 @@ def main():
         ctx.project_tgv(noise, cfg.noise_amp, u)
         return ctx, u
 
+    if args.mode == "copy":
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
     ctx, u = make(cfg.pc_precision)
     stream = torch.cuda.current_stream()
+    if args.mode == "sweep":
+        ctx.precond_build(u, dt * _lam(cfg.scheme))
+        o = ctx.empty()
+        for _ in range(3):
+            ctx.precond_apply(u, o)
+        torch.cuda.synchronize()
+        log(f"3 BRJ applies ({3 * cfg.brj_sweeps} sweeps), {sweep_bytes(ctx, cfg, cfg.pc_precision):.4e} "
+            f"algorithmic bytes per sweep")
+        return
 
     # ---- residual kernel throughput (inputs resident, back-to-back launches)
     R = ctx.empty()
@@ -185,7 +224,8 @@ def main():
                    "gmres": f"GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol}", "brj_sweeps": cfg.brj_sweeps,
                    "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze},
         "roofline": {"bound": "hbm", "kernel": "k_brj_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(cfg.pc_precision) if args.workload == 2 else None,
                      "bytes_per_launch": sb, "avg_launch_ms": sweep_ms},
         "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3)},
         "pc_build_ms": build_ms,
