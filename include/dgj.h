@@ -100,6 +100,8 @@ typedef struct {
   int32_t status;
   double t_total_ms;          /* host wall time of the step */
   double t_pc_build_ms;       /* of which preconditioner build */
+  int32_t guess_used[4];      /* per stage: 0 S_m, 1 extrapolated, 2 learned */
+  double guess_norm[4][3];    /* ||N|| of the S_m, extrapolated and learned guesses (0 if not evaluated) */
 } dgj_step_stats;
 
 /* Create a context on the current device; hip_stream may be NULL (default
@@ -165,6 +167,57 @@ int dgj_newton(dgj_ctx *ctx, const double *S, double dt_a, double *u, int32_t *n
  * pc_freeze steps old, or when dt a^mm changed.  stats may be NULL.  On
  * DGJ_ENOTCONV / DGJ_ENAN u is left unchanged and stats tell where. */
 int dgj_sdirk_step(dgj_ctx *ctx, double *u, double dt, dgj_step_stats *stats);
+
+/* ---- Newton initial guess (not in the paper, which starts from S_m,
+ * Eq. 21).  A learned per-element MLP predicts the stage increment
+ * u^m - S_m from the element's S_m and its previous step's increment; the
+ * extrapolated guess S_m + (u^m - S_m)_{n-1} is the fallback, and whichever
+ * of S_m / extrapolated / learned has the smallest ||N|| starts Newton,
+ * which then stops at the same absolute tolerance alpha ||N(S_m)|| for all.
+ * mode: 0 S_m (the paper), 1 extrapolated, 2 learned with fallback. */
+int dgj_set_guess(dgj_ctx *ctx, int32_t mode);
+
+/* Record, for every stage of each following dgj_sdirk_step, S_m and the
+ * increment u^m - S_m into caller device buffers [stages][n_unknowns]
+ * (training data).  NULL stops recording. */
+int dgj_set_record(dgj_ctx *ctx, double *S_rec, double *inc_rec);
+
+/* MLP of `hidden` units per layer, n_in = 2 nb, n_out = nb (nb = (d+2)(P+1)^d):
+ * z1 = x W1 + b1, h1 = tanh z1, z2 = h1 W2 + b2, h2 = tanh z2, y = h2 W3 + b3.
+ * Parameters packed W1[n_in][H], b1[H], W2[H][H], b2[H], W3[H][n_out], b3[n_out]
+ * (FP32 master copy, BF16 copy for the matrix-core products).  params_host:
+ * host FP32 initial values (NULL: zeros).  For callers that train and use a
+ * learned guess. */
+int dgj_mlp_create(dgj_ctx *ctx, int32_t hidden, const float *params_host);
+int dgj_mlp_sizes(const dgj_ctx *ctx, int64_t *n_params, int32_t *n_in, int32_t *n_out);
+/* device FP32 parameter vectors of n_params values */
+int dgj_mlp_get_params(dgj_ctx *ctx, float *out);
+int dgj_mlp_set_params(dgj_ctx *ctx, const float *params);
+/* Per-variable scales (host, d+2 values each): features x = [S/s_in, inc_prev/s_inc];
+ * the network predicts the correction of the extrapolated increment,
+ * y = (inc - inc_prev)/s_out, and the learned guess is S + inc_prev + s_out y. */
+int dgj_mlp_set_scales(dgj_ctx *ctx, const double *s_in_host, const double *s_inc_host, const double *s_out_host);
+/* X[e][2 nb] (FP32) from S and the previous increment (FP64 states) */
+int dgj_mlp_features(dgj_ctx *ctx, const double *S, const double *inc_prev, float *X);
+/* T[e][nb] = (inc - inc_prev) / s_out (FP32) */
+int dgj_mlp_targets(dgj_ctx *ctx, const double *inc, const double *inc_prev, float *T);
+/* Train on records written through dgj_set_record over n_steps consecutive
+ * steps (S_rec, inc_rec: [n_steps][stages][n_unknowns]): sets the scales to
+ * the per-variable RMS of S, of the increments and of their step-to-step
+ * change, then runs `epochs` passes of Adam steps, one per (step >= 1,
+ * stage) pair with all elements as the batch.  *last_loss: mean loss of the
+ * last pass. */
+int dgj_mlp_fit(dgj_ctx *ctx, const double *S_rec, const double *inc_rec, int32_t n_steps, int32_t epochs, double lr,
+                double *last_loss);
+/* Copy the stored previous-step stage increments out ([3][n_unknowns], may
+ * be NULL) and/or in (may be NULL), to restart a run from a saved point. */
+int dgj_guess_state(dgj_ctx *ctx, double *inc_out, const double *inc_in);
+/* Y[rows][n_out] = MLP(X[rows][n_in]) */
+int dgj_mlp_forward(dgj_ctx *ctx, const float *X, int64_t rows, float *Y);
+/* gradient of mean((Y - T)^2) into grad (device FP32, may be NULL), loss to *loss (host, may be NULL) */
+int dgj_mlp_grad(dgj_ctx *ctx, const float *X, const float *T, int64_t rows, float *grad, double *loss);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error */
+int dgj_mlp_train_step(dgj_ctx *ctx, const float *X, const float *T, int64_t rows, double lr, double *loss);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,8 @@ class Solver(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("stages", C.c_int32), ("newton_its", C.c_int32 * 4), ("gmres_its", (C.c_int32 * 64) * 4),
                 ("nres", (C.c_double * 65) * 4), ("pc_built", C.c_int32), ("residual_evals", C.c_int32),
-                ("status", C.c_int32), ("t_total_ms", C.c_double), ("t_pc_build_ms", C.c_double)]
+                ("status", C.c_int32), ("t_total_ms", C.c_double), ("t_pc_build_ms", C.c_double),
+                ("guess_used", C.c_int32 * 4), ("guess_norm", (C.c_double * 3) * 4)]
 
     def to_dict(self):
         s = self.stages
@@ -58,6 +59,8 @@ class StepStats(C.Structure):
             "nres": [[self.nres[m][i] for i in range(self.newton_its[m] + 1)] for m in range(s)],
             "pc_built": self.pc_built, "residual_evals": self.residual_evals, "status": self.status,
             "t_total_ms": self.t_total_ms, "t_pc_build_ms": self.t_pc_build_ms,
+            "guess_used": [self.guess_used[m] for m in range(s)],
+            "guess_norm": [[self.guess_norm[m][k] for k in range(3)] for m in range(s)],
         }
 
 
@@ -87,6 +90,20 @@ def load_library(path: str = LIB_PATH):
         "dgj_gmres": ([vp, vp, vp, vp, dp, dp, vp, vp, i32p], C.c_int),
         "dgj_newton": ([vp, vp, dp, vp, i32p, i32p], C.c_int),
         "dgj_sdirk_step": ([vp, vp, dp, C.POINTER(StepStats)], C.c_int),
+        "dgj_set_guess": ([vp, C.c_int32], C.c_int),
+        "dgj_set_record": ([vp, vp, vp], C.c_int),
+        "dgj_mlp_create": ([vp, C.c_int32, vp], C.c_int),
+        "dgj_mlp_sizes": ([vp, i64p, i32p, i32p], C.c_int),
+        "dgj_mlp_get_params": ([vp, vp], C.c_int),
+        "dgj_mlp_set_params": ([vp, vp], C.c_int),
+        "dgj_mlp_set_scales": ([vp, vp, vp, vp], C.c_int),
+        "dgj_mlp_fit": ([vp, vp, vp, C.c_int32, C.c_int32, dp, C.POINTER(C.c_double)], C.c_int),
+        "dgj_guess_state": ([vp, vp, vp], C.c_int),
+        "dgj_mlp_features": ([vp, vp, vp, vp], C.c_int),
+        "dgj_mlp_targets": ([vp, vp, vp, vp], C.c_int),
+        "dgj_mlp_forward": ([vp, vp, C.c_int64, vp], C.c_int),
+        "dgj_mlp_grad": ([vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double)], C.c_int),
+        "dgj_mlp_train_step": ([vp, vp, vp, C.c_int64, dp, C.POINTER(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -96,12 +113,16 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-def _ptr(t) -> Optional[int]:
+def _ptr(t, dtype: str = "torch.float64") -> Optional[int]:
     if t is None:
         return None
-    if not t.is_cuda or t.dtype.__repr__() != "torch.float64" or not t.is_contiguous():
-        raise ValueError("expected a contiguous float64 device tensor")
+    if not t.is_cuda or repr(t.dtype) != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} device tensor")
     return t.data_ptr()
+
+
+def _fptr(t) -> Optional[int]:
+    return _ptr(t, "torch.float32")
 
 
 SCHEMES = {"sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3}
@@ -199,3 +220,61 @@ class Context:
         if rc != DGJ_OK:
             raise DgjError(rc, self.lib.dgj_last_error(self.h).decode())
         return st.to_dict()
+
+    # ---- Newton initial guess and the learned predictor
+    GUESS = {"paper": 0, "extrapolated": 1, "learned": 2}
+
+    def set_guess(self, mode):
+        self._check(self.lib.dgj_set_guess(self.h, self.GUESS[mode] if isinstance(mode, str) else int(mode)))
+
+    def set_record(self, S_rec, inc_rec):
+        self._check(self.lib.dgj_set_record(self.h, _ptr(S_rec), _ptr(inc_rec)))
+
+    def mlp_create(self, hidden, params=None):
+        arr = None
+        if params is not None:
+            arr = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.dgj_mlp_create(self.h, int(hidden), arr.ctypes.data if arr is not None else None))
+        npar, nin, nout = C.c_int64(), C.c_int32(), C.c_int32()
+        self._check(self.lib.dgj_mlp_sizes(self.h, C.byref(npar), C.byref(nin), C.byref(nout)))
+        self.mlp_n_params, self.mlp_n_in, self.mlp_n_out = npar.value, nin.value, nout.value
+
+    def mlp_get_params(self, out):
+        self._check(self.lib.dgj_mlp_get_params(self.h, _fptr(out)))
+
+    def mlp_set_params(self, params):
+        self._check(self.lib.dgj_mlp_set_params(self.h, _fptr(params)))
+
+    def mlp_set_scales(self, s_in, s_inc, s_out):
+        a = np.ascontiguousarray(s_in, dtype=np.float64)
+        b = np.ascontiguousarray(s_inc, dtype=np.float64)
+        c = np.ascontiguousarray(s_out, dtype=np.float64)
+        self._check(self.lib.dgj_mlp_set_scales(self.h, a.ctypes.data, b.ctypes.data, c.ctypes.data))
+
+    def mlp_fit(self, S_rec, inc_rec, n_steps, epochs, lr):
+        loss = C.c_double()
+        self._check(self.lib.dgj_mlp_fit(self.h, _ptr(S_rec), _ptr(inc_rec), int(n_steps), int(epochs), float(lr),
+                                         C.byref(loss)))
+        return loss.value
+
+    def guess_state(self, inc_out=None, inc_in=None):
+        self._check(self.lib.dgj_guess_state(self.h, _ptr(inc_out), _ptr(inc_in)))
+
+    def mlp_features(self, S, inc_prev, X):
+        self._check(self.lib.dgj_mlp_features(self.h, _ptr(S), _ptr(inc_prev), _fptr(X)))
+
+    def mlp_targets(self, inc, inc_prev, T):
+        self._check(self.lib.dgj_mlp_targets(self.h, _ptr(inc), _ptr(inc_prev), _fptr(T)))
+
+    def mlp_forward(self, X, Y):
+        self._check(self.lib.dgj_mlp_forward(self.h, _fptr(X), X.shape[0], _fptr(Y)))
+
+    def mlp_grad(self, X, T, grad=None):
+        loss = C.c_double()
+        self._check(self.lib.dgj_mlp_grad(self.h, _fptr(X), _fptr(T), X.shape[0], _fptr(grad), C.byref(loss)))
+        return loss.value
+
+    def mlp_train_step(self, X, T, lr):
+        loss = C.c_double()
+        self._check(self.lib.dgj_mlp_train_step(self.h, _fptr(X), _fptr(T), X.shape[0], float(lr), C.byref(loss)))
+        return loss.value

@@ -17,6 +17,7 @@
 #include "dgj_kernels.h"
 #include "dgj_precond.h"
 #include "dgj_residual.h"
+#include "dgj_mlp.h"
 
 using namespace dgj;
 
@@ -339,6 +340,25 @@ struct dgj_ctx {
   double* d_chi = nullptr;
   int* d_status = nullptr;
   int residual_evals = 0;
+  // initial guess of the stage solves
+  int guess_mode = 0;              // 0 S_m, 1 extrapolated, 2 learned (with fallback)
+  bool have_inc = false;
+  double* d_inc[3] = {nullptr, nullptr, nullptr};   // previous step's stage increments
+  double* d_g2 = nullptr;          // candidate guess
+  double* rec_S = nullptr;         // optional caller buffers [stages][n]
+  double* rec_inc = nullptr;
+  struct Mlp {
+    bool ready = false, scales = false;
+    int n_in = 0, H = 0, n_out = 0;
+    long np = 0, t = 0, cap = 0;
+    long off[6] = {0, 0, 0, 0, 0, 0};
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t* wb = nullptr;
+    uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dYb = nullptr, *dZb = nullptr;
+    float *H1 = nullptr, *H2 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ = nullptr;
+    double *s_in = nullptr, *s_inc = nullptr, *s_out = nullptr, *loss_part = nullptr;
+    float *feat = nullptr, *pred = nullptr, *tgt = nullptr;
+  } mlp;
 };
 
 namespace {
@@ -613,6 +633,95 @@ void precond_build(dgj_ctx* c, const double* up, double dt_a) {
   c->pc_age = 0;
 }
 
+// ---------------------------------------------------------------- MLP
+void mlp_free_acts(dgj_ctx::Mlp& M) {
+  void* ps[] = {M.Xb, M.H1b, M.H2b, M.dYb, M.dZb, M.H1, M.H2, M.Y, M.dY, M.dH, M.dZ};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  M.Xb = M.H1b = M.H2b = M.dYb = M.dZb = nullptr;
+  M.H1 = M.H2 = M.Y = M.dY = M.dH = M.dZ = nullptr;
+  M.cap = 0;
+}
+
+void mlp_free(dgj_ctx::Mlp& M) {
+  mlp_free_acts(M);
+  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_in, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  M = dgj_ctx::Mlp();
+}
+
+void mlp_reserve(dgj_ctx* c, long R) {
+  auto& M = c->mlp;
+  if (R <= M.cap) return;
+  mlp_free_acts(M);
+  const long H = M.H;
+  HIPCHK(hipMalloc(&M.Xb, R * M.n_in * 2));
+  HIPCHK(hipMalloc(&M.H1b, R * H * 2));
+  HIPCHK(hipMalloc(&M.H2b, R * H * 2));
+  HIPCHK(hipMalloc(&M.dYb, R * M.n_out * 2));
+  HIPCHK(hipMalloc(&M.dZb, R * H * 2));
+  HIPCHK(hipMalloc(&M.H1, R * H * 4));
+  HIPCHK(hipMalloc(&M.H2, R * H * 4));
+  HIPCHK(hipMalloc(&M.Y, R * M.n_out * 4));
+  HIPCHK(hipMalloc(&M.dY, R * M.n_out * 4));
+  HIPCHK(hipMalloc(&M.dH, R * H * 4));
+  HIPCHK(hipMalloc(&M.dZ, R * H * 4));
+  M.cap = R;
+}
+
+void gemm(dgj_ctx* c, const uint16_t* A, long a_i, long a_k, const uint16_t* B, long b_k, long b_j, int Mr, int Nc,
+          int K, const float* bias, int act, float* Cf, uint16_t* Cb, long c_ld) {
+  GemmArgs g{A, a_i, a_k, B, b_k, b_j, Mr, Nc, K, bias, act, Cf, Cb, c_ld};
+  dim3 grid((Nc + 63) / 64, (Mr + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, c->stream, g);
+}
+
+// forward pass for R rows of X (fp32) -> M.Y (fp32); keeps activations for backward
+void mlp_forward(dgj_ctx* c, const float* X, long R) {
+  auto& M = c->mlp;
+  mlp_reserve(c, R);
+  const int H = M.H;
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(R * M.n_in)), dim3(256), 0, c->stream, X, M.Xb, R * M.n_in);
+  gemm(c, M.Xb, M.n_in, 1, M.wb + M.off[0], H, 1, (int)R, H, M.n_in, M.w + M.off[1], 1, M.H1, M.H1b, H);
+  gemm(c, M.H1b, H, 1, M.wb + M.off[2], H, 1, (int)R, H, H, M.w + M.off[3], 1, M.H2, M.H2b, H);
+  gemm(c, M.H2b, H, 1, M.wb + M.off[4], M.n_out, 1, (int)R, M.n_out, H, M.w + M.off[5], 0, M.Y, nullptr, M.n_out);
+}
+
+// gradient of the mean squared error into M.g; returns the loss
+double mlp_backward(dgj_ctx* c, const float* T, long R) {
+  auto& M = c->mlp;
+  const int H = M.H;
+  const long ny = R * M.n_out;
+  hipLaunchKernelGGL(k_mse_grad, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, M.Y, T, M.dY, M.dYb, ny,
+                     M.loss_part);
+  // W3, b3
+  gemm(c, M.H2b, 1, H, M.dYb, M.n_out, 1, H, M.n_out, (int)R, nullptr, 0, M.g + M.off[4], nullptr, M.n_out);
+  hipLaunchKernelGGL(k_colsum, dim3((M.n_out + 127) / 128), dim3(128), 0, c->stream, M.dY, R, M.n_out, M.g + M.off[5]);
+  // dH2 = dY W3^T ; dZ2
+  gemm(c, M.dYb, M.n_out, 1, M.wb + M.off[4], 1, M.n_out, (int)R, H, M.n_out, nullptr, 0, M.dH, nullptr, H);
+  hipLaunchKernelGGL(k_tanh_back, dim3(grid_for(R * H)), dim3(256), 0, c->stream, M.dH, M.H2, M.dZ, M.dZb, R * H);
+  // W2, b2
+  gemm(c, M.H1b, 1, H, M.dZb, H, 1, H, H, (int)R, nullptr, 0, M.g + M.off[2], nullptr, H);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 127) / 128), dim3(128), 0, c->stream, M.dZ, R, H, M.g + M.off[3]);
+  // dH1 = dZ2 W2^T ; dZ1
+  gemm(c, M.dZb, H, 1, M.wb + M.off[2], 1, H, (int)R, H, H, nullptr, 0, M.dH, nullptr, H);
+  hipLaunchKernelGGL(k_tanh_back, dim3(grid_for(R * H)), dim3(256), 0, c->stream, M.dH, M.H1, M.dZ, M.dZb, R * H);
+  // W1, b1
+  gemm(c, M.Xb, 1, M.n_in, M.dZb, H, 1, M.n_in, H, (int)R, nullptr, 0, M.g + M.off[0], nullptr, H);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 127) / 128), dim3(128), 0, c->stream, M.dZ, R, H, M.g + M.off[1]);
+  std::vector<double> part(RED_BLOCKS);
+  HIPCHK(hipMemcpyAsync(part.data(), M.loss_part, RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (double p : part) s += p;
+  return s / (double)ny;
+}
+
+void mlp_require(dgj_ctx* c) {
+  if (!c->mlp.ready) fail(DGJ_EINVAL, "no MLP: call dgj_mlp_create first");
+}
+
 // ---------------------------------------------------------------- GMRES
 struct GmresOut {
   int its;
@@ -714,16 +823,19 @@ struct NewtonOut {
   bool nan;
 };
 
-NewtonOut newton(dgj_ctx* c, const double* S, double dt_a, double* u) {
+// tau > 0: absolute tolerance ||N|| < tau (a guess other than S_m is judged
+// against tau = alpha ||N(S_m)||); otherwise ||N|| < alpha ||N(u^0)|| (Eq. 23)
+NewtonOut newton(dgj_ctx* c, const double* S, double dt_a, double* u, double tau = -1.0) {
   NewtonOut o{0, {}, {}, true, false};
   stage_residual(c, u, S, dt_a, c->d_N);
   const double n0 = norm(c, c->d_N);
   o.nres.push_back(n0);
   if (!std::isfinite(n0)) { o.converged = false; o.nan = true; return o; }
   double nrm = n0;
+  const double target = tau > 0.0 ? tau : c->sv.newton_rtol * n0;
   while (true) {
     const double nu = norm(c, u);
-    if (nrm < c->sv.newton_rtol * n0 || nrm <= 1e-14 * nu) break;
+    if (nrm < target || nrm <= 1e-14 * nu) break;
     if (o.its >= c->sv.newton_max) { o.converged = false; break; }
     const double eps = nu * std::sqrt(EPS_HAT);
     axpby(c, c->d_b, -1.0, c->d_N, 0.0);
@@ -869,7 +981,8 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     c->V.assign(c->sv.gmres_restart + 1, nullptr);
     for (auto& p : c->V) HIPCHK(hipMalloc(&p, vb));
     double** bufs[] = {&c->d_z, &c->d_w, &c->d_t1, &c->d_t2, &c->d_ubar, &c->d_N, &c->d_S, &c->d_b, &c->d_x,
-                       &c->d_un, &c->d_E[0], &c->d_E[1], &c->d_E[2], &c->d_pa, &c->d_pb};
+                       &c->d_un, &c->d_E[0], &c->d_E[1], &c->d_E[2], &c->d_pa, &c->d_pb, &c->d_inc[0],
+                       &c->d_inc[1], &c->d_inc[2], &c->d_g2};
     for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
     return DGJ_OK;
   });
@@ -887,9 +1000,10 @@ void dgj_destroy(dgj_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   free_pc(c);
+  mlp_free(c->mlp);
   double* ptrs[] = {c->d_trace, c->d_X, c->d_Lvol, c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
                     c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_E[0], c->d_E[1],
-                    c->d_E[2], c->d_E[3], c->d_pa, c->d_pb};
+                    c->d_E[2], c->d_E[3], c->d_pa, c->d_pb, c->d_inc[0], c->d_inc[1], c->d_inc[2], c->d_g2};
   for (double* p : ptrs)
     if (p) hipFree(p);
   if (c->d_nbr) hipFree(c->d_nbr);
@@ -1043,8 +1157,38 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       // S_m = u^n + sum_{i<m} a^mi E^i
       copy(c, c->d_S, c->d_un);
       for (int i = 0; i < m; ++i) axpby(c, c->d_S, A[m][i], c->d_E[i], 1.0);
+      const double dta_m = dt * A[m][m];
+      double tau = -1.0;
       copy(c, c->d_ubar, c->d_S);
-      NewtonOut o = newton(c, c->d_S, dt * A[m][m], c->d_ubar);
+      st->guess_used[m] = 0;
+      if (c->guess_mode > 0 && c->have_inc) {
+        // candidates judged by ||N|| at the same absolute tolerance alpha ||N(S_m)||
+        stage_residual(c, c->d_S, c->d_S, dta_m, c->d_N);
+        const double nS = norm(c, c->d_N);
+        tau = c->sv.newton_rtol * nS;
+        st->guess_norm[m][0] = nS;
+        double best = nS;
+        // extrapolated: S_m + (u^m - S_m) of the previous step
+        hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_g2, c->d_S, 1.0,
+                           c->d_inc[m], c->n);
+        stage_residual(c, c->d_g2, c->d_S, dta_m, c->d_N);
+        const double nE = norm(c, c->d_N);
+        st->guess_norm[m][1] = nE;
+        if (nE < best) { best = nE; copy(c, c->d_ubar, c->d_g2); st->guess_used[m] = 1; }
+        if (c->guess_mode == 2 && c->mlp.ready && c->mlp.scales) {
+          auto& M = c->mlp;
+          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_S, c->d_inc[m],
+                             c->n_elem, c->NV, c->NM, M.s_in, M.s_inc, M.feat);
+          mlp_forward(c, M.feat, c->n_elem);
+          hipLaunchKernelGGL(k_mlp_guess, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_S, c->d_inc[m], M.Y,
+                             c->n, c->NV, c->NM, M.s_out, c->d_g2);
+          stage_residual(c, c->d_g2, c->d_S, dta_m, c->d_N);
+          const double nM = norm(c, c->d_N);
+          st->guess_norm[m][2] = nM;
+          if (nM < best) { best = nM; copy(c, c->d_ubar, c->d_g2); st->guess_used[m] = 2; }
+        }
+      }
+      NewtonOut o = newton(c, c->d_S, dta_m, c->d_ubar, tau);
       st->newton_its[m] = o.its;
       for (size_t i = 0; i < o.gmres_its.size() && i < 64; ++i) st->gmres_its[m][i] = o.gmres_its[i];
       for (size_t i = 0; i < o.nres.size() && i < 65; ++i) st->nres[m][i] = o.nres[i];
@@ -1053,7 +1197,13 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       // E^m = (u^m - S_m) / a^mm
       hipLaunchKernelGGL(k_sub_div, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_E[m], c->d_ubar, c->d_S,
                          A[m][m], c->n);
+      // stage increment u^m - S_m, kept for the next step's guess
+      hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_inc[m], c->d_ubar, -1.0,
+                         c->d_S, c->n);
+      if (c->rec_S) copy(c, c->rec_S + (long)m * c->n, c->d_S);
+      if (c->rec_inc) copy(c, c->rec_inc + (long)m * c->n, c->d_inc[m]);
     }
+    c->have_inc = true;
     // u^{n+1} = u^n + sum b^i E^i
     copy(c, c->d_t1, c->d_un);
     for (int i = 0; i < s; ++i) axpby(c, c->d_t1, b[i], c->d_E[i], 1.0);
@@ -1066,6 +1216,242 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
   st->residual_evals = c->residual_evals;
   st->t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   return rc;
+}
+
+int dgj_set_guess(dgj_ctx* c, int32_t mode) {
+  if (!c || mode < 0 || mode > 2) return DGJ_EINVAL;
+  c->guess_mode = mode;
+  return DGJ_OK;
+}
+
+int dgj_set_record(dgj_ctx* c, double* S_rec, double* inc_rec) {
+  if (!c) return DGJ_EINVAL;
+  c->rec_S = S_rec;
+  c->rec_inc = inc_rec;
+  return DGJ_OK;
+}
+
+int dgj_mlp_create(dgj_ctx* c, int32_t hidden, const float* params_host) {
+  if (!c || hidden < 1 || hidden > 4096) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_free(c->mlp);
+    auto& M = c->mlp;
+    M.n_in = 2 * c->NB;
+    M.n_out = c->NB;
+    M.H = hidden;
+    const long sz[6] = {(long)M.n_in * M.H, M.H, (long)M.H * M.H, M.H, (long)M.H * M.n_out, M.n_out};
+    long o = 0;
+    for (int i = 0; i < 6; ++i) { M.off[i] = o; o += sz[i]; }
+    M.np = o;
+    HIPCHK(hipMalloc(&M.w, M.np * 4));
+    HIPCHK(hipMalloc(&M.g, M.np * 4));
+    HIPCHK(hipMalloc(&M.m, M.np * 4));
+    HIPCHK(hipMalloc(&M.v, M.np * 4));
+    HIPCHK(hipMalloc(&M.wb, M.np * 2));
+    HIPCHK(hipMalloc(&M.s_in, 8 * sizeof(double)));
+    HIPCHK(hipMalloc(&M.s_inc, 8 * sizeof(double)));
+    HIPCHK(hipMalloc(&M.s_out, 8 * sizeof(double)));
+    HIPCHK(hipMalloc(&M.tgt, (size_t)c->n_elem * M.n_out * 4));
+    HIPCHK(hipMalloc(&M.loss_part, RED_BLOCKS * sizeof(double)));
+    HIPCHK(hipMalloc(&M.feat, (size_t)c->n_elem * M.n_in * 4));
+    std::vector<float> zero(M.np, 0.0f);
+    HIPCHK(hipMemcpy(M.w, params_host ? params_host : zero.data(), M.np * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M.m, zero.data(), M.np * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M.v, zero.data(), M.np * 4, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(M.np)), dim3(256), 0, c->stream, M.w, M.wb, M.np);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    M.t = 0;
+    M.ready = true;
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_sizes(const dgj_ctx* c, int64_t* n_params, int32_t* n_in, int32_t* n_out) {
+  if (!c || !c->mlp.ready) return DGJ_EINVAL;
+  if (n_params) *n_params = c->mlp.np;
+  if (n_in) *n_in = c->mlp.n_in;
+  if (n_out) *n_out = c->mlp.n_out;
+  return DGJ_OK;
+}
+
+int dgj_mlp_get_params(dgj_ctx* c, float* out) {
+  if (!c || !out) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    HIPCHK(hipMemcpyAsync(out, c->mlp.w, c->mlp.np * 4, hipMemcpyDeviceToDevice, c->stream));
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_set_params(dgj_ctx* c, const float* params) {
+  if (!c || !params) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    auto& M = c->mlp;
+    HIPCHK(hipMemcpyAsync(M.w, params, M.np * 4, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(M.np)), dim3(256), 0, c->stream, M.w, M.wb, M.np);
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_set_scales(dgj_ctx* c, const double* s_in_host, const double* s_inc_host, const double* s_out_host) {
+  if (!c || !s_in_host || !s_inc_host || !s_out_host) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    for (int v = 0; v < c->NV; ++v)
+      if (!(s_in_host[v] > 0.0) || !(s_inc_host[v] > 0.0) || !(s_out_host[v] > 0.0))
+        fail(DGJ_EINVAL, "scales must be positive");
+    HIPCHK(hipMemcpy(c->mlp.s_in, s_in_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mlp.s_inc, s_inc_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mlp.s_out, s_out_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
+    c->mlp.scales = true;
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_features(dgj_ctx* c, const double* S, const double* inc_prev, float* X) {
+  if (!c || !S || !inc_prev || !X) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    if (!c->mlp.scales) fail(DGJ_EINVAL, "scales not set");
+    hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, S, inc_prev, c->n_elem, c->NV,
+                       c->NM, c->mlp.s_in, c->mlp.s_inc, X);
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_targets(dgj_ctx* c, const double* inc, const double* inc_prev, float* T) {
+  if (!c || !inc || !inc_prev || !T) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    if (!c->mlp.scales) fail(DGJ_EINVAL, "scales not set");
+    hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(c->n)), dim3(256), 0, c->stream, inc, inc_prev, c->n, c->NV,
+                       c->NM, c->mlp.s_out, T);
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t n_steps, int32_t epochs, double lr,
+                double* last_loss) {
+  if (!c || !S_rec || !inc_rec || n_steps < 2 || epochs < 1 || !(lr > 0.0)) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    auto& M = c->mlp;
+    double A[3][3], b[3];
+    int s = 0;
+    tableau(c->sv.scheme, A, b, s);
+    const long n = c->n;
+    auto rec = [&](const double* base, int step, int st) { return base + ((long)step * s + st) * n; };
+    // per-variable RMS scales of S, of the increments and of their step-to-step change
+    double acc[3][8] = {{0}};
+    long cnt[3] = {0, 0, 0};
+    std::vector<double> part((size_t)RED_BLOCKS * c->NV);
+    auto sumsq = [&](const double* a, const double* bb, int which) {
+      hipLaunchKernelGGL(k_varsq_diff, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, a, bb, c->n_elem, c->NV,
+                         c->NM, c->d_part);
+      HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (int v = 0; v < c->NV; ++v)
+        for (int k = 0; k < RED_BLOCKS; ++k) acc[which][v] += part[(size_t)k * c->NV + v];
+      cnt[which] += c->n_elem * c->NM;
+    };
+    for (int st = 0; st < n_steps; ++st)
+      for (int m = 0; m < s; ++m) {
+        sumsq(rec(S_rec, st, m), nullptr, 0);
+        sumsq(rec(inc_rec, st, m), nullptr, 1);
+        if (st > 0) sumsq(rec(inc_rec, st, m), rec(inc_rec, st - 1, m), 2);
+      }
+    double sc[3][8];
+    for (int w = 0; w < 3; ++w)
+      for (int v = 0; v < c->NV; ++v) {
+        sc[w][v] = std::sqrt(acc[w][v] / (double)cnt[w]);
+        if (!(sc[w][v] > 0.0)) sc[w][v] = 1.0;
+      }
+    HIPCHK(hipMemcpy(M.s_in, sc[0], c->NV * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M.s_inc, sc[1], c->NV * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M.s_out, sc[2], c->NV * sizeof(double), hipMemcpyHostToDevice));
+    M.scales = true;
+    double ep_loss = 0.0;
+    const float b1 = 0.9f, b2 = 0.999f;
+    for (int ep = 0; ep < epochs; ++ep) {
+      ep_loss = 0.0;
+      int nb = 0;
+      for (int st = 1; st < n_steps; ++st)
+        for (int m = 0; m < s; ++m) {
+          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(S_rec, st, m),
+                             rec(inc_rec, st - 1, m), c->n_elem, c->NV, c->NM, M.s_in, M.s_inc, M.feat);
+          hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(inc_rec, st, m),
+                             rec(inc_rec, st - 1, m), n, c->NV, c->NM, M.s_out, M.tgt);
+          mlp_forward(c, M.feat, c->n_elem);
+          const double l = mlp_backward(c, M.tgt, c->n_elem);
+          if (!std::isfinite(l)) fail(DGJ_ENAN, "mlp_fit: non-finite loss");
+          M.t += 1;
+          const float c1 = 1.0f - std::pow(b1, (float)M.t), c2 = 1.0f - std::pow(b2, (float)M.t);
+          hipLaunchKernelGGL(k_adam, dim3(grid_for(M.np)), dim3(256), 0, c->stream, M.w, M.wb, M.g, M.m, M.v, M.np,
+                             (float)lr, b1, b2, 1e-8f, c1, c2);
+          ep_loss += l;
+          ++nb;
+        }
+      ep_loss /= nb;
+    }
+    if (last_loss) *last_loss = ep_loss;
+    return DGJ_OK;
+  });
+}
+
+int dgj_guess_state(dgj_ctx* c, double* inc_out, const double* inc_in) {
+  if (!c) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    for (int m = 0; m < 3; ++m) {
+      if (inc_out) copy(c, inc_out + (long)m * c->n, c->d_inc[m]);
+      if (inc_in) copy(c, c->d_inc[m], inc_in + (long)m * c->n);
+    }
+    if (inc_in) c->have_inc = true;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_forward(dgj_ctx* c, const float* X, int64_t rows, float* Y) {
+  if (!c || !X || !Y || rows <= 0) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    mlp_forward(c, X, rows);
+    HIPCHK(hipMemcpyAsync(Y, c->mlp.Y, rows * c->mlp.n_out * 4, hipMemcpyDeviceToDevice, c->stream));
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_grad(dgj_ctx* c, const float* X, const float* T, int64_t rows, float* grad, double* loss) {
+  if (!c || !X || !T || rows <= 0) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    mlp_forward(c, X, rows);
+    double l = mlp_backward(c, T, rows);
+    if (loss) *loss = l;
+    if (grad) HIPCHK(hipMemcpyAsync(grad, c->mlp.g, c->mlp.np * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DGJ_OK;
+  });
+}
+
+int dgj_mlp_train_step(dgj_ctx* c, const float* X, const float* T, int64_t rows, double lr, double* loss) {
+  if (!c || !X || !T || rows <= 0 || !(lr > 0.0)) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    mlp_require(c);
+    auto& M = c->mlp;
+    mlp_forward(c, X, rows);
+    double l = mlp_backward(c, T, rows);
+    if (loss) *loss = l;
+    if (!std::isfinite(l)) fail(DGJ_ENAN, "mlp_train_step: non-finite loss");
+    M.t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)M.t), c2 = 1.0f - std::pow(b2, (float)M.t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(M.np)), dim3(256), 0, c->stream, M.w, M.wb, M.g, M.m, M.v, M.np,
+                       (float)lr, b1, b2, 1e-8f, c1, c2);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
 }
 
 }  // extern "C"

@@ -197,3 +197,18 @@ def random_vector(n_elem: int, dim: int, P: int, seed: int) -> np.ndarray:
     """Seeded uniform(-1,1) vector in the state layout, for matvec tests."""
     nv = dim + 2
     return noise((n_elem, nv, (P + 1) ** dim), seed)
+
+
+def mlp_init(n_in: int, hidden: int, n_out: int, seed: int, out_scale: float = 1e-2) -> np.ndarray:
+    """Seeded initial MLP parameters, packed W1[n_in][H], b1[H], W2[H][H],
+    b2[H], W3[H][n_out], b3[n_out] (FP32): Glorot-uniform weights, zero
+    biases, the output layer scaled by out_scale so that the first
+    predictions are near zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def glorot(a, b):
+        lim = np.sqrt(6.0 / (a + b))
+        return rng.uniform(-lim, lim, size=(a, b))
+    parts = [glorot(n_in, hidden), np.zeros(hidden), glorot(hidden, hidden), np.zeros(hidden),
+             glorot(hidden, n_out) * out_scale, np.zeros(n_out)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
