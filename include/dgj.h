@@ -169,12 +169,15 @@ int dgj_newton(dgj_ctx *ctx, const double *S, double dt_a, double *u, int32_t *n
 int dgj_sdirk_step(dgj_ctx *ctx, double *u, double dt, dgj_step_stats *stats);
 
 /* ---- Newton initial guess (not in the paper, which starts from S_m,
- * Eq. 21).  A learned per-element MLP predicts the stage increment
- * u^m - S_m from the element's S_m and its previous step's increment; the
- * extrapolated guess S_m + (u^m - S_m)_{n-1} is the fallback, and whichever
- * of S_m / extrapolated / learned has the smallest ||N|| starts Newton,
- * which then stops at the same absolute tolerance alpha ||N(S_m)|| for all.
- * mode: 0 S_m (the paper), 1 extrapolated, 2 learned with fallback. */
+ * Eq. 21).  With inc_n = u^m - S_m the converged increment of stage m at
+ * step n: the extrapolated guess is S_m + inc_{n-1} after one step and
+ * S_m + 2 inc_{n-1} - inc_{n-2} after two; a learned per-element MLP
+ * predicts inc_n - inc_{n-1} from the element's inc_{n-1} and
+ * inc_{n-1} - inc_{n-2} (guess S_m + inc_{n-1} + prediction).  Whichever
+ * candidate has the smallest ||N|| starts Newton, which then stops at the
+ * same absolute tolerance alpha ||N(S_m)|| for all.
+ * mode: 0 S_m (the paper), 1 extrapolated, 2 learned with the extrapolated
+ * guess as fallback. */
 int dgj_set_guess(dgj_ctx *ctx, int32_t mode);
 
 /* Record, for every stage of each following dgj_sdirk_step, S_m and the
@@ -193,24 +196,25 @@ int dgj_mlp_sizes(const dgj_ctx *ctx, int64_t *n_params, int32_t *n_in, int32_t 
 /* device FP32 parameter vectors of n_params values */
 int dgj_mlp_get_params(dgj_ctx *ctx, float *out);
 int dgj_mlp_set_params(dgj_ctx *ctx, const float *params);
-/* Per-variable scales (host, d+2 values each): features x = [S/s_in, inc_prev/s_inc];
- * the network predicts the correction of the extrapolated increment,
- * y = (inc - inc_prev)/s_out, and the learned guess is S + inc_prev + s_out y. */
-int dgj_mlp_set_scales(dgj_ctx *ctx, const double *s_in_host, const double *s_inc_host, const double *s_out_host);
-/* X[e][2 nb] (FP32) from S and the previous increment (FP64 states) */
-int dgj_mlp_features(dgj_ctx *ctx, const double *S, const double *inc_prev, float *X);
+/* Per-variable scales (host, d+2 values each): features
+ * x = [inc_prev/s_inc, (inc_prev - inc_prev2)/s_out]; the network predicts
+ * y = (inc - inc_prev)/s_out and the learned guess is S + inc_prev + s_out y. */
+int dgj_mlp_set_scales(dgj_ctx *ctx, const double *s_inc_host, const double *s_out_host);
+/* X[e][2 nb] (FP32) from the two previous increments (FP64 states) */
+int dgj_mlp_features(dgj_ctx *ctx, const double *inc_prev, const double *inc_prev2, float *X);
 /* T[e][nb] = (inc - inc_prev) / s_out (FP32) */
 int dgj_mlp_targets(dgj_ctx *ctx, const double *inc, const double *inc_prev, float *T);
-/* Train on records written through dgj_set_record over n_steps consecutive
- * steps (S_rec, inc_rec: [n_steps][stages][n_unknowns]): sets the scales to
- * the per-variable RMS of S, of the increments and of their step-to-step
- * change, then runs `epochs` passes of Adam steps, one per (step >= 1,
- * stage) pair with all elements as the batch.  *last_loss: mean loss of the
- * last pass. */
+/* Train on records written through dgj_set_record over n_steps >= 3
+ * consecutive steps (S_rec, inc_rec: [n_steps][stages][n_unknowns]; S_rec
+ * is not used by the current features): sets the scales to the
+ * per-variable RMS of the increments and of their step-to-step change,
+ * then runs `epochs` passes of Adam steps, one per (step >= 2, stage) pair
+ * with all elements as the batch.  *last_loss: mean loss of the last pass. */
 int dgj_mlp_fit(dgj_ctx *ctx, const double *S_rec, const double *inc_rec, int32_t n_steps, int32_t epochs, double lr,
                 double *last_loss);
-/* Copy the stored previous-step stage increments out ([3][n_unknowns], may
- * be NULL) and/or in (may be NULL), to restart a run from a saved point. */
+/* Copy the stored stage increments of the two previous steps out
+ * ([2][3][n_unknowns], may be NULL) and/or in (may be NULL), to restart a
+ * run from a saved point. */
 int dgj_guess_state(dgj_ctx *ctx, double *inc_out, const double *inc_in);
 /* Y[rows][n_out] = MLP(X[rows][n_in]) */
 int dgj_mlp_forward(dgj_ctx *ctx, const float *X, int64_t rows, float *Y);

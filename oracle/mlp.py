@@ -1,13 +1,15 @@
 """Per-element MLP that predicts the Newton initial guess (not in the paper:
 the paper starts Newton from S_m, Eq. 21).  TEST INFRASTRUCTURE ONLY.
 
-Features of element e at stage m of step n (all FP64 here):
-    x = [ S_m[e] / s_in,  (u^m - S_m)_{n-1}[e] / s_inc ]      (2 nb values)
-target / prediction: the correction of the extrapolated increment,
-    y = ((u^m - S_m)_n - (u^m - S_m)_{n-1})[e] / s_out          (nb values)
-with per-variable scales s_in, s_inc, s_out broadcast over the modes of each
-variable, and the guess S_m + (u^m - S_m)_{n-1} + s_out * y (a zero output
-gives the extrapolated guess).
+With inc_n = (u^m - S_m)_n the converged increment of stage m at step n,
+the features of element e at stage m of step n are (all FP64 here)
+    x = [ inc_{n-1}[e] / s_inc,  (inc_{n-1} - inc_{n-2})[e] / s_out ]   (2 nb values)
+and the target / prediction is the correction of the extrapolated increment,
+    y = (inc_n - inc_{n-1})[e] / s_out                                   (nb values)
+with per-variable scales s_inc (RMS of the increments) and s_out (RMS of
+their step-to-step change) broadcast over the modes of each variable; the
+guess is S_m + inc_{n-1} + s_out * y (a zero output gives the extrapolated
+guess S_m + inc_{n-1}).
 
 Network: z1 = x W1 + b1, h1 = tanh z1, z2 = h1 W2 + b2, h2 = tanh z2,
 y = h2 W3 + b3; loss = mean over rows and outputs of (y - t)^2.  Parameters
@@ -64,12 +66,11 @@ def grad(theta, X, T, n_in, hidden, n_out):
     return np.concatenate([g.ravel() for g in (gW1, gb1, gW2, gb2, gW3, gb3)])
 
 
-def features(S, inc_prev, s_in, s_inc):
-    """x rows per element from S_m and the previous increment (layout
-    [e][v][m]); s_in, s_inc per-variable scales."""
-    E, nv, nm = S.shape
-    a = S / s_in[None, :, None]
-    b = inc_prev / s_inc[None, :, None]
+def features(inc_prev, inc_prev2, s_inc, s_out):
+    """x rows per element from the two previous increments (layout [e][v][m])."""
+    E, nv, nm = inc_prev.shape
+    a = inc_prev / s_inc[None, :, None]
+    b = (inc_prev - inc_prev2) / s_out[None, :, None]
     return np.concatenate([a.reshape(E, nv * nm), b.reshape(E, nv * nm)], axis=1)
 
 
@@ -83,16 +84,15 @@ def guess(S, inc_prev, y, s_out):
     return S + inc_prev + y.reshape(E, nv, nm) * s_out[None, :, None]
 
 
-def scales(S_list, inc_list):
-    """Per-variable RMS of S, of the increments and of their step-to-step
-    differences over recorded stages (lists indexed [step][stage])."""
+def scales(inc_list):
+    """Per-variable RMS of the increments and of their step-to-step change
+    over recorded stages (list indexed [step][stage])."""
     def rms(arrs):
         a = np.stack(arrs)
         return np.sqrt(np.mean(a ** 2, axis=tuple(i for i in range(a.ndim) if i != a.ndim - 2)))
-    S_all = [s for step in S_list for s in step]
     inc_all = [x for step in inc_list for x in step]
     d_all = [inc_list[n][m] - inc_list[n - 1][m] for n in range(1, len(inc_list)) for m in range(len(inc_list[n]))]
-    return rms(S_all), rms(inc_all), rms(d_all)
+    return rms(inc_all), rms(d_all)
 
 
 def adam(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -96,7 +96,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_mlp_sizes": ([vp, i64p, i32p, i32p], C.c_int),
         "dgj_mlp_get_params": ([vp, vp], C.c_int),
         "dgj_mlp_set_params": ([vp, vp], C.c_int),
-        "dgj_mlp_set_scales": ([vp, vp, vp, vp], C.c_int),
+        "dgj_mlp_set_scales": ([vp, vp, vp], C.c_int),
         "dgj_mlp_fit": ([vp, vp, vp, C.c_int32, C.c_int32, dp, C.POINTER(C.c_double)], C.c_int),
         "dgj_guess_state": ([vp, vp, vp], C.c_int),
         "dgj_mlp_features": ([vp, vp, vp, vp], C.c_int),
@@ -245,11 +245,10 @@ class Context:
     def mlp_set_params(self, params):
         self._check(self.lib.dgj_mlp_set_params(self.h, _fptr(params)))
 
-    def mlp_set_scales(self, s_in, s_inc, s_out):
-        a = np.ascontiguousarray(s_in, dtype=np.float64)
+    def mlp_set_scales(self, s_inc, s_out):
         b = np.ascontiguousarray(s_inc, dtype=np.float64)
         c = np.ascontiguousarray(s_out, dtype=np.float64)
-        self._check(self.lib.dgj_mlp_set_scales(self.h, a.ctypes.data, b.ctypes.data, c.ctypes.data))
+        self._check(self.lib.dgj_mlp_set_scales(self.h, b.ctypes.data, c.ctypes.data))
 
     def mlp_fit(self, S_rec, inc_rec, n_steps, epochs, lr):
         loss = C.c_double()
@@ -260,8 +259,8 @@ class Context:
     def guess_state(self, inc_out=None, inc_in=None):
         self._check(self.lib.dgj_guess_state(self.h, _ptr(inc_out), _ptr(inc_in)))
 
-    def mlp_features(self, S, inc_prev, X):
-        self._check(self.lib.dgj_mlp_features(self.h, _ptr(S), _ptr(inc_prev), _fptr(X)))
+    def mlp_features(self, inc_prev, inc_prev2, X):
+        self._check(self.lib.dgj_mlp_features(self.h, _ptr(inc_prev), _ptr(inc_prev2), _fptr(X)))
 
     def mlp_targets(self, inc, inc_prev, T):
         self._check(self.lib.dgj_mlp_targets(self.h, _ptr(inc), _ptr(inc_prev), _fptr(T)))

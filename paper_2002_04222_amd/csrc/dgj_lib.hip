@@ -189,6 +189,12 @@ __global__ void k_add_scaled(double* __restrict__ y, const double* __restrict__ 
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = z ? x[i] + a * z[i] : x[i];
 }
+// g = S + inc1 (inc2 null) or S + 2 inc1 - inc2
+__global__ void k_extrap(double* __restrict__ g, const double* __restrict__ S, const double* __restrict__ inc1,
+                         const double* __restrict__ inc2, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    g[i] = inc2 ? S[i] + (2.0 * inc1[i] - inc2[i]) : S[i] + inc1[i];
+}
 // y = (x - z) / a
 __global__ void k_sub_div(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ z, double a,
                           long n) {
@@ -342,8 +348,9 @@ struct dgj_ctx {
   int residual_evals = 0;
   // initial guess of the stage solves
   int guess_mode = 0;              // 0 S_m, 1 extrapolated, 2 learned (with fallback)
-  bool have_inc = false;
+  int have_inc = 0;                // number of previous steps whose increments are held (0, 1, 2)
   double* d_inc[3] = {nullptr, nullptr, nullptr};   // previous step's stage increments
+  double* d_inc2[3] = {nullptr, nullptr, nullptr};  // the step before
   double* d_g2 = nullptr;          // candidate guess
   double* rec_S = nullptr;         // optional caller buffers [stages][n]
   double* rec_inc = nullptr;
@@ -356,7 +363,7 @@ struct dgj_ctx {
     uint16_t* wb = nullptr;
     uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dYb = nullptr, *dZb = nullptr;
     float *H1 = nullptr, *H2 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ = nullptr;
-    double *s_in = nullptr, *s_inc = nullptr, *s_out = nullptr, *loss_part = nullptr;
+    double *s_inc = nullptr, *s_out = nullptr, *loss_part = nullptr;
     float *feat = nullptr, *pred = nullptr, *tgt = nullptr;
   } mlp;
 };
@@ -645,7 +652,7 @@ void mlp_free_acts(dgj_ctx::Mlp& M) {
 
 void mlp_free(dgj_ctx::Mlp& M) {
   mlp_free_acts(M);
-  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_in, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt};
+  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt};
   for (void* p : ps)
     if (p) hipFree(p);
   M = dgj_ctx::Mlp();
@@ -982,7 +989,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     for (auto& p : c->V) HIPCHK(hipMalloc(&p, vb));
     double** bufs[] = {&c->d_z, &c->d_w, &c->d_t1, &c->d_t2, &c->d_ubar, &c->d_N, &c->d_S, &c->d_b, &c->d_x,
                        &c->d_un, &c->d_E[0], &c->d_E[1], &c->d_E[2], &c->d_pa, &c->d_pb, &c->d_inc[0],
-                       &c->d_inc[1], &c->d_inc[2], &c->d_g2};
+                       &c->d_inc[1], &c->d_inc[2], &c->d_inc2[0], &c->d_inc2[1], &c->d_inc2[2], &c->d_g2};
     for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
     return DGJ_OK;
   });
@@ -1003,7 +1010,8 @@ void dgj_destroy(dgj_ctx* c) {
   mlp_free(c->mlp);
   double* ptrs[] = {c->d_trace, c->d_X, c->d_Lvol, c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
                     c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_E[0], c->d_E[1],
-                    c->d_E[2], c->d_E[3], c->d_pa, c->d_pb, c->d_inc[0], c->d_inc[1], c->d_inc[2], c->d_g2};
+                    c->d_E[2], c->d_E[3], c->d_pa, c->d_pb, c->d_inc[0], c->d_inc[1], c->d_inc[2],
+                    c->d_inc2[0], c->d_inc2[1], c->d_inc2[2], c->d_g2};
   for (double* p : ptrs)
     if (p) hipFree(p);
   if (c->d_nbr) hipFree(c->d_nbr);
@@ -1161,24 +1169,25 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       double tau = -1.0;
       copy(c, c->d_ubar, c->d_S);
       st->guess_used[m] = 0;
-      if (c->guess_mode > 0 && c->have_inc) {
+      if (c->guess_mode > 0 && c->have_inc >= 1) {
         // candidates judged by ||N|| at the same absolute tolerance alpha ||N(S_m)||
         stage_residual(c, c->d_S, c->d_S, dta_m, c->d_N);
         const double nS = norm(c, c->d_N);
         tau = c->sv.newton_rtol * nS;
         st->guess_norm[m][0] = nS;
         double best = nS;
-        // extrapolated: S_m + (u^m - S_m) of the previous step
-        hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_g2, c->d_S, 1.0,
-                           c->d_inc[m], c->n);
+        // extrapolated in time: S_m + inc_{n-1} (one previous step) or
+        // S_m + 2 inc_{n-1} - inc_{n-2} (two)
+        hipLaunchKernelGGL(k_extrap, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_g2, c->d_S, c->d_inc[m],
+                           c->have_inc >= 2 ? c->d_inc2[m] : nullptr, c->n);
         stage_residual(c, c->d_g2, c->d_S, dta_m, c->d_N);
         const double nE = norm(c, c->d_N);
         st->guess_norm[m][1] = nE;
         if (nE < best) { best = nE; copy(c, c->d_ubar, c->d_g2); st->guess_used[m] = 1; }
-        if (c->guess_mode == 2 && c->mlp.ready && c->mlp.scales) {
+        if (c->guess_mode == 2 && c->mlp.ready && c->mlp.scales && c->have_inc >= 2) {
           auto& M = c->mlp;
-          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_S, c->d_inc[m],
-                             c->n_elem, c->NV, c->NM, M.s_in, M.s_inc, M.feat);
+          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_inc[m],
+                             c->d_inc2[m], c->n_elem, c->NV, c->NM, M.s_inc, M.s_out, M.feat);
           mlp_forward(c, M.feat, c->n_elem);
           hipLaunchKernelGGL(k_mlp_guess, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_S, c->d_inc[m], M.Y,
                              c->n, c->NV, c->NM, M.s_out, c->d_g2);
@@ -1197,13 +1206,14 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       // E^m = (u^m - S_m) / a^mm
       hipLaunchKernelGGL(k_sub_div, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_E[m], c->d_ubar, c->d_S,
                          A[m][m], c->n);
-      // stage increment u^m - S_m, kept for the next step's guess
+      // stage increment u^m - S_m, kept (with the previous one) for the next steps' guesses
+      copy(c, c->d_inc2[m], c->d_inc[m]);
       hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_inc[m], c->d_ubar, -1.0,
                          c->d_S, c->n);
       if (c->rec_S) copy(c, c->rec_S + (long)m * c->n, c->d_S);
       if (c->rec_inc) copy(c, c->rec_inc + (long)m * c->n, c->d_inc[m]);
     }
-    c->have_inc = true;
+    c->have_inc = std::min(2, c->have_inc + 1);
     // u^{n+1} = u^n + sum b^i E^i
     copy(c, c->d_t1, c->d_un);
     for (int i = 0; i < s; ++i) axpby(c, c->d_t1, b[i], c->d_E[i], 1.0);
@@ -1248,7 +1258,6 @@ int dgj_mlp_create(dgj_ctx* c, int32_t hidden, const float* params_host) {
     HIPCHK(hipMalloc(&M.m, M.np * 4));
     HIPCHK(hipMalloc(&M.v, M.np * 4));
     HIPCHK(hipMalloc(&M.wb, M.np * 2));
-    HIPCHK(hipMalloc(&M.s_in, 8 * sizeof(double)));
     HIPCHK(hipMalloc(&M.s_inc, 8 * sizeof(double)));
     HIPCHK(hipMalloc(&M.s_out, 8 * sizeof(double)));
     HIPCHK(hipMalloc(&M.tgt, (size_t)c->n_elem * M.n_out * 4));
@@ -1294,14 +1303,12 @@ int dgj_mlp_set_params(dgj_ctx* c, const float* params) {
   });
 }
 
-int dgj_mlp_set_scales(dgj_ctx* c, const double* s_in_host, const double* s_inc_host, const double* s_out_host) {
-  if (!c || !s_in_host || !s_inc_host || !s_out_host) return DGJ_EINVAL;
+int dgj_mlp_set_scales(dgj_ctx* c, const double* s_inc_host, const double* s_out_host) {
+  if (!c || !s_inc_host || !s_out_host) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     mlp_require(c);
     for (int v = 0; v < c->NV; ++v)
-      if (!(s_in_host[v] > 0.0) || !(s_inc_host[v] > 0.0) || !(s_out_host[v] > 0.0))
-        fail(DGJ_EINVAL, "scales must be positive");
-    HIPCHK(hipMemcpy(c->mlp.s_in, s_in_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
+      if (!(s_inc_host[v] > 0.0) || !(s_out_host[v] > 0.0)) fail(DGJ_EINVAL, "scales must be positive");
     HIPCHK(hipMemcpy(c->mlp.s_inc, s_inc_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->mlp.s_out, s_out_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
     c->mlp.scales = true;
@@ -1309,13 +1316,13 @@ int dgj_mlp_set_scales(dgj_ctx* c, const double* s_in_host, const double* s_inc_
   });
 }
 
-int dgj_mlp_features(dgj_ctx* c, const double* S, const double* inc_prev, float* X) {
-  if (!c || !S || !inc_prev || !X) return DGJ_EINVAL;
+int dgj_mlp_features(dgj_ctx* c, const double* inc_prev, const double* inc_prev2, float* X) {
+  if (!c || !inc_prev || !inc_prev2 || !X) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     mlp_require(c);
     if (!c->mlp.scales) fail(DGJ_EINVAL, "scales not set");
-    hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, S, inc_prev, c->n_elem, c->NV,
-                       c->NM, c->mlp.s_in, c->mlp.s_inc, X);
+    hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, inc_prev, inc_prev2, c->n_elem,
+                       c->NV, c->NM, c->mlp.s_inc, c->mlp.s_out, X);
     return DGJ_OK;
   });
 }
@@ -1342,7 +1349,8 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
     tableau(c->sv.scheme, A, b, s);
     const long n = c->n;
     auto rec = [&](const double* base, int step, int st) { return base + ((long)step * s + st) * n; };
-    // per-variable RMS scales of S, of the increments and of their step-to-step change
+    if (n_steps < 3) fail(DGJ_EINVAL, "mlp_fit needs at least 3 recorded steps");
+    // per-variable RMS scales of the increments and of their step-to-step change
     double acc[3][8] = {{0}};
     long cnt[3] = {0, 0, 0};
     std::vector<double> part((size_t)RED_BLOCKS * c->NV);
@@ -1357,7 +1365,6 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
     };
     for (int st = 0; st < n_steps; ++st)
       for (int m = 0; m < s; ++m) {
-        sumsq(rec(S_rec, st, m), nullptr, 0);
         sumsq(rec(inc_rec, st, m), nullptr, 1);
         if (st > 0) sumsq(rec(inc_rec, st, m), rec(inc_rec, st - 1, m), 2);
       }
@@ -1367,7 +1374,6 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
         sc[w][v] = std::sqrt(acc[w][v] / (double)cnt[w]);
         if (!(sc[w][v] > 0.0)) sc[w][v] = 1.0;
       }
-    HIPCHK(hipMemcpy(M.s_in, sc[0], c->NV * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(M.s_inc, sc[1], c->NV * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(M.s_out, sc[2], c->NV * sizeof(double), hipMemcpyHostToDevice));
     M.scales = true;
@@ -1376,10 +1382,10 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
     for (int ep = 0; ep < epochs; ++ep) {
       ep_loss = 0.0;
       int nb = 0;
-      for (int st = 1; st < n_steps; ++st)
+      for (int st = 2; st < n_steps; ++st)
         for (int m = 0; m < s; ++m) {
-          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(S_rec, st, m),
-                             rec(inc_rec, st - 1, m), c->n_elem, c->NV, c->NM, M.s_in, M.s_inc, M.feat);
+          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(inc_rec, st - 1, m),
+                             rec(inc_rec, st - 2, m), c->n_elem, c->NV, c->NM, M.s_inc, M.s_out, M.feat);
           hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(inc_rec, st, m),
                              rec(inc_rec, st - 1, m), n, c->NV, c->NM, M.s_out, M.tgt);
           mlp_forward(c, M.feat, c->n_elem);
@@ -1403,10 +1409,16 @@ int dgj_guess_state(dgj_ctx* c, double* inc_out, const double* inc_in) {
   if (!c) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     for (int m = 0; m < 3; ++m) {
-      if (inc_out) copy(c, inc_out + (long)m * c->n, c->d_inc[m]);
-      if (inc_in) copy(c, c->d_inc[m], inc_in + (long)m * c->n);
+      if (inc_out) {
+        copy(c, inc_out + (long)m * c->n, c->d_inc[m]);
+        copy(c, inc_out + (long)(3 + m) * c->n, c->d_inc2[m]);
+      }
+      if (inc_in) {
+        copy(c, c->d_inc[m], inc_in + (long)m * c->n);
+        copy(c, c->d_inc2[m], inc_in + (long)(3 + m) * c->n);
+      }
     }
-    if (inc_in) c->have_inc = true;
+    if (inc_in) c->have_inc = 2;
     HIPCHK(hipStreamSynchronize(c->stream));
     return DGJ_OK;
   });

@@ -1,7 +1,7 @@
 // Per-element MLP predicting the Newton initial guess of an implicit stage:
-// y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3, with x the element's
-// scaled stage source and previous stage increment and y its scaled stage
-// increment.  Weights are held as an FP32 master copy and a BF16 copy; the
+// y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3, with x the element's two
+// previous converged stage increments (scaled) and y the scaled change of the
+// increment from the previous step.  Weights are held as an FP32 master copy and a BF16 copy; the
 // products run on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32
 // accumulate) in one strided GEMM kernel used for the forward pass and for
 // the transposed products of the backward pass.
@@ -146,17 +146,17 @@ __global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ wb, const f
   }
 }
 
-// x rows: [S/s_in | inc_prev/s_inc], per-variable scales, layout [e][v][m]
-__global__ void k_mlp_features(const double* __restrict__ S, const double* __restrict__ inc, long n_elem, int nv,
-                               int nm, const double* __restrict__ s_in, const double* __restrict__ s_inc,
+// x rows: [inc_prev/s_inc | (inc_prev - inc_prev2)/s_out], per-variable scales, layout [e][v][m]
+__global__ void k_mlp_features(const double* __restrict__ inc1, const double* __restrict__ inc2, long n_elem, int nv,
+                               int nm, const double* __restrict__ s_inc, const double* __restrict__ s_out,
                                float* __restrict__ X) {
   const long nb = (long)nv * nm;
   const long total = n_elem * nb;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
     const long e = i / nb, r = i % nb;
     const int v = (int)(r / nm);
-    X[e * 2 * nb + r] = (float)(S[i] / s_in[v]);
-    X[e * 2 * nb + nb + r] = (float)(inc[i] / s_inc[v]);
+    X[e * 2 * nb + r] = (float)(inc1[i] / s_inc[v]);
+    X[e * 2 * nb + nb + r] = (float)((inc1[i] - inc2[i]) / s_out[v]);
   }
 }
 

@@ -88,8 +88,8 @@ def test_learned_guess_gain_and_step_parity():
     alpha ||N(S_m)||; the learned start has a smaller residual and needs no
     more Newton iterations, and the steps agree with the FP64 oracle's plain
     step to 1e-8."""
-    _case("learned guess gain, tgv2d 8x8 P=2")
-    cfg = W.config(1)
+    _case("learned guess gain, tgv2d 12x12 P=2")
+    cfg = W.config(1, ncells=(12, 12))
     mesh = cfg.mesh()
     ctx = _ctx(cfg, mesh)
     n = ctx.n_unknowns
@@ -97,7 +97,7 @@ def test_learned_guess_gain_and_step_parity():
     noise = torch.tensor(W.noise(ctx.shape, cfg.seed), device="cuda")
     ctx.project_tgv(noise, cfg.noise_amp, u)
     dt = cfg.dt()
-    n_train, stages = 12, 2
+    n_train, stages = 16, 2
     S_rec = torch.empty((n_train, stages, n), dtype=torch.float64, device="cuda")
     I_rec = torch.empty_like(S_rec)
     for k in range(n_train):
@@ -111,7 +111,7 @@ def test_learned_guess_gain_and_step_parity():
     assert np.isfinite(loss) and loss < 1.0
     # held-out steps from the same saved state and increment history
     u_save = u.clone()
-    inc_save = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    inc_save = torch.empty((2, 3, n), dtype=torch.float64, device="cuda")
     ctx.guess_state(inc_out=inc_save)
     res = {}
     for mode in ("paper", "learned"):
@@ -126,10 +126,18 @@ def test_learned_guess_gain_and_step_parity():
         res[mode] = (uu.cpu().numpy(), its, norms)
         print(mode, its, norms, flush=True)
     ctx.set_guess("paper")
-    # the learned (or its extrapolated fallback) start beats S_m at every stage
+    # every candidate is evaluated; the chosen start (learned or its
+    # extrapolated fallback) beats S_m at every stage.  The learned / fallback
+    # norm ratios are reported, not asserted: on these data the per-element
+    # net's independent inter-element errors cost more in ||N|| than the
+    # extrapolation's smooth ones.
+    ratios = []
     for stage_norms in res["learned"][2]:
         for nS, nE, nM in stage_norms:
+            assert nS > 0 and nE > 0 and nM > 0
             assert min(nE, nM) < nS
+            ratios.append(nM / nE)
+    print("learned / extrapolated residual norms", ratios, flush=True)
     assert sum(res["learned"][1]) <= sum(res["paper"][1])
     ua, ub = res["paper"][0], res["learned"][0]
     assert np.linalg.norm(ua - ub) <= 1e-8 * np.linalg.norm(ua)

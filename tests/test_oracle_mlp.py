@@ -37,22 +37,22 @@ def test_small_weights_reduce_to_linear_model():
 def test_features_targets_guess_roundtrip():
     rng = np.random.default_rng(2)
     S = rng.normal(size=(4, 3, 5))
-    inc = rng.normal(size=(4, 3, 5))
-    s_in = np.array([1.0, 2.0, 4.0])
+    inc1 = rng.normal(size=(4, 3, 5))
+    inc2 = rng.normal(size=(4, 3, 5))
     s_inc = np.array([0.5, 0.25, 2.0])
     s_out = np.array([0.1, 3.0, 0.7])
-    X = mlp.features(S, inc, s_in, s_inc)
+    X = mlp.features(inc1, inc2, s_inc, s_out)
     assert X.shape == (4, 30)
-    assert np.allclose(X[:, :15].reshape(4, 3, 5) * s_in[None, :, None], S)
-    inc_new = inc + rng.normal(size=inc.shape) * 0.1
-    y = mlp.targets(inc_new, inc, s_out)
-    assert np.allclose(mlp.guess(S, inc, y, s_out), S + inc_new)
+    assert np.allclose(X[:, :15].reshape(4, 3, 5) * s_inc[None, :, None], inc1)
+    assert np.allclose(X[:, 15:].reshape(4, 3, 5) * s_out[None, :, None], inc1 - inc2)
+    inc_new = inc1 + rng.normal(size=inc1.shape) * 0.1
+    y = mlp.targets(inc_new, inc1, s_out)
+    assert np.allclose(mlp.guess(S, inc1, y, s_out), S + inc_new)
     # a zero prediction is the extrapolated guess
-    assert np.allclose(mlp.guess(S, inc, 0 * y, s_out), S + inc)
-    # scales: RMS per variable
-    s1, s2, s3 = mlp.scales([[S, S], [S, S]], [[inc, inc], [inc_new, inc_new]])
-    assert np.allclose(s1, np.sqrt(np.mean(S ** 2, axis=(0, 2))))
-    assert np.allclose(s3, np.sqrt(np.mean((inc_new - inc) ** 2, axis=(0, 2))))
+    assert np.allclose(mlp.guess(S, inc1, 0 * y, s_out), S + inc1)
+    s2, s3 = mlp.scales([[inc2, inc2], [inc1, inc1]])
+    assert np.allclose(s2, np.sqrt(np.mean(np.stack([inc2, inc1]) ** 2, axis=(0, 1, 3))))
+    assert np.allclose(s3, np.sqrt(np.mean((inc1 - inc2) ** 2, axis=(0, 2))))
 
 
 def test_adam_first_step_is_sign_step():
