@@ -223,6 +223,33 @@ int dgj_mlp_grad(dgj_ctx *ctx, const float *X, const float *T, int64_t rows, flo
 /* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error */
 int dgj_mlp_train_step(dgj_ctx *ctx, const float *X, const float *T, int64_t rows, double lr, double *loss);
 
+/* ---- Batches of independent instances (periodic meshes of different
+ * sizes, polynomial orders and gas parameters, one shared solver setting).
+ * Instances of one (dim, P, nq) share every kernel launch; GMRES, Newton and
+ * SDIRK run in lockstep with per-instance scalars and masks, each instance
+ * going through exactly the operations of its single-instance run.  The
+ * batch state is one device vector: instance i occupies
+ * [offsets[i], offsets[i] + counts[i]) in the usual [element][variable][mode]
+ * layout (instances of equal order are stored next to each other, so the
+ * order in the vector can differ from the order of creation).  For callers that advance many
+ * small problems at once. */
+typedef struct dgj_batch dgj_batch;
+int dgj_batch_create(int32_t n, const dgj_mesh *meshes, const dgj_phys *phys, const dgj_solver *solver,
+                     void *hip_stream, dgj_batch **out);
+void dgj_batch_destroy(dgj_batch *batch);
+const char *dgj_batch_last_error(const dgj_batch *batch);
+/* total unknowns; per instance offsets[n] and counts[n] (host, may be NULL) */
+int dgj_batch_sizes(const dgj_batch *batch, int64_t *n_total, int64_t *offsets, int64_t *counts);
+/* dgj_project_tgv for every instance (noise in the batch layout, may be NULL) */
+int dgj_batch_project_tgv(dgj_batch *batch, const double *noise, double noise_amp, double *u);
+/* R = M^-1 L(u) for every instance */
+int dgj_batch_residual(dgj_batch *batch, const double *u, double *R);
+/* One SDIRK step of every instance, dt (host [n]) per instance; optional
+ * host outputs newton_its[n][4] and gmres_its[n][4] (total per stage).
+ * Preconditioners are rebuilt at the incoming state every pc_freeze steps
+ * or when an instance's dt changes. */
+int dgj_batch_sdirk_step(dgj_batch *batch, double *u, const double *dt, int32_t *newton_its, int32_t *gmres_its);
+
 #ifdef __cplusplus
 }
 #endif

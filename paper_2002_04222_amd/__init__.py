@@ -6,5 +6,5 @@ include/dgj.h); this package only marshals arguments to it.  There is no
 CPU fallback: importing the binding fails loudly when the library is
 missing.
 """
-from .binding import (Context, DgjError, load_library, DGJ_OK, DGJ_PC_F64, DGJ_PC_F32,  # noqa: F401
+from .binding import (Batch, Context, DgjError, load_library, DGJ_OK, DGJ_PC_F64, DGJ_PC_F32,  # noqa: F401
                       DGJ_PC_BF16, DGJ_SDIRK2, DGJ_SDIRK3, LIB_PATH)

@@ -104,6 +104,14 @@ def load_library(path: str = LIB_PATH):
         "dgj_mlp_forward": ([vp, vp, C.c_int64, vp], C.c_int),
         "dgj_mlp_grad": ([vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double)], C.c_int),
         "dgj_mlp_train_step": ([vp, vp, vp, C.c_int64, dp, C.POINTER(C.c_double)], C.c_int),
+        "dgj_batch_create": ([C.c_int32, C.POINTER(Mesh), C.POINTER(Phys), C.POINTER(Solver), vp, C.POINTER(vp)],
+                             C.c_int),
+        "dgj_batch_destroy": ([vp], None),
+        "dgj_batch_last_error": ([vp], C.c_char_p),
+        "dgj_batch_sizes": ([vp, i64p, i64p, i64p], C.c_int),
+        "dgj_batch_project_tgv": ([vp, vp, dp, vp], C.c_int),
+        "dgj_batch_residual": ([vp, vp, vp], C.c_int),
+        "dgj_batch_sdirk_step": ([vp, vp, vp, i32p, i32p], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -127,6 +135,88 @@ def _fptr(t) -> Optional[int]:
 
 SCHEMES = {"sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3}
 PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
+
+
+def _mesh_struct(mesh, cfg, keep):
+    arrs = [np.ascontiguousarray(mesh.elem_origin, dtype=np.float64),
+            np.ascontiguousarray(mesh.elem_h, dtype=np.float64),
+            np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)]
+    keep.extend(arrs)
+    return Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem, arrs[0].ctypes.data_as(C.POINTER(C.c_double)),
+                arrs[1].ctypes.data_as(C.POINTER(C.c_double)), arrs[2].ctypes.data_as(C.POINTER(C.c_int32)))
+
+
+def _phys_struct(cfg):
+    return Phys(cfg.gamma, cfg.Pr, cfg.Re, cfg.Ma, cfg.T_ref_K, cfg.visc_law, cfg.flux_mode, cfg.riemann)
+
+
+def _solver_struct(cfg):
+    return Solver(SCHEMES[cfg.scheme], cfg.newton_rtol, cfg.newton_max, cfg.gmres_restart, cfg.gmres_rtol,
+                  cfg.gmres_max, cfg.brj_sweeps, cfg.brj_omega, PRECISIONS[cfg.pc_precision], cfg.pc_freeze)
+
+
+class Batch:
+    """A batch of independent instances (see include/dgj.h, dgj_batch_*).
+    cfgs: per-instance configurations (mesh size, P, gas parameters); the
+    solver settings are the first one's."""
+
+    def __init__(self, cfgs, stream=None):
+        import torch
+        self.lib = load_library()
+        self._keep = []
+        meshes = [c.mesh() for c in cfgs]
+        n = len(cfgs)
+        ms = (Mesh * n)(*[_mesh_struct(m, c, self._keep) for m, c in zip(meshes, cfgs)])
+        ps = (Phys * n)(*[_phys_struct(c) for c in cfgs])
+        sv = _solver_struct(cfgs[0])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = self.lib.dgj_batch_create(n, ms, ps, C.byref(sv), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != DGJ_OK:
+            raise DgjError(rc, "dgj_batch_create failed")
+        self.h = h
+        self.n = n
+        tot = C.c_int64()
+        off = (C.c_int64 * n)()
+        cnt = (C.c_int64 * n)()
+        self._check(self.lib.dgj_batch_sizes(self.h, C.byref(tot), off, cnt))
+        self.n_total = tot.value
+        self.offsets = [off[i] for i in range(n)]
+        self.counts = [cnt[i] for i in range(n)]
+
+    def _check(self, rc):
+        if rc != DGJ_OK:
+            raise DgjError(rc, self.lib.dgj_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dgj_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self):
+        import torch
+        return torch.empty(self.n_total, dtype=torch.float64, device="cuda")
+
+    def project_tgv(self, noise, amp, u):
+        self._check(self.lib.dgj_batch_project_tgv(self.h, _ptr(noise), float(amp), _ptr(u)))
+
+    def residual(self, u, R):
+        self._check(self.lib.dgj_batch_residual(self.h, _ptr(u), _ptr(R)))
+
+    def sdirk_step(self, u, dt):
+        dts = np.ascontiguousarray(dt, dtype=np.float64)
+        nit = (C.c_int32 * (4 * self.n))()
+        git = (C.c_int32 * (4 * self.n))()
+        self._check(self.lib.dgj_batch_sdirk_step(self.h, _ptr(u), dts.ctypes.data, nit, git))
+        return [[nit[4 * i + k] for k in range(4)] for i in range(self.n)], \
+               [[git[4 * i + k] for k in range(4)] for i in range(self.n)]
 
 
 class Context:

@@ -109,7 +109,35 @@ struct ResArgs {
   const double* tables;
   Phys ph;
   long n_elem;
+  // batches of independent instances: per-element instance index and
+  // per-instance gas parameters, eps, dt a^mm and active flag (all null for
+  // a single instance, which then uses ph, in.eps and dt_a)
+  const int* inst;
+  const Phys* phs;
+  const double* epsv;
+  const double* dtav;
+  const int* active;
 };
+
+// instance-resolved view of ResArgs for element e; false if e's instance is inactive
+struct ElemParams {
+  Phys ph;
+  StateIn in;
+  double dt_a;
+};
+__device__ __forceinline__ bool elem_params(const ResArgs& a, long e, ElemParams& p) {
+  p.ph = a.ph;
+  p.in = a.in;
+  p.dt_a = a.dt_a;
+  if (a.inst) {
+    const int i = a.inst[e];
+    if (a.active && !a.active[i]) return false;
+    p.ph = a.phs[i];
+    if (a.epsv) p.in.eps = a.epsv[i];
+    if (a.dtav) p.dt_a = a.dtav[i];
+  }
+  return true;
+}
 
 // ---------------------------------------------------------------- volume transform in LDS
 // LDS sizes of the volume transform used by the preconditioner build.

@@ -5,6 +5,8 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -236,13 +238,15 @@ __global__ void k_dinv_export<double>(const double* __restrict__ Dinv, int nb, l
 template <int D, int N, int Q>
 __global__ void k_project_tgv(const double* __restrict__ origin, const double* __restrict__ geo,
                               const double* __restrict__ tables, Phys ph, long n_elem, const double* __restrict__ noise,
-                              double amp, double* __restrict__ u) {
+                              double amp, double* __restrict__ u, const int* __restrict__ inst,
+                              const Phys* __restrict__ phs) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= n_elem * NM) return;
   const long e = gid / NM;
   const int m = gid % NM;
+  if (inst) ph = phs[inst[e]];
   const double* B = tables;
   const double* w = tables + 2 * Q * N;
   int mi[3] = {0, 0, 0};
@@ -348,6 +352,19 @@ struct dgj_ctx {
   int residual_evals = 0;
   // initial guess of the stage solves
   int guess_mode = 0;              // 0 S_m, 1 extrapolated, 2 learned (with fallback)
+  // instances of a batch held by this context (one shape); null for a single instance
+  int n_inst = 0;
+  std::vector<long> inst_e0;       // host: first element of each instance (n_inst + 1 entries)
+  int* d_inst = nullptr;           // per element instance index
+  Phys* d_phs = nullptr;           // per instance gas parameters
+  double* d_epsv = nullptr;        // per instance eps
+  double* d_dtav = nullptr;        // per instance dt a^mm
+  int* d_active = nullptr;         // per instance active flag
+  std::vector<Phys> h_phs;
+  long* d_ioff = nullptr;          // per instance unknown offsets (n_inst + 1)
+  double* d_hs = nullptr;          // per instance scalar slots [n_inst][64]
+  double* d_part2 = nullptr;       // per instance reduction partials [n_inst][RED_BLOCKS]
+  int* d_kused = nullptr;          // per instance Krylov vectors in use
   int have_inc = 0;                // number of previous steps whose increments are held (0, 1, 2)
   double* d_inc[3] = {nullptr, nullptr, nullptr};   // previous step's stage increments
   double* d_inc2[3] = {nullptr, nullptr, nullptr};  // the step before
@@ -454,6 +471,13 @@ ResArgs res_args(dgj_ctx* c) {
   a.tables = c->d_tab;
   a.ph = c->ph;
   a.n_elem = c->n_elem;
+  if (c->n_inst > 0) {
+    a.inst = c->d_inst;
+    a.phs = c->d_phs;
+    a.epsv = c->d_epsv;
+    a.dtav = c->d_dtav;
+    a.active = c->d_active;
+  }
   return a;
 }
 
@@ -515,7 +539,7 @@ void sweep_t(dgj_ctx* c, const double* q, const double* qold, double* out, doubl
   constexpr int NT = sweep_threads<D, N, Q>();
   hipLaunchKernelGGL((k_brj_sweep<D, N, Q, NT, T, TJ>), dim3(c->n_elem), dim3(NT), 0, c->stream, q, qold, out,
                      (const T*)c->d_Dinv, (const TJ*)c->d_Jp, c->d_nbr, c->d_geo, c->d_tab, dt_a, c->sv.brj_omega,
-                     first, c->n_elem);
+                     first, c->n_elem, c->n_inst > 0 ? c->d_inst : nullptr, c->d_dtav, c->d_active);
 }
 
 template <int D, int N, int Q>
@@ -542,32 +566,33 @@ void precond_apply(dgj_ctx* c, const double* q, double* out) {
 }
 
 template <int D, int N, int Q>
-void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* JmW, void* Dm) {
+void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* JmW, void* Dm, long e0, long ne,
+                 const Phys& ph) {
   using S = Shape<D, N, Q>;
   constexpr int NTV = 64;
-  hipLaunchKernelGGL((k_pc_volume<D, N, Q, NTV>), dim3(c->n_elem), dim3(NTV), 0, c->stream, up, c->d_geo, c->d_tab,
-                     c->ph, c->n_elem, Wt);
-  long nf = c->n_elem * S::NF * S::NQF;
+  hipLaunchKernelGGL((k_pc_volume<D, N, Q, NTV>), dim3(ne), dim3(NTV), 0, c->stream, up, c->d_geo, c->d_tab, ph, ne,
+                     Wt, e0);
+  long nf = ne * S::NF * S::NQF;
   if (c->pc_prec == DGJ_PC_F64)
     hipLaunchKernelGGL((k_pc_face<D, N, Q, double>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
-                       c->d_geo, c->d_beta, c->d_tab, c->ph, c->n_elem, c->d_chi, JmW, (double*)c->d_Jp);
+                       c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (double*)c->d_Jp, e0);
   else
     hipLaunchKernelGGL((k_pc_face<D, N, Q, float>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
-                       c->d_geo, c->d_beta, c->d_tab, c->ph, c->n_elem, c->d_chi, JmW, (float*)c->d_Jp);
+                       c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (float*)c->d_Jp, e0);
   constexpr int NTA = 256;
-  const long nblk = c->n_elem * S::NV * S::NV;
+  const long nblk = ne * S::NV * S::NV;
   hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
-                     c->d_tab, dt_a, c->n_elem, (double*)Dm);
+                     c->d_tab, dt_a, ne, (double*)Dm, e0);
 }
 
 template <typename T, int KB>
-void invert(dgj_ctx* c, T* A) {
+void invert(dgj_ctx* c, T* A, long e0, long ne) {
   const int nb = c->NB;
   int threads = ((nb + 63) / 64) * 64;
   size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int);
   HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(c->n_elem), dim3(threads), lds, c->stream, A, nb, c->n_elem,
-                     c->d_status);
+  hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * nb, nb, ne,
+                     c->d_status + e0);
 }
 
 void free_pc(dgj_ctx* c) {
@@ -578,8 +603,32 @@ void free_pc(dgj_ctx* c) {
   c->pc_ready = false;
 }
 
-void precond_build(dgj_ctx* c, const double* up, double dt_a) {
-  using clk = std::chrono::steady_clock;
+// Build the BRJ blocks of elements [e0, e0+ne) (one instance) at state up.
+void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, long ne, const Phys& ph, double* Wt,
+                         double* JmW, void* Dm) {
+  // chi_v = ||u^(v)||_2 sqrt(eps_hat) over the instance  (Eq. 31)
+  hipLaunchKernelGGL(k_varsq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, up + e0 * c->NB, ne, c->NV,
+                     c->NM, c->d_part);
+  std::vector<double> part((size_t)RED_BLOCKS * c->NV);
+  HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double* chi = c->h_scal;   // pinned; the stream was synchronised above
+  for (int v = 0; v < c->NV; ++v) {
+    double s = 0.0;
+    for (int b = 0; b < RED_BLOCKS; ++b) s += part[(size_t)b * c->NV + v];
+    chi[v] = std::sqrt(s) * std::sqrt(EPS_HAT);
+    if (!(chi[v] > 0.0) || !std::isfinite(chi[v]))
+      fail(DGJ_EINVAL, "precond_build: variable %d of u_p is zero or non-finite", v);
+  }
+  HIPCHK(hipMemcpyAsync(c->d_chi, chi, c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
+#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm, e0, ne, ph); } else
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "unsupported shape");
+  invert<double, 32>(c, (double*)Dm, e0, ne);
+}
+
+void precond_alloc(dgj_ctx* c) {
   const int prec = c->sv.pc_precision;
   if (!c->d_Dinv || c->pc_prec != prec) {
     free_pc(c);
@@ -589,37 +638,31 @@ void precond_build(dgj_ctx* c, const double* up, double dt_a) {
     HIPCHK(hipMalloc(&c->d_Jp, (size_t)c->n_elem * 2 * c->dim * (size_t)std::pow(c->nq, c->dim - 1) * c->NV * c->NV * js));
     c->pc_prec = prec;
   }
+}
+
+// Build the preconditioner of the given instances (all: n_inst == 0 or list
+// empty) at state up with per-instance dt a^mm.
+void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& insts, const std::vector<double>& dta) {
+  const int prec = c->sv.pc_precision;
+  precond_alloc(c);
   c->pc_ready = false;
-  // chi_v = ||u^(v)||_2 sqrt(eps_hat)  (Eq. 31)
-  hipLaunchKernelGGL(k_varsq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, up, c->n_elem, c->NV, c->NM,
-                     c->d_part);
-  std::vector<double> part((size_t)RED_BLOCKS * c->NV);
-  HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  std::vector<double> chi(c->NV, 0.0);
-  for (int v = 0; v < c->NV; ++v) {
-    double s = 0.0;
-    for (int b = 0; b < RED_BLOCKS; ++b) s += part[(size_t)b * c->NV + v];
-    chi[v] = std::sqrt(s) * std::sqrt(EPS_HAT);
-    if (!(chi[v] > 0.0) || !std::isfinite(chi[v])) fail(DGJ_EINVAL, "precond_build: variable %d of u_p is zero or non-finite", v);
-  }
-  HIPCHK(hipMemcpyAsync(c->d_chi, chi.data(), c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
   const long nq_vol = (long)std::pow(c->nq, c->dim);
   const long nqf = (long)std::pow(c->nq, c->dim - 1);
   double *Wt = nullptr, *JmW = nullptr;
   void* Dm = nullptr;
   HIPCHK(hipMalloc(&Wt, (size_t)c->n_elem * nq_vol * c->dim * (c->dim + 1) * c->NV * c->NV * sizeof(double)));
   HIPCHK(hipMalloc(&JmW, (size_t)c->n_elem * 2 * c->dim * nqf * c->NV * c->NV * sizeof(double)));
+  const size_t blk = (size_t)c->n_elem * c->NB * c->NB;
   // blocks are assembled and inverted in FP64 (LU-based inversion in double,
   // as the paper's dgetrf/dgetri), then stored in the chosen precision
-  const size_t blk = (size_t)c->n_elem * c->NB * c->NB;
   if (prec == DGJ_PC_F64) Dm = c->d_Dinv;
   else HIPCHK(hipMalloc(&Dm, blk * sizeof(double)));
-#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm); } else
-  DGJ_FOR_SHAPES(X)
-#undef X
-  fail(DGJ_EUNSUPPORTED, "unsupported shape");
-  invert<double, 32>(c, (double*)Dm);
+  for (size_t k = 0; k < insts.size(); ++k) {
+    const int i = insts[k];
+    const long e0 = c->inst_e0[i], ne = c->inst_e0[i + 1] - e0;
+    const Phys ph = c->n_inst > 0 ? c->h_phs[i] : c->ph;
+    precond_build_range(c, up, dta[k], e0, ne, ph, Wt, JmW, Dm);
+  }
   if (prec == DGJ_PC_F32)
     hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const double*)Dm,
                        (float*)c->d_Dinv, (long)blk);
@@ -633,11 +676,17 @@ void precond_build(dgj_ctx* c, const double* up, double dt_a) {
   hipFree(Wt);
   hipFree(JmW);
   if (prec != DGJ_PC_F64) hipFree(Dm);
-  for (long e = 0; e < c->n_elem; ++e)
-    if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
+  for (int i : insts)
+    for (long e = c->inst_e0[i]; e < c->inst_e0[i + 1]; ++e)
+      if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
   c->pc_ready = true;
-  c->pc_dta = dt_a;
   c->pc_age = 0;
+}
+
+void precond_build(dgj_ctx* c, const double* up, double dt_a) {
+  if (c->n_inst > 0) fail(DGJ_EINVAL, "precond_build on a batch group needs per-instance dt");
+  precond_build_insts(c, up, {0}, {dt_a});
+  c->pc_dta = dt_a;
 }
 
 // ---------------------------------------------------------------- MLP
@@ -920,6 +969,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     if (c->NB > 1024) fail(DGJ_EUNSUPPORTED, "block size %d > 1024", c->NB);
     c->n_elem = mesh->n_elem;
     c->n = c->n_elem * c->NB;
+    c->inst_e0 = {0, c->n_elem};
     c->ph = Phys{phys->gamma, phys->Pr, phys->Re, phys->Ma, phys->T_ref_K, phys->visc_law, phys->flux_mode,
                  phys->riemann};
     c->sv = *solver;
@@ -1015,6 +1065,9 @@ void dgj_destroy(dgj_ctx* c) {
   for (double* p : ptrs)
     if (p) hipFree(p);
   if (c->d_nbr) hipFree(c->d_nbr);
+  void* bps[] = {c->d_inst, c->d_phs, c->d_epsv, c->d_dtav, c->d_active, c->d_ioff, c->d_hs, c->d_part2, c->d_kused};
+  for (void* p : bps)
+    if (p) hipFree(p);
   if (c->d_status) hipFree(c->d_status);
   if (c->h_scal) hipHostFree(c->h_scal);
   for (double* p : c->V)
@@ -1037,7 +1090,8 @@ int dgj_project_tgv(dgj_ctx* c, const double* noise, double amp, double* u) {
 #define X(d, n, q)                                                                                          \
   if (c->dim == d && c->N == n && c->nq == q) {                                                              \
     hipLaunchKernelGGL((k_project_tgv<d, n, q>), dim3((total + 127) / 128), dim3(128), 0, c->stream,         \
-                       c->d_origin, c->d_geo, c->d_tab, c->ph, c->n_elem, noise, amp, u);                   \
+                       c->d_origin, c->d_geo, c->d_tab, c->ph, c->n_elem, noise, amp, u,                    \
+                       c->n_inst > 0 ? c->d_inst : nullptr, c->d_phs);                                     \
   } else
     DGJ_FOR_SHAPES(X)
 #undef X
@@ -1467,3 +1521,5 @@ int dgj_mlp_train_step(dgj_ctx* c, const float* X, const float* T, int64_t rows,
 }
 
 }  // extern "C"
+
+#include "dgj_batch.h"

@@ -76,13 +76,13 @@ __device__ __forceinline__ void trace_point(const Tab& tb, const StateIn& in, lo
 template <int D, int N, int Q, int NT>
 __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, const double* __restrict__ geo,
                                                   const double* __restrict__ tables, Phys ph, long n_elem,
-                                                  double* __restrict__ Wt) {
+                                                  double* __restrict__ Wt, long e0) {
   using S = Shape<D, N, Q>;
   using L = ResidualLDS<D, N, Q>;
   constexpr int NV = S::NV, NQ = S::NQ;
   __shared__ double smem[L::TABSZ + S::NB + L::VOL];
-  const long e = blockIdx.x;
-  if (e >= n_elem) return;
+  const long e = e0 + blockIdx.x;
+  if (blockIdx.x >= n_elem) return;
   Tab tb = load_tables<N, Q>(tables, smem);
   double* sU = smem + L::TABSZ;
   double* W = sU + S::NB;
@@ -155,7 +155,8 @@ __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, 
 template <int D, int N, int Q, typename TJ>
 __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ nbr, const double* __restrict__ geo,
                           const double* __restrict__ beta, const double* __restrict__ tables, Phys ph, long n_elem,
-                          const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp) {
+                          const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp,
+                          long e0) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NQF = S::NQF, NF = S::NF;
   __shared__ double st[S::TAB];
@@ -165,7 +166,7 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
   if (gid >= n_elem * NF * NQF) return;
   const int p = gid % NQF;
   const int f = (gid / NQF) % NF;
-  const long e = gid / (NQF * NF);
+  const long e = e0 + gid / (NQF * NF);
   const long en = nbr[e * NF + f];
   const int ax = f >> 1, s = f & 1;
   StateIn in{u, nullptr, 0.0};
@@ -210,7 +211,7 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
 template <int D, int N, int Q, int NT, typename TD>
 __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ Wt, const double* __restrict__ JmW,
                                                      const double* __restrict__ geo, const double* __restrict__ tables,
-                                                     double dt_a, long n_elem, TD* __restrict__ Dm) {
+                                                     double dt_a, long n_elem, TD* __restrict__ Dm, long e0) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF, NB = S::NB;
   constexpr int PER_Q = D * (D + 1) * NV * NV;
@@ -220,10 +221,10 @@ __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ W
   __shared__ double wv[D + 1];
   Tab tb = load_tables<N, Q>(tables, st);
   const long blk = blockIdx.x;
-  const long e = blk / (NV * NV);
+  if (blk / (NV * NV) >= n_elem) return;
+  const long e = e0 + blk / (NV * NV);
   const int kl = blk % (NV * NV);
   const int k = kl / NV, l = kl % NV;
-  if (e >= n_elem) return;
   double acc[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) acc[o] = 0.0;
@@ -469,7 +470,9 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
                                                    double* __restrict__ out, const T* __restrict__ Dinv,
                                                    const TJ* __restrict__ Jp, const int* __restrict__ nbr,
                                                    const double* __restrict__ geo, const double* __restrict__ tables,
-                                                   double dt_a, double omega, int first, long n_elem) {
+                                                   double dt_a, double omega, int first, long n_elem,
+                                                   const int* __restrict__ inst, const double* __restrict__ dtav,
+                                                   const int* __restrict__ active) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQF = S::NQF, NMF = S::NMF, NF = S::NF, NB = S::NB;
   __shared__ double st[S::TAB];
@@ -481,6 +484,11 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
   Tab tb = load_tables<N, Q>(tables, st);
   const long e = blockIdx.x;
   if (e >= n_elem) return;
+  if (inst) {
+    const int ii = inst[e];
+    if (active && !active[ii]) return;
+    dt_a = dtav[ii];
+  }
   const int tid = threadIdx.x;
   const double* g = geo + e * S::GEO;
   for (int i = tid; i < NB; i += NT) { sr[i] = q[e * NB + i]; sacc[i] = 0.0; }

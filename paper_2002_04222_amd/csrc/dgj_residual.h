@@ -56,13 +56,15 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
   __shared__ double sQ[K::QG];
   const long e = blockIdx.x;
   if (e >= a.n_elem) return;
+  ElemParams ep;
+  if (!elem_params(a, e, ep)) return;
   const int tid = threadIdx.x;
   const double* g = a.geo + e * K::S::GEO;
   double dxi[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) dxi[j] = g[j];
   const double detJ = g[D];
-  for (int i = tid; i < NB; i += NT) sU[i] = a.in(e * NB + i);
+  for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
   __syncthreads();
 
   if constexpr (D == 3) {
@@ -213,8 +215,8 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
 #pragma unroll
       for (int j = 0; j < D; ++j) gU[j][v] = sQ[(1 + j) * NV * NQ + v * NQ + q] * dxi[j];
     }
-    euler_flux<D, double>(a.ph, U, F);
-    viscous_flux<D, double, double>(a.ph, U, gU, G);
+    euler_flux<D, double>(ep.ph, U, F);
+    viscous_flux<D, double, double>(ep.ph, U, gU, G);
     double wq = detJ;
     {
       int r = q;
@@ -349,6 +351,8 @@ __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, cons
   const int p = gid % NQF;
   const int ax = (gid / NQF) % D;
   const long e = gid / (NQF * D);
+  ElemParams ep;
+  if (!elem_params(a, e, ep)) return;
   const long en = a.nbr[e * NF + 2 * ax + 1];
   const double* tL = trace + e * (long)K::TRACE + (2 * ax + 1) * (D + 1) * NV * NQF;
   const double* tR = trace + en * (long)K::TRACE + (2 * ax) * (D + 1) * NV * NQF;
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, cons
 #pragma unroll
   for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? 1.0 : 0.0;
   double H[NV], Sf[D][NV];
-  face_flux<D>(a.ph, UL, UR, gL, gR, nrm, a.beta[e * NF + 2 * ax + 1], H, Sf);
+  face_flux<D>(ep.ph, UL, UR, gL, gR, nrm, a.beta[e * NF + 2 * ax + 1], H, Sf);
   double wf = a.geo[e * K::S::GEO + D + 2 + ax] * tk.w[p % Q];
   if (D == 3) wf *= tk.w[p / Q];
   double* o = X + e * (long)K::XF + ax * (D + 1) * NV * NQF;
@@ -389,6 +393,8 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
   __shared__ double sF[NF * 2 * NV * NMF];
   const long e = blockIdx.x;
   if (e >= a.n_elem) return;
+  ElemParams ep;
+  if (!elem_params(a, e, ep)) return;
   const int tid = threadIdx.x;
   const double* g = a.geo + e * K::S::GEO;
   // face data in the element's own orientation and scaling
@@ -450,10 +456,10 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
     if (a.mode == RES_R) {
       a.out[gi] = R;
     } else {
-      const double w = a.in(gi);
-      const double Nw = (w - a.S[gi]) - a.dt_a * R;
+      const double w = ep.in(gi);
+      const double Nw = (w - a.S[gi]) - ep.dt_a * R;
       if (a.mode == RES_N) a.out[gi] = Nw;
-      else a.out[gi] = (Nw - a.Nu[gi]) / a.in.eps;
+      else a.out[gi] = (Nw - a.Nu[gi]) / ep.in.eps;
     }
   }
 }

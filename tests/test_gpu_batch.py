@@ -1,0 +1,46 @@
+"""Batches of independent instances with different mesh sizes, orders and
+gas parameters: every instance of the batch reproduces its single-instance
+run (same Newton and GMRES iteration counts, same state)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+import workloads as W
+
+
+def test_batch_matches_solo_runs():
+    print("[case] batch of 6 mixed-order instances vs solo", flush=True)
+    from paper_2002_04222_amd import Batch, Context
+    cfgs = W.batch_configs(6, seed=11, nmin=3, nmax=6, pmin=1, pmax=3)
+    batch = Batch(cfgs)
+    u = batch.empty()
+    noise = torch.tensor(W.noise(batch.n_total, 12), device="cuda")
+    batch.project_tgv(noise, 1e-3, u)
+    R = batch.empty()
+    batch.residual(u, R)
+    dts = [c.dt() * 0.3 for c in cfgs]
+    u0 = u.clone()
+    nits, gits = [], []
+    for k in range(2):
+        ni, gi = batch.sdirk_step(u, dts)
+        nits.append(ni)
+        gits.append(gi)
+    for i, cfg in enumerate(cfgs):
+        o0 = batch.offsets[i]
+        o1 = o0 + batch.counts[i]
+        ctx = Context(cfg.mesh(), cfg)
+        ui = u0[o0:o1].clone().reshape(ctx.shape)
+        Ri = ctx.empty()
+        ctx.residual(ui, Ri)
+        assert torch.equal(Ri.reshape(-1), R[o0:o1]), i
+        for k in range(2):
+            st = ctx.sdirk_step(ui, dts[i])
+            assert st["newton_its"] == nits[k][i][:2], (i, k)
+            assert [sum(x) for x in st["gmres_its"]] == gits[k][i][:2], (i, k)
+        a, b = ui.reshape(-1).cpu().numpy(), u[o0:o1].cpu().numpy()
+        assert np.array_equal(a, b), (i, np.abs(a - b).max())
+        ctx.close()

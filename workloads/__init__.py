@@ -154,6 +154,22 @@ def config(i: int, **overrides) -> FlowConfig:
     return dataclasses.replace(c, **overrides)
 
 
+def batch_configs(n: int = 64, seed: int = 5, nmin: int = 4, nmax: int = 32, pmin: int = 2, pmax: int = 5):
+    """Independent 2D periodic Taylor-Green problems on [0, 2 pi]^2:
+    N_x, N_y ~ U{nmin..nmax}, P ~ U{pmin..pmax}, Ma ~ U[0.1, 0.5],
+    Re ~ logU[100, 2000], SDIRK2 at CFL 20 (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        nx, ny = (int(x) for x in rng.integers(nmin, nmax + 1, size=2))
+        P = int(rng.integers(pmin, pmax + 1))
+        Ma = float(rng.uniform(0.1, 0.5))
+        Re = float(np.exp(rng.uniform(np.log(100.0), np.log(2000.0))))
+        out.append(FlowConfig(name=f"tgv2d-batch{i}", dim=2, ncells=(nx, ny), lengths=(TWO_PI, TWO_PI), P=P,
+                              nq=P + 2, Re=Re, Ma=Ma, scheme="sdirk2", seed=seed * 1000 + i))
+    return out
+
+
 def noise(shape, seed: int) -> np.ndarray:
     """Seeded uniform(-1, 1) array (PCG64)."""
     rng = np.random.Generator(np.random.PCG64(seed))
