@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--pc", default=None, help="preconditioner storage f64|f32|bf16 (default: workload's)")
     ap.add_argument("--forms", action="store_true", help="also time the f32 and bf16 preconditioner forms")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the batch of 64 independent 2D problems, batched against one by one")
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--mode", default="full", choices=["full", "sweep", "copy"],
@@ -258,10 +261,74 @@ def main():
             forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
         out["forms"] = forms
 
+    if args.batch:
+        out["batch"] = bench_batch(args.batch_steps)
+
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(steps):
+    """64 independent 2D periodic Taylor-Green problems (N_x, N_y in 4..32,
+    P in 2..5, Ma 0.1-0.5, Re 100-2000, SDIRK2 at CFL 20): SDIRK steps of the
+    whole batch in lockstep against the same steps one instance at a time."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2002_04222_amd import Batch, Context
+    cfgs = W.batch_configs(64, seed=5)
+    dts = [c.dt() for c in cfgs]
+    batch = Batch(cfgs)
+    u = batch.empty()
+    batch.project_tgv(torch.tensor(W.noise(batch.n_total, 5), device="cuda"), 1e-3, u)
+    u0 = u.clone()
+    R = batch.empty()
+    for _ in range(3):
+        batch.residual(u, R)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        batch.residual(u, R)
+    torch.cuda.synchronize()
+    res_ms = (time.perf_counter() - t) * 100.0
+    batch.sdirk_step(u, dts)                       # warm-up (builds the preconditioners)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        ni, gi = batch.sdirk_step(u, dts)
+        its.append(sum(sum(x) for x in gi))
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t) * 1e3 / steps
+    log(f"batch: {batch_ms:.1f} ms per step of 64 instances, residual {res_ms:.3f} ms")
+    # the same steps one instance at a time
+    solo_ms = 0.0
+    dofs = 0
+    max_rel = 0.0
+    for i, cfg in enumerate(cfgs):
+        ctx = Context(cfg.mesh(), cfg)
+        o = batch.offsets[i]
+        ui = u0[o:o + batch.counts[i]].clone().reshape(ctx.shape)
+        ctx.sdirk_step(ui, dts[i])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.sdirk_step(ui, dts[i])
+        torch.cuda.synchronize()
+        solo_ms += (time.perf_counter() - t) * 1e3 / steps
+        a = ui.reshape(-1)
+        b = u[o:o + batch.counts[i]]
+        max_rel = max(max_rel, float((a - b).abs().max() / b.abs().max()))
+        dofs += cfg.dofs()
+        ctx.close()
+    log(f"one by one: {solo_ms:.1f} ms per step of 64 instances")
+    return {"instances": 64, "dofs_per_var": dofs, "unknowns": batch.n_total, "steps": steps,
+            "ms_per_step_batched": batch_ms, "ms_per_step_one_by_one": solo_ms,
+            "speedup": solo_ms / batch_ms, "residual_ms_batched": res_ms,
+            "residual_dofs_per_s_batched": dofs / (res_ms * 1e-3),
+            "gmres_its_per_step": its, "max_rel_diff_vs_one_by_one": max_rel}
 
 
 def _lam(scheme):

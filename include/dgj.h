@@ -238,6 +238,10 @@ int dgj_batch_create(int32_t n, const dgj_mesh *meshes, const dgj_phys *phys, co
                      void *hip_stream, dgj_batch **out);
 void dgj_batch_destroy(dgj_batch *batch);
 const char *dgj_batch_last_error(const dgj_batch *batch);
+/* on != 0 (default): each Krylov step of each order's instances (BRJ sweeps,
+ * matvec, Gram-Schmidt) is captured once into a hipGraph on the batch's own
+ * stream and replayed; 0: plain launches. */
+int dgj_batch_set_graphs(dgj_batch *batch, int32_t on);
 /* total unknowns; per instance offsets[n] and counts[n] (host, may be NULL) */
 int dgj_batch_sizes(const dgj_batch *batch, int64_t *n_total, int64_t *offsets, int64_t *counts);
 /* dgj_project_tgv for every instance (noise in the batch layout, may be NULL) */

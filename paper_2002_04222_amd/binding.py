@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_batch_create": ([C.c_int32, C.POINTER(Mesh), C.POINTER(Phys), C.POINTER(Solver), vp, C.POINTER(vp)],
                              C.c_int),
         "dgj_batch_destroy": ([vp], None),
+        "dgj_batch_set_graphs": ([vp, C.c_int32], C.c_int),
         "dgj_batch_last_error": ([vp], C.c_char_p),
         "dgj_batch_sizes": ([vp, i64p, i64p, i64p], C.c_int),
         "dgj_batch_project_tgv": ([vp, vp, dp, vp], C.c_int),
@@ -203,6 +204,9 @@ class Batch:
     def empty(self):
         import torch
         return torch.empty(self.n_total, dtype=torch.float64, device="cuda")
+
+    def set_graphs(self, on):
+        self._check(self.lib.dgj_batch_set_graphs(self.h, 1 if on else 0))
 
     def project_tgv(self, noise, amp, u):
         self._check(self.lib.dgj_batch_project_tgv(self.h, _ptr(noise), float(amp), _ptr(u)))

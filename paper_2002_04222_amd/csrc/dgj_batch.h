@@ -110,7 +110,60 @@ struct Batch {
   std::string err;
   std::vector<std::vector<int>> act;   // per group host copy of the active flags
   std::vector<double> dt_prev;         // per instance dt of the last step
+  // hipGraph replay of the Krylov step (own stream: the legacy stream cannot be captured)
+  bool use_graphs = true;
+  hipStream_t own = nullptr;
+  hipStream_t caller = nullptr;
+  std::vector<std::vector<hipGraphExec_t>> gexec;   // [group][k]
+  std::vector<double*> h_slots;                    // pinned [group][n_inst*64]
+  std::vector<int*> h_act;                         // pinned [group][n_inst]
 };
+
+// one Arnoldi step of group c: z = P^-1 V_k, V_{k+1} = J z, MGS against V_0..V_k, ||V_{k+1}||
+void arnoldi_body(dgj_ctx* c, int k) {
+  if (c->pc_ready) precond_apply(c, c->V[k], c->d_z);
+  else hipLaunchKernelGGL(k_copy_seg, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_z, c->V[k], 0.0, nullptr,
+                          c->d_inst, c->NB, c->d_active, c->n);
+  double* w = c->V[k + 1];
+  matvec(c, c->d_ubar, c->d_N, c->d_S, 0.0, c->d_z, 0.0, w);
+  for (int i = 0; i <= k; ++i) {
+    hipLaunchKernelGGL(k_dot_seg, dim3(RED_BLOCKS, c->n_inst), dim3(RED_THREADS), 0, c->stream, w, c->V[i], c->d_ioff,
+                       c->d_active, c->d_part2);
+    hipLaunchKernelGGL(k_reduce_seg, dim3(c->n_inst), dim3(RED_THREADS), 0, c->stream, c->d_part2, RED_BLOCKS,
+                       c->d_active, c->d_hs, i, 0);
+    hipLaunchKernelGGL(k_axpy_seg, dim3(grid_for(c->n)), dim3(256), 0, c->stream, w, c->V[i], c->d_hs, i, -1.0,
+                       c->d_inst, c->NB, c->d_active, c->n);
+  }
+  hipLaunchKernelGGL(k_dot_seg, dim3(RED_BLOCKS, c->n_inst), dim3(RED_THREADS), 0, c->stream, w, w, c->d_ioff,
+                     c->d_active, c->d_part2);
+  hipLaunchKernelGGL(k_reduce_seg, dim3(c->n_inst), dim3(RED_THREADS), 0, c->stream, c->d_part2, RED_BLOCKS,
+                     c->d_active, c->d_hs, k + 1, 1);
+}
+
+void arnoldi_launch(Batch& B, int gi, int k) {
+  dgj_ctx* c = B.g[gi];
+  if (!B.use_graphs) {
+    arnoldi_body(c, k);
+    return;
+  }
+  auto& ge = B.gexec[gi];
+  if ((int)ge.size() <= k) ge.resize(k + 1, nullptr);
+  if (!ge[k]) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    arnoldi_body(c, k);
+    HIPCHK(hipStreamEndCapture(c->stream, &graph));
+    HIPCHK(hipGraphInstantiate(&ge[k], graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(graph));
+  }
+  HIPCHK(hipGraphLaunch(ge[k], c->stream));
+}
+
+void drop_graphs(Batch& B) {
+  for (auto& v : B.gexec)
+    for (auto& x : v)
+      if (x) { hipGraphExecDestroy(x); x = nullptr; }
+}
 
 void set_active(dgj_ctx* c, std::vector<int>& h) {
   HIPCHK(hipMemcpyAsync(c->d_active, h.data(), c->n_inst * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -209,25 +262,26 @@ void batch_gmres(Batch& B, std::vector<std::vector<IG>>& ig) {
     }
     first = false;
     if (!any) break;
-    // Arnoldi steps in lockstep
+    // Arnoldi steps in lockstep: one replayed graph per group, one host sync per step
     for (int k = 0; k < m; ++k) {
+      std::vector<int> live(G, 0);
+      for (int gi = 0; gi < G; ++gi) {
+        for (int i = 0; i < B.g[gi]->n_inst; ++i) live[gi] |= B.act[gi][i];
+        if (!live[gi]) continue;
+        arnoldi_launch(B, gi, k);
+        dgj_ctx* c = B.g[gi];
+        HIPCHK(hipMemcpyAsync(B.h_slots[gi], c->d_hs, (size_t)c->n_inst * 64 * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+      }
+      HIPCHK(hipStreamSynchronize(B.own));
       bool running = false;
       for (int gi = 0; gi < G; ++gi) {
+        if (!live[gi]) continue;
         dgj_ctx* c = B.g[gi];
-        bool grp_any = false;
-        for (int i = 0; i < c->n_inst; ++i) grp_any |= (bool)B.act[gi][i];
-        if (!grp_any) continue;
-        prec(c, c->V[k], c->d_z);
-        double* w = c->V[k + 1];
-        matvec(c, c->d_ubar, c->d_N, c->d_S, 0.0, c->d_z, 0.0, w);
-        for (int i = 0; i <= k; ++i) {
-          dot_seg(c, w, c->V[i], i, 0);
-          hipLaunchKernelGGL(k_axpy_seg, SEGL(c), w, c->V[i], c->d_hs, i, -1.0, c->d_inst, c->NB, c->d_active, c->n);
-        }
-        dot_seg(c, w, w, k + 1, 1);
-        auto h = fetch_slots(c, k + 2);
-        std::vector<int> a = B.act[gi];
+        const double* h = B.h_slots[gi];
+        int* a = B.h_act[gi];
         for (int ii = 0; ii < c->n_inst; ++ii) {
+          a[ii] = B.act[gi][ii];
           if (!a[ii]) continue;
           IG& s = ig[gi][ii];
           s.its++;
@@ -255,14 +309,18 @@ void batch_gmres(Batch& B, std::vector<std::vector<IG>>& ig) {
           }
         }
         // normalise the new vector for the instances without breakdown
-        set_active(c, a);
-        hipLaunchKernelGGL(k_div_seg, SEGL(c), w, w, c->d_hs, k + 1, c->d_inst, c->NB, c->d_active, c->n);
+        HIPCHK(hipMemcpyAsync(c->d_active, a, c->n_inst * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_div_seg, SEGL(c), c->V[k + 1], c->V[k + 1], c->d_hs, k + 1, c->d_inst, c->NB, c->d_active,
+                           c->n);
         for (int ii = 0; ii < c->n_inst; ++ii) {
           if (!B.act[gi][ii]) continue;
           if (ig[gi][ii].stop) B.act[gi][ii] = 0;
           running |= (bool)B.act[gi][ii];
         }
-        set_active(c, B.act[gi]);
+        // next step's mask (pinned copy is reused only after the next sync)
+        int* a2 = B.h_act[gi] + c->n_inst;
+        for (int ii = 0; ii < c->n_inst; ++ii) a2[ii] = B.act[gi][ii];
+        HIPCHK(hipMemcpyAsync(c->d_active, a2, c->n_inst * sizeof(int), hipMemcpyHostToDevice, c->stream));
       }
       if (!running) break;
     }
@@ -401,9 +459,11 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
   dgj_batch* b = new dgj_batch();
   b->n = n;
   b->sv = *solver;
-  b->stream = (hipStream_t)hip_stream;
+  b->caller = (hipStream_t)hip_stream;
   int rc = DGJ_OK;
   try {
+    HIPCHK(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking));
+    b->stream = b->own;
     // groups by (dim, P, nq), in order of first appearance
     std::vector<std::array<int, 3>> keys;
     b->grp.assign(n, -1);
@@ -448,7 +508,7 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
       e0[members.size()] = eo;
       dgj_mesh gm{D, keys[gi][1], keys[gi][2], E, org.data(), h.data(), nbr.data()};
       dgj_ctx* c = nullptr;
-      int r = dgj_create(&gm, &phys[members[0]], solver, hip_stream, &c);
+      int r = dgj_create(&gm, &phys[members[0]], solver, (void*)b->own, &c);
       if (r != DGJ_OK) throw Status{r, "batch: creating a group context failed"};
       b->g.push_back(c);
       c->n_inst = (int)members.size();
@@ -479,6 +539,13 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
       HIPCHK(hipMemcpy(c->d_dtav, zeros.data(), ni * sizeof(double), hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(c->d_ioff, ioff.data(), (ni + 1) * sizeof(long), hipMemcpyHostToDevice));
       b->act.push_back(ones);
+      double* hs = nullptr;
+      int* ha = nullptr;
+      HIPCHK(hipHostMalloc(&hs, (size_t)ni * 64 * sizeof(double), hipHostMallocDefault));
+      HIPCHK(hipHostMalloc(&ha, (size_t)ni * 2 * sizeof(int), hipHostMallocDefault));
+      b->h_slots.push_back(hs);
+      b->h_act.push_back(ha);
+      b->gexec.emplace_back();
       b->goff.push_back(pos);
       pos += c->n;
     }
@@ -499,8 +566,7 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
   }
   if (rc != DGJ_OK) {
     fprintf(stderr, "dgj_batch_create: %s\n", b->err.c_str());
-    for (auto* c : b->g) dgj_destroy(c);
-    delete b;
+    dgj_batch_destroy(b);
     return rc;
   }
   *out = b;
@@ -509,8 +575,21 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
 
 void dgj_batch_destroy(dgj_batch* b) {
   if (!b) return;
+  if (b->own) hipStreamSynchronize(b->own);
+  drop_graphs(*b);
   for (auto* c : b->g) dgj_destroy(c);
+  for (double* p : b->h_slots)
+    if (p) hipHostFree(p);
+  for (int* p : b->h_act)
+    if (p) hipHostFree(p);
+  if (b->own) hipStreamDestroy(b->own);
   delete b;
+}
+
+int dgj_batch_set_graphs(dgj_batch* b, int32_t on) {
+  if (!b) return DGJ_EINVAL;
+  b->use_graphs = on != 0;
+  return DGJ_OK;
 }
 
 const char* dgj_batch_last_error(const dgj_batch* b) { return b ? b->err.c_str() : "null batch"; }
@@ -528,7 +607,12 @@ int dgj_batch_sizes(const dgj_batch* b, int64_t* n_total, int64_t* offsets, int6
 
 static int batch_guard(dgj_batch* b, const std::function<int()>& f) {
   try {
-    return f();
+    // the batch works on its own stream: wait for the caller's work first and
+    // finish before returning
+    HIPCHK(hipStreamSynchronize(b->caller));
+    int r = f();
+    HIPCHK(hipStreamSynchronize(b->own));
+    return r;
   } catch (const HipError& h) {
     b->err = std::string("HIP error ") + hipGetErrorString(h.e) + " in " + h.what;
     return DGJ_EHIP;
@@ -584,6 +668,7 @@ int dgj_batch_sdirk_step(dgj_batch* b, double* u, const double* dt, int32_t* new
       for (int i = 0; i < b->n; ++i)
         if (b->grp[i] == gi && std::fabs(b->dt_prev[i] - dt[i]) > 1e-12 * dt[i]) stale = true;
       if (stale) {
+        drop_graphs(*b);   // captured Krylov steps refer to the preconditioner state
         for (int k = 0; k < c->n_inst; ++k) insts.push_back(k);
         for (int i = 0; i < b->n; ++i)
           if (b->grp[i] == gi) dta.push_back(0.0);

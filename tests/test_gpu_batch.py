@@ -12,11 +12,16 @@ torch = pytest.importorskip("torch")
 import workloads as W
 
 
-def test_batch_matches_solo_runs():
-    print("[case] batch of 6 mixed-order instances vs solo", flush=True)
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_matches_solo_runs(graphs):
+    """With graphs the captured Krylov steps are replayed many times (every
+    iteration of every Newton step of both steps), each checked through the
+    final states against eager single-instance runs."""
+    print(f"[case] batch of 6 mixed-order instances vs solo, graphs={graphs}", flush=True)
     from paper_2002_04222_amd import Batch, Context
     cfgs = W.batch_configs(6, seed=11, nmin=3, nmax=6, pmin=1, pmax=3)
     batch = Batch(cfgs)
+    batch.set_graphs(graphs)
     u = batch.empty()
     noise = torch.tensor(W.noise(batch.n_total, 12), device="cuda")
     batch.project_tgv(noise, 1e-3, u)
