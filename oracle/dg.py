@@ -40,7 +40,9 @@ class Disc:
     elem_origin: np.ndarray
     elem_h: np.ndarray
     face_nbr: np.ndarray
-    bc: Optional[Callable] = None   # boundary ghost-state hook (unused on periodic grids)
+    bc: Optional[Callable] = None   # extra boundary contribution hook (tests)
+    bc_kind: Optional[np.ndarray] = None    # per boundary id: BC_FARFIELD or BC_WALL
+    bc_state: Optional[np.ndarray] = None   # per boundary id: freestream conserved state [nv]
 
     def __post_init__(self):
         self.ref = ref_element(self.dim, self.P, self.nq)
@@ -125,9 +127,62 @@ class Disc:
             np.add.at(L, eL, contribL)
             np.add.at(L, eR, contribR)
         if np.any(self.face_nbr < 0):
-            if self.bc is None:
+            if self.bc is not None:
+                L += self.bc(self, u)
+            elif self.bc_kind is not None:
+                L += self.boundary_terms(u)
+            else:
                 raise ValueError("mesh has boundary faces but no boundary condition")
-            L += self.bc(self, u)
+        return L
+
+    def boundary_faces(self):
+        """(elements, face f, boundary id) of every boundary face."""
+        out = []
+        for f in range(2 * self.dim):
+            e = np.nonzero(self.face_nbr[:, f] < 0)[0]
+            if e.size:
+                out.append((e, f, -self.face_nbr[e, f] - 1))
+        return out
+
+    def boundary_normal(self, k, f):
+        axis, side = divmod(f, 2)
+        n = np.zeros((k, self.ref.nqf, self.dim))
+        n[..., axis] = -1.0 if side == 0 else 1.0
+        return n
+
+    def boundary_beta(self, e, f):
+        axis = f // 2
+        area = np.prod(np.delete(self.elem_h[e], axis, axis=-1), axis=-1)
+        return (self.P + 1) ** 2 / (self.vol[e] / area)
+
+    def boundary_flux(self, u, e, f, bid, Qo=None, go=None):
+        """Flux (H^n, S) of the boundary faces (e, f) in e's orientation."""
+        from .physics import boundary_flux_own
+        if Qo is None:
+            Qo, go = self.trace(u, e, f)
+        n = self.boundary_normal(len(e), f)
+        beta = np.broadcast_to(self.boundary_beta(e, f)[:, None], Qo.shape[:-1])
+        H = np.zeros(Qo.shape, dtype=np.result_type(Qo, go))
+        S = np.zeros(go.shape, dtype=H.dtype)
+        for b in np.unique(bid):
+            k = bid == b
+            Hb, Sb = boundary_flux_own(self.gas, int(self.bc_kind[b]), Qo[k], go[k], n[k], beta[k],
+                                       self.bc_state[b])
+            H[k], S[k] = Hb, Sb
+        return H, S
+
+    def boundary_terms(self, u):
+        """Lifted boundary face fluxes: -phi H + grad phi . S on each boundary face."""
+        ref = self.ref
+        L = np.zeros(u.shape, dtype=np.result_type(u, np.float64))
+        for e, f, bid in self.boundary_faces():
+            H, S = self.boundary_flux(u, e, f, bid)
+            wf = ref.WF[None, :] * self.face_det(e, f // 2)[:, None]
+            c = -np.einsum('pm,kpv->kvm', ref.BF[f], H * wf[..., None])
+            for j in range(self.dim):
+                c = c + np.einsum('pm,kpv->kvm', ref.DF[f][j], S[:, :, j, :] * wf[..., None]) \
+                    * self.dxi[e, j, None, None]
+            np.add.at(L, e, c)
         return L
 
     def apply_Minv(self, L):

@@ -219,3 +219,69 @@ def face_flux_own(gas: Gas, Uo, Un, go, gn, n, beta_p):
     F = riemann_flux(gas, Uo, Un, n)
     Gn, S = ip_face_fluxes(gas, Uo, Un, go, gn, n, beta_p)
     return F - Gn, S
+
+
+# ---------------------------------------------------------------- boundary ghost states
+# The paper names its boundary conditions (Sec. 4.3) but gives no formulas.
+# Readings: a boundary face takes the interior trace Q- and a ghost state Q+
+# with the interior gradient, and the interior-face fluxes are applied.
+BC_FARFIELD, BC_WALL = 0, 1
+
+
+def farfield_ghost(gas: Gas, U, n, Uinf):
+    """Riemann-invariant far field: with u_n the outward normal velocity and
+    c the sound speed, R+ = u_n + 2c/(gamma-1) from the interior, R- = u_n -
+    2c/(gamma-1) from the freestream (for |u_n| < c); u_nb = (R+ + R-)/2,
+    c_b = (gamma-1)(R+ - R-)/4; tangential velocity and entropy p/rho^gamma
+    from the interior on outflow (u_nb > 0), from the freestream on inflow.
+    Supersonic: all from the interior (outflow) or the freestream (inflow)."""
+    g = gas.gamma
+    Uinf = np.broadcast_to(Uinf, U.shape)
+    ri, vi, Ei, pi = primitives(gas, U)
+    ro, vo, Eo, po = primitives(gas, Uinf)
+    ci, co = np.sqrt(g * pi / ri), np.sqrt(g * po / ro)
+    uni = np.sum(vi * n, axis=-1)
+    uno = np.sum(vo * n, axis=-1)
+    Rp = uni + 2.0 * ci / (g - 1.0)
+    Rm = uno - 2.0 * co / (g - 1.0)
+    unb = 0.5 * (Rp + Rm)
+    cb = 0.25 * (g - 1.0) * (Rp - Rm)
+    out = np.real(unb) > 0.0
+    s_i, s_o = pi / ri ** g, po / ro ** g
+    s = np.where(out, s_i, s_o)
+    vt = np.where(out[..., None], vi - uni[..., None] * n, vo - uno[..., None] * n)
+    rb = (cb * cb / (g * s)) ** (1.0 / (g - 1.0))
+    pb = rb * cb * cb / g
+    vb = vt + unb[..., None] * n
+    Ub = np.concatenate([rb[..., None], rb[..., None] * vb,
+                         (pb / (g - 1.0) + 0.5 * rb * np.sum(vb * vb, axis=-1))[..., None]], axis=-1)
+    sup_out = np.real(uni) >= np.real(ci)
+    sup_in = np.real(uno) <= -np.real(co)
+    Ub = np.where(sup_out[..., None], U, Ub)
+    Ub = np.where(sup_in[..., None], Uinf, Ub)
+    return Ub
+
+
+def wall_ghost(U):
+    """No-slip wall: the momentum mirrored, density and energy kept, so the
+    face average has zero velocity and the interior temperature."""
+    G = U.copy()
+    G[..., 1:-1] = -U[..., 1:-1]
+    return G
+
+
+def boundary_flux_own(gas: Gas, kind, Uo, go, n, beta_p, Uinf=None):
+    """Boundary face flux (H^n, S) seen from the interior with outward normal
+    n: ghost state per kind, ghost gradient = interior gradient; at an
+    adiabatic wall the heat flux through the wall is zero, so the energy
+    components of the viscous face fluxes vanish (the work term vanishes with
+    the zero wall velocity)."""
+    Un = farfield_ghost(gas, Uo, n, Uinf) if kind == BC_FARFIELD else wall_ghost(Uo)
+    F = riemann_flux(gas, Uo, Un, n)
+    Gn, S = ip_face_fluxes(gas, Uo, Un, go, go, n, beta_p)
+    if kind == BC_WALL:
+        Gn = Gn.copy()
+        S = S.copy()
+        Gn[..., -1] = 0.0
+        S[..., -1] = 0.0
+    return F - Gn, S

@@ -147,6 +147,20 @@ class BRJ:
             wf = ref.WF[None, :] * disc.face_det(elems, f // 2)[:, None]
             A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f])
             self.face_jp[f] = (elems, nbrs, fn, wf, Jp)
+        # boundary faces: the boundary condition is inside the flux that is
+        # differenced (Eq. 31), so only the own-side Jacobian exists
+        if disc.bc_kind is not None:
+            for elems, f, bid in disc.boundary_faces():
+                Qo, go = disc.trace(u_p, elems, f)
+                H0, _ = disc.boundary_flux(u_p, elems, f, bid, Qo, go)
+                Jm = np.zeros(Qo.shape + (nv,))
+                for l in range(nv):
+                    dq = np.zeros(nv)
+                    dq[l] = self.chi[l]
+                    H1, _ = disc.boundary_flux(u_p, elems, f, bid, Qo + dq, go)
+                    Jm[..., l] = (H1 - H0) / self.chi[l]
+                wf = ref.WF[None, :] * disc.face_det(elems, f // 2)[:, None]
+                A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f])
         self.A_diag = A.reshape(E, nb, nb)
         Minv = np.linalg.inv(disc.M)                                       # [E, nm, nm]
         MinvA = np.einsum('emn,eknlo->ekmlo', Minv, A).reshape(E, nb, nb)
