@@ -21,7 +21,8 @@
  *    i + n (j + n k), x fastest, n = P + 1.  n_unknowns = n_elem (d+2) n^d.
  *  - Elements are affine boxes; faces are f = 2*axis + side (side 0 at
  *    xi_axis = -1).  face_nbr[e][f] is the element across face f, which
- *    meets it with its face 2*axis + (1 - side), face points aligned.
+ *    meets it with its face 2*axis + (1 - side), face points aligned, or
+ *    marks a boundary face (dgj_mesh).
  *  - Work is enqueued on the context's stream.  Entry points that need a
  *    scalar on the host (norms for eps, chi and the GMRES Hessenberg
  *    entries) synchronise that stream; the rest are asynchronous.
@@ -55,6 +56,23 @@ enum { DGJ_PC_F64 = 0, DGJ_PC_F32 = 1, DGJ_PC_BF16 = 2 };
 
 typedef struct dgj_ctx dgj_ctx;
 
+/* Boundary condition kinds.  No formulas are given in the paper, which
+ * only names the kinds its solver offers (Sec. 5); the two built are the
+ * ones of its cylinder case.  A boundary face takes the interior trace and
+ * a ghost state with the interior gradient, and the interior face fluxes
+ * (Riemann flux, interior-penalty viscous terms) apply:
+ *  DGJ_BC_FARFIELD: 1D characteristic far field.  With u_n the outward
+ *    normal velocity and c the sound speed, R+ = u_n + 2c/(gamma-1) comes
+ *    from the interior and R- = u_n - 2c/(gamma-1) from the freestream;
+ *    tangential velocity and entropy p/rho^gamma come from the interior
+ *    where (R+ + R-)/2 > 0, else from the freestream.  Supersonic inflow:
+ *    the freestream state; supersonic outflow: the interior state.
+ *  DGJ_BC_WALL: adiabatic no-slip wall.  Ghost = interior with the
+ *    momentum negated (zero wall velocity); the energy components of the
+ *    viscous flux and of the symmetric interior-penalty term are zero (no
+ *    heat flux through the wall). */
+enum { DGJ_BC_FARFIELD = 0, DGJ_BC_WALL = 1 };
+
 /* Mesh of affine boxes (host arrays, copied by dgj_create). */
 typedef struct {
   int32_t dim;                /* 2 or 3 */
@@ -63,7 +81,12 @@ typedef struct {
   int64_t n_elem;
   const double *elem_origin;  /* host [n_elem][dim] lower corner */
   const double *elem_h;       /* host [n_elem][dim] edge lengths */
-  const int32_t *face_nbr;    /* host [n_elem][2*dim]; all >= 0 (periodic grids) */
+  const int32_t *face_nbr;    /* host [n_elem][2*dim]: element across the face, or -(id+1)
+                                 for a face on boundary id (0 <= id < n_bc) */
+  int32_t n_bc;               /* number of boundary ids; 0 for periodic meshes */
+  const int32_t *bc_kind;     /* host [n_bc]: DGJ_BC_FARFIELD or DGJ_BC_WALL (NULL if n_bc = 0) */
+  const double *bc_state;     /* host [n_bc][dim+2]: freestream conserved state of each far-field
+                                 id (rho > 0, p > 0); entries of wall ids are not read */
 } dgj_mesh;
 
 /* Non-dimensional gas and flux options (Sec. 2). */

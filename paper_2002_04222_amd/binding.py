@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libdgj.so")
 DGJ_OK = 0
 DGJ_SDIRK2, DGJ_SDIRK3 = 2, 3
 DGJ_PC_F64, DGJ_PC_F32, DGJ_PC_BF16 = 0, 1, 2
+DGJ_BC_FARFIELD, DGJ_BC_WALL = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOTCONV", -5: "ENAN", -6: "ESINGULAR",
           -7: "EUNSUPPORTED"}
 
@@ -28,7 +29,8 @@ class DgjError(RuntimeError):
 class Mesh(C.Structure):
     _fields_ = [("dim", C.c_int32), ("P", C.c_int32), ("nq", C.c_int32), ("n_elem", C.c_int64),
                 ("elem_origin", C.POINTER(C.c_double)), ("elem_h", C.POINTER(C.c_double)),
-                ("face_nbr", C.POINTER(C.c_int32))]
+                ("face_nbr", C.POINTER(C.c_int32)), ("n_bc", C.c_int32), ("bc_kind", C.POINTER(C.c_int32)),
+                ("bc_state", C.POINTER(C.c_double))]
 
 
 class Phys(C.Structure):
@@ -138,13 +140,23 @@ SCHEMES = {"sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3}
 PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
 
 
-def _mesh_struct(mesh, cfg, keep):
+def _mesh_struct(mesh, cfg, keep, bc_kind=None, bc_state=None):
+    """dgj_mesh over host copies held in keep; bc_kind[n_bc] and
+    bc_state[n_bc][dim+2] describe the boundary ids of face_nbr < 0."""
     arrs = [np.ascontiguousarray(mesh.elem_origin, dtype=np.float64),
             np.ascontiguousarray(mesh.elem_h, dtype=np.float64),
             np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)]
     keep.extend(arrs)
-    return Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem, arrs[0].ctypes.data_as(C.POINTER(C.c_double)),
-                arrs[1].ctypes.data_as(C.POINTER(C.c_double)), arrs[2].ctypes.data_as(C.POINTER(C.c_int32)))
+    m = Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem, arrs[0].ctypes.data_as(C.POINTER(C.c_double)),
+             arrs[1].ctypes.data_as(C.POINTER(C.c_double)), arrs[2].ctypes.data_as(C.POINTER(C.c_int32)))
+    if bc_kind is not None:
+        kind = np.ascontiguousarray(bc_kind, dtype=np.int32).ravel()
+        state = np.ascontiguousarray(bc_state, dtype=np.float64).reshape(len(kind), mesh.dim + 2)
+        keep.extend([kind, state])
+        m.n_bc = len(kind)
+        m.bc_kind = kind.ctypes.data_as(C.POINTER(C.c_int32))
+        m.bc_state = state.ctypes.data_as(C.POINTER(C.c_double))
+    return m
 
 
 def _phys_struct(cfg):
@@ -226,18 +238,13 @@ class Batch:
 class Context:
     """A dgj context for one mesh and set of options (see include/dgj.h)."""
 
-    def __init__(self, mesh, cfg, stream=None, **over):
+    def __init__(self, mesh, cfg, stream=None, bc_kind=None, bc_state=None, **over):
         import torch
         self.lib = load_library()
         self.dim, self.P, self.nq = mesh.dim, cfg.P, cfg.nq
         self.n_elem = mesh.n_elem
-        self._keep = [np.ascontiguousarray(mesh.elem_origin, dtype=np.float64),
-                      np.ascontiguousarray(mesh.elem_h, dtype=np.float64),
-                      np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)]
-        m = Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem,
-                 self._keep[0].ctypes.data_as(C.POINTER(C.c_double)),
-                 self._keep[1].ctypes.data_as(C.POINTER(C.c_double)),
-                 self._keep[2].ctypes.data_as(C.POINTER(C.c_int32)))
+        self._keep = []
+        m = _mesh_struct(mesh, cfg, self._keep, bc_kind, bc_state)
         g = lambda k: over.get(k, getattr(cfg, k))
         ph = Phys(g("gamma"), g("Pr"), g("Re"), g("Ma"), g("T_ref_K"), g("visc_law"), g("flux_mode"), g("riemann"))
         sv = Solver(SCHEMES[g("scheme")], g("newton_rtol"), g("newton_max"), g("gmres_restart"), g("gmres_rtol"),

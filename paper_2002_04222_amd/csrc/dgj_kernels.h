@@ -109,6 +109,10 @@ struct ResArgs {
   const double* tables;
   Phys ph;
   long n_elem;
+  // boundary conditions: kind and freestream state per boundary id
+  // (face_nbr = -(id + 1))
+  const int* bc_kind;
+  const double* bc_state;
   // batches of independent instances: per-element instance index and
   // per-instance gas parameters, eps, dt a^mm and active flag (all null for
   // a single instance, which then uses ph, in.eps and dt_a)

@@ -326,6 +326,9 @@ struct dgj_ctx {
   double* d_geo = nullptr;
   double* d_beta = nullptr;
   int* d_nbr = nullptr;
+  int n_bc = 0;
+  int* d_bc_kind = nullptr;       // per boundary id
+  double* d_bc_state = nullptr;   // per boundary id, freestream [NV]
   double* d_origin = nullptr;
   double* d_tab = nullptr;
   std::vector<double> h_tab;   // tables + Lagrange weights, passed by value to the residual kernels
@@ -466,6 +469,8 @@ void launch_residual(dgj_ctx* c, const ResArgs& a) {
 ResArgs res_args(dgj_ctx* c) {
   ResArgs a{};
   a.nbr = c->d_nbr;
+  a.bc_kind = c->d_bc_kind;
+  a.bc_state = c->d_bc_state;
   a.geo = c->d_geo;
   a.beta = c->d_beta;
   a.tables = c->d_tab;
@@ -575,10 +580,12 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
   long nf = ne * S::NF * S::NQF;
   if (c->pc_prec == DGJ_PC_F64)
     hipLaunchKernelGGL((k_pc_face<D, N, Q, double>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
-                       c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (double*)c->d_Jp, e0);
+                       c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (double*)c->d_Jp, e0, c->d_bc_kind,
+                       c->d_bc_state);
   else
     hipLaunchKernelGGL((k_pc_face<D, N, Q, float>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
-                       c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (float*)c->d_Jp, e0);
+                       c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (float*)c->d_Jp, e0, c->d_bc_kind,
+                       c->d_bc_state);
   constexpr int NTA = 256;
   const long nblk = ne * S::NV * S::NV;
   hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
@@ -995,28 +1002,58 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
         geo[e * GEO + D + 2 + a] = fd;
       }
     }
+    if (mesh->n_bc < 0 || (mesh->n_bc > 0 && (!mesh->bc_kind || !mesh->bc_state)))
+      fail(DGJ_EINVAL, "n_bc > 0 needs bc_kind and bc_state");
+    const int NVh = D + 2;
+    for (int b = 0; b < mesh->n_bc; ++b) {
+      const int k = mesh->bc_kind[b];
+      if (k != DGJ_BC_FARFIELD && k != DGJ_BC_WALL) fail(DGJ_EINVAL, "boundary %d: unknown kind %d", b, k);
+      if (k == DGJ_BC_FARFIELD) {
+        const double* U = mesh->bc_state + b * NVh;
+        double ke = 0.0;
+        for (int j = 0; j < D; ++j) ke += U[1 + j] * U[1 + j];
+        const double p = (phys->gamma - 1.0) * (U[D + 1] - 0.5 * ke / U[0]);
+        if (!(U[0] > 0.0) || !(p > 0.0)) fail(DGJ_EINVAL, "boundary %d: freestream needs rho > 0 and p > 0", b);
+      }
+    }
     for (long e = 0; e < E; ++e) {
       for (int f = 0; f < NF; ++f) {
         long en = nbr[e * NF + f];
-        if (en < 0 || en >= E) fail(DGJ_EUNSUPPORTED, "element %ld face %d: boundary faces are not supported", e, f);
+        if (en >= E || en < -(long)mesh->n_bc)
+          fail(DGJ_EINVAL, "element %ld face %d: neighbour %ld out of range", e, f, en);
         const int a = f / 2;
-        long eL = (f & 1) ? e : en, eR = (f & 1) ? en : e;
         double volL = 1.0, volR = 1.0, area = 1.0;
-        for (int j = 0; j < D; ++j) {
-          volL *= mesh->elem_h[eL * D + j];
-          volR *= mesh->elem_h[eR * D + j];
-          if (j != a) area *= mesh->elem_h[eL * D + j];
+        if (en >= 0) {
+          long eL = (f & 1) ? e : en, eR = (f & 1) ? en : e;
+          for (int j = 0; j < D; ++j) {
+            volL *= mesh->elem_h[eL * D + j];
+            volR *= mesh->elem_h[eR * D + j];
+            if (j != a) area *= mesh->elem_h[eL * D + j];
+          }
+        } else {   // boundary face: the element's own size
+          for (int j = 0; j < D; ++j) {
+            volL *= mesh->elem_h[e * D + j];
+            if (j != a) area *= mesh->elem_h[e * D + j];
+          }
+          volR = volL;
         }
         double hf = std::min(volL, volR) / area;
         beta[e * NF + f] = (c->P + 1.0) * (c->P + 1.0) / hf;
       }
+    }
+    c->n_bc = mesh->n_bc;
+    if (mesh->n_bc > 0) {
+      HIPCHK(hipMalloc(&c->d_bc_kind, mesh->n_bc * sizeof(int)));
+      HIPCHK(hipMalloc(&c->d_bc_state, mesh->n_bc * NVh * sizeof(double)));
+      HIPCHK(hipMemcpy(c->d_bc_kind, mesh->bc_kind, mesh->n_bc * sizeof(int), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(c->d_bc_state, mesh->bc_state, mesh->n_bc * NVh * sizeof(double), hipMemcpyHostToDevice));
     }
     std::vector<double> tab = build_tables(c->P, c->nq);
     c->h_tab = tab;
     {
       const long nqf = (long)std::pow(c->nq, D - 1);
       HIPCHK(hipMalloc(&c->d_trace, (size_t)E * NF * (D + 1) * c->NV * nqf * sizeof(double)));
-      HIPCHK(hipMalloc(&c->d_X, (size_t)E * D * (D + 1) * c->NV * nqf * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_X, (size_t)E * NF * (D + 1) * c->NV * nqf * sizeof(double)));
       HIPCHK(hipMalloc(&c->d_Lvol, (size_t)E * c->NB * sizeof(double)));
     }
     HIPCHK(hipMalloc(&c->d_geo, geo.size() * sizeof(double)));
@@ -1065,6 +1102,8 @@ void dgj_destroy(dgj_ctx* c) {
   for (double* p : ptrs)
     if (p) hipFree(p);
   if (c->d_nbr) hipFree(c->d_nbr);
+  if (c->d_bc_kind) hipFree(c->d_bc_kind);
+  if (c->d_bc_state) hipFree(c->d_bc_state);
   void* bps[] = {c->d_inst, c->d_phs, c->d_epsv, c->d_dtav, c->d_active, c->d_ioff, c->d_hs, c->d_part2, c->d_kused};
   for (void* p : bps)
     if (p) hipFree(p);

@@ -353,4 +353,93 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, cons
   }
 }
 
+// ---------------------------------------------------------------- boundary conditions
+// A boundary face takes the interior trace and a ghost state with the
+// interior gradient, and the interior-face fluxes apply.  Far field: 1D
+// characteristic (Riemann-invariant) state against the freestream Uinf;
+// no-slip wall: mirrored momentum (zero wall velocity), with the heat flux
+// through the wall zero (adiabatic), so the viscous energy fluxes vanish.
+enum { BC_FARFIELD = 0, BC_WALL = 1 };
+
+template <int D>
+__device__ __forceinline__ void farfield_ghost(const Phys& ph, const double* Ui, const double* n, const double* Uo,
+                                               double* Ub) {
+  constexpr int NV = D + 2;
+  const double g = ph.gamma;
+  double ri = Ui[0], ro = Uo[0];
+  double vi[D], vo[D], ki = 0.0, ko = 0.0, uni = 0.0, uno = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    vi[c] = Ui[1 + c] / ri; vo[c] = Uo[1 + c] / ro;
+    ki += vi[c] * vi[c]; ko += vo[c] * vo[c];
+    uni += vi[c] * n[c]; uno += vo[c] * n[c];
+  }
+  const double pi = (g - 1.0) * (Ui[D + 1] - 0.5 * ri * ki);
+  const double po = (g - 1.0) * (Uo[D + 1] - 0.5 * ro * ko);
+  const double ci = sqrt(g * pi / ri), co = sqrt(g * po / ro);
+  if (uno <= -co) {   // supersonic inflow (takes precedence)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ub[v] = Uo[v];
+    return;
+  }
+  if (uni >= ci) {    // supersonic outflow
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ub[v] = Ui[v];
+    return;
+  }
+  const double Rp = uni + 2.0 * ci / (g - 1.0);
+  const double Rm = uno - 2.0 * co / (g - 1.0);
+  const double unb = 0.5 * (Rp + Rm);
+  const double cb = 0.25 * (g - 1.0) * (Rp - Rm);
+  const bool out = unb > 0.0;
+  const double s = out ? pi / pow(ri, g) : po / pow(ro, g);
+  const double rb = pow(cb * cb / (g * s), 1.0 / (g - 1.0));
+  const double pb = rb * cb * cb / g;
+  double vb[D], kb = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double vt = out ? vi[c] - uni * n[c] : vo[c] - uno * n[c];
+    vb[c] = vt + unb * n[c];
+    kb += vb[c] * vb[c];
+  }
+  Ub[0] = rb;
+#pragma unroll
+  for (int c = 0; c < D; ++c) Ub[1 + c] = rb * vb[c];
+  Ub[D + 1] = pb / (g - 1.0) + 0.5 * rb * kb;
+}
+
+// boundary face flux seen from the interior (outward normal n)
+template <int D>
+__device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const double* Uo, const double (*go)[D + 2],
+                                              const double* n, double beta, const double* Uinf, double* H,
+                                              double (*S)[D + 2]) {
+  constexpr int NV = D + 2;
+  double Un[NV];
+  if (kind == BC_FARFIELD) {
+    farfield_ghost<D>(ph, Uo, n, Uinf, Un);
+  } else {
+    Un[0] = Uo[0];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Un[1 + c] = -Uo[1 + c];
+    Un[D + 1] = Uo[D + 1];
+  }
+  face_flux<D>(ph, Uo, Un, go, go, n, beta, H, S);
+  if (kind == BC_WALL) {
+    double F[NV];
+    if (ph.flux_mode == 2) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = 0.0;
+    } else if (ph.riemann == 0) {
+      roe_flux<D>(ph, Uo, Un, n, F);
+    } else {
+      llf_flux<D>(ph, Uo, Un, n, F);
+    }
+    H[D + 1] = F[D + 1];
+    if (S) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) S[j][D + 1] = 0.0;
+    }
+  }
+}
+
 }  // namespace dgj

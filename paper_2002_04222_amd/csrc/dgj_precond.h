@@ -156,7 +156,7 @@ template <int D, int N, int Q, typename TJ>
 __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ nbr, const double* __restrict__ geo,
                           const double* __restrict__ beta, const double* __restrict__ tables, Phys ph, long n_elem,
                           const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp,
-                          long e0) {
+                          long e0, const int* __restrict__ bc_kind, const double* __restrict__ bc_state) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NQF = S::NQF, NF = S::NF;
   __shared__ double st[S::TAB];
@@ -172,22 +172,41 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
   StateIn in{u, nullptr, 0.0};
   double Uo[NV], Un[NV], go[D][NV], gn[D][NV];
   trace_point<D, N, Q>(tb, in, e, geo + e * S::GEO, f, p, Uo, go);
-  trace_point<D, N, Q>(tb, in, en, geo + en * S::GEO, f ^ 1, p, Un, gn);
   double nrm[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
   const double b = beta[e * NF + f];
-  double H0[NV], H1[NV];
-  face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H0, nullptr);
   const double* g = geo + e * S::GEO;
   double wf = g[D + 2 + ax];
   {
-    int tax[2] = {0, 0};
-    tang_axes<D>(ax, tax);
     wf *= tb.w[p % Q];
     if (D == 3) wf *= tb.w[p / Q];
   }
   const long base = ((e * NF + f) * NQF + p) * NV * NV;
+  double H0[NV], H1[NV];
+  if (en < 0) {
+    // boundary face: the condition is inside the differenced flux (Eq. 31);
+    // no neighbour, so no off-diagonal Jacobian
+    const int bid = -en - 1;
+    const int kind = bc_kind[bid];
+    const double* Uinf = bc_state + bid * NV;
+    boundary_flux<D>(ph, kind, Uo, go, nrm, b, Uinf, H0, nullptr);
+    for (int l = 0; l < NV; ++l) {
+      const double chi = chi_dev[l];
+      const double save = Uo[l];
+      Uo[l] = save + chi;
+      boundary_flux<D>(ph, kind, Uo, go, nrm, b, Uinf, H1, nullptr);
+      Uo[l] = save;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        JmW[base + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
+        Jp[base + k * NV + l] = (TJ)0.0;
+      }
+    }
+    return;
+  }
+  trace_point<D, N, Q>(tb, in, en, geo + en * S::GEO, f ^ 1, p, Un, gn);
+  face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H0, nullptr);
   for (int l = 0; l < NV; ++l) {
     const double chi = chi_dev[l];
     double save = Uo[l];
@@ -497,6 +516,7 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
     for (int f = 0; f < NF; ++f) {
       const int ax = f >> 1, s = f & 1;
       const long en = nbr[e * NF + f];
+      if (en < 0) continue;   // boundary face: no neighbour block
       const int sg = 1 - s;
       int tax[2] = {0, 0};
       tang_axes<D>(ax, tax);

@@ -39,7 +39,7 @@ struct ResK {
   static constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NMF = S::NMF, NF = S::NF, NB = S::NB;
   // sizes of the per-element scratch arrays
   static constexpr int TRACE = NF * (D + 1) * NV * NQF;    // trace[e]
-  static constexpr int XF = D * (D + 1) * NV * NQF;        // X[e] (faces normal to each axis, side 1)
+  static constexpr int XF = 2 * D * (D + 1) * NV * NQF;    // X[e][f]: the flux of each face e computes
   static constexpr int T1 = (D == 3) ? 2 * NV * Q * N * N : 2 * NV * Q * N;
   static constexpr int T2 = (D == 3) ? 3 * NV * Q * Q * N : 0;
   static constexpr int QG = (D + 1) * NV * NQ;
@@ -341,11 +341,62 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
 }
 
 // ---------------------------------------------------------------- face fluxes
+// Flux of face f of element e at face point p, weighted by w^G |J^G|, into
+// X[e][f]: (H^n, S_j) in e's orientation (outward normal of face f).
+template <int D, int N, int Q>
+__device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, Q>& tk, const Phys& ph,
+                                                const double* __restrict__ trace, double* __restrict__ X, long e,
+                                                int f, long en, int p) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NQF = K::NQF;
+  const int ax = f >> 1, s = f & 1;
+  const double* tL = trace + e * (long)K::TRACE + f * (D + 1) * NV * NQF;
+  double UL[NV], gL[D][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    UL[v] = tL[v * NQF + p];
+#pragma unroll
+    for (int j = 0; j < D; ++j) gL[j][v] = tL[((1 + j) * NV + v) * NQF + p];
+  }
+  double nrm[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
+  double H[NV], Sf[D][NV];
+  const double beta = a.beta[e * K::NF + f];
+  if (en >= 0) {
+    const double* tR = trace + en * (long)K::TRACE + (f ^ 1) * (D + 1) * NV * NQF;
+    double UR[NV], gR[D][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      UR[v] = tR[v * NQF + p];
+#pragma unroll
+      for (int j = 0; j < D; ++j) gR[j][v] = tR[((1 + j) * NV + v) * NQF + p];
+    }
+    face_flux<D>(ph, UL, UR, gL, gR, nrm, beta, H, Sf);
+  } else {
+    const int bid = -(int)en - 1;
+    boundary_flux<D>(ph, a.bc_kind[bid], UL, gL, nrm, beta, a.bc_state + bid * NV, H, Sf);
+  }
+  double wf = a.geo[e * K::S::GEO + D + 2 + ax] * tk.w[p % Q];
+  if (D == 3) wf *= tk.w[p / Q];
+  double* o = X + e * (long)K::XF + f * (D + 1) * NV * NQF;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    o[v * NQF + p] = wf * H[v];
+#pragma unroll
+    for (int j = 0; j < D; ++j) o[((1 + j) * NV + v) * NQF + p] = wf * Sf[j][v];
+  }
+}
+
+// One thread per (element, axis, point).  Each interior face is computed
+// once, by the element that meets it with side 1 (normal +e_axis); a
+// boundary face by its element, in its own orientation, so the thread of
+// axis a also computes its element's side-0 face when that is a boundary.
 template <int D, int N, int Q>
 __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, const double* __restrict__ trace,
                                                   double* __restrict__ X) {
   using K = ResK<D, N, Q>;
-  constexpr int NV = K::NV, NQF = K::NQF, NF = K::NF;
+  constexpr int NQF = K::NQF, NF = K::NF;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= a.n_elem * D * NQF) return;
   const int p = gid % NQF;
@@ -353,34 +404,9 @@ __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, cons
   const long e = gid / (NQF * D);
   ElemParams ep;
   if (!elem_params(a, e, ep)) return;
-  const long en = a.nbr[e * NF + 2 * ax + 1];
-  const double* tL = trace + e * (long)K::TRACE + (2 * ax + 1) * (D + 1) * NV * NQF;
-  const double* tR = trace + en * (long)K::TRACE + (2 * ax) * (D + 1) * NV * NQF;
-  double UL[NV], UR[NV], gL[D][NV], gR[D][NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    UL[v] = tL[v * NQF + p];
-    UR[v] = tR[v * NQF + p];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      gL[j][v] = tL[((1 + j) * NV + v) * NQF + p];
-      gR[j][v] = tR[((1 + j) * NV + v) * NQF + p];
-    }
-  }
-  double nrm[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? 1.0 : 0.0;
-  double H[NV], Sf[D][NV];
-  face_flux<D>(ep.ph, UL, UR, gL, gR, nrm, a.beta[e * NF + 2 * ax + 1], H, Sf);
-  double wf = a.geo[e * K::S::GEO + D + 2 + ax] * tk.w[p % Q];
-  if (D == 3) wf *= tk.w[p / Q];
-  double* o = X + e * (long)K::XF + ax * (D + 1) * NV * NQF;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    o[v * NQF + p] = wf * H[v];
-#pragma unroll
-    for (int j = 0; j < D; ++j) o[((1 + j) * NV + v) * NQF + p] = wf * Sf[j][v];
-  }
+  face_point_flux<D, N, Q>(a, tk, ep.ph, trace, X, e, 2 * ax + 1, a.nbr[e * NF + 2 * ax + 1], p);
+  const long e0 = a.nbr[e * NF + 2 * ax];
+  if (e0 < 0) face_point_flux<D, N, Q>(a, tk, ep.ph, trace, X, e, 2 * ax, e0, p);
 }
 
 // ---------------------------------------------------------------- lift + epilogue
@@ -403,11 +429,13 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
     const int v = (it / NQF) % NV;
     const int k = (it / (NQF * NV)) % (D + 1);
     const int f = it / (NQF * NV * (D + 1));
-    const int ax = f >> 1, s = f & 1;
-    const long src = (s == 1) ? e : (long)a.nbr[e * NF + f];
-    const double x = X[src * (long)K::XF + ((ax * (D + 1) + k) * NV + v) * NQF + p];
-    // k = 0: -Hhat_own = -(+-Hhat); k >= 1: Shat_j dxi_j
-    sA[it] = (k == 0) ? ((s == 1) ? -x : x) : x * g[k - 1];
+    const long en = a.nbr[e * NF + f];
+    const bool mine = (f & 1) == 1 || en < 0;   // flux stored in this element's orientation
+    const long src = mine ? e : en;
+    const int fs = mine ? f : (f ^ 1);
+    const double x = X[src * (long)K::XF + ((fs * (D + 1) + k) * NV + v) * NQF + p];
+    // k = 0: -Hhat_own (the neighbour's flux has the opposite orientation); k >= 1: Shat_j dxi_j
+    sA[it] = (k == 0) ? (mine ? -x : x) : x * g[k - 1];
   }
   __syncthreads();
   // tangential contraction to face modes: F0 (multiplies phi(+-1)), F1 (phi'(+-1))
