@@ -15,9 +15,13 @@ element width normal to the face on a Cartesian grid (the paper does not
 define h).  Traces are evaluated directly at the face quadrature points
 (equal to interpolation from the volume points on affine elements).
 
-Elements are affine boxes: x = origin + (xi + 1) h / 2, so d/dx_j =
-(2/h_j) d/dxi_j, |J| = prod(h)/2^d and |J^Gamma| is the product of the
-tangential half-widths.
+Geometry (oracle/geometry.py): affine boxes x = origin + (xi + 1) h / 2,
+with d/dx_j = (2/h_j) d/dxi_j, |J| = prod(h)/2^d and |J^Gamma| the product
+of the tangential half-widths; or isoparametric curved elements with the
+metrics d xi / d x, |J|, the outward normal and |J^Gamma| taken pointwise,
+gradients grad Q = (d xi/d x)^T grad_xi Q, and the dense mass matrix
+M_e = B^T diag(w |J|) B.  On curved elements h = min(|Omega_e|,
+|Omega_e'|) / |Gamma_f| uses quadrature volumes and areas.
 """
 from __future__ import annotations
 
@@ -27,33 +31,41 @@ from typing import Callable, Optional
 import numpy as np
 
 from .basis import ref_element
+from .geometry import Geometry
 from .physics import Gas, euler_flux, viscous_flux, face_flux_own
 
 
 @dataclasses.dataclass
 class Disc:
-    """A DG discretisation on a structured mesh of affine boxes."""
+    """A DG discretisation on a structured mesh of affine boxes or of
+    isoparametric curved elements (geo_nodes [E, (geo_order+1)^d, d])."""
     gas: Gas
     dim: int
     P: int
     nq: int
-    elem_origin: np.ndarray
-    elem_h: np.ndarray
+    elem_origin: Optional[np.ndarray]
+    elem_h: Optional[np.ndarray]
     face_nbr: np.ndarray
     bc: Optional[Callable] = None   # extra boundary contribution hook (tests)
     bc_kind: Optional[np.ndarray] = None    # per boundary id: BC_FARFIELD or BC_WALL
     bc_state: Optional[np.ndarray] = None   # per boundary id: freestream conserved state [nv]
+    geo_nodes: Optional[np.ndarray] = None  # curved elements: isoparametric nodes
+    geo_order: int = 1
 
     def __post_init__(self):
         self.ref = ref_element(self.dim, self.P, self.nq)
         self.nv = self.dim + 2
-        self.n_elem = self.elem_h.shape[0]
-        self.detJ = np.prod(self.elem_h / 2.0, axis=1)            # [E]
-        self.dxi = 2.0 / self.elem_h                                # [E, d] dxi_j/dx_j
-        self.vol = np.prod(self.elem_h, axis=1)
+        self.n_elem = self.face_nbr.shape[0]
         ref = self.ref
+        self.geo = Geometry(ref, self.dim, self.elem_origin, self.elem_h, self.geo_nodes, self.geo_order)
+        self.detJ = self.geo.detJ                                   # [E] (boxes only)
+        self.dxi = self.geo.dxi                                     # [E, d] dxi_j/dx_j (boxes only)
+        self.vol = self.geo.vol
         # mass matrix M_e = B^T diag(w |J|) B   (Eq. 13)
-        self.M = np.einsum('qm,q,qn->mn', ref.B, ref.W, ref.B)[None] * self.detJ[:, None, None]
+        if self.geo.curved:
+            self.M = np.einsum('qm,eq,qn->emn', ref.B, self.geo.wJ, ref.B)
+        else:
+            self.M = np.einsum('qm,q,qn->mn', ref.B, ref.W, ref.B)[None] * self.detJ[:, None, None]
 
     @property
     def shape(self):
@@ -64,18 +76,35 @@ class Disc:
         return np.prod(np.delete(h, axis, axis=-1) / 2.0, axis=-1)
 
     def beta_p(self, eL, eR, axis):
-        area = np.prod(np.delete(self.elem_h[eL], axis, axis=-1), axis=-1)
+        """Penalty of the faces between eL (side 1) and eR (side 0)."""
+        area = self.geo.area[2 * axis + 1][eL]
         hf = np.minimum(self.vol[eL], self.vol[eR]) / area
         return (self.P + 1) ** 2 / hf
 
+    def phys_grad(self, G, dref):
+        """grad Q[..., j, v] = sum_k (d xi_k / d x_j) d Q_v / d xi_k."""
+        return np.einsum('...kj,k...v->...jv', G, dref)
+
+    def lift_S(self, f, elems, Sw):
+        """sum_k (D_k B^G_f)^T (sum_j (d xi_k/d x_j) S_j w|J^G|) for the
+        weighted symmetric-term flux Sw[k, p, j, v] of face f of elems."""
+        ref = self.ref
+        Gf = self.geo.Gf[f][elems]
+        out = 0.0
+        for k in range(self.dim):
+            Sk = np.einsum('epj,epjv->epv', Gf[:, :, k, :], Sw)
+            out = out + np.einsum('pm,kpv->kvm', ref.DF[f][k], Sk)
+        return out
+
     # -- element-level evaluations ------------------------------------------------
-    def vol_values(self, u):
-        """Q[e, q, v] and grad Q[e, q, j, v] at the volume points."""
+    def vol_values(self, u, elems=None):
+        """Q[e, q, v] and grad Q[e, q, j, v] at the volume points of the
+        elements elems (all if None; u holds their coefficients)."""
         ref = self.ref
         Q = np.einsum('qm,evm->eqv', ref.B, u)
-        G = np.stack([np.einsum('qm,evm->eqv', ref.D[j], u) * self.dxi[:, j, None, None]
-                      for j in range(self.dim)], axis=2)
-        return Q, G
+        dref = np.stack([np.einsum('qm,evm->eqv', ref.D[k], u) for k in range(self.dim)])
+        Gq = self.geo.Gq if elems is None else self.geo.Gq[elems]
+        return Q, self.phys_grad(Gq, dref)
 
     def trace(self, u, elems, f):
         """Trace value [k, p, v] and broken gradient [k, p, j, v] of the
@@ -83,9 +112,8 @@ class Disc:
         ref = self.ref
         ue = u[elems]
         Q = np.einsum('pm,evm->epv', ref.BF[f], ue)
-        G = np.stack([np.einsum('pm,evm->epv', ref.DF[f][j], ue) * self.dxi[elems, j, None, None]
-                      for j in range(self.dim)], axis=2)
-        return Q, G
+        dref = np.stack([np.einsum('pm,evm->epv', ref.DF[f][k], ue) for k in range(self.dim)])
+        return Q, self.phys_grad(self.geo.Gf[f][elems], dref)
 
     def interior_faces(self, axis):
         """Interior faces normal to `axis` as (left elems, right elems): the
@@ -103,27 +131,25 @@ class Disc:
         u = np.asarray(u)
         Q, gQ = self.vol_values(u)
         H = euler_flux(gas, Q) - viscous_flux(gas, Q, gQ)                  # [e, q, j, v]
-        wq = ref.W[None, :] * self.detJ[:, None]                             # [e, q]
+        wq = self.geo.wJ                                                     # [e, q]
         L = np.zeros(u.shape, dtype=np.result_type(u, np.float64))
-        for j in range(d):
-            L += np.einsum('qm,eqv->evm', ref.D[j],
-                           H[:, :, j, :] * (wq * self.dxi[:, j, None])[:, :, None])
+        for k in range(d):
+            Hk = np.einsum('eqj,eqjv->eqv', self.geo.Gq[:, :, k, :], H)      # contravariant flux
+            L += np.einsum('qm,eqv->evm', ref.D[k], Hk * wq[:, :, None])
         for axis in range(d):
             eL, eR = self.interior_faces(axis)
             fL, fR = 2 * axis + 1, 2 * axis
             QL, gL = self.trace(u, eL, fL)
             QR, gR = self.trace(u, eR, fR)
-            n = np.zeros(QL.shape[:-1] + (d,))
-            n[..., axis] = 1.0
+            n = self.geo.nf[fL][eL]                                          # side 1's outward normal
             beta = np.broadcast_to(self.beta_p(eL, eR, axis)[:, None], QL.shape[:-1])
             Hn, S = face_flux_own(gas, QL, QR, gL, gR, n, beta)
-            wf = ref.WF[None, :] * self.face_det(eL, axis)[:, None]         # [k, p]
+            wf = self.geo.wJf[fL][eL]                                        # [k, p]
             contribL = -np.einsum('pm,kpv->kvm', ref.BF[fL], Hn * wf[..., None])
             contribR = np.einsum('pm,kpv->kvm', ref.BF[fR], Hn * wf[..., None])
-            for j in range(d):
-                Sw = S[:, :, j, :] * wf[..., None]
-                contribL += np.einsum('pm,kpv->kvm', ref.DF[fL][j], Sw) * self.dxi[eL, j, None, None]
-                contribR += np.einsum('pm,kpv->kvm', ref.DF[fR][j], Sw) * self.dxi[eR, j, None, None]
+            Sw = S * wf[..., None, None]
+            contribL = contribL + self.lift_S(fL, eL, Sw)
+            contribR = contribR + self.lift_S(fR, eR, Sw)
             np.add.at(L, eL, contribL)
             np.add.at(L, eR, contribR)
         if np.any(self.face_nbr < 0):
@@ -144,23 +170,15 @@ class Disc:
                 out.append((e, f, -self.face_nbr[e, f] - 1))
         return out
 
-    def boundary_normal(self, k, f):
-        axis, side = divmod(f, 2)
-        n = np.zeros((k, self.ref.nqf, self.dim))
-        n[..., axis] = -1.0 if side == 0 else 1.0
-        return n
-
     def boundary_beta(self, e, f):
-        axis = f // 2
-        area = np.prod(np.delete(self.elem_h[e], axis, axis=-1), axis=-1)
-        return (self.P + 1) ** 2 / (self.vol[e] / area)
+        return (self.P + 1) ** 2 / (self.vol[e] / self.geo.area[f][e])
 
     def boundary_flux(self, u, e, f, bid, Qo=None, go=None):
         """Flux (H^n, S) of the boundary faces (e, f) in e's orientation."""
         from .physics import boundary_flux_own
         if Qo is None:
             Qo, go = self.trace(u, e, f)
-        n = self.boundary_normal(len(e), f)
+        n = self.geo.nf[f][e]
         beta = np.broadcast_to(self.boundary_beta(e, f)[:, None], Qo.shape[:-1])
         H = np.zeros(Qo.shape, dtype=np.result_type(Qo, go))
         S = np.zeros(go.shape, dtype=H.dtype)
@@ -177,11 +195,9 @@ class Disc:
         L = np.zeros(u.shape, dtype=np.result_type(u, np.float64))
         for e, f, bid in self.boundary_faces():
             H, S = self.boundary_flux(u, e, f, bid)
-            wf = ref.WF[None, :] * self.face_det(e, f // 2)[:, None]
+            wf = self.geo.wJf[f][e]
             c = -np.einsum('pm,kpv->kvm', ref.BF[f], H * wf[..., None])
-            for j in range(self.dim):
-                c = c + np.einsum('pm,kpv->kvm', ref.DF[f][j], S[:, :, j, :] * wf[..., None]) \
-                    * self.dxi[e, j, None, None]
+            c = c + self.lift_S(f, e, S * wf[..., None, None])
             np.add.at(L, e, c)
         return L
 
@@ -200,12 +216,12 @@ class Disc:
     # -- initial conditions -------------------------------------------------------
     def points(self):
         """Physical coordinates of the volume quadrature points [e, q, j]."""
-        return self.elem_origin[:, None, :] + (self.ref.xi[None] + 1.0) * 0.5 * self.elem_h[:, None, :]
+        return self.geo.xq
 
     def project(self, fn):
         """L2 projection of a pointwise field fn(x[..., d]) -> [..., nv]."""
         vals = fn(self.points())
-        wq = self.ref.W[None, :] * self.detJ[:, None]
+        wq = self.geo.wJ
         rhs = np.einsum('qm,eqv->evm', self.ref.B, vals * wq[..., None])
         return self.apply_Minv(rhs)
 
@@ -215,7 +231,8 @@ def make_disc(cfg, mesh, **gas_overrides) -> Disc:
               T_ref_K=cfg.T_ref_K, flux_mode=cfg.flux_mode, riemann=cfg.riemann)
     kw.update(gas_overrides)
     return Disc(gas=Gas(**kw), dim=mesh.dim, P=cfg.P, nq=cfg.nq, elem_origin=mesh.elem_origin,
-                elem_h=mesh.elem_h, face_nbr=mesh.face_nbr)
+                elem_h=mesh.elem_h, face_nbr=mesh.face_nbr, geo_nodes=getattr(mesh, "geo_nodes", None),
+                geo_order=getattr(mesh, "geo_order", 1))
 
 
 def conserved_from_primitive(gamma, rho, vel, p):

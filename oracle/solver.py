@@ -105,9 +105,9 @@ def face_fd_jacobians(disc, u, chi, elems, f, nbrs, fn, sign):
     axis = f // 2
     Qo, go = disc.trace(u, elems, f)
     Qn, gn = disc.trace(u, nbrs, fn)
-    n = np.zeros(Qo.shape[:-1] + (d,))
-    n[..., axis] = sign
-    beta = np.broadcast_to(disc.beta_p(elems, nbrs, axis)[:, None], Qo.shape[:-1])
+    n = disc.geo.nf[f][elems]                       # own outward normal
+    eL, eR = (elems, nbrs) if f % 2 == 1 else (nbrs, elems)
+    beta = np.broadcast_to(disc.beta_p(eL, eR, axis)[:, None], Qo.shape[:-1])
     H0, _ = face_flux_own(gas, Qo, Qn, go, gn, n, beta)
     Jm = np.zeros(Qo.shape + (nv,))
     Jp = np.zeros(Qo.shape + (nv,))
@@ -134,17 +134,18 @@ class BRJ:
         # volume terms (first two terms of Eq. 30)
         for s in range(0, E, chunk):
             el = np.arange(s, min(E, s + chunk))
-            Q, gQ = disc.vol_values(u_p[el])
+            Q, gQ = disc.vol_values(u_p[el], el)
             dHdQ, dHdG = volume_flux_jacobians(gas, Q, gQ)
-            wq = ref.W[None, :] * disc.detJ[el, None]
-            Dx = np.stack([ref.D[j][None] * disc.dxi[el, j, None, None] for j in range(d)], axis=1)  # [e,j,q,m]
+            wq = disc.geo.wJ[el]
+            # physical derivatives of the basis at the points: sum_k dxi_k/dx_j D_k B
+            Dx = np.einsum('eqkj,kqm->ejqm', disc.geo.Gq[el], np.stack(ref.D))                # [e,j,q,m]
             A[el] += np.einsum('ejqm,eq,eqjkl,qn->ekmln', Dx, wq, dHdQ, ref.B)
             A[el] += np.einsum('ejqm,eq,eqjikl,eiqn->ekmln', Dx, wq, dHdG, Dx)
         # own-side face term (third term of Eq. 30) and stored neighbour Jacobians
         self.face_jp = {}
         for elems, f, nbrs, fn, sign in face_sides(disc):
             Jm, Jp = face_fd_jacobians(disc, u_p, self.chi, elems, f, nbrs, fn, sign)
-            wf = ref.WF[None, :] * disc.face_det(elems, f // 2)[:, None]
+            wf = disc.geo.wJf[f][elems]
             A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f])
             self.face_jp[f] = (elems, nbrs, fn, wf, Jp)
         # boundary faces: the boundary condition is inside the flux that is
@@ -159,7 +160,7 @@ class BRJ:
                     dq[l] = self.chi[l]
                     H1, _ = disc.boundary_flux(u_p, elems, f, bid, Qo + dq, go)
                     Jm[..., l] = (H1 - H0) / self.chi[l]
-                wf = ref.WF[None, :] * disc.face_det(elems, f // 2)[:, None]
+                wf = disc.geo.wJf[f][elems]
                 A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f])
         self.A_diag = A.reshape(E, nb, nb)
         Minv = np.linalg.inv(disc.M)                                       # [E, nm, nm]

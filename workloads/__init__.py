@@ -32,13 +32,15 @@ TWO_PI = 2.0 * math.pi
 class Mesh:
     dim: int
     ncells: tuple
-    elem_origin: np.ndarray   # [n_elem, dim] float64, lower corner
-    elem_h: np.ndarray        # [n_elem, dim] float64, edge lengths
-    face_nbr: np.ndarray      # [n_elem, 2*dim] int32
+    elem_origin: Optional[np.ndarray]   # [n_elem, dim] float64, lower corner (boxes)
+    elem_h: Optional[np.ndarray]        # [n_elem, dim] float64, edge lengths (boxes)
+    face_nbr: np.ndarray                # [n_elem, 2*dim] int32
+    geo_nodes: Optional[np.ndarray] = None   # [n_elem, (geo_order+1)^dim, dim] (curved)
+    geo_order: int = 1
 
     @property
     def n_elem(self) -> int:
-        return int(self.elem_h.shape[0])
+        return int(self.face_nbr.shape[0])
 
 
 def cartesian_mesh(ncells: Sequence[int], lengths: Sequence[float],
@@ -78,6 +80,88 @@ def cartesian_mesh(ncells: Sequence[int], lengths: Sequence[float],
                 face_nbr=face_nbr)
 
 
+def _lattice_elements(ncells, geo_order):
+    """Global lattice indices [n_elem, (geo_order+1)^dim, dim] of the
+    isoparametric nodes of each element of a structured grid (elements x
+    fastest; nodes i0 + (g+1)(i1 + (g+1) i2) at equispaced reference
+    positions -1 + 2 i / g)."""
+    dim = len(ncells)
+    g = geo_order
+    eidx = np.indices(ncells[::-1]).reshape(dim, -1)[::-1].T           # [E, dim]
+    nidx = np.indices((g + 1,) * dim).reshape(dim, -1)[::-1].T         # [nn, dim], x fastest
+    return eidx[:, None, :] * g + nidx[None, :, :]
+
+
+def curved_box_mesh(ncells: Sequence[int], lengths: Sequence[float], geo_order: int = 2,
+                    amp: float = 0.1, seed: int = 7, periodic: Sequence[bool] | bool = True,
+                    bc_ids: Optional[Sequence[int]] = None) -> Mesh:
+    """Box [0, L]^d split as a structured grid, with curved elements: the
+    isoparametric nodes of order geo_order are a Cartesian lattice moved by
+    a smooth seeded displacement, periodic over the box,
+      d_j(x) = amp h_j sum_{t<3} c_jt sin(2 pi m_t . x / L + phi_jt),
+    h_j the cell size, c ~ U(-1/3, 1/3), integer wave numbers m_t in {0, 1, 2}
+    (not all zero), phi ~ U(0, 2 pi).  Neighbours share their face nodes."""
+    dim = len(ncells)
+    nc = [int(c) for c in ncells]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = np.array([lengths[a] / nc[a] for a in range(dim)])
+    L = np.asarray(lengths, dtype=np.float64)
+    m = rng.integers(0, 3, size=(3, dim))
+    m[:, 0] = np.maximum(m[:, 0], 1)
+    c = rng.uniform(-1.0 / 3.0, 1.0 / 3.0, size=(dim, 3))
+    ph = rng.uniform(0.0, TWO_PI, size=(dim, 3))
+    lat = _lattice_elements(nc, geo_order)                                   # [E, nn, dim]
+    x0 = lat * (h / geo_order)[None, None, :]
+    nodes = x0.copy()
+    arg = TWO_PI * np.einsum('td,end->ent', m, x0 / L)                        # [E, nn, 3]
+    for j in range(dim):
+        nodes[..., j] += amp * h[j] * np.sum(c[j] * np.sin(arg + ph[j]), axis=-1)
+    base = cartesian_mesh(nc, lengths, periodic=periodic, bc_ids=bc_ids)
+    return Mesh(dim=dim, ncells=tuple(nc), elem_origin=None, elem_h=None, face_nbr=base.face_nbr,
+                geo_nodes=nodes, geo_order=geo_order)
+
+
+def annulus_mesh(nr: int, nth: int, nz: int = 0, r0: float = 0.5, r1: float = 10.0, Lz: float = math.pi,
+                 geo_order: int = 2, amp: float = 0.1, seed: int = 4) -> Mesh:
+    """O-grid around a cylinder of radius r0 out to r1, extruded over Lz
+    (periodic) when nz > 0: axis 0 radial (face side 0 on r = r0: boundary
+    id 0; side 1 on r = r1: id 1), axis 1 angular (periodic), axis 2
+    spanwise (periodic).  Radial node positions r = r0 (r1/r0)^s, s
+    uniform; nodes strictly inside are moved in r and theta by a smooth
+    seeded field, amp times the local spacing times sin(pi s) (zero on both
+    circles), periodic in theta and z.  Node x = r cos(theta), y = r
+    sin(theta), z."""
+    dim = 3 if nz > 0 else 2
+    nc = [nr, nth] + ([nz] if nz > 0 else [])
+    g = geo_order
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lat = _lattice_elements(nc, g)
+    s = lat[..., 0] / (nr * g)
+    th = TWO_PI * (lat[..., 1] % (nth * g)) / (nth * g)    # the seam's nodes are theta = 0's
+    zz = lat[..., 2] * (Lz / (nz * g)) if dim == 3 else None
+    ratio = (r1 / r0) ** (1.0 / (nr * g))
+    mth = rng.integers(1, 4, size=3)
+    mz = rng.integers(0, 2, size=3)
+    cr, ct = rng.uniform(-1.0 / 3.0, 1.0 / 3.0, size=(2, 3))
+    pr, pt = rng.uniform(0.0, TWO_PI, size=(2, 3))
+    wave_r = np.zeros(s.shape)
+    wave_t = np.zeros(s.shape)
+    for t in range(3):
+        arg = mth[t] * th + (TWO_PI * mz[t] * zz / Lz if dim == 3 else 0.0)
+        wave_r += cr[t] * np.sin(arg + pr[t])
+        wave_t += ct[t] * np.sin(arg + pt[t])
+    bump = np.sin(math.pi * s)
+    r = r0 * (r1 / r0) ** s
+    r = r + amp * r * (ratio - 1.0) * bump * wave_r
+    th = th + amp * (TWO_PI / (nth * g)) * bump * wave_t
+    cols = [r * np.cos(th), r * np.sin(th)] + ([zz] if dim == 3 else [])
+    nodes = np.stack(cols, axis=-1)
+    base = cartesian_mesh(nc, [1.0] * dim, periodic=[False] + [True] * (dim - 1),
+                          bc_ids=[0, 1] + [0] * (2 * dim - 2))
+    return Mesh(dim=dim, ncells=tuple(nc), elem_origin=None, elem_h=None, face_nbr=base.face_nbr,
+                geo_nodes=nodes, geo_order=g)
+
+
 @dataclasses.dataclass
 class FlowConfig:
     """Physical, discretisation and solver parameters of one workload."""
@@ -109,6 +193,9 @@ class FlowConfig:
     brj_omega: float = 1.0
     pc_freeze: int = 10
     pc_precision: str = "f64"
+    geometry: str = "box"     # "box" (periodic affine boxes) or "annulus" (curved O-grid, walls + far field)
+    r0: float = 0.5
+    r1: float = 10.0
 
     @property
     def nv(self) -> int:
@@ -119,7 +206,24 @@ class FlowConfig:
         return (self.P + 1) ** self.dim
 
     def mesh(self) -> Mesh:
+        if self.geometry == "annulus":
+            return annulus_mesh(self.ncells[0], self.ncells[1], self.ncells[2] if self.dim == 3 else 0,
+                                r0=self.r0, r1=self.r1, Lz=self.lengths[-1], seed=self.seed)
         return cartesian_mesh(self.ncells, self.lengths, periodic=True)
+
+    def freestream(self) -> np.ndarray:
+        """Freestream in conserved variables: rho = 1, velocity (1, 0, ..),
+        p = 1/(gamma Ma^2), so E = p/(gamma-1) + 1/2."""
+        p = 1.0 / (self.gamma * self.Ma ** 2)
+        return np.array([1.0, 1.0] + [0.0] * (self.dim - 1) + [p / (self.gamma - 1.0) + 0.5])
+
+    def boundary(self):
+        """(bc_kind, bc_state) of the boundary ids: annulus id 0 = no-slip
+        adiabatic wall on the cylinder, id 1 = far field; none on boxes."""
+        if self.geometry != "annulus":
+            return None, None
+        U = self.freestream()
+        return np.array([1, 0], dtype=np.int32), np.stack([U, U])
 
     def dofs(self) -> int:
         """Degrees of freedom per variable, N_e (P+1)^d."""
@@ -129,7 +233,10 @@ class FlowConfig:
         """Time step from the standard CFL number (c_lambda = 0.2,
         d_RK = 2) with the freestream estimate c + |u| = 1/Ma + umax and
         dx the element edge."""
-        dx = min(self.lengths[a] / self.ncells[a] for a in range(self.dim))
+        if self.geometry == "annulus":
+            dx = self.r0 * ((self.r1 / self.r0) ** (1.0 / self.ncells[0]) - 1.0)   # first radial cell
+        else:
+            dx = min(self.lengths[a] / self.ncells[a] for a in range(self.dim))
         lam = 1.0 / self.Ma + umax
         return self.cfl * 2.0 * dx / (0.2 * lam * self.P ** 2)
 
@@ -137,7 +244,10 @@ class FlowConfig:
 def config(i: int, **overrides) -> FlowConfig:
     """Workloads: 1 = 2D 8x8 P=2 Taylor-Green (Re 100, Ma 0.1, SDIRK2);
     2 = 3D 16^3 P=3 Taylor-Green (Re 1600, Ma 0.1, SDIRK3);
-    3 = workload 2 with a reduced-precision preconditioner."""
+    3 = workload 2 with a reduced-precision preconditioner;
+    4 = flow past a cylinder: curved O-grid annulus r in [0.5, 10], 32
+    radial x 64 angular x 8 spanwise hexes (span pi), P=4, Re 3900, Ma 0.2,
+    wall + far field, SDIRK2."""
     if i == 1:
         c = FlowConfig(name="tgv2d-8x8-p2", dim=2, ncells=(8, 8), lengths=(TWO_PI, TWO_PI),
                        P=2, nq=4, Re=100.0, Ma=0.1, scheme="sdirk2", seed=1)
@@ -149,6 +259,10 @@ def config(i: int, **overrides) -> FlowConfig:
         c = FlowConfig(name="tgv3d-16c-p3-f32pc", dim=3, ncells=(16, 16, 16),
                        lengths=(TWO_PI, TWO_PI, TWO_PI), P=3, nq=5, Re=1600.0, Ma=0.1,
                        scheme="sdirk3", seed=3, pc_precision="f32")
+    elif i == 4:
+        c = FlowConfig(name="cylinder-annulus-64x32x8-p4", dim=3, ncells=(32, 64, 8),
+                       lengths=(1.0, TWO_PI, math.pi), P=4, nq=6, Re=3900.0, Ma=0.2, scheme="sdirk2", seed=4,
+                       geometry="annulus", ic="freestream")
     else:
         raise ValueError(f"unknown workload {i}")
     return dataclasses.replace(c, **overrides)
@@ -168,6 +282,19 @@ def batch_configs(n: int = 64, seed: int = 5, nmin: int = 4, nmax: int = 32, pmi
         out.append(FlowConfig(name=f"tgv2d-batch{i}", dim=2, ncells=(nx, ny), lengths=(TWO_PI, TWO_PI), P=P,
                               nq=P + 2, Re=Re, Ma=Ma, scheme="sdirk2", seed=seed * 1000 + i))
     return out
+
+
+def freestream_state(cfg: FlowConfig, n_elem: int) -> np.ndarray:
+    """Uniform freestream (mode-0 coefficient U_inf 2^(d/2)) plus
+    cfg.noise_amp * sigma_v * noise(seed) on every coefficient, sigma =
+    (1, .., 1, E_inf): an impulsive start."""
+    U = cfg.freestream()
+    shape = (n_elem, cfg.dim + 2, (cfg.P + 1) ** cfg.dim)
+    u = np.zeros(shape)
+    u[:, :, 0] = U * 2.0 ** (cfg.dim / 2.0)
+    sigma = np.ones(cfg.dim + 2)
+    sigma[-1] = U[-1]
+    return u + cfg.noise_amp * sigma[None, :, None] * noise(shape, cfg.seed)
 
 
 def noise(shape, seed: int) -> np.ndarray:
