@@ -87,6 +87,16 @@ typedef struct {
   const int32_t *bc_kind;     /* host [n_bc]: DGJ_BC_FARFIELD or DGJ_BC_WALL (NULL if n_bc = 0) */
   const double *bc_state;     /* host [n_bc][dim+2]: freestream conserved state of each far-field
                                  id (rho > 0, p > 0); entries of wall ids are not read */
+  int32_t geo_order;          /* curved elements: order g of the element maps (1..7) */
+  const double *geo_nodes;    /* host [n_elem][(g+1)^dim][dim] or NULL (affine boxes).  When
+                                 set, elements are isoparametric: x(xi) = sum_c X_c l_c(xi),
+                                 tensor Lagrange polynomials through the equispaced nodes
+                                 -1 + 2i/g, node c = i0 + (g+1)(i1 + (g+1) i2); every map must
+                                 have a positive Jacobian at the Gauss points.  Neighbours
+                                 must share their face nodes (face points aligned as above).
+                                 elem_origin and elem_h are then not read.  Curved meshes
+                                 carry per-point metrics and a dense mass matrix per element
+                                 (Sec. 3.1), and dgj_project_tgv is not available on them. */
 } dgj_mesh;
 
 /* Non-dimensional gas and flux options (Sec. 2). */

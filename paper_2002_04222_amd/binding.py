@@ -30,7 +30,7 @@ class Mesh(C.Structure):
     _fields_ = [("dim", C.c_int32), ("P", C.c_int32), ("nq", C.c_int32), ("n_elem", C.c_int64),
                 ("elem_origin", C.POINTER(C.c_double)), ("elem_h", C.POINTER(C.c_double)),
                 ("face_nbr", C.POINTER(C.c_int32)), ("n_bc", C.c_int32), ("bc_kind", C.POINTER(C.c_int32)),
-                ("bc_state", C.POINTER(C.c_double))]
+                ("bc_state", C.POINTER(C.c_double)), ("geo_order", C.c_int32), ("geo_nodes", C.POINTER(C.c_double))]
 
 
 class Phys(C.Structure):
@@ -143,12 +143,20 @@ PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
 def _mesh_struct(mesh, cfg, keep, bc_kind=None, bc_state=None):
     """dgj_mesh over host copies held in keep; bc_kind[n_bc] and
     bc_state[n_bc][dim+2] describe the boundary ids of face_nbr < 0."""
-    arrs = [np.ascontiguousarray(mesh.elem_origin, dtype=np.float64),
-            np.ascontiguousarray(mesh.elem_h, dtype=np.float64),
-            np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)]
-    keep.extend(arrs)
-    m = Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem, arrs[0].ctypes.data_as(C.POINTER(C.c_double)),
-             arrs[1].ctypes.data_as(C.POINTER(C.c_double)), arrs[2].ctypes.data_as(C.POINTER(C.c_int32)))
+    dp = C.POINTER(C.c_double)
+    nbr = np.ascontiguousarray(mesh.face_nbr, dtype=np.int32)
+    keep.append(nbr)
+    m = Mesh(mesh.dim, cfg.P, cfg.nq, mesh.n_elem, dp(), dp(), nbr.ctypes.data_as(C.POINTER(C.c_int32)))
+    if mesh.elem_h is not None:
+        org = np.ascontiguousarray(mesh.elem_origin, dtype=np.float64)
+        h = np.ascontiguousarray(mesh.elem_h, dtype=np.float64)
+        keep.extend([org, h])
+        m.elem_origin, m.elem_h = org.ctypes.data_as(dp), h.ctypes.data_as(dp)
+    if getattr(mesh, "geo_nodes", None) is not None:
+        nodes = np.ascontiguousarray(mesh.geo_nodes, dtype=np.float64)
+        keep.append(nodes)
+        m.geo_order = mesh.geo_order
+        m.geo_nodes = nodes.ctypes.data_as(dp)
     if bc_kind is not None:
         kind = np.ascontiguousarray(bc_kind, dtype=np.int32).ravel()
         state = np.ascontiguousarray(bc_state, dtype=np.float64).reshape(len(kind), mesh.dim + 2)

@@ -469,6 +469,8 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
     b->grp.assign(n, -1);
     b->loc.assign(n, -1);
     for (int i = 0; i < n; ++i) {
+      if (meshes[i].geo_nodes || !meshes[i].elem_h || !meshes[i].elem_origin || !meshes[i].face_nbr)
+        throw Status{DGJ_EUNSUPPORTED, "batch: instances must be periodic meshes of affine boxes"};
       std::array<int, 3> k = {meshes[i].dim, meshes[i].P, meshes[i].nq};
       auto it = std::find(keys.begin(), keys.end(), k);
       if (it == keys.end()) { keys.push_back(k); b->grp[i] = (int)keys.size() - 1; }

@@ -10,6 +10,9 @@
 //   beta    beta[e][2D]: interior-penalty beta_p of that face
 //   tables  B[Q][N] = phi_n(xi_q), Dq[Q][N] = phi_n'(xi_q), w[Q],
 //           phiE[2][N] = phi_n(-1), phi_n(+1), dphiE[2][N] the derivatives.
+//   curved elements (instead of geo): vg[e][c][q] (c < D*D: d xi_k/d x_j at
+//           c = k*D + j; c = D*D: w_q |J_q|), fg[e][f][c][p] (c < D*D: d xi/d x;
+//           D*D + j: outward unit normal; D*D + D: w^G_p |J^G_p|), minv[e][NM][NM].
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
@@ -113,6 +116,12 @@ struct ResArgs {
   // (face_nbr = -(id + 1))
   const int* bc_kind;
   const double* bc_state;
+  // curved elements (all null for affine boxes): per-point metrics
+  // vg[e][D*D+1][NQ], fg[e][NF][D*D+D+1][NQF] and the dense inverse mass
+  // matrix minv[e][NM][NM]
+  const double* vg;
+  const double* fg;
+  const double* minv;
   // batches of independent instances: per-element instance index and
   // per-instance gas parameters, eps, dt a^mm and active flag (all null for
   // a single instance, which then uses ph, in.eps and dt_a)

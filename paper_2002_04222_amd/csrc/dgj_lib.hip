@@ -18,6 +18,7 @@
 #include "../../include/dgj.h"
 #include "dgj_kernels.h"
 #include "dgj_precond.h"
+#include "dgj_geometry.h"
 #include "dgj_residual.h"
 #include "dgj_mlp.h"
 
@@ -234,6 +235,54 @@ __global__ void k_dinv_export<double>(const double* __restrict__ Dinv, int nb, l
   }
 }
 
+// Mass matrix of curved elements, M[e][m][n] = sum_q phi_m(xi_q) w_q|J_q| phi_n(xi_q)
+template <int D, int N, int Q>
+__global__ void k_mass_build(const double* __restrict__ tables, const double* __restrict__ vg, long n_elem,
+                             double* __restrict__ M) {
+  using S = Shape<D, N, Q>;
+  constexpr int NM = S::NM, NQ = S::NQ;
+  const long total = n_elem * NM * NM;
+  for (long gid = (long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += (long)gridDim.x * blockDim.x) {
+    const long e = gid / (NM * NM);
+    const int m = (gid / NM) % NM, n = gid % NM;
+    int mi[3] = {0, 0, 0}, ni[3] = {0, 0, 0};
+    split<D, N>(m, mi);
+    split<D, N>(n, ni);
+    const double* wJ = vg + (e * (D * D + 1) + D * D) * (long)NQ;
+    double s = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+      int r = q;
+      double b = 1.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int aq = r % Q;
+        r /= Q;
+        b *= tables[aq * N + mi[a]] * tables[aq * N + ni[a]];
+      }
+      s += b * wJ[q];
+    }
+    M[gid] = s;
+  }
+}
+
+// out[e][v][m] = sum_n M[e][m][n] q[e][v][n] (M symmetric), one workgroup per element
+__global__ void k_mass_apply(const double* __restrict__ M, const double* __restrict__ q, double* __restrict__ out,
+                             int NM, int NV, long n_elem) {
+  __shared__ double sq[1024];
+  const long e = blockIdx.x;
+  if (e >= n_elem) return;
+  const int NB = NV * NM;
+  for (int i = threadIdx.x; i < NB; i += blockDim.x) sq[i] = q[e * NB + i];
+  __syncthreads();
+  const double* Me = M + e * (long)NM * NM;
+  for (int i = threadIdx.x; i < NB; i += blockDim.x) {
+    const int m = i % NM, v = i / NM;
+    double s = 0.0;
+    for (int n = 0; n < NM; ++n) s += Me[(long)n * NM + m] * sq[v * NM + n];
+    out[e * NB + i] = s;
+  }
+}
+
 // Taylor-Green projection: u[e][v][m] = sum_q w_q phi_m(xi_q) f_v(x_q) (+ noise)
 template <int D, int N, int Q>
 __global__ void k_project_tgv(const double* __restrict__ origin, const double* __restrict__ geo,
@@ -327,6 +376,9 @@ struct dgj_ctx {
   double* d_beta = nullptr;
   int* d_nbr = nullptr;
   int n_bc = 0;
+  // curved elements: per-point metrics, mass matrix and its inverse, M q scratch
+  bool curved = false;
+  double *d_vg = nullptr, *d_fg = nullptr, *d_M = nullptr, *d_Minv = nullptr, *d_Mq = nullptr;
   int* d_bc_kind = nullptr;       // per boundary id
   double* d_bc_state = nullptr;   // per boundary id, freestream [NV]
   double* d_origin = nullptr;
@@ -471,6 +523,11 @@ ResArgs res_args(dgj_ctx* c) {
   a.nbr = c->d_nbr;
   a.bc_kind = c->d_bc_kind;
   a.bc_state = c->d_bc_state;
+  if (c->curved) {
+    a.vg = c->d_vg;
+    a.fg = c->d_fg;
+    a.minv = c->d_Minv;
+  }
   a.geo = c->d_geo;
   a.beta = c->d_beta;
   a.tables = c->d_tab;
@@ -544,7 +601,8 @@ void sweep_t(dgj_ctx* c, const double* q, const double* qold, double* out, doubl
   constexpr int NT = sweep_threads<D, N, Q>();
   hipLaunchKernelGGL((k_brj_sweep<D, N, Q, NT, T, TJ>), dim3(c->n_elem), dim3(NT), 0, c->stream, q, qold, out,
                      (const T*)c->d_Dinv, (const TJ*)c->d_Jp, c->d_nbr, c->d_geo, c->d_tab, dt_a, c->sv.brj_omega,
-                     first, c->n_elem, c->n_inst > 0 ? c->d_inst : nullptr, c->d_dtav, c->d_active);
+                     first, c->n_elem, c->n_inst > 0 ? c->d_inst : nullptr, c->d_dtav, c->d_active,
+                     c->curved ? c->d_fg : nullptr);
 }
 
 template <int D, int N, int Q>
@@ -556,6 +614,12 @@ void sweep_shape(dgj_ctx* c, const double* q, const double* qold, double* out, d
 
 void precond_apply(dgj_ctx* c, const double* q, double* out) {
   const int J = std::max(1, c->sv.brj_sweeps);
+  if (c->curved) {
+    // curved elements store (M_e - dt a A_e)^-1: the sweeps take M q
+    hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_M, q, c->d_Mq, c->NM, c->NV,
+                       c->n_elem);
+    q = c->d_Mq;
+  }
   // ping-pong so the last sweep lands in out
   double* bufs[2] = {c->d_pa, c->d_pb};
   const double* prev = nullptr;
@@ -576,25 +640,24 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
   using S = Shape<D, N, Q>;
   constexpr int NTV = 64;
   hipLaunchKernelGGL((k_pc_volume<D, N, Q, NTV>), dim3(ne), dim3(NTV), 0, c->stream, up, c->d_geo, c->d_tab, ph, ne,
-                     Wt, e0);
+                     Wt, e0, c->curved ? c->d_vg : nullptr);
   long nf = ne * S::NF * S::NQF;
   if (c->pc_prec == DGJ_PC_F64)
     hipLaunchKernelGGL((k_pc_face<D, N, Q, double>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
                        c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (double*)c->d_Jp, e0, c->d_bc_kind,
-                       c->d_bc_state);
+                       c->d_bc_state, c->curved ? c->d_fg : nullptr);
   else
     hipLaunchKernelGGL((k_pc_face<D, N, Q, float>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
                        c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (float*)c->d_Jp, e0, c->d_bc_kind,
-                       c->d_bc_state);
+                       c->d_bc_state, c->curved ? c->d_fg : nullptr);
   constexpr int NTA = 256;
   const long nblk = ne * S::NV * S::NV;
   hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
-                     c->d_tab, dt_a, ne, (double*)Dm, e0);
+                     c->d_tab, dt_a, ne, (double*)Dm, e0, c->curved ? c->d_M : nullptr);
 }
 
 template <typename T, int KB>
-void invert(dgj_ctx* c, T* A, long e0, long ne) {
-  const int nb = c->NB;
+void invert(dgj_ctx* c, T* A, long e0, long ne, int nb) {
   int threads = ((nb + 63) / 64) * 64;
   size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int);
   HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -632,7 +695,7 @@ void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, lon
   DGJ_FOR_SHAPES(X)
 #undef X
   fail(DGJ_EUNSUPPORTED, "unsupported shape");
-  invert<double, 32>(c, (double*)Dm, e0, ne);
+  invert<double, 32>(c, (double*)Dm, e0, ne, c->NB);
 }
 
 void precond_alloc(dgj_ctx* c) {
@@ -955,7 +1018,8 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
   dgj_ctx* c = new dgj_ctx();
   int rc = guarded(c, [&]() -> int {
     if (mesh->dim != 2 && mesh->dim != 3) fail(DGJ_EINVAL, "dim must be 2 or 3");
-    if (mesh->n_elem <= 0 || !mesh->elem_h || !mesh->face_nbr || !mesh->elem_origin)
+    const bool curved = mesh->geo_nodes != nullptr;
+    if (mesh->n_elem <= 0 || !mesh->face_nbr || (!curved && (!mesh->elem_h || !mesh->elem_origin)))
       fail(DGJ_EINVAL, "mesh arrays missing or empty mesh");
     if (mesh->P < 1) fail(DGJ_EINVAL, "P must be >= 1");
     if (!shape_supported(mesh->dim, mesh->P + 1, mesh->nq))
@@ -985,7 +1049,15 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     const long E = c->n_elem;
     std::vector<double> geo(E * GEO), beta(E * NF);
     std::vector<int> nbr(mesh->face_nbr, mesh->face_nbr + E * NF);
-    for (long e = 0; e < E; ++e) {
+    dgj_geo::Curved cg;
+    if (curved) {
+      std::vector<double> xg, wg;
+      gauss_legendre(c->nq, xg, wg);
+      const std::string why = dgj_geo::curved_metrics(D, mesh->geo_order, c->nq, E, mesh->geo_nodes, xg, wg, cg);
+      if (!why.empty()) fail(DGJ_EINVAL, "curved mesh: %s", why.c_str());
+      c->curved = true;
+    }
+    for (long e = 0; e < E && !curved; ++e) {
       const double* h = mesh->elem_h + e * D;
       double detJ = 1.0;
       for (int j = 0; j < D; ++j) {
@@ -1023,7 +1095,12 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
           fail(DGJ_EINVAL, "element %ld face %d: neighbour %ld out of range", e, f, en);
         const int a = f / 2;
         double volL = 1.0, volR = 1.0, area = 1.0;
-        if (en >= 0) {
+        if (curved) {
+          const long eL = (en < 0 || (f & 1)) ? e : en;
+          volL = cg.vol[e];
+          volR = en >= 0 ? cg.vol[en] : volL;
+          area = cg.area[eL * NF + (en < 0 ? f : 2 * a + 1)];
+        } else if (en >= 0) {
           long eL = (f & 1) ? e : en, eR = (f & 1) ? en : e;
           for (int j = 0; j < D; ++j) {
             volL *= mesh->elem_h[eL * D + j];
@@ -1064,7 +1141,15 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     HIPCHK(hipMemcpy(c->d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_beta, beta.data(), beta.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->d_origin, mesh->elem_origin, E * D * sizeof(double), hipMemcpyHostToDevice));
+    if (curved) {
+      HIPCHK(hipMemset(c->d_origin, 0, E * D * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_vg, cg.vg.size() * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_fg, cg.fg.size() * sizeof(double)));
+      HIPCHK(hipMemcpy(c->d_vg, cg.vg.data(), cg.vg.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(c->d_fg, cg.fg.data(), cg.fg.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      HIPCHK(hipMemcpy(c->d_origin, mesh->elem_origin, E * D * sizeof(double), hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&c->d_part, RED_BLOCKS * 8 * sizeof(double)));
     HIPCHK(hipMalloc(&c->d_scal, 64 * sizeof(double)));
@@ -1078,6 +1163,30 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
                        &c->d_un, &c->d_E[0], &c->d_E[1], &c->d_E[2], &c->d_pa, &c->d_pb, &c->d_inc[0],
                        &c->d_inc[1], &c->d_inc[2], &c->d_inc2[0], &c->d_inc2[1], &c->d_inc2[2], &c->d_g2};
     for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
+    if (curved) {
+      // dense mass matrices and their inverses (Gauss-Jordan on the device)
+      const size_t mm = (size_t)E * c->NM * c->NM;
+      HIPCHK(hipMalloc(&c->d_M, mm * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_Minv, mm * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_Mq, vb));
+      bool launched = false;
+#define X(d, n, q)                                                                                         \
+  if (c->dim == d && c->N == n && c->nq == q) {                                                             \
+    hipLaunchKernelGGL((k_mass_build<d, n, q>), dim3(grid_for((long)mm)), dim3(256), 0, c->stream, c->d_tab, \
+                       c->d_vg, E, c->d_M);                                                                \
+    launched = true;                                                                                       \
+  }
+      DGJ_FOR_SHAPES(X)
+#undef X
+      if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
+      HIPCHK(hipMemcpyAsync(c->d_Minv, c->d_M, mm * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      invert<double, 32>(c, c->d_Minv, 0, E, c->NM);
+      std::vector<int> st(E);
+      HIPCHK(hipMemcpyAsync(st.data(), c->d_status, E * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (long e = 0; e < E; ++e)
+        if (st[e]) fail(DGJ_ESINGULAR, "element %ld: singular mass matrix", e);
+    }
     return DGJ_OK;
   });
   if (rc != DGJ_OK) {
@@ -1095,7 +1204,7 @@ void dgj_destroy(dgj_ctx* c) {
   else hipDeviceSynchronize();
   free_pc(c);
   mlp_free(c->mlp);
-  double* ptrs[] = {c->d_trace, c->d_X, c->d_Lvol, c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
+  double* ptrs[] = {c->d_vg, c->d_fg, c->d_M, c->d_Minv, c->d_Mq, c->d_trace, c->d_X, c->d_Lvol, c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
                     c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_E[0], c->d_E[1],
                     c->d_E[2], c->d_E[3], c->d_pa, c->d_pb, c->d_inc[0], c->d_inc[1], c->d_inc[2],
                     c->d_inc2[0], c->d_inc2[1], c->d_inc2[2], c->d_g2};
@@ -1125,6 +1234,7 @@ const char* dgj_last_error(const dgj_ctx* c) { return c ? c->err.c_str() : "null
 int dgj_project_tgv(dgj_ctx* c, const double* noise, double amp, double* u) {
   if (!c || !u) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
+    if (c->curved) fail(DGJ_EUNSUPPORTED, "project_tgv: the Taylor-Green projection is built for boxes only");
     long total = c->n_elem * c->NM;
 #define X(d, n, q)                                                                                          \
   if (c->dim == d && c->N == n && c->nq == q) {                                                              \

@@ -16,10 +16,13 @@
 
 namespace dgj {
 
-// value of the element's trace at face point p of its face f: sum over modes
+// value of the element's trace at face point p of its face f: sum over modes;
+// the gradient by dxi_j = gX[j] (boxes) or by the face-point metrics fgF
+// (curved: the element's fg block of face f, or null)
 template <int D, int N, int Q>
 __device__ __forceinline__ void trace_point(const Tab& tb, const StateIn& in, long X, const double* gX, int f,
-                                            int p, double* U, double (*gU)[D + 2]) {
+                                            int p, double* U, double (*gU)[D + 2],
+                                            const double* fgF = nullptr) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM;
   const int ax = f >> 1, s = f & 1;
@@ -63,6 +66,19 @@ __device__ __forceinline__ void trace_point(const Tab& tb, const StateIn& in, lo
       for (int j = 0; j < D; ++j) dref[j][v] += dphi[j] * uu;
     }
   }
+  if (fgF) {
+    constexpr int NQF = S::NQF;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s += fgF[(k * D + j) * NQF + p] * dref[k][v];
+        gU[j][v] = s;
+      }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -72,11 +88,13 @@ __device__ __forceinline__ void trace_point(const Tab& tb, const StateIn& in, lo
 // ---------------------------------------------------------------- volume flux Jacobians
 // Wt[e][q][j][b][k][l]: b = 0 -> dH_j,k/dQ_l at fixed gradient (exact, forward-mode
 // duals), b = 1+i -> dH_j,k/d(d_i Q_l) = -K (exact, G is linear in grad Q);
-// scaled by w_q |J| dxi_j (and dxi_i for b > 0).
+// in reference directions j, i: scaled by w_q |J| dxi_j (and dxi_i for b > 0)
+// on boxes; on curved elements (vg) contracted with d xi/d x on both sides,
+// w|J| sum_j' G[j][j'] dH_j'/dQ and w|J| sum_j' G[j][j'] dH_j'/d(grad Q) . G[i].
 template <int D, int N, int Q, int NT>
 __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, const double* __restrict__ geo,
                                                   const double* __restrict__ tables, Phys ph, long n_elem,
-                                                  double* __restrict__ Wt, long e0) {
+                                                  double* __restrict__ Wt, long e0, const double* __restrict__ vg) {
   using S = Shape<D, N, Q>;
   using L = ResidualLDS<D, N, Q>;
   constexpr int NV = S::NV, NQ = S::NQ;
@@ -93,19 +111,36 @@ __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, 
   __syncthreads();
   const double* g = geo + e * S::GEO;
   constexpr int PER_Q = D * (D + 1) * NV * NV;
+  const double* vge = vg ? vg + e * (long)(D * D + 1) * NQ : nullptr;
   for (int q = threadIdx.x; q < NQ; q += NT) {
-    double U[NV], gU[D][NV];
+    double U[NV], gU[D][NV], Gm[D][D];
+    double wq;
+    if (vge) {
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Gm[k][j] = vge[(k * D + j) * NQ + q];
+      wq = vge[D * D * NQ + q];
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Gm[k][j] = (k == j) ? g[j] : 0.0;
+      wq = g[D];
+      int r = q;
+#pragma unroll
+      for (int k = 0; k < D; ++k) { wq *= tb.w[r % Q]; r /= Q; }
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       U[v] = sQ[v * NQ + q];
 #pragma unroll
-      for (int j = 0; j < D; ++j) gU[j][v] = sQ[(1 + j) * NV * NQ + v * NQ + q] * g[j];
-    }
-    double wq = g[D];
-    {
-      int r = q;
+      for (int j = 0; j < D; ++j) {
+        double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) { wq *= tb.w[r % Q]; r /= Q; }
+        for (int k = 0; k < D; ++k) s += Gm[k][j] * sQ[(1 + k) * NV * NQ + v * NQ + q];
+        gU[j][v] = s;
+      }
     }
     double* out = Wt + (e * NQ + q) * (long)PER_Q;
     // dH/dQ via duals, one flux direction at a time to bound register use
@@ -118,28 +153,36 @@ __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, 
       viscous_flux<D, Dual<NV>, double>(ph, Ud, gU, G);
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        double sc = wq * g[j];
 #pragma unroll
         for (int k = 0; k < NV; ++k)
 #pragma unroll
-          for (int l = 0; l < NV; ++l)
-            out[((j * (D + 1) + 0) * NV + k) * NV + l] = (F[j][k].d[l] - G[j][k].d[l]) * sc;
+          for (int l = 0; l < NV; ++l) {
+            double s = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < D; ++jj) s += Gm[j][jj] * (F[jj][k].d[l] - G[jj][k].d[l]);
+            out[((j * (D + 1) + 0) * NV + k) * NV + l] = s * wq;
+          }
       }
     }
-    // dH/d grad Q = -K: probe the linear viscous flux with unit gradients
+    // dH/d grad Q = -K: probe the linear viscous flux with the physical
+    // gradient of a unit reference derivative, d_x Q_l = G[i][.]
     for (int i = 0; i < D; ++i) {
       for (int l = 0; l < NV; ++l) {
         double E[D][NV], G[D][NV];
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-          for (int v = 0; v < NV; ++v) E[a][v] = (a == i && v == l) ? 1.0 : 0.0;
+          for (int v = 0; v < NV; ++v) E[a][v] = (v == l) ? Gm[i][a] : 0.0;
         viscous_flux<D, double, double>(ph, U, E, G);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-          double sc = wq * g[j] * g[i];
 #pragma unroll
-          for (int k = 0; k < NV; ++k) out[((j * (D + 1) + 1 + i) * NV + k) * NV + l] = -G[j][k] * sc;
+          for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < D; ++jj) s += Gm[j][jj] * G[jj][k];
+            out[((j * (D + 1) + 1 + i) * NV + k) * NV + l] = -s * wq;
+          }
         }
       }
     }
@@ -156,7 +199,8 @@ template <int D, int N, int Q, typename TJ>
 __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ nbr, const double* __restrict__ geo,
                           const double* __restrict__ beta, const double* __restrict__ tables, Phys ph, long n_elem,
                           const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp,
-                          long e0, const int* __restrict__ bc_kind, const double* __restrict__ bc_state) {
+                          long e0, const int* __restrict__ bc_kind, const double* __restrict__ bc_state,
+                          const double* __restrict__ fg) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NQF = S::NQF, NF = S::NF;
   __shared__ double st[S::TAB];
@@ -171,17 +215,22 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
   const int ax = f >> 1, s = f & 1;
   StateIn in{u, nullptr, 0.0};
   double Uo[NV], Un[NV], go[D][NV], gn[D][NV];
-  trace_point<D, N, Q>(tb, in, e, geo + e * S::GEO, f, p, Uo, go);
+  constexpr int CF = D * D + D + 1;
+  const double* fgo = fg ? fg + (e * NF + f) * (long)CF * NQF : nullptr;
+  trace_point<D, N, Q>(tb, in, e, geo + e * S::GEO, f, p, Uo, go, fgo);
   double nrm[D];
+  double wf;
+  if (fgo) {
 #pragma unroll
-  for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
-  const double b = beta[e * NF + f];
-  const double* g = geo + e * S::GEO;
-  double wf = g[D + 2 + ax];
-  {
-    wf *= tb.w[p % Q];
+    for (int j = 0; j < D; ++j) nrm[j] = fgo[(D * D + j) * NQF + p];
+    wf = fgo[(D * D + D) * NQF + p];
+  } else {
+#pragma unroll
+    for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
+    wf = geo[e * S::GEO + D + 2 + ax] * tb.w[p % Q];
     if (D == 3) wf *= tb.w[p / Q];
   }
+  const double b = beta[e * NF + f];
   const long base = ((e * NF + f) * NQF + p) * NV * NV;
   double H0[NV], H1[NV];
   if (en < 0) {
@@ -205,7 +254,8 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
     }
     return;
   }
-  trace_point<D, N, Q>(tb, in, en, geo + en * S::GEO, f ^ 1, p, Un, gn);
+  trace_point<D, N, Q>(tb, in, en, geo + en * S::GEO, f ^ 1, p, Un, gn,
+                       fg ? fg + (en * NF + (f ^ 1)) * (long)CF * NQF : nullptr);
   face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H0, nullptr);
   for (int l = 0; l < NV; ++l) {
     const double chi = chi_dev[l];
@@ -226,11 +276,14 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
 
 // ---------------------------------------------------------------- block assembly
 // One workgroup per (element, k, l): the NM x NM sub-block A_kl of A_e, then
-// D = I - dt_a / |J| A written column-major into Dm[e][col][row].
+// D = I - dt_a / |J| A (boxes) or D = M_e - dt_a A (curved, mass[e][NM][NM];
+// its inverse is (M_e - dt_a A_e)^-1 = D_e^-1 M_e^-1) written column-major
+// into Dm[e][col][row].
 template <int D, int N, int Q, int NT, typename TD>
 __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ Wt, const double* __restrict__ JmW,
                                                      const double* __restrict__ geo, const double* __restrict__ tables,
-                                                     double dt_a, long n_elem, TD* __restrict__ Dm, long e0) {
+                                                     double dt_a, long n_elem, TD* __restrict__ Dm, long e0,
+                                                     const double* __restrict__ mass) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF, NB = S::NB;
   constexpr int PER_Q = D * (D + 1) * NV * NV;
@@ -331,14 +384,15 @@ __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ W
       __syncthreads();
     }
   }
-  const double sc = dt_a * geo[e * S::GEO + D + 1];
+  const double sc = mass ? dt_a : dt_a * geo[e * S::GEO + D + 1];
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     int oi = tid + o * NT;
     if (oi < NM * NM) {
       int m = oi / NM, n = oi % NM;
       int row = k * NM + m, col = l * NM + n;
-      double val = ((row == col) ? 1.0 : 0.0) - sc * acc[o];
+      const double dg = mass ? ((k == l) ? mass[(e * NM + m) * (long)NM + n] : 0.0) : ((row == col) ? 1.0 : 0.0);
+      double val = dg - sc * acc[o];
       Dm[(e * NB + col) * (long)NB + row] = (TD)val;
     }
   }
@@ -484,6 +538,9 @@ template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { retu
 // One BRJ sweep for element e (one workgroup, blockDim >= nb):
 //   r = q - (L+U) qold   (skipped when first),  out = omega Dinv r + (1-omega) qold.
 // (L+U) qold = -dt_a / |J| sum_f -(B^G_f)^T diag(w^G|J^G| Jp (B^G_f' qold_nbr)).
+// Curved elements (fg): q holds M_e q, Dinv holds (M_e - dt_a A_e)^-1, the
+// face weights are per point and r = M_e q + dt_a sum_f (...), which equals
+// M_e times the r above (M_e^-1 is not applied).
 template <int D, int N, int Q, int NT, typename T, typename TJ>
 __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, const double* __restrict__ qold,
                                                    double* __restrict__ out, const T* __restrict__ Dinv,
@@ -491,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
                                                    const double* __restrict__ geo, const double* __restrict__ tables,
                                                    double dt_a, double omega, int first, long n_elem,
                                                    const int* __restrict__ inst, const double* __restrict__ dtav,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active, const double* __restrict__ fg) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQF = S::NQF, NMF = S::NMF, NF = S::NF, NB = S::NB;
   __shared__ double st[S::TAB];
@@ -546,8 +603,13 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
         double sacc2 = 0.0;
 #pragma unroll
         for (int l = 0; l < NV; ++l) sacc2 += jp_ld<TJ>(J + l) * tpt[l * NQF + p];
-        double wf = g[D + 2 + ax] * tb.w[p % Q];
-        if (D == 3) wf *= tb.w[p / Q];
+        double wf;
+        if (fg) {
+          wf = fg[((e * NF + f) * (long)(D * D + D + 1) + D * D + D) * NQF + p];
+        } else {
+          wf = g[D + 2 + ax] * tb.w[p % Q];
+          if (D == 3) wf *= tb.w[p / Q];
+        }
         flx[k * NQF + p] = sacc2 * wf;
       }
       __syncthreads();
@@ -566,8 +628,8 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
       }
       __syncthreads();
     }
-    // r = q - (L+U) qold, (L+U) qold = -dt_a / |J| sacc
-    const double sc = dt_a * g[D + 1];
+    // r = q - (L+U) qold, (L+U) qold = -dt_a / |J| sacc (curved: times M_e)
+    const double sc = fg ? dt_a : dt_a * g[D + 1];
     for (int i = tid; i < NB; i += NT) sr[i] = sr[i] + sc * sacc[i];
     __syncthreads();
   }

@@ -179,7 +179,45 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
   __syncthreads();
 
   // own face traces: value and physical gradient at the face points
-  {
+  if (a.vg) {
+    // curved: interpolate value and reference gradient, then grad = G^T grad_xi
+    constexpr int CF = D * D + D + 1;
+    double* tr = trace + e * (long)K::TRACE;
+    const double* fge = a.fg + e * (long)NF * CF * NQF;
+    for (int it = tid; it < NF * NV * NQF; it += NT) {
+      const int p = it % NQF;
+      const int v = (it / NQF) % NV;
+      const int f = it / (NQF * NV);
+      const int ax = f >> 1, s = f & 1;
+      int qstride = 1, base = 0;
+      {
+        int t[2] = {0, 0};
+        tang_axes<D>(ax, t);
+        int st[3] = {1, Q, Q * Q};
+        qstride = st[ax];
+        base = (p % Q) * st[t[0]];
+        if (D == 3) base += (p / Q) * st[t[1]];
+      }
+      double rv[D + 1];
+#pragma unroll
+      for (int c = 0; c <= D; ++c) {
+        const double* y = sQ + c * NV * NQ + v * NQ + base;
+        double acc = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < Q; ++aa) acc += tk.lag[s][aa] * y[aa * qstride];
+        rv[c] = acc;
+      }
+      const double* Gp = fge + f * CF * NQF + p;
+      tr[((f * (D + 1)) * NV + v) * NQF + p] = rv[0];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double gj = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) gj += Gp[(kk * D + j) * NQF] * rv[1 + kk];
+        tr[((f * (D + 1) + 1 + j) * NV + v) * NQF + p] = gj;
+      }
+    }
+  } else {
     double* tr = trace + e * (long)K::TRACE;
     for (int it = tid; it < K::TRACE; it += NT) {
       const int p = it % NQF;
@@ -206,7 +244,44 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
   }
   __syncthreads();   // the flux loop below overwrites the gradients read above
 
-  // pointwise volume flux, scaled by w |J| dxi_j (overwrites the gradients)
+  // pointwise volume flux, scaled by w |J| dxi_j (overwrites the gradients);
+  // curved: the contravariant flux w|J| sum_j (d xi_k/d x_j) H_j
+  if (a.vg) {
+    const double* vge = a.vg + e * (long)(D * D + 1) * NQ;
+    for (int q = tid; q < NQ; q += NT) {
+      double U[NV], gU[D][NV], F[D][NV], G[D][NV], Gm[D][D];
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Gm[kk][j] = vge[(kk * D + j) * NQ + q];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        U[v] = sQ[v * NQ + q];
+        double dr[D];
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) dr[kk] = sQ[(1 + kk) * NV * NQ + v * NQ + q];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          double s = 0.0;
+#pragma unroll
+          for (int kk = 0; kk < D; ++kk) s += Gm[kk][j] * dr[kk];
+          gU[j][v] = s;
+        }
+      }
+      euler_flux<D, double>(ep.ph, U, F);
+      viscous_flux<D, double, double>(ep.ph, U, gU, G);
+      const double wJ = vge[D * D * NQ + q];
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < D; ++j) s += Gm[kk][j] * (F[j][v] - G[j][v]);
+          sQ[(1 + kk) * NV * NQ + v * NQ + q] = wJ * s;
+        }
+    }
+  } else
   for (int q = tid; q < NQ; q += NT) {
     double U[NV], gU[D][NV], F[D][NV], G[D][NV];
 #pragma unroll
@@ -359,8 +434,19 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
     for (int j = 0; j < D; ++j) gL[j][v] = tL[((1 + j) * NV + v) * NQF + p];
   }
   double nrm[D];
+  double wf;
+  if (a.fg) {
+    constexpr int CF = D * D + D + 1;
+    const double* Gp = a.fg + (e * K::NF + f) * (long)CF * NQF + p;
 #pragma unroll
-  for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
+    for (int j = 0; j < D; ++j) nrm[j] = Gp[(D * D + j) * NQF];
+    wf = Gp[(D * D + D) * NQF];
+  } else {
+#pragma unroll
+    for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
+    wf = a.geo[e * K::S::GEO + D + 2 + ax] * tk.w[p % Q];
+    if (D == 3) wf *= tk.w[p / Q];
+  }
   double H[NV], Sf[D][NV];
   const double beta = a.beta[e * K::NF + f];
   if (en >= 0) {
@@ -377,8 +463,6 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
     const int bid = -(int)en - 1;
     boundary_flux<D>(ph, a.bc_kind[bid], UL, gL, nrm, beta, a.bc_state + bid * NV, H, Sf);
   }
-  double wf = a.geo[e * K::S::GEO + D + 2 + ax] * tk.w[p % Q];
-  if (D == 3) wf *= tk.w[p / Q];
   double* o = X + e * (long)K::XF + f * (D + 1) * NV * NQF;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -409,6 +493,18 @@ __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, cons
   if (e0 < 0) face_point_flux<D, N, Q>(a, tk, ep.ph, trace, X, e, 2 * ax, e0, p);
 }
 
+// output of the residual kernels for unknown gi with R = (M^-1 L)_gi
+__device__ __forceinline__ void epilogue(const ResArgs& a, const ElemParams& ep, long gi, double R) {
+  if (a.mode == RES_R) {
+    a.out[gi] = R;
+  } else {
+    const double w = ep.in(gi);
+    const double Nw = (w - a.S[gi]) - ep.dt_a * R;
+    if (a.mode == RES_N) a.out[gi] = Nw;
+    else a.out[gi] = (Nw - a.Nu[gi]) / ep.in.eps;
+  }
+}
+
 // ---------------------------------------------------------------- lift + epilogue
 template <int D, int N, int Q, int NT>
 __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const double* __restrict__ Lvol,
@@ -433,9 +529,22 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
     const bool mine = (f & 1) == 1 || en < 0;   // flux stored in this element's orientation
     const long src = mine ? e : en;
     const int fs = mine ? f : (f ^ 1);
-    const double x = X[src * (long)K::XF + ((fs * (D + 1) + k) * NV + v) * NQF + p];
-    // k = 0: -Hhat_own (the neighbour's flux has the opposite orientation); k >= 1: Shat_j dxi_j
-    sA[it] = (k == 0) ? (mine ? -x : x) : x * g[k - 1];
+    const double* Xs = X + src * (long)K::XF + (fs * (D + 1) * NV + v) * NQF + p;
+    // k = 0: -Hhat_own (the neighbour's flux has the opposite orientation);
+    // k >= 1: sum_j (d xi_{k-1} / d x_j) Shat_j
+    if (k == 0) {
+      const double x = Xs[0];
+      sA[it] = mine ? -x : x;
+    } else if (a.fg) {
+      constexpr int CF = D * D + D + 1;
+      const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s += Gp[((k - 1) * D + j) * NQF] * Xs[(1 + j) * NV * NQF];
+      sA[it] = s;
+    } else {
+      sA[it] = Xs[k * NV * NQF] * g[k - 1];
+    }
   }
   __syncthreads();
   // tangential contraction to face modes: F0 (multiplies phi(+-1)), F1 (phi'(+-1))
@@ -465,6 +574,8 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
   }
   __syncthreads();
   const double invdetJ = g[D + 1];
+  double* sL = sA;   // curved: L staged for the dense M^-1 (sA is no longer read)
+  const bool curved = a.minv != nullptr;
   for (int i = tid; i < NB; i += NT) {
     const int m = i % NM, v = i / NM;
     int mi[3] = {0, 0, 0};
@@ -479,15 +590,17 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
       L += tk.phiE[s][mi[ax]] * sF[(f * 2 + 0) * NV * NMF + v * NMF + tm] +
            tk.dphiE[s][mi[ax]] * sF[(f * 2 + 1) * NV * NMF + v * NMF + tm];
     }
-    const long gi = e * NB + i;
-    const double R = L * invdetJ;
-    if (a.mode == RES_R) {
-      a.out[gi] = R;
-    } else {
-      const double w = ep.in(gi);
-      const double Nw = (w - a.S[gi]) - ep.dt_a * R;
-      if (a.mode == RES_N) a.out[gi] = Nw;
-      else a.out[gi] = (Nw - a.Nu[gi]) / ep.in.eps;
+    if (curved) sL[i] = L;
+    else epilogue(a, ep, e * NB + i, L * invdetJ);
+  }
+  if (curved) {
+    __syncthreads();
+    const double* Mi = a.minv + e * (long)NM * NM;
+    for (int i = tid; i < NB; i += NT) {
+      const int m = i % NM, v = i / NM;
+      double R = 0.0;
+      for (int n = 0; n < NM; ++n) R += Mi[(long)n * NM + m] * sL[v * NM + n];   // M^-1 is symmetric
+      epilogue(a, ep, e * NB + i, R);
     }
   }
 }
