@@ -61,11 +61,18 @@ class Disc:
         self.detJ = self.geo.detJ                                   # [E] (boxes only)
         self.dxi = self.geo.dxi                                     # [E, d] dxi_j/dx_j (boxes only)
         self.vol = self.geo.vol
-        # mass matrix M_e = B^T diag(w |J|) B   (Eq. 13)
-        if self.geo.curved:
-            self.M = np.einsum('qm,eq,qn->emn', ref.B, self.geo.wJ, ref.B)
-        else:
-            self.M = np.einsum('qm,q,qn->mn', ref.B, ref.W, ref.B)[None] * self.detJ[:, None, None]
+        self._M = None
+
+    @property
+    def M(self):
+        """Mass matrices M_e = B^T diag(w |J|) B (Eq. 13), formed on first use."""
+        if self._M is None:
+            ref = self.ref
+            if self.geo.curved:
+                self._M = np.einsum('qm,eq,qn->emn', ref.B, self.geo.wJ, ref.B)
+            else:
+                self._M = np.einsum('qm,q,qn->mn', ref.B, ref.W, ref.B)[None] * self.detJ[:, None, None]
+        return self._M
 
     @property
     def shape(self):
@@ -224,6 +231,41 @@ class Disc:
         wq = self.geo.wJ
         rhs = np.einsum('qm,eqv->evm', self.ref.B, vals * wq[..., None])
         return self.apply_Minv(rhs)
+
+
+def restricted_disc(gas, dim, P, nq, face_nbr, sample, elem_origin=None, elem_h=None, geo_nodes=None,
+                    geo_order=1, bc_kind=None, bc_state=None) -> tuple:
+    """Discretisation of the elements `sample` of a mesh and their face
+    neighbours, in which faces that leave this set become far-field faces
+    of an extra boundary id.  The residual of each sample element is then
+    the full mesh's (its own and its neighbours' traces are all present);
+    the other elements' are not meaningful.  Returns (sub, kept element
+    ids, positions of the sample elements in sub)."""
+    from .physics import BC_FARFIELD
+    sample = [int(e) for e in sample]
+    keep = sorted(set(sample) | {int(x) for e in sample for x in face_nbr[e] if x >= 0})
+    loc = {e: i for i, e in enumerate(keep)}
+    n_bc = 0 if bc_kind is None else len(bc_kind)
+    sub = np.empty((len(keep), face_nbr.shape[1]), dtype=np.int32)
+    for i, e in enumerate(keep):
+        for f in range(face_nbr.shape[1]):
+            x = int(face_nbr[e, f])
+            sub[i, f] = x if x < 0 else (loc[x] if x in loc else -(n_bc + 1))
+    free = np.zeros((1, dim + 2))
+    free[0, 0] = 1.0
+    free[0, -1] = 1.0 / (gas.gamma * gas.Ma ** 2) / (gas.gamma - 1.0)
+    kinds = np.concatenate([[] if bc_kind is None else bc_kind, [BC_FARFIELD]]).astype(int)
+    states = free if bc_state is None else np.concatenate([bc_state, free])
+    pick = lambda a: None if a is None else np.asarray(a)[keep]
+    d = Disc(gas=gas, dim=dim, P=P, nq=nq, elem_origin=pick(elem_origin), elem_h=pick(elem_h), face_nbr=sub,
+             bc_kind=kinds, bc_state=states, geo_nodes=pick(geo_nodes), geo_order=geo_order)
+    return d, keep, [loc[e] for e in sample]
+
+
+def restrict(disc: Disc, sample) -> tuple:
+    """restricted_disc of an existing discretisation."""
+    return restricted_disc(disc.gas, disc.dim, disc.P, disc.nq, disc.face_nbr, sample, disc.elem_origin,
+                           disc.elem_h, disc.geo_nodes, disc.geo_order, disc.bc_kind, disc.bc_state)
 
 
 def make_disc(cfg, mesh, **gas_overrides) -> Disc:

@@ -505,10 +505,22 @@ void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
   std::memcpy(&tk, c->h_tab.data(), sizeof(tk));
   constexpr int NTV = D == 2 ? 64 : 128;
   constexpr int NTL = D == 2 ? 64 : 256;
-  hipLaunchKernelGGL((k_res_vol<D, N, Q, NTV>), dim3(c->n_elem), dim3(NTV), 0, c->stream, a, tk, c->d_trace, c->d_Lvol);
   const long nf = c->n_elem * D * K::NQF;
-  hipLaunchKernelGGL((k_res_face<D, N, Q>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, a, tk, c->d_trace, c->d_X);
-  hipLaunchKernelGGL((k_res_lift<D, N, Q, NTL>), dim3(c->n_elem), dim3(NTL), 0, c->stream, a, tk, c->d_Lvol, c->d_X);
+  if (c->curved) {
+    hipLaunchKernelGGL((k_res_vol<D, N, Q, NTV, true>), dim3(c->n_elem), dim3(NTV), 0, c->stream, a, tk, c->d_trace,
+                       c->d_Lvol);
+    hipLaunchKernelGGL((k_res_face<D, N, Q, true>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, a, tk,
+                       c->d_trace, c->d_X);
+    hipLaunchKernelGGL((k_res_lift<D, N, Q, NTL, true>), dim3(c->n_elem), dim3(NTL), 0, c->stream, a, tk, c->d_Lvol,
+                       c->d_X);
+  } else {
+    hipLaunchKernelGGL((k_res_vol<D, N, Q, NTV, false>), dim3(c->n_elem), dim3(NTV), 0, c->stream, a, tk,
+                       c->d_trace, c->d_Lvol);
+    hipLaunchKernelGGL((k_res_face<D, N, Q, false>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, a, tk,
+                       c->d_trace, c->d_X);
+    hipLaunchKernelGGL((k_res_lift<D, N, Q, NTL, false>), dim3(c->n_elem), dim3(NTL), 0, c->stream, a, tk,
+                       c->d_Lvol, c->d_X);
+  }
 }
 
 void launch_residual(dgj_ctx* c, const ResArgs& a) {
@@ -658,11 +670,26 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
 
 template <typename T, int KB>
 void invert(dgj_ctx* c, T* A, long e0, long ne, int nb) {
-  int threads = ((nb + 63) / 64) * 64;
+  // one row per thread in the panel phase; extra waves share the trailing update
+  const int threads = nb > 128 ? 1024 : 256;
   size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int);
   HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * nb, nb, ne,
                      c->d_status + e0);
+}
+
+// In-place inversion of ne blocks of size nb with the widest column panel
+// whose LDS footprint fits the device's per-workgroup limit.
+void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb) {
+  int dev = 0, lim = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t L = (size_t)lim;
+  auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 32 * 8 + 32 * 4; };
+  if (lds(32) <= L) invert<double, 32>(c, A, e0, ne, nb);
+  else if (lds(16) <= L) invert<double, 16>(c, A, e0, ne, nb);
+  else if (lds(8) <= L) invert<double, 8>(c, A, e0, ne, nb);
+  else fail(DGJ_EUNSUPPORTED, "block size %d too large for the in-LDS inversion", nb);
 }
 
 void free_pc(dgj_ctx* c) {
@@ -695,7 +722,7 @@ void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, lon
   DGJ_FOR_SHAPES(X)
 #undef X
   fail(DGJ_EUNSUPPORTED, "unsupported shape");
-  invert<double, 32>(c, (double*)Dm, e0, ne, c->NB);
+  invert_blocks(c, (double*)Dm, e0, ne, c->NB);
 }
 
 void precond_alloc(dgj_ctx* c) {
@@ -1180,7 +1207,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
 #undef X
       if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
       HIPCHK(hipMemcpyAsync(c->d_Minv, c->d_M, mm * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      invert<double, 32>(c, c->d_Minv, 0, E, c->NM);
+      invert_blocks(c, c->d_Minv, 0, E, c->NM);
       std::vector<int> st(E);
       HIPCHK(hipMemcpyAsync(st.data(), c->d_status, E * sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));

@@ -489,24 +489,48 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
         int tmp = perm[k]; perm[k] = perm[p]; perm[p] = tmp;
       }
     __syncthreads();
-    const int myperm = r < nb ? perm[r] : 0;
-    const bool pivrow = (r >= k0) && (r < k0 + kb);
-    T prow[KB];
+    // Trailing update, one column per wave at a time (columns are
+    // independent, so no workgroup barrier): with the panel's composed row
+    // permutation perm, x(r) <- [r not a pivot row] x(perm[r]) +
+    // sum_t Panel[r][t] x(perm[k0+t]).  Each wave reads the whole column
+    // (pivot entries broadcast by shuffles) before it writes any of it.
+    {
+      constexpr int RPL = 16;                 // rows per lane, nb <= 1024
+      const int nrow = (nb + 63) >> 6;
+      int prm[RPL];
 #pragma unroll
-    for (int t = 0; t < KB; ++t) prow[t] = (r < nb && t < kb) ? Pan[r * (KB + 1) + t] : (T)0;
-    for (int j = 0; j < nb; ++j) {
-      if (j >= k0 && j < k0 + kb) continue;
-      T* col = Ae + (long)j * nb;
-      T x = (r < nb) ? col[myperm] : (T)0;
-      T acc = pivrow ? (T)0 : x;
-#pragma unroll
-      for (int t = 0; t < KB; ++t) {
-        if (t < kb) acc += prow[t] * col[perm[k0 + t]];
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        prm[i] = (i < nrow && row < nb) ? perm[row] : 0;
       }
-      __syncthreads();
-      if (r < nb) col[r] = acc;
-      __syncthreads();
+      const int ppv = lane < kb ? perm[k0 + lane] : 0;
+      for (int j = wid; j < nb; j += nw) {
+        if (j >= k0 && j < k0 + kb) continue;
+        T* col = Ae + (long)j * nb;
+        const T pvl = lane < kb ? col[ppv] : (T)0;
+        T acc[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = lane + 64 * i;
+          const bool piv_row = row >= k0 && row < k0 + kb;
+          acc[i] = (i < nrow && row < nb && !piv_row) ? col[prm[i]] : (T)0;
+        }
+        for (int t = 0; t < kb; ++t) {
+          const T pt = __shfl(pvl, t, 64);
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (i < nrow && row < nb) acc[i] += Pan[row * (KB + 1) + t] * pt;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = lane + 64 * i;
+          if (i < nrow && row < nb) col[row] = acc[i];
+        }
+      }
     }
+    __syncthreads();
   }
   // unscramble columns
   for (int k = nb - 1; k >= 0; --k) {

@@ -46,7 +46,7 @@ struct ResK {
 };
 
 // ---------------------------------------------------------------- volume + traces
-template <int D, int N, int Q, int NT>
+template <int D, int N, int Q, int NT, bool CV>
 __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
                                                 double* __restrict__ Lvol) {
   using K = ResK<D, N, Q>;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
   __syncthreads();
 
   // own face traces: value and physical gradient at the face points
-  if (a.vg) {
+  if constexpr (CV) {
     // curved: interpolate value and reference gradient, then grad = G^T grad_xi
     constexpr int CF = D * D + D + 1;
     double* tr = trace + e * (long)K::TRACE;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
 
   // pointwise volume flux, scaled by w |J| dxi_j (overwrites the gradients);
   // curved: the contravariant flux w|J| sum_j (d xi_k/d x_j) H_j
-  if (a.vg) {
+  if constexpr (CV) {
     const double* vge = a.vg + e * (long)(D * D + 1) * NQ;
     for (int q = tid; q < NQ; q += NT) {
       double U[NV], gU[D][NV], F[D][NV], G[D][NV], Gm[D][D];
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
 // ---------------------------------------------------------------- face fluxes
 // Flux of face f of element e at face point p, weighted by w^G |J^G|, into
 // X[e][f]: (H^n, S_j) in e's orientation (outward normal of face f).
-template <int D, int N, int Q>
+template <int D, int N, int Q, bool CV>
 __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, Q>& tk, const Phys& ph,
                                                 const double* __restrict__ trace, double* __restrict__ X, long e,
                                                 int f, long en, int p) {
@@ -435,7 +435,7 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
   }
   double nrm[D];
   double wf;
-  if (a.fg) {
+  if constexpr (CV) {
     constexpr int CF = D * D + D + 1;
     const double* Gp = a.fg + (e * K::NF + f) * (long)CF * NQF + p;
 #pragma unroll
@@ -476,7 +476,7 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
 // once, by the element that meets it with side 1 (normal +e_axis); a
 // boundary face by its element, in its own orientation, so the thread of
 // axis a also computes its element's side-0 face when that is a boundary.
-template <int D, int N, int Q>
+template <int D, int N, int Q, bool CV>
 __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, const double* __restrict__ trace,
                                                   double* __restrict__ X) {
   using K = ResK<D, N, Q>;
@@ -488,9 +488,9 @@ __global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, cons
   const long e = gid / (NQF * D);
   ElemParams ep;
   if (!elem_params(a, e, ep)) return;
-  face_point_flux<D, N, Q>(a, tk, ep.ph, trace, X, e, 2 * ax + 1, a.nbr[e * NF + 2 * ax + 1], p);
+  face_point_flux<D, N, Q, CV>(a, tk, ep.ph, trace, X, e, 2 * ax + 1, a.nbr[e * NF + 2 * ax + 1], p);
   const long e0 = a.nbr[e * NF + 2 * ax];
-  if (e0 < 0) face_point_flux<D, N, Q>(a, tk, ep.ph, trace, X, e, 2 * ax, e0, p);
+  if (e0 < 0) face_point_flux<D, N, Q, CV>(a, tk, ep.ph, trace, X, e, 2 * ax, e0, p);
 }
 
 // output of the residual kernels for unknown gi with R = (M^-1 L)_gi
@@ -506,7 +506,7 @@ __device__ __forceinline__ void epilogue(const ResArgs& a, const ElemParams& ep,
 }
 
 // ---------------------------------------------------------------- lift + epilogue
-template <int D, int N, int Q, int NT>
+template <int D, int N, int Q, int NT, bool CV>
 __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const double* __restrict__ Lvol,
                                                  const double* __restrict__ X) {
   using K = ResK<D, N, Q>;
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
     if (k == 0) {
       const double x = Xs[0];
       sA[it] = mine ? -x : x;
-    } else if (a.fg) {
+    } else if constexpr (CV) {
       constexpr int CF = D * D + D + 1;
       const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
       double s = 0.0;
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
   __syncthreads();
   const double invdetJ = g[D + 1];
   double* sL = sA;   // curved: L staged for the dense M^-1 (sA is no longer read)
-  const bool curved = a.minv != nullptr;
+  constexpr bool curved = CV;
   for (int i = tid; i < NB; i += NT) {
     const int m = i % NM, v = i / NM;
     int mi[3] = {0, 0, 0};
@@ -590,16 +590,42 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
       L += tk.phiE[s][mi[ax]] * sF[(f * 2 + 0) * NV * NMF + v * NMF + tm] +
            tk.dphiE[s][mi[ax]] * sF[(f * 2 + 1) * NV * NMF + v * NMF + tm];
     }
-    if (curved) sL[i] = L;
+    if constexpr (curved) sL[i] = L;
     else epilogue(a, ep, e * NB + i, L * invdetJ);
   }
-  if (curved) {
+  if constexpr (curved) {
     __syncthreads();
+    // R[v][m] = sum_n M^-1[m][n] L[v][n]: the NT threads split into NS
+    // groups of MP (>= NM) that each own one m for all variables and take
+    // every NS-th n, so M^-1 is streamed once per element, coalesced over m
+    // (the stored M^-1 is symmetric up to rounding and is read by columns);
+    // the group partial sums meet in LDS.
+    constexpr int MP = ((NM + 63) / 64) * 64;
+    constexpr int NS = NT / MP >= 1 ? NT / MP : 1;
+    static_assert(NB + NS * NB <= NF * (D + 1) * NV * NQF, "LDS staging of the mass-matrix product");
+    double* part = sA + NB;
     const double* Mi = a.minv + e * (long)NM * NM;
+    for (int t = tid; t < NS * MP; t += NT) {
+      const int m = t % MP, h = t / MP;
+      if (m >= NM) continue;
+      double R[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] = 0.0;
+#pragma unroll 4
+      for (int n = h; n < NM; n += NS) {
+        const double w = Mi[(long)n * NM + m];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[v] += w * sL[v * NM + n];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) part[(h * NV + v) * NM + m] = R[v];
+    }
+    __syncthreads();
     for (int i = tid; i < NB; i += NT) {
       const int m = i % NM, v = i / NM;
       double R = 0.0;
-      for (int n = 0; n < NM; ++n) R += Mi[(long)n * NM + m] * sL[v * NM + n];   // M^-1 is symmetric
+#pragma unroll
+      for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
       epilogue(a, ep, e * NB + i, R);
     }
   }

@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 
 import workloads as W
 from oracle import solver as OS
-from oracle.dg import Disc
+from oracle.dg import Disc, restricted_disc
 from oracle.physics import Gas, BC_FARFIELD, BC_WALL
 from tests.gpu_util import rel_err_per_var
 
@@ -160,26 +160,6 @@ def test_annulus_sdirk_step_parity(scheme):
         assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
 
 
-def _sub_disc(cfg, mesh, kinds, states, sample):
-    """Oracle on the sample elements and their face neighbours: faces that
-    leave this set become far-field faces (their elements are not compared),
-    so the residual of every sample element is exactly the full mesh's."""
-    nbr = mesh.face_nbr
-    keep = sorted(set(sample) | {int(x) for e in sample for x in nbr[e] if x >= 0})
-    loc = {e: i for i, e in enumerate(keep)}
-    extra = len(kinds)
-    sub = np.empty((len(keep), nbr.shape[1]), dtype=np.int32)
-    for i, e in enumerate(keep):
-        for f in range(nbr.shape[1]):
-            x = int(nbr[e, f])
-            sub[i, f] = loc[x] if x >= 0 and x in loc else (x if x < 0 else -(extra + 1))
-    k2 = np.concatenate([kinds, [BC_FARFIELD]])
-    s2 = np.concatenate([states, states[-1:]])
-    d = Disc(gas=_gas(cfg), dim=mesh.dim, P=cfg.P, nq=cfg.nq, elem_origin=None, elem_h=None, face_nbr=sub,
-             bc_kind=k2, bc_state=s2, geo_nodes=mesh.geo_nodes[keep], geo_order=mesh.geo_order)
-    return d, keep, [loc[e] for e in sample]
-
-
 def test_cylinder_annulus_full_size_sampled_residual():
     """The cylinder workload at full size (32 x 64 x 8 hexes, P=4, 10.24M
     unknowns): the device residual of the impulsive-start state against the
@@ -196,9 +176,11 @@ def test_cylinder_annulus_full_size_sampled_residual():
     nr, nth, nz = cfg.ncells
     rng = np.random.Generator(np.random.PCG64(41))
     picks = [0, nr - 1, nr * (nth - 1), nr * nth * nz - 1] + list(rng.integers(0, mesh.n_elem, size=12))
-    d, keep, idx = _sub_disc(cfg, mesh, k, st, sorted(set(int(x) for x in picks)))
-    Ro = d.residual(u[keep])[idx]
     sample = sorted(set(int(x) for x in picks))
+    # the oracle on the sample elements and their neighbours only
+    d, keep, idx = restricted_disc(_gas(cfg), mesh.dim, cfg.P, cfg.nq, mesh.face_nbr, sample,
+                                   geo_nodes=mesh.geo_nodes, geo_order=mesh.geo_order, bc_kind=k, bc_state=st)
+    Ro = d.residual(u[keep])[idx]
     assert np.all(np.isfinite(Rg))
     # As on the box workload, the single terms summed into R are of size
     # U (c+|u|)(P+1)^2 2/h (h the smallest element width, next to the
