@@ -284,11 +284,16 @@ def batch_configs(n: int = 64, seed: int = 5, nmin: int = 4, nmax: int = 32, pmi
     return out
 
 
-def freestream_state(cfg: FlowConfig, n_elem: int) -> np.ndarray:
+def freestream_state(cfg: FlowConfig, n_elem: int, at_rest: bool = False) -> np.ndarray:
     """Uniform freestream (mode-0 coefficient U_inf 2^(d/2)) plus
     cfg.noise_amp * sigma_v * noise(seed) on every coefficient, sigma =
-    (1, .., 1, E_inf): an impulsive start."""
+    (1, .., 1, E_inf): an impulsive start.  at_rest: the fluid starts at
+    rest (rho = 1, p = p_inf) and the far field sets it moving."""
     U = cfg.freestream()
+    if at_rest:
+        U = U.copy()
+        U[1:1 + cfg.dim] = 0.0
+        U[-1] -= 0.5
     shape = (n_elem, cfg.dim + 2, (cfg.P + 1) ** cfg.dim)
     u = np.zeros(shape)
     u[:, :, 0] = U * 2.0 ** (cfg.dim / 2.0)
