@@ -206,6 +206,10 @@ def main():
             f"algorithmic bytes per sweep")
         return
 
+    # ---- workgroup sizes of the residual kernels by the autotuner
+    tuned, tune_ms = ctx.autotune(u, reps=10)
+    log(f"autotuned residual workgroups (volume, face, lift): {tuned}")
+
     # ---- residual kernel throughput (inputs resident, back-to-back launches)
     R = ctx.empty()
     for _ in range(5):
@@ -220,7 +224,9 @@ def main():
     log(f"residual kernel {res_ms:.4f} ms")
 
     if cfg.geometry == "annulus" and not args.cylinder_steps:
-        print(json.dumps(cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream)), flush=True)
+        line = cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream)
+        line["residual_kernel"]["workgroups"] = dict(zip(("volume", "face", "lift"), tuned))
+        print(json.dumps(line), flush=True)
         return
 
     # ---- warmup steps (the cylinder starts impulsively: its warmup steps ramp
@@ -282,7 +288,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(cfg.pc_precision) if args.workload == 2 else None,
                      "bytes_per_launch": sb, "avg_launch_ms": sweep_ms},
-        "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3)},
+        "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3),
+                            "workgroups": dict(zip(("volume", "face", "lift"), tuned))},
         "pc_build_ms": build_ms,
         "residual_evals": evals,
         "newton_its": [s["newton_its"] for s in stats],
@@ -336,6 +343,8 @@ def bench_batch(steps):
     u = batch.empty()
     batch.project_tgv(torch.tensor(W.noise(batch.n_total, 5), device="cuda"), 1e-3, u)
     u0 = u.clone()
+    tuned = batch.autotune(u, reps=5)
+    log(f"batch autotuned residual workgroups per order group: {tuned}")
     R = batch.empty()
     for _ in range(3):
         batch.residual(u, R)
@@ -380,7 +389,8 @@ def bench_batch(steps):
             "ms_per_step_batched": batch_ms, "ms_per_step_one_by_one": solo_ms,
             "speedup": solo_ms / batch_ms, "residual_ms_batched": res_ms,
             "residual_dofs_per_s_batched": dofs / (res_ms * 1e-3),
-            "gmres_its_per_step": its, "max_rel_diff_vs_one_by_one": max_rel}
+            "gmres_its_per_step": its, "max_rel_diff_vs_one_by_one": max_rel,
+            "autotuned_workgroups_per_group": tuned}
 
 
 def cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream):

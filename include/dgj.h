@@ -158,6 +158,17 @@ int dgj_project_tgv(dgj_ctx *ctx, const double *noise, double noise_amp, double 
 
 /* R = M^-1 L(u)  (Eq. 13). */
 int dgj_residual(dgj_ctx *ctx, const double *u, double *R);
+/* Autotuner of the residual's workgroup shapes (not in the paper; the
+ * residual is evaluated by a volume, a face-flux and a lift kernel).  Times
+ * each kernel alone at state u with workgroups of 64, 128 and 256 threads,
+ * reps launches each (its other inputs left in place by one evaluation),
+ * and keeps the fastest for every later evaluation on this context.
+ * chosen: host [3] (volume, face, lift) or NULL; times_ms: host [3][3]
+ * ([kernel][64, 128, 256]) or NULL.  Results are unchanged (the kernels
+ * sum in the same order for every workgroup size) except on curved meshes,
+ * where the M^-1 product's partial sums follow the workgroup size.
+ * Synchronises the stream.  Not for batch groups (dgj_batch_autotune). */
+int dgj_autotune(dgj_ctx *ctx, const double *u, int32_t reps, int32_t *chosen, double *times_ms);
 
 /* N = u - S - dt_a M^-1 L(u)  (Eq. 20), dt_a = dt a^mm. */
 int dgj_stage_residual(dgj_ctx *ctx, const double *u, const double *S, double dt_a, double *N);
@@ -275,6 +286,11 @@ const char *dgj_batch_last_error(const dgj_batch *batch);
  * matvec, Gram-Schmidt) is captured once into a hipGraph on the batch's own
  * stream and replayed; 0: plain launches. */
 int dgj_batch_set_graphs(dgj_batch *batch, int32_t on);
+/* dgj_autotune for every order group of the batch at the batch state u
+ * (layout of dgj_batch_sizes); drops captured graphs.  chosen: host
+ * [n_groups][3] or NULL (at most one entry per distinct (dim, P, nq));
+ * n_groups: host, set to the number of groups, or NULL. */
+int dgj_batch_autotune(dgj_batch *batch, const double *u, int32_t reps, int32_t *chosen, int32_t *n_groups);
 /* total unknowns; per instance offsets[n] and counts[n] (host, may be NULL) */
 int dgj_batch_sizes(const dgj_batch *batch, int64_t *n_total, int64_t *offsets, int64_t *counts);
 /* dgj_project_tgv for every instance (noise in the batch layout, may be NULL) */

@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_last_error": ([vp], C.c_char_p),
         "dgj_project_tgv": ([vp, vp, dp, vp], C.c_int),
         "dgj_residual": ([vp, vp, vp], C.c_int),
+        "dgj_autotune": ([vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
         "dgj_stage_residual": ([vp, vp, vp, dp, vp], C.c_int),
         "dgj_jfnk_matvec": ([vp, vp, vp, vp, dp, vp, dp, vp], C.c_int),
         "dgj_precond_build": ([vp, vp, dp], C.c_int),
@@ -110,6 +111,7 @@ def load_library(path: str = LIB_PATH):
                              C.c_int),
         "dgj_batch_destroy": ([vp], None),
         "dgj_batch_set_graphs": ([vp, C.c_int32], C.c_int),
+        "dgj_batch_autotune": ([vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
         "dgj_batch_last_error": ([vp], C.c_char_p),
         "dgj_batch_sizes": ([vp, i64p, i64p, i64p], C.c_int),
         "dgj_batch_project_tgv": ([vp, vp, dp, vp], C.c_int),
@@ -234,6 +236,13 @@ class Batch:
     def residual(self, u, R):
         self._check(self.lib.dgj_batch_residual(self.h, _ptr(u), _ptr(R)))
 
+    def autotune(self, u, reps=20):
+        """Residual workgroup sizes per order group; returns [[volume, face, lift], ...]."""
+        ch = (C.c_int32 * (3 * self.n))()
+        ng = C.c_int32()
+        self._check(self.lib.dgj_batch_autotune(self.h, _ptr(u), int(reps), ch, C.byref(ng)))
+        return [[ch[3 * g + k] for k in range(3)] for g in range(ng.value)]
+
     def sdirk_step(self, u, dt):
         dts = np.ascontiguousarray(dt, dtype=np.float64)
         nit = (C.c_int32 * (4 * self.n))()
@@ -294,6 +303,14 @@ class Context:
 
     def residual(self, u, R):
         self._check(self.lib.dgj_residual(self.h, _ptr(u), _ptr(R)))
+
+    def autotune(self, u, reps=20):
+        """Workgroup sizes of the residual kernels chosen by timing; returns
+        (chosen [volume, face, lift], times_ms [kernel][64, 128, 256])."""
+        ch = (C.c_int32 * 3)()
+        tm = (C.c_double * 9)()
+        self._check(self.lib.dgj_autotune(self.h, _ptr(u), int(reps), ch, tm))
+        return list(ch), [[tm[3 * k + i] for i in range(3)] for k in range(3)]
 
     def stage_residual(self, u, S, dt_a, N):
         self._check(self.lib.dgj_stage_residual(self.h, _ptr(u), _ptr(S), float(dt_a), _ptr(N)))

@@ -649,6 +649,22 @@ int dgj_batch_residual(dgj_batch* b, const double* u, double* R) {
   });
 }
 
+int dgj_batch_autotune(dgj_batch* b, const double* u, int32_t reps, int32_t* chosen, int32_t* n_groups) {
+  if (!b || !u || reps < 1) return DGJ_EINVAL;
+  return batch_guard(b, [&]() -> int {
+    for (size_t gi = 0; gi < b->g.size(); ++gi) {
+      dgj_ctx* c = b->g[gi];
+      std::vector<int> ones(c->n_inst, 1);
+      set_active(c, ones);
+      autotune(c, u + b->goff[gi], reps, chosen ? chosen + 3 * gi : nullptr, nullptr);
+    }
+    drop_graphs(*b);   // captured launches hold the old workgroup sizes
+    if (n_groups) *n_groups = (int32_t)b->g.size();
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
 int dgj_batch_sdirk_step(dgj_batch* b, double* u, const double* dt, int32_t* newton_its, int32_t* gmres_its) {
   if (!b || !u || !dt) return DGJ_EINVAL;
   for (int i = 0; i < b->n; ++i)

@@ -405,6 +405,7 @@ struct dgj_ctx {
   double* d_chi = nullptr;
   int* d_status = nullptr;
   int residual_evals = 0;
+  int res_nt[3] = {0, 0, 0};       // block sizes of the volume, face and lift kernels (0: default)
   // initial guess of the stage solves
   int guess_mode = 0;              // 0 S_m, 1 extrapolated, 2 learned (with fallback)
   // instances of a batch held by this context (one shape); null for a single instance
@@ -497,30 +498,92 @@ bool shape_supported(int D, int N, int Q) {
   return false;
 }
 
+// The three residual kernels with the context's block sizes (0: the defaults)
 template <int D, int N, int Q>
-void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
+int default_nt(int k) { return k == 1 ? 128 : (D == 2 ? 64 : (k == 0 ? 128 : 256)); }
+
+template <int D, int N, int Q, bool CV>
+void launch_res_kernel(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int k, int nt) {
   using K = ResK<D, N, Q>;
+  if (k == 0) {
+    hipLaunchKernelGGL((k_res_vol<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk, c->d_trace,
+                       c->d_Lvol);
+  } else if (k == 1) {
+    const long nf = c->n_elem * D * K::NQF;
+    hipLaunchKernelGGL((k_res_face<D, N, Q, CV>), dim3((nf + nt - 1) / nt), dim3(nt), 0, c->stream, a, tk,
+                       c->d_trace, c->d_X);
+  } else {
+    hipLaunchKernelGGL((k_res_lift<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk, c->d_Lvol,
+                       c->d_X);
+  }
+}
+
+template <int D, int N, int Q>
+TabK<N, Q> tables_by_value(dgj_ctx* c) {
   TabK<N, Q> tk;
   static_assert(sizeof(TabK<N, Q>) == sizeof(double) * (2 * Q * N + Q + 4 * N + 2 * Q), "TabK layout");
   std::memcpy(&tk, c->h_tab.data(), sizeof(tk));
-  constexpr int NTV = D == 2 ? 64 : 128;
-  constexpr int NTL = D == 2 ? 64 : 256;
-  const long nf = c->n_elem * D * K::NQF;
-  if (c->curved) {
-    hipLaunchKernelGGL((k_res_vol<D, N, Q, NTV, true>), dim3(c->n_elem), dim3(NTV), 0, c->stream, a, tk, c->d_trace,
-                       c->d_Lvol);
-    hipLaunchKernelGGL((k_res_face<D, N, Q, true>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, a, tk,
-                       c->d_trace, c->d_X);
-    hipLaunchKernelGGL((k_res_lift<D, N, Q, NTL, true>), dim3(c->n_elem), dim3(NTL), 0, c->stream, a, tk, c->d_Lvol,
-                       c->d_X);
-  } else {
-    hipLaunchKernelGGL((k_res_vol<D, N, Q, NTV, false>), dim3(c->n_elem), dim3(NTV), 0, c->stream, a, tk,
-                       c->d_trace, c->d_Lvol);
-    hipLaunchKernelGGL((k_res_face<D, N, Q, false>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, a, tk,
-                       c->d_trace, c->d_X);
-    hipLaunchKernelGGL((k_res_lift<D, N, Q, NTL, false>), dim3(c->n_elem), dim3(NTL), 0, c->stream, a, tk,
-                       c->d_Lvol, c->d_X);
+  return tk;
+}
+
+template <int D, int N, int Q>
+void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
+  const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
+  for (int k = 0; k < 3; ++k) {
+    const int nt = c->res_nt[k] > 0 ? c->res_nt[k] : default_nt<D, N, Q>(k);
+    if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, tk, k, nt);
+    else launch_res_kernel<D, N, Q, false>(c, a, tk, k, nt);
   }
+}
+
+ResArgs res_args(dgj_ctx* c);
+
+// Autotuner: time each residual kernel alone with block sizes 64, 128 and
+// 256 at the state u (the other kernels' inputs left in place by one full
+// evaluation) and keep the fastest per kernel.
+template <int D, int N, int Q>
+void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* times) {
+  ResArgs a = res_args(c);
+  a.in = StateIn{u, nullptr, 0.0};
+  a.out = c->d_t1;
+  a.mode = RES_R;
+  launch_residual_t<D, N, Q>(c, a);
+  const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int cand[3] = {64, 128, 256};
+  for (int k = 0; k < 3; ++k) {
+    float best = 0.0f;
+    int bnt = 0;
+    for (int ci = 0; ci < 3; ++ci) {
+      auto run = [&]() {
+        if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, tk, k, cand[ci]);
+        else launch_res_kernel<D, N, Q, false>(c, a, tk, k, cand[ci]);
+      };
+      run();
+      HIPCHK(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) run();
+      HIPCHK(hipEventRecord(e1, c->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (times) times[3 * k + ci] = ms;
+      if (bnt == 0 || ms < best) { best = ms; bnt = cand[ci]; }
+    }
+    c->res_nt[k] = bnt;
+    if (chosen) chosen[k] = bnt;
+  }
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+}
+
+void autotune(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* times) {
+#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { autotune_t<d, n, q>(c, u, reps, chosen, times); return; }
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "unsupported shape");
 }
 
 void launch_residual(dgj_ctx* c, const ResArgs& a) {
@@ -1281,6 +1344,16 @@ int dgj_residual(dgj_ctx* c, const double* u, double* R) {
   if (!c || !u || !R) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     residual(c, u, R);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_autotune(dgj_ctx* c, const double* u, int32_t reps, int32_t* chosen, double* times_ms) {
+  if (!c || !u || reps < 1) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (c->n_inst > 0) fail(DGJ_EINVAL, "autotune a batch with dgj_batch_autotune");
+    autotune(c, u, reps, chosen, times_ms);
     HIPCHK(hipGetLastError());
     return DGJ_OK;
   });

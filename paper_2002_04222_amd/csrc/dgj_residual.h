@@ -46,8 +46,10 @@ struct ResK {
 };
 
 // ---------------------------------------------------------------- volume + traces
-template <int D, int N, int Q, int NT, bool CV>
-__global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
+// Block size (runtime, a multiple of 64, at most 256) is chosen per shape by
+// the autotuner; every loop strides by blockDim.x.
+template <int D, int N, int Q, bool CV>
+__global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
                                                 double* __restrict__ Lvol) {
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
@@ -59,6 +61,7 @@ __global__ __launch_bounds__(NT) void k_res_vol(ResArgs a, TabK<N, Q> tk, double
   ElemParams ep;
   if (!elem_params(a, e, ep)) return;
   const int tid = threadIdx.x;
+  const int NT = blockDim.x;
   const double* g = a.geo + e * K::S::GEO;
   double dxi[D];
 #pragma unroll
@@ -477,7 +480,7 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
 // boundary face by its element, in its own orientation, so the thread of
 // axis a also computes its element's side-0 face when that is a boundary.
 template <int D, int N, int Q, bool CV>
-__global__ __launch_bounds__(128) void k_res_face(ResArgs a, TabK<N, Q> tk, const double* __restrict__ trace,
+__global__ __launch_bounds__(256) void k_res_face(ResArgs a, TabK<N, Q> tk, const double* __restrict__ trace,
                                                   double* __restrict__ X) {
   using K = ResK<D, N, Q>;
   constexpr int NQF = K::NQF, NF = K::NF;
@@ -506,8 +509,8 @@ __device__ __forceinline__ void epilogue(const ResArgs& a, const ElemParams& ep,
 }
 
 // ---------------------------------------------------------------- lift + epilogue
-template <int D, int N, int Q, int NT, bool CV>
-__global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const double* __restrict__ Lvol,
+template <int D, int N, int Q, bool CV>
+__global__ __launch_bounds__(256) void k_res_lift(ResArgs a, TabK<N, Q> tk, const double* __restrict__ Lvol,
                                                  const double* __restrict__ X) {
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQF = K::NQF, NMF = K::NMF, NF = K::NF, NB = K::NB;
@@ -518,6 +521,7 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
   ElemParams ep;
   if (!elem_params(a, e, ep)) return;
   const int tid = threadIdx.x;
+  const int NT = blockDim.x;
   const double* g = a.geo + e * K::S::GEO;
   // face data in the element's own orientation and scaling
   for (int it = tid; it < NF * (D + 1) * NV * NQF; it += NT) {
@@ -601,8 +605,9 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
     // (the stored M^-1 is symmetric up to rounding and is read by columns);
     // the group partial sums meet in LDS.
     constexpr int MP = ((NM + 63) / 64) * 64;
-    constexpr int NS = NT / MP >= 1 ? NT / MP : 1;
-    static_assert(NB + NS * NB <= NF * (D + 1) * NV * NQF, "LDS staging of the mass-matrix product");
+    constexpr int NSC = (NF * (D + 1) * NV * NQF - NB) / NB;   // groups whose partial sums fit in sA
+    static_assert(NSC >= 1, "LDS staging of the mass-matrix product");
+    const int NS = NT / MP < 1 ? 1 : (NT / MP > NSC ? NSC : NT / MP);
     double* part = sA + NB;
     const double* Mi = a.minv + e * (long)NM * NM;
     for (int t = tid; t < NS * MP; t += NT) {
@@ -624,7 +629,6 @@ __global__ __launch_bounds__(NT) void k_res_lift(ResArgs a, TabK<N, Q> tk, const
     for (int i = tid; i < NB; i += NT) {
       const int m = i % NM, v = i / NM;
       double R = 0.0;
-#pragma unroll
       for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
       epilogue(a, ep, e * NB + i, R);
     }
