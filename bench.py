@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--P", type=int, default=None, help="polynomial order (default: the workload's; nq = P+2)")
     ap.add_argument("--pc", default=None, help="preconditioner storage f64|f32|bf16 (default: workload's)")
     ap.add_argument("--forms", action="store_true", help="also time the f32 and bf16 preconditioner forms")
+    ap.add_argument("--learned", action="store_true",
+                    help="also time the learned Newton guess against the paper's and the extrapolated one")
+    ap.add_argument("--learned-train", type=int, default=20, help="plain steps recorded to train the MLP")
     ap.add_argument("--batch", action="store_true",
                     help="also time the batch of 64 independent 2D problems, batched against one by one")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -320,6 +323,9 @@ def main():
             forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
         out["forms"] = forms
 
+    if args.learned:
+        out["learned"] = bench_learned(cfg, make, args.learned_train, min(args.steps, 3))
+
     if args.batch:
         out["batch"] = bench_batch(args.batch_steps)
 
@@ -391,6 +397,72 @@ def bench_batch(steps):
             "residual_dofs_per_s_batched": dofs / (res_ms * 1e-3),
             "gmres_its_per_step": its, "max_rel_diff_vs_one_by_one": max_rel,
             "autotuned_workgroups_per_group": tuned}
+
+
+def bench_learned(cfg, make, n_train, held):
+    """The learned-guess form: record n_train plain steps, fit the per-element
+    MLP on the recorded stages (in the library), then from one saved state
+    time `held` steps with each Newton initial guess (the paper's S_m, the
+    extrapolated one, the learned one with its fallback), all stopping at the
+    same absolute Newton tolerance."""
+    import numpy as np
+    import torch
+    import workloads as W
+    ctx, u = make("f64")
+    dt = cfg.dt()
+    n = ctx.n_unknowns
+    stages = 2 if cfg.scheme == "sdirk2" else 3
+    ctx.sdirk_step(u, dt)
+    S_rec = torch.empty((n_train, stages, n), dtype=torch.float64, device="cuda")
+    I_rec = torch.empty_like(S_rec)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(n_train):
+        ctx.set_record(S_rec[k], I_rec[k])
+        ctx.sdirk_step(u, dt)
+    ctx.set_record(None, None)
+    torch.cuda.synchronize()
+    rec_s = time.perf_counter() - t
+    nb = ctx.shape[1] * ctx.shape[2]
+    ctx.mlp_create(256, W.mlp_init(2 * nb, 256, nb, seed=8))
+    t = time.perf_counter()
+    loss = ctx.mlp_fit(S_rec, I_rec, n_train, 150, 1e-3)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t
+    del S_rec, I_rec
+    log(f"learned: recorded {n_train} steps in {rec_s:.1f} s, fit loss {loss:.3e} in {fit_s:.1f} s")
+    u_save = u.clone()
+    inc_save = torch.empty((2, 3, n), dtype=torch.float64, device="cuda")
+    ctx.guess_state(inc_out=inc_save)
+    res = {}
+    for mode in ("paper", "extrapolated", "learned"):
+        ctx.guess_state(inc_in=inc_save)
+        ctx.set_guess(mode)
+        uu = u_save.clone()
+        ctx.precond_build(uu, dt * _lam(cfg.scheme))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its, used, norms = [], [], []
+        for _ in range(held):
+            st = ctx.sdirk_step(uu, dt)
+            its.append(st["newton_its"])
+            used.append(st["guess_used"])
+            norms.append(st["guess_norm"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / held
+        res[mode] = {"ms_per_step": ms, "newton_its": its, "u": uu, "used": used, "norms": norms}
+        log(f"guess {mode}: {ms:.1f} ms/step, newton {its}")
+    ctx.set_guess("paper")
+    base = res["paper"]["u"]
+    out = {"train_steps": n_train, "fit_loss": loss, "record_s": rec_s, "fit_s": fit_s, "held_out_steps": held}
+    for mode, r in res.items():
+        out[mode] = {"ms_per_step": r["ms_per_step"], "newton_its": r["newton_its"],
+                     "guess_used": r["used"],
+                     "guess_norm_N_S_extrap_learned": r["norms"] if mode != "paper" else None,
+                     "speedup_vs_paper_guess": res["paper"]["ms_per_step"] / r["ms_per_step"],
+                     "rel_diff_vs_paper_guess": float(torch.linalg.norm(r["u"] - base) / torch.linalg.norm(base))}
+    ctx.close()
+    return out
 
 
 def cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream):

@@ -120,6 +120,11 @@ typedef struct {
   double brj_omega;           /* omega of Eq. 28 (1) */
   int32_t pc_precision;       /* DGJ_PC_F64 / F32 / BF16 storage of D^-1 */
   int32_t pc_freeze;          /* steps a built preconditioner is kept (10) */
+  int32_t pc_refresh_its;     /* single instances: rebuild the preconditioner at S_m before a
+                                 stage when the last Newton step's GMRES took more iterations
+                                 than this, and retry a failed stage once from S_m with blocks
+                                 rebuilt at S_m (0: the paper's fixed freeze only); not in the
+                                 paper, which keeps the blocks for pc_freeze steps */
 } dgj_solver;
 
 /* Per-step statistics filled by dgj_sdirk_step. */
@@ -208,8 +213,10 @@ int dgj_newton(dgj_ctx *ctx, const double *S, double dt_a, double *u, int32_t *n
 
 /* One SDIRK step of size dt on u (in/out) (Eq. 17-23).  (Re)builds the
  * preconditioner at the incoming u when none is held, when it is
- * pc_freeze steps old, or when dt a^mm changed.  stats may be NULL.  On
- * DGJ_ENOTCONV / DGJ_ENAN u is left unchanged and stats tell where. */
+ * pc_freeze steps old, or when dt a^mm changed, and at a stage's S_m under
+ * the pc_refresh_its rules.  stats may be NULL (the stats of a retried
+ * stage are the retry's).  On DGJ_ENOTCONV / DGJ_ENAN u is left unchanged
+ * and stats tell where. */
 int dgj_sdirk_step(dgj_ctx *ctx, double *u, double dt, dgj_step_stats *stats);
 
 /* ---- Newton initial guess (not in the paper, which starts from S_m,
@@ -300,7 +307,7 @@ int dgj_batch_residual(dgj_batch *batch, const double *u, double *R);
 /* One SDIRK step of every instance, dt (host [n]) per instance; optional
  * host outputs newton_its[n][4] and gmres_its[n][4] (total per stage).
  * Preconditioners are rebuilt at the incoming state every pc_freeze steps
- * or when an instance's dt changes. */
+ * or when an instance's dt changes (pc_refresh_its is not applied). */
 int dgj_batch_sdirk_step(dgj_batch *batch, double *u, const double *dt, int32_t *newton_its, int32_t *gmres_its);
 
 #ifdef __cplusplus

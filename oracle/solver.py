@@ -268,6 +268,7 @@ class SolverOpts:
     brj_sweeps: int = 7
     brj_omega: float = 1.0
     pc_freeze: int = 10
+    pc_refresh_its: int = 30      # rebuild before a stage when the last Newton step's GMRES took more (0: never)
     use_pc: bool = True
 
 
@@ -314,7 +315,12 @@ def newton_solve(disc, S, dt_a, pc, opts: SolverOpts, guess=None):
 
 
 class SDIRK:
-    """Implicit Runge-Kutta stepper with a frozen BRJ preconditioner."""
+    """Implicit Runge-Kutta stepper with a frozen BRJ preconditioner: built at
+    u^n and kept for pc_freeze steps while dt a^mm is unchanged (Sec. 4.2.2).
+    Two refresh rules beyond the paper's fixed freeze: before a stage, when
+    the last Newton step's GMRES needed more than pc_refresh_its iterations,
+    the blocks are rebuilt at the stage's S_m; a stage whose Newton solve
+    fails is retried once from S_m with blocks rebuilt at S_m."""
 
     def __init__(self, disc, opts: SolverOpts):
         self.disc, self.opts = disc, opts
@@ -322,14 +328,19 @@ class SDIRK:
         self.pc: Optional[BRJ] = None
         self.pc_age = 0
         self.pc_dta = None
+        self.last_gmres_max = 0
+
+    def build_pc(self, u_p, dt_a):
+        self.pc = BRJ(self.disc, u_p, dt_a, self.opts.brj_sweeps, self.opts.brj_omega)
+        self.pc_age = 0
+        self.pc_dta = dt_a
+        self.last_gmres_max = 0
 
     def ensure_pc(self, u_n, dt_a):
         if not self.opts.use_pc:
             return
         if self.pc is None or self.pc_age >= self.opts.pc_freeze or self.pc_dta != dt_a:
-            self.pc = BRJ(self.disc, u_n, dt_a, self.opts.brj_sweeps, self.opts.brj_omega)
-            self.pc_age = 0
-            self.pc_dta = dt_a
+            self.build_pc(u_n, dt_a)
 
     def step(self, u_n, dt, guesses=None):
         A, b = self.A, self.b
@@ -341,8 +352,15 @@ class SDIRK:
             dt_a = dt * A[m, m]
             if m == 0:
                 self.ensure_pc(u_n, dt_a)
+            refresh = self.opts.use_pc and self.opts.pc_refresh_its > 0
+            if refresh and self.last_gmres_max > self.opts.pc_refresh_its:
+                self.build_pc(S, dt_a)
             g = None if guesses is None else guesses[m]
             u_m, st = newton_solve(self.disc, S, dt_a, self.pc, self.opts, guess=g)
+            if not st.converged and refresh:
+                self.build_pc(S, dt_a)
+                u_m, st = newton_solve(self.disc, S, dt_a, self.pc, self.opts)
+            self.last_gmres_max = max(st.gmres_its) if st.gmres_its else 0
             stats.append(st)
             if not st.converged:
                 raise NotConverged(f"stage {m}: Newton did not converge: {st.nres}")

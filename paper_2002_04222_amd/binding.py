@@ -43,7 +43,7 @@ class Solver(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("newton_rtol", C.c_double), ("newton_max", C.c_int32),
                 ("gmres_restart", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_max", C.c_int32),
                 ("brj_sweeps", C.c_int32), ("brj_omega", C.c_double), ("pc_precision", C.c_int32),
-                ("pc_freeze", C.c_int32)]
+                ("pc_freeze", C.c_int32), ("pc_refresh_its", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -175,7 +175,8 @@ def _phys_struct(cfg):
 
 def _solver_struct(cfg):
     return Solver(SCHEMES[cfg.scheme], cfg.newton_rtol, cfg.newton_max, cfg.gmres_restart, cfg.gmres_rtol,
-                  cfg.gmres_max, cfg.brj_sweeps, cfg.brj_omega, PRECISIONS[cfg.pc_precision], cfg.pc_freeze)
+                  cfg.gmres_max, cfg.brj_sweeps, cfg.brj_omega, PRECISIONS[cfg.pc_precision], cfg.pc_freeze,
+                  cfg.pc_refresh_its)
 
 
 class Batch:
@@ -265,7 +266,8 @@ class Context:
         g = lambda k: over.get(k, getattr(cfg, k))
         ph = Phys(g("gamma"), g("Pr"), g("Re"), g("Ma"), g("T_ref_K"), g("visc_law"), g("flux_mode"), g("riemann"))
         sv = Solver(SCHEMES[g("scheme")], g("newton_rtol"), g("newton_max"), g("gmres_restart"), g("gmres_rtol"),
-                    g("gmres_max"), g("brj_sweeps"), g("brj_omega"), PRECISIONS[g("pc_precision")], g("pc_freeze"))
+                    g("gmres_max"), g("brj_sweeps"), g("brj_omega"), PRECISIONS[g("pc_precision")], g("pc_freeze"),
+                    g("pc_refresh_its"))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

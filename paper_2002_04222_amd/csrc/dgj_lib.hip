@@ -406,6 +406,7 @@ struct dgj_ctx {
   int* d_status = nullptr;
   int residual_evals = 0;
   int res_nt[3] = {0, 0, 0};       // block sizes of the volume, face and lift kernels (0: default)
+  int last_gmres_max = 0;          // largest GMRES count of the last Newton solve since the last build
   // initial guess of the stage solves
   int guess_mode = 0;              // 0 S_m, 1 extrapolated, 2 learned (with fallback)
   // instances of a batch held by this context (one shape); null for a single instance
@@ -841,6 +842,7 @@ void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& i
       if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
   c->pc_ready = true;
   c->pc_age = 0;
+  c->last_gmres_max = 0;
 }
 
 void precond_build(dgj_ctx* c, const double* up, double dt_a) {
@@ -1500,7 +1502,27 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
           if (nM < best) { best = nM; copy(c, c->d_ubar, c->d_g2); st->guess_used[m] = 2; }
         }
       }
+      const bool refresh = c->sv.pc_refresh_its > 0;
+      if (refresh && c->last_gmres_max > c->sv.pc_refresh_its) {
+        // the frozen blocks have lost too much: rebuild at S_m
+        auto tb = clk::now();
+        precond_build(c, c->d_S, dta_m);
+        st->pc_built += 1;
+        st->t_pc_build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
+      }
       NewtonOut o = newton(c, c->d_S, dta_m, c->d_ubar, tau);
+      if (!o.converged && !o.nan && refresh) {
+        // retry the stage once from S_m with blocks rebuilt at S_m
+        auto tb = clk::now();
+        precond_build(c, c->d_S, dta_m);
+        st->pc_built += 1;
+        st->t_pc_build_ms += std::chrono::duration<double, std::milli>(clk::now() - tb).count();
+        copy(c, c->d_ubar, c->d_S);
+        st->guess_used[m] = 0;
+        o = newton(c, c->d_S, dta_m, c->d_ubar, -1.0);
+      }
+      c->last_gmres_max = 0;
+      for (int g : o.gmres_its) c->last_gmres_max = std::max(c->last_gmres_max, g);
       st->newton_its[m] = o.its;
       for (size_t i = 0; i < o.gmres_its.size() && i < 64; ++i) st->gmres_its[m][i] = o.gmres_its[i];
       for (size_t i = 0; i < o.nres.size() && i < 65; ++i) st->nres[m][i] = o.nres[i];

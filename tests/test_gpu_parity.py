@@ -260,3 +260,24 @@ def test_residual_bitwise_repeatable_and_full_workload():
     ctx.jfnk_matvec(_dev(u0), _dev(No), _dev(u0), dt_a, _dev(v), eps, Jv)
     Jo = OS.jfnk_matvec(disc, u0, No, u0, dt_a, v, eps)
     assert np.linalg.norm(_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+
+
+def test_sdirk_step_parity_with_preconditioner_refresh():
+    """The refresh rules (rebuild at S_m after a stage whose GMRES took more
+    than pc_refresh_its iterations) taken on both sides: identical counts."""
+    _case("sdirk step with refresh")
+    cfg, mesh, disc = setup(2, (4, 3), 2, Ma=0.3, Re=40.0, scheme="sdirk3", pc_refresh_its=2)
+    ctx = _ctx(cfg, mesh)
+    u0 = W.random_state(mesh.n_elem, 2, 2, seed=43)
+    du = _dev(u0)
+    stepper = OS.SDIRK(disc, OS.SolverOpts(scheme="sdirk3", pc_refresh_its=2))
+    uo = u0
+    builds = 0
+    for k in range(2):
+        st = ctx.sdirk_step(du, 0.2)
+        builds += st["pc_built"]
+        uo, sto = stepper.step(uo, 0.2)
+        assert st["newton_its"] == [s.newton_its for s in sto]
+        assert st["gmres_its"] == [s.gmres_its for s in sto]
+        assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
+    assert builds >= 2

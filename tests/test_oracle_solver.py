@@ -280,3 +280,25 @@ def test_sdirk_temporal_order_linear(scheme, order):
         errs.append(np.abs(u - ref).max())
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > order - 0.3), (errs, rates)
+
+
+def test_sdirk_preconditioner_refresh_rule():
+    """With pc_refresh_its = 1 every stage after one whose GMRES took more
+    than one iteration rebuilds the blocks at its S_m; the step still meets
+    the Newton tolerance and stays within it of the frozen-blocks step."""
+    d = tiny_disc(dim=2, cells=(3, 3), P=2, Ma=0.3, Re=40.0)
+    u0 = W.random_state(d.n_elem, 2, 2, seed=51)
+    frozen = S.SDIRK(d, S.SolverOpts(scheme="sdirk3", pc_refresh_its=0))
+    fresh = S.SDIRK(d, S.SolverOpts(scheme="sdirk3", pc_refresh_its=1))
+    builds = []
+    orig = fresh.build_pc
+
+    def counting(u_p, dt_a):
+        builds.append(u_p.copy())
+        return orig(u_p, dt_a)
+    fresh.build_pc = counting
+    ua, sa = frozen.step(u0, 0.2)
+    ub, sb = fresh.step(u0, 0.2)
+    assert len(builds) >= 2                           # the step's own build plus refreshes
+    assert all(x.converged for x in sb)
+    assert np.linalg.norm(ub - ua) <= 1e-6 * np.linalg.norm(ua)

@@ -192,6 +192,7 @@ class FlowConfig:
     brj_sweeps: int = 7
     brj_omega: float = 1.0
     pc_freeze: int = 10
+    pc_refresh_its: int = 30
     pc_precision: str = "f64"
     geometry: str = "box"     # "box" (periodic affine boxes) or "annulus" (curved O-grid, walls + far field)
     r0: float = 0.5
