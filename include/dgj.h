@@ -65,8 +65,11 @@ typedef struct dgj_ctx dgj_ctx;
  *    normal velocity and c the sound speed, R+ = u_n + 2c/(gamma-1) comes
  *    from the interior and R- = u_n - 2c/(gamma-1) from the freestream;
  *    tangential velocity and entropy p/rho^gamma come from the interior
- *    where (R+ + R-)/2 > 0, else from the freestream.  Supersonic inflow:
- *    the freestream state; supersonic outflow: the interior state.
+ *    where u_nb = (R+ + R-)/2 > 0, else from the freestream, blended by
+ *    w = (1 + tanh(u_nb / (0.02 c_b)))/2, c_b = (gamma-1)(R+ - R-)/4, so that
+ *    the ghost state is differentiable where u_nb changes sign (a sharp
+ *    switch there stalls Newton).  Supersonic inflow: the freestream state;
+ *    supersonic outflow: the interior state.
  *  DGJ_BC_WALL: adiabatic no-slip wall.  Ghost = interior with the
  *    momentum negated (zero wall velocity); the energy components of the
  *    viscous flux and of the symmetric interior-penalty term are zero (no

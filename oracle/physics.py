@@ -228,13 +228,19 @@ def face_flux_own(gas: Gas, Uo, Un, go, gn, n, beta_p):
 BC_FARFIELD, BC_WALL = 0, 1
 
 
+FARFIELD_BLEND = 0.02   # half-width of the inflow/outflow blend in u_nb, relative to c_b
+
+
 def farfield_ghost(gas: Gas, U, n, Uinf):
     """Riemann-invariant far field: with u_n the outward normal velocity and
     c the sound speed, R+ = u_n + 2c/(gamma-1) from the interior, R- = u_n -
     2c/(gamma-1) from the freestream (for |u_n| < c); u_nb = (R+ + R-)/2,
     c_b = (gamma-1)(R+ - R-)/4; tangential velocity and entropy p/rho^gamma
-    from the interior on outflow (u_nb > 0), from the freestream on inflow.
-    Supersonic: all from the interior (outflow) or the freestream (inflow)."""
+    taken from the interior on outflow (u_nb > 0) and from the freestream on
+    inflow, blended by w = (1 + tanh(u_nb / (0.02 c_b)))/2 so that the ghost
+    state is differentiable where u_nb changes sign (w is 0 or 1 to double
+    precision once |u_nb| > c_b).  Supersonic: all from the freestream
+    (inflow, checked first) or the interior (outflow)."""
     g = gas.gamma
     Uinf = np.broadcast_to(Uinf, U.shape)
     ri, vi, Ei, pi = primitives(gas, U)
@@ -246,10 +252,10 @@ def farfield_ghost(gas: Gas, U, n, Uinf):
     Rm = uno - 2.0 * co / (g - 1.0)
     unb = 0.5 * (Rp + Rm)
     cb = 0.25 * (g - 1.0) * (Rp - Rm)
-    out = np.real(unb) > 0.0
+    w = 0.5 * (1.0 + np.tanh(unb / (FARFIELD_BLEND * cb)))
     s_i, s_o = pi / ri ** g, po / ro ** g
-    s = np.where(out, s_i, s_o)
-    vt = np.where(out[..., None], vi - uni[..., None] * n, vo - uno[..., None] * n)
+    s = w * s_i + (1.0 - w) * s_o
+    vt = w[..., None] * (vi - uni[..., None] * n) + (1.0 - w)[..., None] * (vo - uno[..., None] * n)
     rb = (cb * cb / (g * s)) ** (1.0 / (g - 1.0))
     pb = rb * cb * cb / g
     vb = vt + unb[..., None] * n

@@ -356,7 +356,9 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, cons
 // ---------------------------------------------------------------- boundary conditions
 // A boundary face takes the interior trace and a ghost state with the
 // interior gradient, and the interior-face fluxes apply.  Far field: 1D
-// characteristic (Riemann-invariant) state against the freestream Uinf;
+// characteristic (Riemann-invariant) state against the freestream Uinf,
+// with the inflow/outflow choice of entropy and tangential velocity blended
+// by w = (1 + tanh(u_nb / (0.02 c_b)))/2;
 // no-slip wall: mirrored momentum (zero wall velocity), with the heat flux
 // through the wall zero (adiabatic), so the viscous energy fluxes vanish.
 enum { BC_FARFIELD = 0, BC_WALL = 1 };
@@ -391,14 +393,16 @@ __device__ __forceinline__ void farfield_ghost(const Phys& ph, const double* Ui,
   const double Rm = uno - 2.0 * co / (g - 1.0);
   const double unb = 0.5 * (Rp + Rm);
   const double cb = 0.25 * (g - 1.0) * (Rp - Rm);
-  const bool out = unb > 0.0;
-  const double s = out ? pi / pow(ri, g) : po / pow(ro, g);
+  // entropy and tangential velocity upwinded (interior on outflow,
+  // freestream on inflow), blended smoothly where u_nb changes sign
+  const double w = 0.5 * (1.0 + tanh(unb / (0.02 * cb)));
+  const double s = w * (pi / pow(ri, g)) + (1.0 - w) * (po / pow(ro, g));
   const double rb = pow(cb * cb / (g * s), 1.0 / (g - 1.0));
   const double pb = rb * cb * cb / g;
   double vb[D], kb = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
-    const double vt = out ? vi[c] - uni * n[c] : vo[c] - uno * n[c];
+    const double vt = w * (vi[c] - uni * n[c]) + (1.0 - w) * (vo[c] - uno * n[c]);
     vb[c] = vt + unb * n[c];
     kb += vb[c] * vb[c];
   }

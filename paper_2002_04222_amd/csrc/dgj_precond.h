@@ -196,7 +196,8 @@ __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, 
 // to the neighbour trace (Jp, stored for the off-diagonal product), at fixed
 // trace gradients.
 template <int D, int N, int Q, typename TJ>
-__global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ nbr, const double* __restrict__ geo,
+__global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, const int* __restrict__ nbr,
+                                                 const double* __restrict__ geo,
                           const double* __restrict__ beta, const double* __restrict__ tables, Phys ph, long n_elem,
                           const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp,
                           long e0, const int* __restrict__ bc_kind, const double* __restrict__ bc_state,
@@ -275,27 +276,37 @@ __global__ void k_pc_face(const double* __restrict__ u, const int* __restrict__ 
 }
 
 // ---------------------------------------------------------------- block assembly
-// One workgroup per (element, k, l): the NM x NM sub-block A_kl of A_e, then
-// D = I - dt_a / |J| A (boxes) or D = M_e - dt_a A (curved, mass[e][NM][NM];
-// its inverse is (M_e - dt_a A_e)^-1 = D_e^-1 M_e^-1) written column-major
-// into Dm[e][col][row].
+// One workgroup per (element, k, l, tile): a tile of NT*NO entries of the
+// NM x NM sub-block A_kl of A_e (a thread keeps NO <= 16 accumulators in
+// registers), then D = I - dt_a / |J| A (boxes) or D = M_e - dt_a A
+// (curved, mass[e][NM][NM]; its inverse is (M_e - dt_a A_e)^-1 =
+// D_e^-1 M_e^-1) written column-major into Dm[e][col][row].
+template <int D, int N, int Q, int NT>
+struct AssembleTiles {
+  static constexpr int NM2 = Shape<D, N, Q>::NM * Shape<D, N, Q>::NM;
+  static constexpr int NO = (NM2 + NT - 1) / NT < 16 ? (NM2 + NT - 1) / NT : 16;
+  static constexpr int NTILE = (NM2 + NT * NO - 1) / (NT * NO);
+};
+
 template <int D, int N, int Q, int NT, typename TD>
 __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ Wt, const double* __restrict__ JmW,
                                                      const double* __restrict__ geo, const double* __restrict__ tables,
                                                      double dt_a, long n_elem, TD* __restrict__ Dm, long e0,
                                                      const double* __restrict__ mass) {
   using S = Shape<D, N, Q>;
+  using AT = AssembleTiles<D, N, Q, NT>;
   constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF, NB = S::NB;
   constexpr int PER_Q = D * (D + 1) * NV * NV;
-  constexpr int NO = (NM * NM + NT - 1) / NT;
+  constexpr int NO = AT::NO, NTILE = AT::NTILE;
   __shared__ double st[S::TAB];
   __shared__ double Z[NM];
   __shared__ double wv[D + 1];
   Tab tb = load_tables<N, Q>(tables, st);
   const long blk = blockIdx.x;
-  if (blk / (NV * NV) >= n_elem) return;
-  const long e = e0 + blk / (NV * NV);
-  const int kl = blk % (NV * NV);
+  if (blk / (NV * NV * NTILE) >= n_elem) return;
+  const long e = e0 + blk / (NV * NV * NTILE);
+  const int kl = (blk / NTILE) % (NV * NV);
+  const int tile = blk % NTILE;
   const int k = kl / NV, l = kl % NV;
   double acc[NO];
 #pragma unroll
@@ -335,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ W
       __syncthreads();
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
-        int oi = tid + o * NT;
+        int oi = tile * NT * NO + tid + o * NT;
         if (oi < NM * NM) {
           int m = oi / NM, n = oi % NM;
           int mi[3] = {0, 0, 0};
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ W
       __syncthreads();
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
-        int oi = tid + o * NT;
+        int oi = tile * NT * NO + tid + o * NT;
         if (oi < NM * NM) {
           int m = oi / NM, n = oi % NM;
           int mi[3] = {0, 0, 0};
@@ -387,7 +398,7 @@ __global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ W
   const double sc = mass ? dt_a : dt_a * geo[e * S::GEO + D + 1];
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    int oi = tid + o * NT;
+    int oi = tile * NT * NO + tid + o * NT;
     if (oi < NM * NM) {
       int m = oi / NM, n = oi % NM;
       int row = k * NM + m, col = l * NM + n;

@@ -37,7 +37,7 @@ def test_batch_matches_solo_runs(graphs):
     for i, cfg in enumerate(cfgs):
         o0 = batch.offsets[i]
         o1 = o0 + batch.counts[i]
-        ctx = Context(cfg.mesh(), cfg)
+        ctx = Context(cfg.mesh(), cfg, pc_refresh_its=0)   # batches keep the fixed freeze
         ui = u0[o0:o1].clone().reshape(ctx.shape)
         Ri = ctx.empty()
         ctx.residual(ui, Ri)

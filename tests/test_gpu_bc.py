@@ -1,8 +1,13 @@
 """Parity of the HIP path with the oracle on meshes with boundary faces:
 1D characteristic far field and adiabatic no-slip walls (ghost states with
 the interior gradient).  Tolerances as for the periodic parity tests:
-residual 1e-12 relative per variable, matvec and BRJ 1e-6 (forward
-differences), SDIRK steps 1e-10."""
+residual 1e-12 relative per variable, matvec 1e-6, SDIRK steps 1e-10.
+BRJ blocks 5e-6 and applies 1e-5: where a far-field face lies in the
+inflow/outflow blend (|u_nb| below ~0.02 c_b) the forward difference of Eq.
+31 divides the rounding of u_nb = (R+ + R-)/2 (|R+-| ~ 2c/(gamma-1)),
+steepened by the blend's slope 1/(0.04 c_b), by chi (~1e-8 for the smallest
+variable): both sides' blocks then differ by ~1e-6, and 7 sweeps compound
+it."""
 import dataclasses
 import sys
 
@@ -122,12 +127,12 @@ def test_bc_matvec_and_precond_parity():
     out = torch.empty((mesh.n_elem, nb, nb), dtype=torch.float64, device="cuda")
     ctx.precond_diag_inverse(out)
     Dg = _host(out)
-    assert np.abs(Dg - pc.Dinv).max() <= 1e-6 * np.abs(pc.Dinv).max()
+    assert np.abs(Dg - pc.Dinv).max() <= 5e-6 * np.abs(pc.Dinv).max()
     q = W.random_vector(mesh.n_elem, 2, 2, seed=213)
     o = ctx.empty()
     ctx.precond_apply(_dev(q), o)
     ref = pc.apply(q)
-    assert np.abs(_host(o) - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert np.abs(_host(o) - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
 def test_bc_precond_parity_3d():
@@ -141,7 +146,7 @@ def test_bc_precond_parity_3d():
     o = ctx.empty()
     ctx.precond_apply(_dev(q), o)
     ref = pc.apply(q)
-    assert np.abs(_host(o) - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert np.abs(_host(o) - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("scheme", ["sdirk2", "sdirk3"])

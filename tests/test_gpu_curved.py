@@ -1,7 +1,9 @@
 """Parity of the HIP path with the oracle on curved (isoparametric)
 elements: periodic curved boxes and the cylinder annulus with wall and far
 field.  Tolerances as for boxes: residual 1e-12 relative per variable,
-matvec and BRJ 1e-6 (forward differences), SDIRK steps 1e-10.  On curved
+matvec and BRJ 1e-6 (forward differences), SDIRK steps 1e-10; with far-field
+faces the BRJ blocks 5e-6 and applies 1e-5 (see the boundary-condition
+parity tests).  On curved
 meshes the library stores (M_e - dt a A_e)^-1, which is compared with the
 oracle's D_e^-1 M_e^-1."""
 import dataclasses
@@ -118,12 +120,14 @@ def test_annulus_matvec_and_precond_parity():
     ctx.precond_diag_inverse(out)
     Dg = _host(out)
     Do = np.einsum('eab,ebc->eac', pc.Dinv, np.stack([np.kron(np.eye(disc.nv), m) for m in pc.Minv]))
-    assert np.abs(Dg - Do).max() <= 1e-6 * np.abs(Do).max()
+    # far-field faces in the inflow/outflow blend: see the tolerances of the
+    # boundary-condition parity tests
+    assert np.abs(Dg - Do).max() <= 5e-6 * np.abs(Do).max()
     q = W.random_vector(mesh.n_elem, 2, 2, seed=313)
     o = ctx.empty()
     ctx.precond_apply(_dev(q), o)
     ref = pc.apply(q)
-    assert np.abs(_host(o) - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert np.abs(_host(o) - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
 def test_curved_box_precond_parity_3d():

@@ -28,20 +28,50 @@ def _inv(gas, U, n):
 
 @pytest.mark.parametrize("un_sign", [1.0, -1.0])
 def test_farfield_ghost_characteristics(un_sign):
+    """Away from u_nb = 0 (|u_nb| >> 0.02 c_b) the ghost has R+ of the
+    interior, R- of the freestream, and the upwind side's entropy and
+    tangential velocity."""
     gas = Gas(Ma=0.3)
     n = np.array([0.6, 0.8])
-    Ui = _cons(gas, 1.1, [0.3 * un_sign * 0.6 + 0.1, 0.3 * un_sign * 0.8 - 0.075], 8.5)
-    Uo = _cons(gas, 1.0, [0.2, -0.1], 7.9)
+    c = np.sqrt(1.4 * 8.5 / 1.1)
+    t = np.array([-0.8, 0.6])
+    Ui = _cons(gas, 1.1, un_sign * 0.6 * c * n + 0.25 * t, 8.5)
+    Uo = _cons(gas, 1.0, un_sign * 0.6 * c * n - 0.3 * t, 7.9)
     Ub = farfield_ghost(gas, Ui, n, Uo)
     Rpi, _, si, vti = _inv(gas, Ui, n)
     _, Rmo, so, vto = _inv(gas, Uo, n)
     Rpb, Rmb, sb, vtb = _inv(gas, Ub, n)
     assert np.isclose(Rpb, Rpi, rtol=1e-13) and np.isclose(Rmb, Rmo, rtol=1e-13)
     out = (Rpb + Rmb) > 0
+    assert out == (un_sign > 0)
     assert np.isclose(sb, si if out else so, rtol=1e-12)
     assert np.allclose(vtb, vti if out else vto, atol=1e-13)
     # a ghost computed from the freestream itself is the freestream
     assert np.allclose(farfield_ghost(gas, Uo, n, Uo), Uo, rtol=1e-13)
+
+
+def test_farfield_blend_is_continuous_across_un_zero():
+    """Where u_nb changes sign the entropy and tangential velocity are
+    blended: at u_nb = 0 they are the two sides' means, and the ghost state
+    changes continuously (no jump between the inflow and outflow choices)."""
+    gas = Gas(Ma=0.3)
+    n = np.array([1.0, 0.0])
+    Uo = _cons(gas, 1.0, [0.0, 0.4], 8.0)
+    Ri_of = lambda un: _cons(gas, 1.2, [un, -0.2], 9.0)
+    # interior normal velocity giving u_nb = 0 exactly: R+ = -R-
+    ro, vo, Eo, po = primitives(gas, Uo)
+    co = np.sqrt(1.4 * po / ro)
+    ci = np.sqrt(1.4 * 9.0 / 1.2)
+    un0 = -(0.0 - 2 * co / 0.4) - 2 * ci / 0.4
+    Ub = farfield_ghost(gas, Ri_of(un0), n, Uo)
+    _, _, sb, vtb = _inv(gas, Ub, n)
+    _, _, si, vti = _inv(gas, Ri_of(un0), n)
+    _, _, so, vto = _inv(gas, Uo, n)
+    assert np.isclose(sb, 0.5 * (si + so), rtol=1e-12)
+    assert np.allclose(vtb, 0.5 * (vti + vto), atol=1e-12)
+    h = 1e-7
+    jump = np.abs(farfield_ghost(gas, Ri_of(un0 + h), n, Uo) - farfield_ghost(gas, Ri_of(un0 - h), n, Uo)).max()
+    assert jump < 1e-3
 
 
 def test_farfield_supersonic():
@@ -108,7 +138,10 @@ def test_walls_conserve_mass_and_energy(dim):
 def test_brj_blocks_exact_with_boundaries_euler():
     """P8a with far-field and wall faces: the boundary conditions are inside
     the differenced flux (Eq. 31), so the BRJ diagonal blocks equal the exact
-    Jacobian blocks to forward-difference accuracy."""
+    Jacobian blocks to forward-difference accuracy.  The far-field blend
+    varies on the scale 0.02 c_b ~ 0.07 in u_n here, so the forward
+    difference's truncation (~ chi / (2 delta^2) relative) is ~5e-6, not the
+    ~3e-7 of the other faces."""
     gas = dict(Ma=0.3, flux_mode=1)
     Uinf = _cons(Gas(**gas), 1.0, [0.3, 0.1], 20.0 * 0.4)
     d = _bc_disc(2, (3, 3), 1, [False, False], [BC_FARFIELD, BC_FARFIELD, BC_WALL, BC_WALL],
@@ -119,4 +152,4 @@ def test_brj_blocks_exact_with_boundaries_euler():
     nb = d.nv * d.ref.nm
     for e in range(d.n_elem):
         blk = J[e * nb:(e + 1) * nb, e * nb:(e + 1) * nb]
-        assert np.abs(pc.D[e] - blk).max() <= 1e-6 * np.abs(blk).max()
+        assert np.abs(pc.D[e] - blk).max() <= 2e-5 * np.abs(blk).max()
