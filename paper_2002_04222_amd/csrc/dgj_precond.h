@@ -570,6 +570,35 @@ __device__ __forceinline__ double ld_acc<double>(const double* p) { return *p; }
 
 template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { return (double)(*p); }
 
+// 16-byte load of 16/sizeof(T) consecutive entries (p 16-byte aligned),
+// widened to the accumulation type
+template <typename T>
+__device__ __forceinline__ void ld16(const T* p, typename AccT<T>::type* v);
+template <>
+__device__ __forceinline__ void ld16<double>(const double* p, double* v) {
+  const double2 x = *reinterpret_cast<const double2*>(p);
+  v[0] = x.x;
+  v[1] = x.y;
+}
+template <>
+__device__ __forceinline__ void ld16<float>(const float* p, float* v) {
+  const float4 x = *reinterpret_cast<const float4*>(p);
+  v[0] = x.x;
+  v[1] = x.y;
+  v[2] = x.z;
+  v[3] = x.w;
+}
+template <>
+__device__ __forceinline__ void ld16<__hip_bfloat16>(const __hip_bfloat16* p, float* v) {
+  const uint4 x = *reinterpret_cast<const uint4*>(p);
+  const unsigned w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __uint_as_float(w[i] << 16);              // bfloat16 -> float: the high half of the bits
+    v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
 // One BRJ sweep for element e (one workgroup, blockDim >= nb):
 //   r = q - (L+U) qold   (skipped when first),  out = omega Dinv r + (1-omega) qold.
 // (L+U) qold = -dt_a / |J| sum_f -(B^G_f)^T diag(w^G|J^G| Jp (B^G_f' qold_nbr)).
@@ -670,12 +699,48 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
   }
   using A = typename AccT<T>::type;
   const T* De = Dinv + e * (long)NB * NB;
-  for (int row = tid; row < NB; row += NT) {
-    A acc = (A)0;
-    for (int c = 0; c < NB; ++c) acc += ld_acc<T>(De + (long)c * NB + row) * (A)sr[c];
-    double res = omega * (double)acc;
-    if (!first && omega != 1.0) res += (1.0 - omega) * qold[e * NB + row];
-    out[e * NB + row] = res;
+  constexpr int VW = 16 / (int)sizeof(T);                 // rows per 16-byte load
+  if constexpr (NB % VW == 0 && (NB * (int)sizeof(T)) % 16 == 0) {
+    // every thread busy: VW rows by one 16-byte load per column, the
+    // columns split into SEG segments, partial sums added in LDS in a fixed
+    // order
+    constexpr int NR = NB / VW;
+    constexpr int SEG = NT / NR >= 1 ? NT / NR : 1;
+    __shared__ A part[SEG * NB];
+    for (int t = tid; t < SEG * NR; t += NT) {
+      const int rg = t % NR, sg = t / NR;
+      const int c0 = sg * NB / SEG, c1 = (sg + 1) * NB / SEG;
+      A acc[VW];
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc[i] = (A)0;
+#pragma unroll 4
+      for (int c = c0; c < c1; ++c) {
+        A v[VW];
+        ld16<T>(De + (long)c * NB + rg * VW, v);
+        const A x = (A)sr[c];
+#pragma unroll
+        for (int i = 0; i < VW; ++i) acc[i] += v[i] * x;
+      }
+#pragma unroll
+      for (int i = 0; i < VW; ++i) part[sg * NB + rg * VW + i] = acc[i];
+    }
+    __syncthreads();
+    for (int row = tid; row < NB; row += NT) {
+      A acc = (A)0;
+#pragma unroll
+      for (int sg = 0; sg < SEG; ++sg) acc += part[sg * NB + row];
+      double res = omega * (double)acc;
+      if (!first && omega != 1.0) res += (1.0 - omega) * qold[e * NB + row];
+      out[e * NB + row] = res;
+    }
+  } else {
+    for (int row = tid; row < NB; row += NT) {
+      A acc = (A)0;
+      for (int c = 0; c < NB; ++c) acc += ld_acc<T>(De + (long)c * NB + row) * (A)sr[c];
+      double res = omega * (double)acc;
+      if (!first && omega != 1.0) res += (1.0 - omega) * qold[e * NB + row];
+      out[e * NB + row] = res;
+    }
   }
 }
 
