@@ -149,8 +149,8 @@ def measured_traffic(prec):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is designed, not built)"}))
         sys.exit(2)
     import numpy as np
     import torch
