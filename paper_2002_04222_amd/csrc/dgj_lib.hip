@@ -821,11 +821,20 @@ void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& i
   // as the paper's dgetrf/dgetri), then stored in the chosen precision
   if (prec == DGJ_PC_F64) Dm = c->d_Dinv;
   else HIPCHK(hipMalloc(&Dm, blk * sizeof(double)));
-  for (size_t k = 0; k < insts.size(); ++k) {
-    const int i = insts[k];
-    const long e0 = c->inst_e0[i], ne = c->inst_e0[i + 1] - e0;
-    const Phys ph = c->n_inst > 0 ? c->h_phs[i] : c->ph;
-    precond_build_range(c, up, dta[k], e0, ne, ph, Wt, JmW, Dm);
+  try {
+    for (size_t k = 0; k < insts.size(); ++k) {
+      const int i = insts[k];
+      const long e0 = c->inst_e0[i], ne = c->inst_e0[i + 1] - e0;
+      const Phys ph = c->n_inst > 0 ? c->h_phs[i] : c->ph;
+      precond_build_range(c, up, dta[k], e0, ne, ph, Wt, JmW, Dm);
+    }
+  } catch (...) {
+    // the build scratch is released before the error propagates
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(Wt);
+    (void)hipFree(JmW);
+    if (prec != DGJ_PC_F64) (void)hipFree(Dm);
+    throw;
   }
   if (prec == DGJ_PC_F32)
     hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const double*)Dm,
