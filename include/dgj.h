@@ -197,6 +197,10 @@ int dgj_precond_build(dgj_ctx *ctx, const double *u_p, double dt_a);
  * built preconditioner.  out must not alias q. */
 int dgj_precond_apply(dgj_ctx *ctx, const double *q, double *out);
 
+/* Export of the stored inverse mass matrices of a curved mesh (tests):
+ * out[e][m][n] (device, n_elem (P+1)^(2d) values).  DGJ_EINVAL on boxes. */
+int dgj_mass_inverse(dgj_ctx *ctx, double *out);
+
 /* Copy the stored block inverses, converted to FP64, into out
  * [n_elem][nb][nb] with nb = (d+2)(P+1)^d, row-major per element. */
 int dgj_precond_diag_inverse(dgj_ctx *ctx, double *out);

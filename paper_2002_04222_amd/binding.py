@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_last_error": ([vp], C.c_char_p),
         "dgj_project_tgv": ([vp, vp, dp, vp], C.c_int),
         "dgj_residual": ([vp, vp, vp], C.c_int),
+        "dgj_mass_inverse": ([vp, vp], C.c_int),
         "dgj_autotune": ([vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
         "dgj_stage_residual": ([vp, vp, vp, dp, vp], C.c_int),
         "dgj_jfnk_matvec": ([vp, vp, vp, vp, dp, vp, dp, vp], C.c_int),
@@ -326,6 +327,9 @@ class Context:
 
     def precond_apply(self, q, out):
         self._check(self.lib.dgj_precond_apply(self.h, _ptr(q), _ptr(out)))
+
+    def mass_inverse(self, out):
+        self._check(self.lib.dgj_mass_inverse(self.h, _ptr(out)))
 
     def precond_diag_inverse(self, out):
         self._check(self.lib.dgj_precond_diag_inverse(self.h, _ptr(out)))

@@ -1412,6 +1412,16 @@ int dgj_precond_apply(dgj_ctx* c, const double* q, double* out) {
   });
 }
 
+int dgj_mass_inverse(dgj_ctx* c, double* out) {
+  if (!c || !out) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!c->curved) fail(DGJ_EINVAL, "mass_inverse: boxes use 1/|J| (no stored inverse)");
+    HIPCHK(hipMemcpyAsync(out, c->d_Minv, (size_t)c->n_elem * c->NM * c->NM * sizeof(double),
+                          hipMemcpyDeviceToDevice, c->stream));
+    return DGJ_OK;
+  });
+}
+
 int dgj_precond_diag_inverse(dgj_ctx* c, double* out) {
   if (!c || !out) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {

@@ -471,6 +471,7 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
       __syncthreads();
       const T pv = Pan[k * (KB + 1) + t];
       const T pinv = bad ? (T)0 : (T)1 / pv;
+      __syncthreads();   // every wave has read the pivot before the pivot row is scaled in place
       // scale the pivot row
       if (r < kb) {
         T x = Pan[k * (KB + 1) + r];

@@ -523,17 +523,27 @@ __global__ __launch_bounds__(256) void k_res_lift(ResArgs a, TabK<N, Q> tk, cons
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
   const double* g = a.geo + e * K::S::GEO;
+  // where each face's flux is stored: this element's slot (side-1 and
+  // boundary faces, own orientation) or the neighbour's side-1 slot
+  __shared__ long s_src[NF];
+  __shared__ int s_fs[NF], s_mine[NF];
+  if (tid < NF) {
+    const long en = a.nbr[e * NF + tid];
+    const bool mine = (tid & 1) == 1 || en < 0;
+    s_src[tid] = mine ? e : en;
+    s_fs[tid] = mine ? tid : (tid ^ 1);
+    s_mine[tid] = mine;
+  }
+  __syncthreads();
   // face data in the element's own orientation and scaling
+#pragma unroll 4
   for (int it = tid; it < NF * (D + 1) * NV * NQF; it += NT) {
     const int p = it % NQF;
     const int v = (it / NQF) % NV;
     const int k = (it / (NQF * NV)) % (D + 1);
     const int f = it / (NQF * NV * (D + 1));
-    const long en = a.nbr[e * NF + f];
-    const bool mine = (f & 1) == 1 || en < 0;   // flux stored in this element's orientation
-    const long src = mine ? e : en;
-    const int fs = mine ? f : (f ^ 1);
-    const double* Xs = X + src * (long)K::XF + (fs * (D + 1) * NV + v) * NQF + p;
+    const bool mine = s_mine[f];
+    const double* Xs = X + s_src[f] * (long)K::XF + (s_fs[f] * (D + 1) * NV + v) * NQF + p;
     // k = 0: -Hhat_own (the neighbour's flux has the opposite orientation);
     // k >= 1: sum_j (d xi_{k-1} / d x_j) Shat_j
     if (k == 0) {

@@ -1,0 +1,75 @@
+"""Error behaviour of the C ABI: invalid meshes and options are rejected with
+the documented status before any device work, calls that need a built
+preconditioner say so, and a failed call leaves the context usable."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+from tests.gpu_util import setup
+
+EINVAL, EUNSUPPORTED = -1, -7
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _raises(code, fn):
+    from paper_2002_04222_amd import DgjError
+    with pytest.raises(DgjError) as ei:
+        fn()
+    assert ei.value.code == code, ei.value
+
+
+def test_create_rejects_bad_meshes_and_options():
+    _case("create errors")
+    from paper_2002_04222_amd import Context
+    cfg, mesh, _ = setup(2, (3, 3), 2)
+    empty = dataclasses.replace(mesh, elem_origin=mesh.elem_origin[:0], elem_h=mesh.elem_h[:0],
+                                face_nbr=mesh.face_nbr[:0])
+    _raises(EINVAL, lambda: Context(empty, cfg))                                  # no elements
+    bad_h = dataclasses.replace(mesh, elem_h=-mesh.elem_h)
+    _raises(EINVAL, lambda: Context(bad_h, cfg))                                  # negative sizes
+    bad_nbr = dataclasses.replace(mesh, face_nbr=np.where(mesh.face_nbr == 0, 99, mesh.face_nbr).astype(np.int32))
+    _raises(EINVAL, lambda: Context(bad_nbr, cfg))                                # neighbour out of range
+    cfg3, mesh3, _ = setup(3, (2, 2, 2), 2)
+    _raises(EUNSUPPORTED, lambda: Context(mesh3, dataclasses.replace(cfg3, P=5, nq=7)))   # 3D P = 5 not built
+    _raises(EUNSUPPORTED, lambda: Context(mesh, dataclasses.replace(cfg, nq=cfg.P + 3)))  # nq != P + 2
+    _raises(EINVAL, lambda: Context(mesh, cfg, gmres_restart=61))
+    _raises(EINVAL, lambda: Context(mesh, cfg, gmres_restart=0))
+    _raises(EINVAL, lambda: Context(mesh, cfg, flux_mode=3))
+
+
+def test_calls_needing_state_fail_cleanly_and_context_stays_usable():
+    _case("call errors")
+    from paper_2002_04222_amd import Context
+    cfg, mesh, _ = setup(2, (3, 3), 2)
+    ctx = Context(mesh, cfg)
+    u = torch.tensor(W.random_state(mesh.n_elem, 2, 2, seed=3), dtype=torch.float64, device="cuda")
+    out = ctx.empty()
+    _raises(EINVAL, lambda: ctx.precond_diag_inverse(torch.empty(1, dtype=torch.float64, device="cuda")))
+    _raises(EINVAL, lambda: ctx.precond_build(torch.zeros_like(u), 0.1))          # chi = 0: zero state
+    R1, R2 = ctx.empty(), ctx.empty()
+    ctx.residual(u, R1)
+    ctx.precond_build(u, 0.1)
+    ctx.precond_apply(R1, out)
+    ctx.residual(u, R2)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2)
+    assert torch.isfinite(out).all()
+
+
+def test_batch_rejects_boundaries_and_curved_instances():
+    _case("batch errors")
+    from paper_2002_04222_amd import Batch
+    cfgs = W.batch_configs(n=2, seed=9, nmin=3, nmax=4)
+    ann = dataclasses.replace(W.config(4), dim=2, ncells=(2, 6), lengths=(1.0, 2 * np.pi), P=2, nq=4, r1=3.0)
+    _raises(EUNSUPPORTED, lambda: Batch([cfgs[0], ann]))
