@@ -29,9 +29,16 @@
     initial residual is already at rounding level.
   * SDIRK (Eq. 17-20): S_m = u^n + sum_{i<m} a^mi E^i; after the stage solve
     E^m = (u^m - S_m) / a^mm (equal to dt M^-1 L(u^m) at convergence);
-    u^{n+1} = u^n + sum b^i E^i.  The preconditioner is built at u^n of the
-    step where it is (re)built and kept for pc_freeze steps or until
-    dt a^mm changes.
+    u^{n+1} = u^n + sum b^i E^i.  A stage with a^mm = 0 (the first stage of
+    the six-stage SDIRK4, every stage of ERK2) is explicit: u^m = S_m and
+    E^m = dt M^-1 L(S_m).  The preconditioner is built at u^n of the step
+    where it is (re)built and kept for pc_freeze steps or until dt a^mm
+    changes.
+  * BDF2 (Sec. 4.3 lists it among the implicit integrators; the paper gives
+    no formula, the constant-step form is used): u^{n+1} - (4/3) u^n
+    + (1/3) u^{n-1} = (2/3) dt M^-1 L(u^{n+1}), i.e. Eq. 20 with
+    S = (4 u^n - u^{n-1}) / 3 and dt a = 2 dt / 3; the first step, and a
+    step whose dt differs from the previous one's, is a backward-Euler step.
 """
 from __future__ import annotations
 
@@ -342,25 +349,41 @@ class SDIRK:
         if self.pc is None or self.pc_age >= self.opts.pc_freeze or self.pc_dta != dt_a:
             self.build_pc(u_n, dt_a)
 
+    def first_implicit(self):
+        d = np.diag(self.A)
+        nz = [m for m in range(len(d)) if d[m] != 0.0]
+        return nz[0] if nz else None
+
+    def solve_stage(self, S, dt_a, guess=None):
+        """Newton solve of one implicit stage with the refresh rules."""
+        refresh = self.opts.use_pc and self.opts.pc_refresh_its > 0
+        if refresh and self.last_gmres_max > self.opts.pc_refresh_its:
+            self.build_pc(S, dt_a)
+        u_m, st = newton_solve(self.disc, S, dt_a, self.pc, self.opts, guess=guess)
+        if not st.converged and refresh:
+            self.build_pc(S, dt_a)
+            u_m, st = newton_solve(self.disc, S, dt_a, self.pc, self.opts)
+        self.last_gmres_max = max(st.gmres_its) if st.gmres_its else 0
+        return u_m, st
+
     def step(self, u_n, dt, guesses=None):
         A, b = self.A, self.b
         s = A.shape[0]
         Es = []
         stats = []
+        m0 = self.first_implicit()
+        if m0 is not None:
+            self.ensure_pc(u_n, dt * A[m0, m0])
         for m in range(s):
             S = u_n + sum(A[m, i] * Es[i] for i in range(m)) if m > 0 else u_n.copy()
+            if A[m, m] == 0.0:
+                # explicit stage: the stage value is S_m itself
+                Es.append(dt * self.disc.residual(S))
+                stats.append(StageStats())
+                continue
             dt_a = dt * A[m, m]
-            if m == 0:
-                self.ensure_pc(u_n, dt_a)
-            refresh = self.opts.use_pc and self.opts.pc_refresh_its > 0
-            if refresh and self.last_gmres_max > self.opts.pc_refresh_its:
-                self.build_pc(S, dt_a)
             g = None if guesses is None else guesses[m]
-            u_m, st = newton_solve(self.disc, S, dt_a, self.pc, self.opts, guess=g)
-            if not st.converged and refresh:
-                self.build_pc(S, dt_a)
-                u_m, st = newton_solve(self.disc, S, dt_a, self.pc, self.opts)
-            self.last_gmres_max = max(st.gmres_its) if st.gmres_its else 0
+            u_m, st = self.solve_stage(S, dt_a, g)
             stats.append(st)
             if not st.converged:
                 raise NotConverged(f"stage {m}: Newton did not converge: {st.nres}")
@@ -368,3 +391,35 @@ class SDIRK:
         self.pc_age += 1
         u_new = u_n + sum(b[i] * Es[i] for i in range(s))
         return u_new, stats
+
+
+class BDF2(SDIRK):
+    """Constant-step BDF2 with a backward-Euler start (see the module notes);
+    the preconditioner and its refresh rules are those of the RK steppers."""
+
+    def __init__(self, disc, opts: SolverOpts):
+        super().__init__(disc, dataclasses.replace(opts, scheme="beuler"))
+        self.u_prev = None
+        self.dt_prev = None
+
+    def step(self, u_n, dt, guesses=None):
+        if self.u_prev is None or self.dt_prev != dt:
+            S, dt_a = u_n.copy(), dt
+        else:
+            S, dt_a = (4.0 * u_n - self.u_prev) / 3.0, 2.0 * dt / 3.0
+        self.ensure_pc(u_n, dt_a)
+        g = None if guesses is None else guesses[0]
+        u_new, st = self.solve_stage(S, dt_a, g)
+        if not st.converged:
+            raise NotConverged(f"BDF2: Newton did not converge: {st.nres}")
+        self.u_prev, self.dt_prev = u_n.copy(), dt
+        self.pc_age += 1
+        return u_new, [st]
+
+
+def make_stepper(disc, opts: SolverOpts):
+    """The time stepper named by opts.scheme: sdirk2, sdirk3, sdirk4, beuler,
+    erk2 (Runge-Kutta tableaus) or bdf2."""
+    if opts.scheme == "bdf2":
+        return BDF2(disc, opts)
+    return SDIRK(disc, opts)

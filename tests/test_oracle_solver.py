@@ -28,24 +28,62 @@ def _golden_rows(name):
 
 
 # ---------------------------------------------------------------- tableaus
-@pytest.mark.parametrize("name,order", [("sdirk2", 2), ("sdirk3", 3), ("erk2", 2)])
+@pytest.mark.parametrize("name,order", [("sdirk2", 2), ("sdirk3", 3), ("sdirk4", 4), ("beuler", 1), ("erk2", 2)])
 def test_butcher_order_conditions(name, order):
     A, b, c = tableau(name)
     assert abs(b.sum() - 1) < 1e-15
-    assert abs(b @ c - 1 / 2) < 1e-15
+    if order >= 2:
+        assert abs(b @ c - 1 / 2) < 1e-15
     if order >= 3:
         assert abs(b @ c ** 2 - 1 / 3) < 1e-15
         assert abs(b @ (A @ c) - 1 / 6) < 1e-15
-    # row sums are the abscissae; SDIRK tableaus are stiffly accurate
+    if order >= 4:
+        assert abs(b @ c ** 3 - 1 / 4) < 1e-15
+        assert abs(b @ (c * (A @ c)) - 1 / 8) < 1e-15
+        assert abs(b @ (A @ c ** 2) - 1 / 12) < 1e-15
+        assert abs(b @ (A @ (A @ c)) - 1 / 24) < 1e-15
+    # row sums are the abscissae; the implicit tableaus are stiffly accurate
+    # with a single nonzero diagonal value
     assert np.allclose(A.sum(1), c)
-    if name.startswith("sdirk"):
-        assert np.allclose(A[-1], b) and np.allclose(np.diag(A), A[0, 0])
+    if name != "erk2":
+        d = np.diag(A)
+        assert np.allclose(A[-1], b) and np.allclose(d[d != 0], d[-1])
+        # L-stable: the stability function R(z) = 1 + z b (I - z A)^-1 1 vanishes at infinity
+        for z in (-1e6, -1e8):
+            R = 1 + z * b @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b)))
+            assert abs(R) < 1e2 / abs(z)
+    else:
+        assert np.all(np.triu(A) == 0)
 
 
 def test_printed_sdirk3_lambda():
-    lam = float(dict(_golden_rows("butcher_printed.txt"))["sdirk3_lambda"])
+    lam = float(dict(r for r in _golden_rows("butcher_printed.txt") if len(r) == 2)["sdirk3_lambda"])
     assert abs(sdirk3_lambda() - lam) < 5e-11
     assert abs(round(sdirk3_lambda(), 10) - lam) < 1e-15
+
+
+def test_printed_sdirk4_entries():
+    """The six-stage SDIRK4 equals the printed entries a^{mk}, k >= 1; its
+    first column repeats the second and its abscissae are the row sums, which
+    agree with the printed ones except c_2 (printed (2 - sqrt 2)/2, here
+    (2 - sqrt 2)/4, the reading under which the order conditions hold)."""
+    A, b, c = tableau("sdirk4")
+    r2 = math.sqrt(2.0)
+    rows = [r for r in _golden_rows("butcher_printed.txt") if len(r) == 7]
+    seen = set()
+    for kind, m, k, f, p, q, r in rows:
+        m, k = int(m), int(k)
+        v = float(f) * (float(p) + float(q) * r2) / float(r)
+        if kind == "a":
+            assert abs(A[m, k] - v) < 1e-15, (m, k)
+            seen.add((m, k))
+        elif m == 2:
+            assert abs(v - (2 - r2) / 2) < 1e-15 and abs(c[2] - (2 - r2) / 4) < 1e-15
+        else:
+            assert abs(c[m] - v) < 1e-14, m
+    assert len(seen) == 15                              # every printed entry below and on the diagonal
+    assert np.array_equal(A[1:, 0], A[1:, 1]) and A[0, 0] == 0.0
+    assert np.all(np.triu(A, 1) == 0)
 
 
 def test_brj_memory_table():
@@ -255,10 +293,12 @@ def test_newton_jfnk_matches_dense_newton():
     assert np.abs(u1 - u2).max() <= 1e-9 * np.abs(u2).max()
 
 
-@pytest.mark.parametrize("scheme,order", [("sdirk2", 2), ("sdirk3", 3)])
+@pytest.mark.parametrize("scheme,order", [("sdirk2", 2), ("sdirk3", 3), ("sdirk4", 4), ("beuler", 1),
+                                          ("bdf2", 2), ("erk2", 2)])
 def test_sdirk_temporal_order_linear(scheme, order):
     """P13 on a linear problem: the scalar-diffusion test operator makes
-    M du/dt = L u linear, so u(T) = expm(T M^-1 dL/du) u0 exactly."""
+    M du/dt = L u linear, so u(T) = expm(T M^-1 dL/du) u0 exactly; each
+    stepper converges at its order."""
     d = tiny_disc(dim=2, cells=(2, 2), P=2, lengths=(2 * np.pi, 2 * np.pi), Re=2.0, flux_mode=2)
     n = int(np.prod(d.shape))
     K = np.zeros((n, n))
@@ -270,10 +310,11 @@ def test_sdirk_temporal_order_linear(scheme, order):
     T = 0.4
     ref = (scipy.linalg.expm(T * K) @ u0.ravel()).reshape(u0.shape)
     errs = []
-    for nsteps in (4, 8, 16):
+    # BDF2's backward-Euler start leaves the asymptotic range at 4 steps
+    for nsteps in ((8, 16, 32) if scheme == "bdf2" else (4, 8, 16)):
         opts = S.SolverOpts(scheme=scheme, newton_rtol=1e-13, gmres_rtol=1e-12, gmres_restart=200,
                             gmres_max=2000, pc_freeze=1000)
-        st = S.SDIRK(d, opts)
+        st = S.make_stepper(d, opts)
         u = u0.copy()
         for _ in range(nsteps):
             u, _ = st.step(u, T / nsteps)
@@ -302,3 +343,25 @@ def test_sdirk_preconditioner_refresh_rule():
     assert len(builds) >= 2                           # the step's own build plus refreshes
     assert all(x.converged for x in sb)
     assert np.linalg.norm(ub - ua) <= 1e-6 * np.linalg.norm(ua)
+
+
+def test_erk2_step_is_second_order_taylor_polynomial():
+    """On a linear problem one ERK2 step multiplies by the stability
+    polynomial of every two-stage second-order explicit method,
+    I + dt K + (dt K)^2 / 2; the step builds no preconditioner and runs no
+    Newton iteration."""
+    d = tiny_disc(dim=2, cells=(2, 2), P=2, lengths=(2 * np.pi, 2 * np.pi), Re=2.0, flux_mode=2)
+    n = int(np.prod(d.shape))
+    K = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        K[:, i] = d.residual(e.reshape(d.shape)).ravel()
+    u0 = W.random_state(d.n_elem, 2, 2, seed=52, decay=0.3)
+    dt = 0.05
+    st = S.make_stepper(d, S.SolverOpts(scheme="erk2"))
+    u1, stats = st.step(u0, dt)
+    Kd = dt * K
+    ref = (u0.ravel() + Kd @ u0.ravel() + 0.5 * Kd @ (Kd @ u0.ravel())).reshape(u0.shape)
+    assert np.abs(u1 - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert st.pc is None and all(x.newton_its == 0 for x in stats)
