@@ -51,7 +51,12 @@ enum {
   DGJ_EUNSUPPORTED = -7  /* combination of sizes or options not built */
 };
 
-enum { DGJ_SDIRK2 = 2, DGJ_SDIRK3 = 3 };
+/* Time integrators (Sec. 4.3, Appendix A).  SDIRK4 is the six-stage table with
+ * an explicit first stage, its first column equal to the second and its
+ * abscissae the row sums; BDF2 is the constant-step form with a
+ * backward-Euler start; ERK2 is explicit (no preconditioner, no Newton). */
+enum { DGJ_BEULER = 1, DGJ_SDIRK2 = 2, DGJ_SDIRK3 = 3, DGJ_SDIRK4 = 4, DGJ_BDF2 = 12, DGJ_ERK2 = 20 };
+#define DGJ_MAX_STAGES 6
 enum { DGJ_PC_F64 = 0, DGJ_PC_F32 = 1, DGJ_PC_BF16 = 2 };
 
 typedef struct dgj_ctx dgj_ctx;
@@ -113,7 +118,8 @@ typedef struct {
 
 /* Implicit solver options (Sec. 3.2, Sec. 4.2.2). */
 typedef struct {
-  int32_t scheme;             /* DGJ_SDIRK2 or DGJ_SDIRK3 (Appendix A) */
+  int32_t scheme;             /* DGJ_SDIRK2, DGJ_SDIRK3, DGJ_SDIRK4, DGJ_BEULER, DGJ_BDF2 or
+                                 DGJ_ERK2 (batches: SDIRK2 and SDIRK3 only) */
   double newton_rtol;         /* alpha of Eq. 23 */
   int32_t newton_max;
   int32_t gmres_restart;      /* 30 in the paper; 1..60 */
@@ -133,16 +139,17 @@ typedef struct {
 /* Per-step statistics filled by dgj_sdirk_step. */
 typedef struct {
   int32_t stages;
-  int32_t newton_its[4];
-  int32_t gmres_its[4][64];   /* per stage, per Newton iteration */
-  double nres[4][65];         /* ||N|| per stage before each Newton iteration and at exit */
+  int32_t newton_its[DGJ_MAX_STAGES];      /* 0 for an explicit stage */
+  int32_t gmres_its[DGJ_MAX_STAGES][64];   /* per stage, per Newton iteration */
+  double nres[DGJ_MAX_STAGES][65];         /* ||N|| per stage before each Newton iteration and at exit */
   int32_t pc_built;           /* 1 if this step (re)built the preconditioner */
   int32_t residual_evals;     /* residual evaluations in the step */
   int32_t status;
   double t_total_ms;          /* host wall time of the step */
   double t_pc_build_ms;       /* of which preconditioner build */
-  int32_t guess_used[4];      /* per stage: 0 S_m, 1 extrapolated, 2 learned */
-  double guess_norm[4][3];    /* ||N|| of the S_m, extrapolated and learned guesses (0 if not evaluated) */
+  int32_t guess_used[DGJ_MAX_STAGES];      /* per stage: 0 S_m, 1 extrapolated, 2 learned */
+  double guess_norm[DGJ_MAX_STAGES][3];    /* ||N|| of the S_m, extrapolated and learned guesses
+                                              (0 if not evaluated) */
 } dgj_step_stats;
 
 /* Create a context on the current device; hip_stream may be NULL (default
@@ -218,13 +225,25 @@ int dgj_gmres(dgj_ctx *ctx, const double *u, const double *N_u, const double *S,
  * if any. */
 int dgj_newton(dgj_ctx *ctx, const double *S, double dt_a, double *u, int32_t *newton_its, int32_t *gmres_its);
 
-/* One SDIRK step of size dt on u (in/out) (Eq. 17-23).  (Re)builds the
- * preconditioner at the incoming u when none is held, when it is
+/* One time step of size dt on u (in/out) with the context's scheme
+ * (Eq. 17-23).  Runge-Kutta: S_m = u^n + sum_{i<m} a^mi E^i; an implicit
+ * stage solves N(u^m) = 0 by Newton and sets E^m = (u^m - S_m)/a^mm, an
+ * explicit stage (a^mm = 0) sets E^m = dt M^-1 L(S_m); u^{n+1} = u^n +
+ * sum b^i E^i.  BDF2: one solve with S = (4 u^n - u^{n-1})/3 and dt a =
+ * 2 dt/3, where u^{n-1} is the incoming u of the previous call; the first
+ * call after create or dgj_reset_history, and a call whose dt differs
+ * (exactly) from the previous call's, is a backward-Euler step.  (Re)builds
+ * the preconditioner at the incoming u when none is held, when it is
  * pc_freeze steps old, or when dt a^mm changed, and at a stage's S_m under
- * the pc_refresh_its rules.  stats may be NULL (the stats of a retried
- * stage are the retry's).  On DGJ_ENOTCONV / DGJ_ENAN u is left unchanged
- * and stats tell where. */
+ * the pc_refresh_its rules (ERK2 builds none).  stats may be NULL (the
+ * stats of a retried stage are the retry's).  On DGJ_ENOTCONV / DGJ_ENAN u
+ * is left unchanged and stats tell where. */
 int dgj_sdirk_step(dgj_ctx *ctx, double *u, double dt, dgj_step_stats *stats);
+
+/* Forget the step history: BDF2's previous state and the stage increments
+ * the Newton guesses extrapolate from.  For callers that change u between
+ * steps (a restart, a new initial condition). */
+int dgj_reset_history(dgj_ctx *ctx);
 
 /* ---- Newton initial guess (not in the paper, which starts from S_m,
  * Eq. 21).  With inc_n = u^m - S_m the converged increment of stage m at
@@ -271,7 +290,7 @@ int dgj_mlp_targets(dgj_ctx *ctx, const double *inc, const double *inc_prev, flo
 int dgj_mlp_fit(dgj_ctx *ctx, const double *S_rec, const double *inc_rec, int32_t n_steps, int32_t epochs, double lr,
                 double *last_loss);
 /* Copy the stored stage increments of the two previous steps out
- * ([2][3][n_unknowns], may be NULL) and/or in (may be NULL), to restart a
+ * ([2][stages][n_unknowns], stages of the context's scheme; may be NULL) and/or in (may be NULL), to restart a
  * run from a saved point. */
 int dgj_guess_state(dgj_ctx *ctx, double *inc_out, const double *inc_in);
 /* Y[rows][n_out] = MLP(X[rows][n_in]) */

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libdgj.so")
 
 DGJ_OK = 0
-DGJ_SDIRK2, DGJ_SDIRK3 = 2, 3
+DGJ_BEULER, DGJ_SDIRK2, DGJ_SDIRK3, DGJ_SDIRK4, DGJ_BDF2, DGJ_ERK2 = 1, 2, 3, 4, 12, 20
+MAX_STAGES = 6
 DGJ_PC_F64, DGJ_PC_F32, DGJ_PC_BF16 = 0, 1, 2
 DGJ_BC_FARFIELD, DGJ_BC_WALL = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOTCONV", -5: "ENAN", -6: "ESINGULAR",
@@ -47,10 +48,11 @@ class Solver(C.Structure):
 
 
 class StepStats(C.Structure):
-    _fields_ = [("stages", C.c_int32), ("newton_its", C.c_int32 * 4), ("gmres_its", (C.c_int32 * 64) * 4),
-                ("nres", (C.c_double * 65) * 4), ("pc_built", C.c_int32), ("residual_evals", C.c_int32),
-                ("status", C.c_int32), ("t_total_ms", C.c_double), ("t_pc_build_ms", C.c_double),
-                ("guess_used", C.c_int32 * 4), ("guess_norm", (C.c_double * 3) * 4)]
+    _fields_ = [("stages", C.c_int32), ("newton_its", C.c_int32 * MAX_STAGES),
+                ("gmres_its", (C.c_int32 * 64) * MAX_STAGES), ("nres", (C.c_double * 65) * MAX_STAGES),
+                ("pc_built", C.c_int32), ("residual_evals", C.c_int32), ("status", C.c_int32),
+                ("t_total_ms", C.c_double), ("t_pc_build_ms", C.c_double), ("guess_used", C.c_int32 * MAX_STAGES),
+                ("guess_norm", (C.c_double * 3) * MAX_STAGES)]
 
     def to_dict(self):
         s = self.stages
@@ -95,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_newton": ([vp, vp, dp, vp, i32p, i32p], C.c_int),
         "dgj_sdirk_step": ([vp, vp, dp, C.POINTER(StepStats)], C.c_int),
         "dgj_set_guess": ([vp, C.c_int32], C.c_int),
+        "dgj_reset_history": ([vp], C.c_int),
         "dgj_set_record": ([vp, vp, vp], C.c_int),
         "dgj_mlp_create": ([vp, C.c_int32, vp], C.c_int),
         "dgj_mlp_sizes": ([vp, i64p, i32p, i32p], C.c_int),
@@ -139,7 +142,8 @@ def _fptr(t) -> Optional[int]:
     return _ptr(t, "torch.float32")
 
 
-SCHEMES = {"sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3}
+SCHEMES = {"beuler": DGJ_BEULER, "sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3, "sdirk4": DGJ_SDIRK4,
+           "bdf2": DGJ_BDF2, "erk2": DGJ_ERK2}
 PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
 
 
@@ -352,6 +356,9 @@ class Context:
         if rc != DGJ_OK:
             raise DgjError(rc, self.lib.dgj_last_error(self.h).decode())
         return st.to_dict()
+
+    def reset_history(self):
+        self._check(self.lib.dgj_reset_history(self.h))
 
     # ---- Newton initial guess and the learned predictor
     GUESS = {"paper": 0, "extrapolated": 1, "learned": 2}

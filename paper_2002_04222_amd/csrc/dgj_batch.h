@@ -468,6 +468,8 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
     std::vector<std::array<int, 3>> keys;
     b->grp.assign(n, -1);
     b->loc.assign(n, -1);
+    if (solver->scheme != DGJ_SDIRK2 && solver->scheme != DGJ_SDIRK3)
+      throw Status{DGJ_EUNSUPPORTED, "batch: scheme must be SDIRK2 or SDIRK3"};
     for (int i = 0; i < n; ++i) {
       if (meshes[i].geo_nodes || !meshes[i].elem_h || !meshes[i].elem_origin || !meshes[i].face_nbr)
         throw Status{DGJ_EUNSUPPORTED, "batch: instances must be periodic meshes of affine boxes"};
@@ -670,7 +672,7 @@ int dgj_batch_sdirk_step(dgj_batch* b, double* u, const double* dt, int32_t* new
   for (int i = 0; i < b->n; ++i)
     if (!(dt[i] > 0.0)) return DGJ_EINVAL;
   return batch_guard(b, [&]() -> int {
-    double A[3][3], bb[3];
+    double A[DGJ_MAX_STAGES][DGJ_MAX_STAGES], bb[DGJ_MAX_STAGES];
     int s = 0;
     tableau(b->sv.scheme, A, bb, s);
     const int G = (int)b->g.size();

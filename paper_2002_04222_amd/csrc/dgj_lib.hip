@@ -393,7 +393,7 @@ struct dgj_ctx {
   std::vector<double*> V;      // restart+1 Krylov vectors
   double *d_z = nullptr, *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr;
   double *d_ubar = nullptr, *d_N = nullptr, *d_S = nullptr, *d_b = nullptr, *d_x = nullptr, *d_un = nullptr;
-  double* d_E[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* d_E[DGJ_MAX_STAGES] = {};   // stage derivatives (the scheme's stage count allocated)
   double *d_pa = nullptr, *d_pb = nullptr;   // BRJ ping-pong
   // preconditioner
   bool pc_ready = false;
@@ -423,8 +423,12 @@ struct dgj_ctx {
   double* d_part2 = nullptr;       // per instance reduction partials [n_inst][RED_BLOCKS]
   int* d_kused = nullptr;          // per instance Krylov vectors in use
   int have_inc = 0;                // number of previous steps whose increments are held (0, 1, 2)
-  double* d_inc[3] = {nullptr, nullptr, nullptr};   // previous step's stage increments
-  double* d_inc2[3] = {nullptr, nullptr, nullptr};  // the step before
+  double* d_inc[DGJ_MAX_STAGES] = {};    // previous step's stage increments
+  double* d_inc2[DGJ_MAX_STAGES] = {};   // the step before
+  int n_stages = 0;                // stages of the scheme
+  double* d_uprev = nullptr;       // BDF2: u^{n-1}
+  bool have_prev = false;          // BDF2: d_uprev holds the previous step's u^n
+  double dt_prev = 0.0;            // BDF2: that step's dt
   double* d_g2 = nullptr;          // candidate guess
   double* rec_S = nullptr;         // optional caller buffers [stages][n]
   double* rec_inc = nullptr;
@@ -1081,9 +1085,38 @@ NewtonOut newton(dgj_ctx* c, const double* S, double dt_a, double* u, double tau
   return o;
 }
 
-void tableau(int scheme, double A[3][3], double b[3], int& s) {
-  std::memset(A, 0, sizeof(double) * 9);
-  if (scheme == DGJ_SDIRK2) {
+// Runge-Kutta tables of Appendix A and backward Euler; BDF2 reports the
+// backward-Euler table (one implicit stage), which its first step uses.
+void tableau(int scheme, double A[DGJ_MAX_STAGES][DGJ_MAX_STAGES], double b[DGJ_MAX_STAGES], int& s) {
+  std::memset(A, 0, sizeof(double) * DGJ_MAX_STAGES * DGJ_MAX_STAGES);
+  std::memset(b, 0, sizeof(double) * DGJ_MAX_STAGES);
+  if (scheme == DGJ_BEULER || scheme == DGJ_BDF2) {
+    s = 1;
+    A[0][0] = 1.0;
+  } else if (scheme == DGJ_ERK2) {
+    s = 2;
+    A[1][0] = 1.0;
+    b[0] = b[1] = 0.5;
+    return;
+  } else if (scheme == DGJ_SDIRK4) {
+    // six stages, explicit first stage, diagonal 1/4; the first column
+    // repeats the second so that the abscissae are the row sums and the
+    // fourth-order conditions hold
+    const double q = std::sqrt(2.0);
+    s = 6;
+    for (int m = 1; m < 6; ++m) A[m][m] = 0.25;
+    A[2][1] = (1.0 - q) / 8.0;
+    A[3][1] = (5.0 - 7.0 * q) / 64.0;
+    A[3][2] = 7.0 * (1.0 + q) / 32.0;
+    A[4][1] = (-13796.0 - 54539.0 * q) / 125000.0;
+    A[4][2] = (506605.0 + 132109.0 * q) / 437500.0;
+    A[4][3] = 166.0 * (-97.0 + 376.0 * q) / 109375.0;
+    A[5][1] = (1181.0 - 987.0 * q) / 13782.0;
+    A[5][2] = 47.0 * (-267.0 + 1783.0 * q) / 273343.0;
+    A[5][3] = -16.0 * (-22922.0 + 3525.0 * q) / 571953.0;
+    A[5][4] = -15625.0 * (97.0 + 376.0 * q) / 90749876.0;
+    for (int m = 1; m < 6; ++m) A[m][0] = A[m][1];
+  } else if (scheme == DGJ_SDIRK2) {
     const double lam = 1.0 - std::sqrt(2.0) / 2.0;
     s = 2;
     A[0][0] = lam;
@@ -1110,6 +1143,11 @@ void tableau(int scheme, double A[3][3], double b[3], int& s) {
   for (int i = 0; i < s; ++i) b[i] = A[s - 1][i];
 }
 
+bool scheme_known(int scheme) {
+  return scheme == DGJ_BEULER || scheme == DGJ_SDIRK2 || scheme == DGJ_SDIRK3 || scheme == DGJ_SDIRK4 ||
+         scheme == DGJ_BDF2 || scheme == DGJ_ERK2;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -1130,7 +1168,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       fail(DGJ_EUNSUPPORTED, "dim %d, P %d, nq %d not built (nq = P+2, P <= %d)", mesh->dim, mesh->P, mesh->nq,
            mesh->dim == 2 ? 5 : 4);
     if (solver->gmres_restart < 1 || solver->gmres_restart > 60) fail(DGJ_EINVAL, "gmres_restart must be in 1..60");
-    if (solver->scheme != DGJ_SDIRK2 && solver->scheme != DGJ_SDIRK3) fail(DGJ_EINVAL, "scheme must be SDIRK2 or SDIRK3");
+    if (!scheme_known(solver->scheme)) fail(DGJ_EINVAL, "unknown scheme %d", solver->scheme);
     if (solver->pc_precision < 0 || solver->pc_precision > 2) fail(DGJ_EINVAL, "bad pc_precision");
     if (phys->flux_mode < 0 || phys->flux_mode > 2 || phys->riemann < 0 || phys->riemann > 1)
       fail(DGJ_EINVAL, "bad flux options");
@@ -1264,9 +1302,21 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     c->V.assign(c->sv.gmres_restart + 1, nullptr);
     for (auto& p : c->V) HIPCHK(hipMalloc(&p, vb));
     double** bufs[] = {&c->d_z, &c->d_w, &c->d_t1, &c->d_t2, &c->d_ubar, &c->d_N, &c->d_S, &c->d_b, &c->d_x,
-                       &c->d_un, &c->d_E[0], &c->d_E[1], &c->d_E[2], &c->d_pa, &c->d_pb, &c->d_inc[0],
-                       &c->d_inc[1], &c->d_inc[2], &c->d_inc2[0], &c->d_inc2[1], &c->d_inc2[2], &c->d_g2};
+                       &c->d_un, &c->d_pa, &c->d_pb, &c->d_g2};
     for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
+    {
+      double At[DGJ_MAX_STAGES][DGJ_MAX_STAGES], bt[DGJ_MAX_STAGES];
+      tableau(c->sv.scheme, At, bt, c->n_stages);
+    }
+    for (int m = 0; m < c->n_stages; ++m) {
+      HIPCHK(hipMalloc(&c->d_E[m], vb));
+      HIPCHK(hipMalloc(&c->d_inc[m], vb));
+      HIPCHK(hipMalloc(&c->d_inc2[m], vb));
+      // explicit stages never write their increments
+      HIPCHK(hipMemsetAsync(c->d_inc[m], 0, vb, c->stream));
+      HIPCHK(hipMemsetAsync(c->d_inc2[m], 0, vb, c->stream));
+    }
+    if (c->sv.scheme == DGJ_BDF2) HIPCHK(hipMalloc(&c->d_uprev, vb));
     if (curved) {
       // dense mass matrices and their inverses (Gauss-Jordan on the device)
       const size_t mm = (size_t)E * c->NM * c->NM;
@@ -1308,12 +1358,15 @@ void dgj_destroy(dgj_ctx* c) {
   else hipDeviceSynchronize();
   free_pc(c);
   mlp_free(c->mlp);
-  double* ptrs[] = {c->d_vg, c->d_fg, c->d_M, c->d_Minv, c->d_Mq, c->d_trace, c->d_X, c->d_Lvol, c->d_geo, c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
-                    c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_E[0], c->d_E[1],
-                    c->d_E[2], c->d_E[3], c->d_pa, c->d_pb, c->d_inc[0], c->d_inc[1], c->d_inc[2],
-                    c->d_inc2[0], c->d_inc2[1], c->d_inc2[2], c->d_g2};
+  double* ptrs[] = {c->d_vg, c->d_fg, c->d_M, c->d_Minv, c->d_Mq, c->d_trace, c->d_X, c->d_Lvol, c->d_geo,
+                    c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
+                    c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_pa, c->d_pb,
+                    c->d_g2, c->d_uprev};
   for (double* p : ptrs)
     if (p) hipFree(p);
+  for (int m = 0; m < DGJ_MAX_STAGES; ++m)
+    for (double* p : {c->d_E[m], c->d_inc[m], c->d_inc2[m]})
+      if (p) hipFree(p);
   if (c->d_nbr) hipFree(c->d_nbr);
   if (c->d_bc_kind) hipFree(c->d_bc_kind);
   if (c->d_bc_state) hipFree(c->d_bc_state);
@@ -1476,12 +1529,18 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
   auto t0 = clk::now();
   c->residual_evals = 0;
   int rc = guarded(c, [&]() -> int {
-    double A[3][3], b[3];
+    double A[DGJ_MAX_STAGES][DGJ_MAX_STAGES], b[DGJ_MAX_STAGES];
     int s = 0;
     tableau(c->sv.scheme, A, b, s);
     st->stages = s;
-    const double dt_a = dt * A[0][0];
-    if (!c->pc_ready || c->pc_age >= c->sv.pc_freeze || std::fabs(c->pc_dta - dt_a) > 1e-12 * std::fabs(dt_a)) {
+    // BDF2 with a history of the same dt; otherwise its step is backward Euler
+    const bool bdf2 = c->sv.scheme == DGJ_BDF2 && c->have_prev && c->dt_prev == dt;
+    // dt a^mm of the implicit stages (one value: singly diagonal); 0 for an explicit scheme
+    double dt_a = 0.0;
+    for (int m = 0; m < s && dt_a == 0.0; ++m) dt_a = dt * A[m][m];
+    if (bdf2) dt_a = 2.0 * dt / 3.0;
+    if (dt_a != 0.0 &&
+        (!c->pc_ready || c->pc_age >= c->sv.pc_freeze || std::fabs(c->pc_dta - dt_a) > 1e-12 * std::fabs(dt_a))) {
       auto tb = clk::now();
       precond_build(c, u, dt_a);
       st->pc_built = 1;
@@ -1489,10 +1548,23 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
     }
     copy(c, c->d_un, u);
     for (int m = 0; m < s; ++m) {
-      // S_m = u^n + sum_{i<m} a^mi E^i
-      copy(c, c->d_S, c->d_un);
-      for (int i = 0; i < m; ++i) axpby(c, c->d_S, A[m][i], c->d_E[i], 1.0);
-      const double dta_m = dt * A[m][m];
+      if (bdf2) {
+        // S = (4 u^n - u^{n-1}) / 3
+        axpby(c, c->d_S, -1.0 / 3.0, c->d_uprev, 0.0);
+        axpby(c, c->d_S, 4.0 / 3.0, c->d_un, 1.0);
+      } else {
+        // S_m = u^n + sum_{i<m} a^mi E^i
+        copy(c, c->d_S, c->d_un);
+        for (int i = 0; i < m; ++i) axpby(c, c->d_S, A[m][i], c->d_E[i], 1.0);
+      }
+      const double dta_m = bdf2 ? dt_a : dt * A[m][m];
+      if (dta_m == 0.0) {
+        // explicit stage: u^m = S_m, E^m = dt M^-1 L(S_m)
+        residual(c, c->d_S, c->d_t1);
+        axpby(c, c->d_E[m], dt, c->d_t1, 0.0);
+        st->newton_its[m] = 0;
+        continue;
+      }
       double tau = -1.0;
       copy(c, c->d_ubar, c->d_S);
       st->guess_used[m] = 0;
@@ -1550,9 +1622,10 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       for (size_t i = 0; i < o.nres.size() && i < 65; ++i) st->nres[m][i] = o.nres[i];
       if (o.nan) fail(DGJ_ENAN, "stage %d: non-finite residual", m);
       if (!o.converged) fail(DGJ_ENOTCONV, "stage %d: Newton not converged in %d iterations", m, o.its);
-      // E^m = (u^m - S_m) / a^mm
-      hipLaunchKernelGGL(k_sub_div, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_E[m], c->d_ubar, c->d_S,
-                         A[m][m], c->n);
+      // E^m = (u^m - S_m) / a^mm (BDF2 takes u^m itself as u^{n+1})
+      if (!bdf2)
+        hipLaunchKernelGGL(k_sub_div, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_E[m], c->d_ubar, c->d_S,
+                           A[m][m], c->n);
       // stage increment u^m - S_m, kept (with the previous one) for the next steps' guesses
       copy(c, c->d_inc2[m], c->d_inc[m]);
       hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_inc[m], c->d_ubar, -1.0,
@@ -1561,10 +1634,20 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       if (c->rec_inc) copy(c, c->rec_inc + (long)m * c->n, c->d_inc[m]);
     }
     c->have_inc = std::min(2, c->have_inc + 1);
-    // u^{n+1} = u^n + sum b^i E^i
-    copy(c, c->d_t1, c->d_un);
-    for (int i = 0; i < s; ++i) axpby(c, c->d_t1, b[i], c->d_E[i], 1.0);
-    copy(c, u, c->d_t1);
+    if (bdf2) {
+      copy(c, u, c->d_ubar);
+    } else {
+      // u^{n+1} = u^n + sum b^i E^i
+      copy(c, c->d_t1, c->d_un);
+      for (int i = 0; i < s; ++i) axpby(c, c->d_t1, b[i], c->d_E[i], 1.0);
+      copy(c, u, c->d_t1);
+    }
+    if (c->sv.scheme == DGJ_BDF2) {
+      // this step's u^n is the next step's u^{n-1}
+      copy(c, c->d_uprev, c->d_un);
+      c->have_prev = true;
+      c->dt_prev = dt;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->pc_age++;
     return DGJ_OK;
@@ -1573,6 +1656,13 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
   st->residual_evals = c->residual_evals;
   st->t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   return rc;
+}
+
+int dgj_reset_history(dgj_ctx* c) {
+  if (!c) return DGJ_EINVAL;
+  c->have_prev = false;
+  c->have_inc = 0;
+  return DGJ_OK;
 }
 
 int dgj_set_guess(dgj_ctx* c, int32_t mode) {
@@ -1691,7 +1781,7 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
   return guarded(c, [&]() -> int {
     mlp_require(c);
     auto& M = c->mlp;
-    double A[3][3], b[3];
+    double A[DGJ_MAX_STAGES][DGJ_MAX_STAGES], b[DGJ_MAX_STAGES];
     int s = 0;
     tableau(c->sv.scheme, A, b, s);
     const long n = c->n;
@@ -1755,14 +1845,15 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
 int dgj_guess_state(dgj_ctx* c, double* inc_out, const double* inc_in) {
   if (!c) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
-    for (int m = 0; m < 3; ++m) {
+    const int S = c->n_stages;
+    for (int m = 0; m < S; ++m) {
       if (inc_out) {
         copy(c, inc_out + (long)m * c->n, c->d_inc[m]);
-        copy(c, inc_out + (long)(3 + m) * c->n, c->d_inc2[m]);
+        copy(c, inc_out + (long)(S + m) * c->n, c->d_inc2[m]);
       }
       if (inc_in) {
         copy(c, c->d_inc[m], inc_in + (long)m * c->n);
-        copy(c, c->d_inc2[m], inc_in + (long)(3 + m) * c->n);
+        copy(c, c->d_inc2[m], inc_in + (long)(S + m) * c->n);
       }
     }
     if (inc_in) c->have_inc = 2;

@@ -73,3 +73,5 @@ def test_batch_rejects_boundaries_and_curved_instances():
     cfgs = W.batch_configs(n=2, seed=9, nmin=3, nmax=4)
     ann = dataclasses.replace(W.config(4), dim=2, ncells=(2, 6), lengths=(1.0, 2 * np.pi), P=2, nq=4, r1=3.0)
     _raises(EUNSUPPORTED, lambda: Batch([cfgs[0], ann]))
+    # the batched stepper runs the SDIRK2/3 tables only
+    _raises(EUNSUPPORTED, lambda: Batch([dataclasses.replace(c, scheme="sdirk4") for c in cfgs]))
