@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cylinder-steps", action="store_true",
                     help="cylinder workload: also time implicit steps (warmup steps ramp dt from dt/100)")
+    ap.add_argument("--no-explicit", action="store_true",
+                    help="skip the explicit ERK2 comparison (its largest stable CFL and its time to reach the "
+                         "same physical time as the timed implicit steps)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--mode", default="full", choices=["full", "sweep", "copy", "residual"],
                     help="sweep: only build the preconditioner and apply it (for counter runs); "
@@ -243,6 +246,7 @@ def main():
             f"{st['t_total_ms']:.1f} ms")
 
     # ---- timed steps: a preconditioner build then K steps
+    u_start = u.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tb0 = time.perf_counter()
@@ -323,6 +327,9 @@ def main():
             forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
         out["forms"] = forms
 
+    if not args.no_explicit:
+        out["explicit_erk2"] = bench_explicit(cfg, mesh, u_start, u, wall * 1e3, args.steps * dt, kinds, states)
+
     if args.learned:
         out["learned"] = bench_learned(cfg, make, args.learned_train, min(args.steps, 3))
 
@@ -333,6 +340,68 @@ def main():
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
+
+
+def bench_explicit(cfg, mesh, u_start, u_impl, impl_ms, T, kinds, states):
+    """The paper's implicit-versus-explicit comparison on this workload: the
+    explicit ERK2 of Appendix A at its largest stable CFL (Eq. 32; found by
+    bisection, a CFL counting as stable when, after 300 steps from the timed
+    steps' start state, every value is finite and ||M^-1 L(u)|| has not grown
+    past twice its start value: unstable modes are the highest ones, whose
+    rate of change dominates that norm),
+    timed over the same physical time T as the timed implicit steps (which
+    include their preconditioner build), and the relative L2 difference of
+    the two end states (the implicit run's temporal error at its CFL)."""
+    import dataclasses
+    import math
+    import torch
+    from paper_2002_04222_amd import Context
+    ecfg = dataclasses.replace(cfg, scheme="erk2")
+    ctx = Context(mesh, ecfg, bc_kind=kinds, bc_state=states)
+    R = ctx.empty()
+
+    def rate_norm(v):
+        ctx.residual(v, R)
+        return float(torch.linalg.vector_norm(R))
+
+    r0 = rate_norm(u_start)
+    dt20 = cfg.dt()                       # dt at cfg.cfl
+
+    def stable(cfl, n=300):
+        v = u_start.clone()
+        dte = dt20 * cfl / cfg.cfl
+        for _ in range(n):
+            ctx.sdirk_step(v, dte)
+        r = rate_norm(v)
+        return math.isfinite(r) and r <= 2.0 * r0
+
+    lo, hi = 0.01, 1.0
+    if not stable(lo):
+        ctx.close()
+        return {"error": "ERK2 unstable at CFL 0.01"}
+    for _ in range(8):
+        mid = math.sqrt(lo * hi)
+        if stable(mid):
+            lo = mid
+        else:
+            hi = mid
+    cfl = lo
+    n_steps = int(math.ceil(T / (dt20 * cfl / cfg.cfl)))
+    dte = T / n_steps
+    v = u_start.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        ctx.sdirk_step(v, dte)
+    torch.cuda.synchronize()
+    ems = (time.perf_counter() - t0) * 1e3
+    diff = float(torch.linalg.vector_norm(v - u_impl) / torch.linalg.vector_norm(v))
+    ctx.close()
+    log(f"ERK2: largest stable CFL {cfl:.4f}, {n_steps} steps over T = {T:.4g} in {ems:.1f} ms; "
+        f"implicit {impl_ms:.1f} ms; end states differ by {diff:.2e}")
+    return {"cfl_max_stable": cfl, "cfl_implicit": cfg.cfl, "T": T, "explicit_steps": n_steps,
+            "explicit_ms": ems, "implicit_ms": impl_ms, "implicit_speedup": ems / impl_ms,
+            "rel_l2_diff_end_states": diff}
 
 
 def bench_batch(steps):
