@@ -39,6 +39,11 @@ def parse():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--P", type=int, default=None, help="polynomial order (default: the workload's; nq = P+2)")
     ap.add_argument("--pc", default=None, help="preconditioner storage f64|f32|bf16 (default: workload's)")
+    ap.add_argument("--pc-freeze", type=int, default=None,
+                    help="steps a built preconditioner is kept (default: the workload's, 10 as in the paper)")
+    ap.add_argument("--pc-refresh-its", type=int, default=None,
+                    help="GMRES count of a Newton step above which the next stage rebuilds the blocks "
+                         "(default: the workload's; 0 = fixed freeze only)")
     ap.add_argument("--forms", action="store_true", help="also time the f32 and bf16 preconditioner forms")
     ap.add_argument("--learned", action="store_true",
                     help="also time the learned Newton guess against the paper's and the extrapolated one")
@@ -167,6 +172,12 @@ def main():
     if args.pc:
         import dataclasses
         cfg = dataclasses.replace(cfg, pc_precision=args.pc)
+    if args.pc_freeze is not None:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, pc_freeze=args.pc_freeze)
+    if args.pc_refresh_its is not None:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, pc_refresh_its=args.pc_refresh_its)
     mesh = cfg.mesh()
     dt = cfg.dt()
     log(f"workload {cfg.name}: {mesh.n_elem} elements, P={cfg.P}, dt={dt:.4f}, pc={cfg.pc_precision}")
@@ -290,7 +301,8 @@ def main():
                    "dofs_per_var": cfg.dofs(), "unknowns": ctx.n_unknowns, "scheme": cfg.scheme,
                    "cfl": cfg.cfl, "dt": dt, "Re": cfg.Re, "Ma": cfg.Ma, "newton_rtol": cfg.newton_rtol,
                    "gmres": f"GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol}", "brj_sweeps": cfg.brj_sweeps,
-                   "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze},
+                   "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze,
+                   "pc_refresh_its": cfg.pc_refresh_its},
         "roofline": {"bound": "hbm", "kernel": "k_brj_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(cfg.pc_precision) if args.workload == 2 else None,
