@@ -137,7 +137,8 @@ def sweep_bytes(ctx, cfg, prec):
 
 def measured_traffic(prec):
     """HBM bytes per BRJ sweep launch from the committed counter runs, or None
-    when the sweep kernel's source has changed since they were taken."""
+    when the sweep's source (the apply section of its header, which holds the
+    sweep kernel and its load helpers) has changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_brj_sweep_tgv3d-16c-p3_traffic.md")
     src = os.path.join(ROOT, "paper_2002_04222_amd", "csrc", "dgj_precond.h")
@@ -146,8 +147,12 @@ def measured_traffic(prec):
         for line in open(path):
             if line.startswith("TRAFFIC "):
                 rec = json.loads(line[len("TRAFFIC "):])
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if rec is None or rec.get("kernel_source_sha256_16") != h:
+        text = open(src).read()
+        marker = "// ---------------------------------------------------------------- apply"
+        if marker not in text:
+            return None
+        h = hashlib.sha256(text[text.index(marker):].encode()).hexdigest()[:16]
+        if rec is None or rec.get("sweep_section_sha256_16") != h:
             return None
         return rec.get(prec)
     except OSError:
