@@ -32,7 +32,7 @@ import numpy as np
 
 from .basis import ref_element
 from .geometry import Geometry
-from .physics import Gas, euler_flux, viscous_flux, face_flux_own
+from .physics import Gas, euler_flux, viscous_flux, face_flux_own, BC_DIRICHLET
 
 
 @dataclasses.dataclass
@@ -51,6 +51,8 @@ class Disc:
     bc_state: Optional[np.ndarray] = None   # per boundary id: freestream conserved state [nv]
     geo_nodes: Optional[np.ndarray] = None  # curved elements: isoparametric nodes
     geo_order: int = 1
+    bc_field: Optional[np.ndarray] = None   # Dirichlet ghost states [E, 2d, nv, nqf] (faces of that kind)
+    source: Optional[np.ndarray] = None     # modal source [E, nv, nm] added to M^-1 L
 
     def __post_init__(self):
         self.ref = ref_element(self.dim, self.P, self.nq)
@@ -191,8 +193,12 @@ class Disc:
         S = np.zeros(go.shape, dtype=H.dtype)
         for b in np.unique(bid):
             k = bid == b
-            Hb, Sb = boundary_flux_own(self.gas, int(self.bc_kind[b]), Qo[k], go[k], n[k], beta[k],
-                                       self.bc_state[b])
+            kind = int(self.bc_kind[b])
+            if kind == BC_DIRICHLET:
+                Ub = np.transpose(self.bc_field[e[k], f], (0, 2, 1))       # [k, p, v]
+            else:
+                Ub = self.bc_state[b]
+            Hb, Sb = boundary_flux_own(self.gas, kind, Qo[k], go[k], n[k], beta[k], Ub)
             H[k], S[k] = Hb, Sb
         return H, S
 
@@ -213,8 +219,12 @@ class Disc:
         return np.linalg.solve(self.M[:, None, :, :], L[..., None])[..., 0]
 
     def residual(self, u):
-        """R(u) = M^-1 L(u)."""
-        return self.apply_Minv(self.L(u))
+        """R(u) = M^-1 L(u), plus the modal source when one is set (a forcing
+        f of the equations, projected: M^-1 of the integrals of phi f)."""
+        R = self.apply_Minv(self.L(u))
+        if self.source is not None:
+            R = R + self.source
+        return R
 
     def stage_residual(self, u, S, dt_a):
         """N(u) = u - S - dt a^mm M^-1 L(u)   (Eq. 20)."""
@@ -224,6 +234,12 @@ class Disc:
     def points(self):
         """Physical coordinates of the volume quadrature points [e, q, j]."""
         return self.geo.xq
+
+    def project_values(self, vals):
+        """L2 projection of values [E, nv, nq^d] given at the volume points."""
+        wq = self.geo.wJ
+        rhs = np.einsum('qm,evq->evm', self.ref.B, vals * wq[:, None, :])
+        return self.apply_Minv(rhs)
 
     def project(self, fn):
         """L2 projection of a pointwise field fn(x[..., d]) -> [..., nv]."""

@@ -225,7 +225,10 @@ def face_flux_own(gas: Gas, Uo, Un, go, gn, n, beta_p):
 # The paper names its boundary conditions (Sec. 4.3) but gives no formulas.
 # Readings: a boundary face takes the interior trace Q- and a ghost state Q+
 # with the interior gradient, and the interior-face fluxes are applied.
-BC_FARFIELD, BC_WALL = 0, 1
+# Dirichlet ("time dependent Dirichlet" in its list; the manufactured
+# Poiseuille case applies the exact solution weakly): the ghost state is a
+# given state at every face point.
+BC_FARFIELD, BC_WALL, BC_DIRICHLET = 0, 1, 2
 
 
 FARFIELD_BLEND = 0.02   # half-width of the inflow/outflow blend in u_nb, relative to c_b
@@ -278,11 +281,17 @@ def wall_ghost(U):
 
 def boundary_flux_own(gas: Gas, kind, Uo, go, n, beta_p, Uinf=None):
     """Boundary face flux (H^n, S) seen from the interior with outward normal
-    n: ghost state per kind, ghost gradient = interior gradient; at an
+    n: ghost state per kind (Dirichlet: Uinf holds the ghost state of every
+    point), ghost gradient = interior gradient; at an
     adiabatic wall the heat flux through the wall is zero, so the energy
     components of the viscous face fluxes vanish (the work term vanishes with
     the zero wall velocity)."""
-    Un = farfield_ghost(gas, Uo, n, Uinf) if kind == BC_FARFIELD else wall_ghost(Uo)
+    if kind == BC_DIRICHLET:
+        Un = np.broadcast_to(Uinf, Uo.shape)
+    elif kind == BC_FARFIELD:
+        Un = farfield_ghost(gas, Uo, n, Uinf)
+    else:
+        Un = wall_ghost(Uo)
     F = riemann_flux(gas, Uo, Un, n)
     Gn, S = ip_face_fluxes(gas, Uo, Un, go, go, n, beta_p)
     if kind == BC_WALL:

@@ -18,7 +18,8 @@
     dropped, as the paper does.  (L+U) q is applied on the fly from the
     stored face Jacobians dHhat/dQ^+ (Eq. 31) and the neighbour trace of q.
     chi_v = ||u^(v)||_2 sqrt(eps_hat) with u^(v) all coefficients of
-    variable v.  D_e is inverted explicitly with LU and partial pivoting.
+    variable v (||u||_2 sqrt(eps_hat) for a variable that is zero
+    everywhere, where the paper's rule gives no step).  D_e is inverted explicitly with LU and partial pivoting.
   * GMRES (Sec. 3.2): restarted right-preconditioned GMRES(m) of Saad and
     Schultz with modified Gram-Schmidt and Givens rotations, x0 = 0,
     stopping when the residual has dropped by the factor rtol (5e-2) or
@@ -136,7 +137,10 @@ class BRJ:
         ref, gas, d, nv, nm = disc.ref, disc.gas, disc.dim, disc.nv, disc.ref.nm
         E = disc.n_elem
         nb = nv * nm
-        self.chi = np.array([l2(u_p[:, v, :]) for v in range(nv)]) * np.sqrt(EPS_HAT)
+        # a variable that is zero everywhere (a velocity component of a
+        # parallel flow) takes the norm of the whole state instead
+        norms = np.array([l2(u_p[:, v, :]) for v in range(nv)])
+        self.chi = np.where(norms > 0.0, norms, l2(u_p)) * np.sqrt(EPS_HAT)
         A = np.zeros((E, nv, nm, nv, nm))
         # volume terms (first two terms of Eq. 30)
         for s in range(0, E, chunk):

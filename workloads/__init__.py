@@ -194,7 +194,8 @@ class FlowConfig:
     pc_freeze: int = 10
     pc_refresh_its: int = 30
     pc_precision: str = "f64"
-    geometry: str = "box"     # "box" (periodic affine boxes) or "annulus" (curved O-grid, walls + far field)
+    geometry: str = "box"     # "box" (periodic affine boxes), "annulus" (curved O-grid, walls + far
+                              # field) or "channel" (affine boxes, Dirichlet on every side)
     r0: float = 0.5
     r1: float = 10.0
 
@@ -210,6 +211,8 @@ class FlowConfig:
         if self.geometry == "annulus":
             return annulus_mesh(self.ncells[0], self.ncells[1], self.ncells[2] if self.dim == 3 else 0,
                                 r0=self.r0, r1=self.r1, Lz=self.lengths[-1], seed=self.seed)
+        if self.geometry == "channel":
+            return cartesian_mesh(self.ncells, self.lengths, periodic=False)
         return cartesian_mesh(self.ncells, self.lengths, periodic=True)
 
     def freestream(self) -> np.ndarray:
@@ -220,7 +223,11 @@ class FlowConfig:
 
     def boundary(self):
         """(bc_kind, bc_state) of the boundary ids: annulus id 0 = no-slip
-        adiabatic wall on the cylinder, id 1 = far field; none on boxes."""
+        adiabatic wall on the cylinder, id 1 = far field; channel: id 0 =
+        Dirichlet on all four sides; none on periodic boxes."""
+        if self.geometry == "channel":
+            # one id, Dirichlet (ghost states per face point from mms_inputs)
+            return np.array([2], dtype=np.int32), self.freestream()[None]
         if self.geometry != "annulus":
             return None, None
         U = self.freestream()
@@ -361,3 +368,90 @@ def mlp_init(n_in: int, hidden: int, n_out: int, seed: int, out_scale: float = 1
     parts = [glorot(n_in, hidden), np.zeros(hidden), glorot(hidden, hidden), np.zeros(hidden),
              glorot(hidden, n_out) * out_scale, np.zeros(n_out)]
     return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+# ---------------------------------------------------------------- manufactured Poiseuille flow
+def poiseuille_mms(gamma: float, Ma: float, Re: float, L: float = 1.0, theta: float = 0.01):
+    """Manufactured compressible Poiseuille flow of Sec. 6.1 and Appendix B:
+    rho = 1, u = -(dp/dx)/(2 mu) [y(L-y) + theta y^2 (L-y)^2], v = 0,
+    p = 1/(gamma Ma^2) + (dp/dx) x, mu = 1/Re, dp/dx = -8 mu / L^2; and the
+    forcing f that makes it a steady solution (dU/dt + div(F - G) = f).
+    f_4 carries the factor (1 + theta y (L - y)) in its first term, which
+    the printed expression lacks (with it f follows from the exact
+    solution).  Returns (exact(x) -> U[..., 4], forcing(x) -> f[..., 4])."""
+    mu = 1.0 / Re
+    dpdx = -8.0 * mu / L ** 2
+
+    def exact(x):
+        X, Y = x[..., 0], x[..., 1]
+        s = Y * (L - Y)
+        u = -(dpdx / (2.0 * mu)) * (s + theta * s * s)
+        p = 1.0 / (gamma * Ma ** 2) + dpdx * X
+        E = p / (gamma - 1.0) + 0.5 * u * u
+        return np.stack([np.ones_like(X), u, np.zeros_like(X), E], axis=-1)
+
+    def forcing(x):
+        Y = x[..., 1]
+        c = L ** 2 - 6.0 * Y * L + 6.0 * Y ** 2
+        f2 = dpdx * theta * c
+        f4 = (dpdx ** 2 / (2.0 * mu)) * Y * (L - Y) * (1.0 + theta * Y * (L - Y)) \
+            * (1.0 - theta * c - gamma / (gamma - 1.0)) \
+            - (dpdx ** 2 / (4.0 * mu)) * (L - 2.0 * Y) ** 2 * (2.0 * theta * Y * L - 2.0 * theta * Y ** 2 + 1.0) ** 2
+        return np.stack([np.zeros_like(Y), f2, np.zeros_like(Y), f4], axis=-1)
+
+    return exact, forcing
+
+
+def mms_config(P: int, n: int, **overrides) -> FlowConfig:
+    """The manufactured Poiseuille case on [0, 1]^2 with n x n elements:
+    Re 100, Ma 0.1 (maximum velocity about 1), Dirichlet data from the exact
+    solution on every side, backward-Euler pseudo-time steps."""
+    c = FlowConfig(name=f"poiseuille-mms-{n}x{n}-p{P}", dim=2, ncells=(n, n), lengths=(1.0, 1.0), P=P, nq=P + 2,
+                   Re=100.0, Ma=0.1, scheme="beuler", geometry="channel", ic="mms", cfl=500.0, seed=6)
+    return dataclasses.replace(c, **overrides)
+
+
+def box_points(mesh: Mesh, nq: int):
+    """Physical coordinates where inputs given at quadrature points are
+    sampled, on affine boxes: volume points [E, nq^d, d] (Gauss-Legendre
+    points, x fastest) and face points [E, 2d, nq^(d-1), d] (face f =
+    2 axis + side; the tangential axes in increasing order, the first
+    fastest)."""
+    x1, _ = np.polynomial.legendre.leggauss(nq)
+    d = mesh.dim
+    org, h = mesh.elem_origin, mesh.elem_h
+    idx = np.indices((nq,) * d).reshape(d, -1)[::-1].T          # [nq^d, d], first axis fastest
+    xi = x1[idx]
+    xv = org[:, None, :] + (xi[None] + 1.0) * 0.5 * h[:, None, :]
+    nqf = nq ** (d - 1)
+    tid = np.indices((nq,) * (d - 1)).reshape(d - 1, -1)[::-1].T if d > 1 else np.zeros((1, 0), int)
+    xf = np.zeros((mesh.face_nbr.shape[0], 2 * d, nqf, d))
+    for axis in range(d):
+        tang = [a for a in range(d) if a != axis]
+        for side in (0, 1):
+            ref = np.zeros((nqf, d))
+            ref[:, axis] = 1.0 if side else -1.0
+            for t, a in enumerate(tang):
+                ref[:, a] = x1[tid[:, t]]
+            xf[:, 2 * axis + side] = org[:, None, :] + (ref[None] + 1.0) * 0.5 * h[:, None, :]
+    return xv, xf
+
+
+def mms_inputs(cfg: FlowConfig, mesh: Mesh) -> Dict[str, np.ndarray]:
+    """Inputs of the manufactured Poiseuille case, sampled at the
+    quadrature points: 'bc_field' [E, 2d, nv, nqf] the exact solution at the
+    face points (the Dirichlet ghost states); 'forcing', 'exact' and
+    'initial' [E, nv, nq^d] at the volume points; the initial state has the
+    exact density and pressure and a uniform velocity 1."""
+    exact, forcing = poiseuille_mms(cfg.gamma, cfg.Ma, cfg.Re)
+    xv, xf = box_points(mesh, cfg.nq)
+    U = exact(xv)
+    U0 = U.copy()
+    U0[..., 1] = 1.0
+    U0[..., 2] = 0.0
+    p = (U[..., 3] - 0.5 * U[..., 1] ** 2) * (cfg.gamma - 1.0)
+    U0[..., 3] = p / (cfg.gamma - 1.0) + 0.5
+    return {"bc_field": np.ascontiguousarray(np.transpose(exact(xf), (0, 1, 3, 2))),
+            "forcing": np.ascontiguousarray(np.transpose(forcing(xv), (0, 2, 1))),
+            "exact": np.ascontiguousarray(np.transpose(U, (0, 2, 1))),
+            "initial": np.ascontiguousarray(np.transpose(U0, (0, 2, 1)))}
