@@ -62,8 +62,9 @@ enum { DGJ_PC_F64 = 0, DGJ_PC_F32 = 1, DGJ_PC_BF16 = 2 };
 typedef struct dgj_ctx dgj_ctx;
 
 /* Boundary condition kinds.  No formulas are given in the paper, which
- * only names the kinds its solver offers (Sec. 5); the two built are the
- * ones of its cylinder case.  A boundary face takes the interior trace and
+ * only names the kinds its solver offers (Sec. 5); the ones built are
+ * those of its cylinder case and the Dirichlet data of its manufactured
+ * Poiseuille case (Sec. 6.1).  A boundary face takes the interior trace and
  * a ghost state with the interior gradient, and the interior face fluxes
  * (Riemann flux, interior-penalty viscous terms) apply:
  *  DGJ_BC_FARFIELD: 1D characteristic far field.  With u_n the outward
@@ -78,8 +79,10 @@ typedef struct dgj_ctx dgj_ctx;
  *  DGJ_BC_WALL: adiabatic no-slip wall.  Ghost = interior with the
  *    momentum negated (zero wall velocity); the energy components of the
  *    viscous flux and of the symmetric interior-penalty term are zero (no
- *    heat flux through the wall). */
-enum { DGJ_BC_FARFIELD = 0, DGJ_BC_WALL = 1 };
+ *    heat flux through the wall).
+ *  DGJ_BC_DIRICHLET: the ghost state is a given state at every face point
+ *    (dgj_set_bc_field), e.g. an exact solution applied weakly. */
+enum { DGJ_BC_FARFIELD = 0, DGJ_BC_WALL = 1, DGJ_BC_DIRICHLET = 2 };
 
 /* Mesh of affine boxes (host arrays, copied by dgj_create). */
 typedef struct {
@@ -92,9 +95,10 @@ typedef struct {
   const int32_t *face_nbr;    /* host [n_elem][2*dim]: element across the face, or -(id+1)
                                  for a face on boundary id (0 <= id < n_bc) */
   int32_t n_bc;               /* number of boundary ids; 0 for periodic meshes */
-  const int32_t *bc_kind;     /* host [n_bc]: DGJ_BC_FARFIELD or DGJ_BC_WALL (NULL if n_bc = 0) */
+  const int32_t *bc_kind;     /* host [n_bc]: DGJ_BC_FARFIELD, DGJ_BC_WALL or DGJ_BC_DIRICHLET
+                                 (NULL if n_bc = 0) */
   const double *bc_state;     /* host [n_bc][dim+2]: freestream conserved state of each far-field
-                                 id (rho > 0, p > 0); entries of wall ids are not read */
+                                 id (rho > 0, p > 0); entries of other ids are not read */
   int32_t geo_order;          /* curved elements: order g of the element maps (1..7) */
   const double *geo_nodes;    /* host [n_elem][(g+1)^dim][dim] or NULL (affine boxes).  When
                                  set, elements are isoparametric: x(xi) = sum_c X_c l_c(xi),
@@ -203,6 +207,27 @@ int dgj_precond_build(dgj_ctx *ctx, const double *u_p, double dt_a);
 /* out = P^-1 q by brj_sweeps sweeps of Eq. 28 from q^0 = 0.  Requires a
  * built preconditioner.  out must not alias q. */
 int dgj_precond_apply(dgj_ctx *ctx, const double *q, double *out);
+
+/* L2 projection onto the modes of values given at the volume Gauss points:
+ * f[e][v][q] (device, q = q0 + nq (q1 + nq q2), x fastest) -> u[e][v][m],
+ * u_e = M_e^-1 (integral of phi_m f over the element, by the Gauss rule)
+ * (Sec. 3.1, Eq. 13's mass matrix).  Initial states, forcing terms. */
+int dgj_project(dgj_ctx *ctx, const double *f, double *u);
+
+/* Source term: s[e][v][m] (device, copied; NULL removes it) is added to
+ * M^-1 L(u) in every residual the context evaluates, so R, N (Eq. 20), the
+ * Frechet matvec and the steps solve M du/dt = L(u) + M s.  For a forcing f
+ * of the equations, s is its projection (dgj_project). */
+int dgj_set_source(dgj_ctx *ctx, const double *s);
+
+/* Ghost states of the Dirichlet faces: g[e][f][v][p] (device, copied;
+ * n_elem x 2 dim x (dim+2) x nq^(dim-1) values), f = 2 axis + side, p over the
+ * face's Gauss points with the tangential reference axes in increasing
+ * order, the first fastest.  Only faces whose boundary id has the Dirichlet
+ * kind are read.  Needed before any residual or preconditioner build on a
+ * mesh with Dirichlet boundaries (DGJ_EINVAL otherwise, or when the mesh has
+ * none). */
+int dgj_set_bc_field(dgj_ctx *ctx, const double *g);
 
 /* Export of the stored inverse mass matrices of a curved mesh (tests):
  * out[e][m][n] (device, n_elem (P+1)^(2d) values).  DGJ_EINVAL on boxes. */

@@ -16,7 +16,7 @@ DGJ_OK = 0
 DGJ_BEULER, DGJ_SDIRK2, DGJ_SDIRK3, DGJ_SDIRK4, DGJ_BDF2, DGJ_ERK2 = 1, 2, 3, 4, 12, 20
 MAX_STAGES = 6
 DGJ_PC_F64, DGJ_PC_F32, DGJ_PC_BF16 = 0, 1, 2
-DGJ_BC_FARFIELD, DGJ_BC_WALL = 0, 1
+DGJ_BC_FARFIELD, DGJ_BC_WALL, DGJ_BC_DIRICHLET = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOTCONV", -5: "ENAN", -6: "ESINGULAR",
           -7: "EUNSUPPORTED"}
 
@@ -97,6 +97,9 @@ def load_library(path: str = LIB_PATH):
         "dgj_newton": ([vp, vp, dp, vp, i32p, i32p], C.c_int),
         "dgj_sdirk_step": ([vp, vp, dp, C.POINTER(StepStats)], C.c_int),
         "dgj_set_guess": ([vp, C.c_int32], C.c_int),
+        "dgj_project": ([vp, vp, vp], C.c_int),
+        "dgj_set_source": ([vp, vp], C.c_int),
+        "dgj_set_bc_field": ([vp, vp], C.c_int),
         "dgj_reset_history": ([vp], C.c_int),
         "dgj_set_record": ([vp, vp, vp], C.c_int),
         "dgj_mlp_create": ([vp, C.c_int32, vp], C.c_int),
@@ -356,6 +359,18 @@ class Context:
         if rc != DGJ_OK:
             raise DgjError(rc, self.lib.dgj_last_error(self.h).decode())
         return st.to_dict()
+
+    def project(self, f, u):
+        """u = L2 projection of the values f[e][v][q] at the volume points."""
+        self._check(self.lib.dgj_project(self.h, _ptr(f), _ptr(u)))
+
+    def set_source(self, s):
+        """Add s (modal, copied) to M^-1 L in every residual; None removes it."""
+        self._check(self.lib.dgj_set_source(self.h, _ptr(s)))
+
+    def set_bc_field(self, g):
+        """Dirichlet ghost states g[e][f][v][p] at the face points (copied)."""
+        self._check(self.lib.dgj_set_bc_field(self.h, _ptr(g)))
 
     def reset_history(self):
         self._check(self.lib.dgj_reset_history(self.h))

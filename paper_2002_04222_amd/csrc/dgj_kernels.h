@@ -116,6 +116,11 @@ struct ResArgs {
   // (face_nbr = -(id + 1))
   const int* bc_kind;
   const double* bc_state;
+  // Dirichlet ghost states at the face points, bc_field[e][NF][NV][NQF]
+  // (read at faces whose id has the Dirichlet kind; may be null otherwise)
+  const double* bc_field;
+  // modal source [e][NV][NM] added to M^-1 L (null: none)
+  const double* src;
   // curved elements (all null for affine boxes): per-point metrics
   // vg[e][D*D+1][NQ], fg[e][NF][D*D+D+1][NQF] and the dense inverse mass
   // matrix minv[e][NM][NM]

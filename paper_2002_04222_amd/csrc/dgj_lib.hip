@@ -283,6 +283,40 @@ __global__ void k_mass_apply(const double* __restrict__ M, const double* __restr
   }
 }
 
+// Right-hand side of the L2 projection of point values f[e][v][q] given at
+// the volume Gauss points: out[e][v][m] = sum_q W_q phi_m(xi_q) f[e][v][q],
+// W_q the tensor weight (boxes, where M = |J| I cancels the |J| of the
+// integral) or w|J| at the point (curved, followed by M^-1).
+template <int D, int N, int Q>
+__global__ void k_project_rhs(const double* __restrict__ tables, const double* __restrict__ vg, long n_elem,
+                              const double* __restrict__ f, double* __restrict__ out) {
+  using S = Shape<D, N, Q>;
+  constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ;
+  const long total = n_elem * NV * NM;
+  for (long gid = (long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += (long)gridDim.x * blockDim.x) {
+    const long e = gid / (NV * NM);
+    const int v = (gid / NM) % NV, m = gid % NM;
+    int mi[3] = {0, 0, 0};
+    split<D, N>(m, mi);
+    const double* fe = f + (e * NV + v) * (long)NQ;
+    const double* wJ = vg ? vg + (e * (D * D + 1) + D * D) * (long)NQ : nullptr;
+    double s = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+      int r = q;
+      double b = 1.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int aq = r % Q;
+        r /= Q;
+        b *= tables[aq * N + mi[a]];
+        if (!wJ) b *= tables[2 * Q * N + aq];
+      }
+      s += b * (wJ ? wJ[q] : 1.0) * fe[q];
+    }
+    out[gid] = s;
+  }
+}
+
 // Taylor-Green projection: u[e][v][m] = sum_q w_q phi_m(xi_q) f_v(x_q) (+ noise)
 template <int D, int N, int Q>
 __global__ void k_project_tgv(const double* __restrict__ origin, const double* __restrict__ geo,
@@ -381,6 +415,9 @@ struct dgj_ctx {
   double *d_vg = nullptr, *d_fg = nullptr, *d_M = nullptr, *d_Minv = nullptr, *d_Mq = nullptr;
   int* d_bc_kind = nullptr;       // per boundary id
   double* d_bc_state = nullptr;   // per boundary id, freestream [NV]
+  bool has_dirichlet = false;     // some boundary id has the Dirichlet kind
+  double* d_bc_field = nullptr;   // Dirichlet ghost states [E][NF][NV][NQF] (dgj_set_bc_field)
+  double* d_src = nullptr;        // modal source [E][NV][NM] added to M^-1 L (dgj_set_source)
   double* d_origin = nullptr;
   double* d_tab = nullptr;
   std::vector<double> h_tab;   // tables + Lagrange weights, passed by value to the residual kernels
@@ -599,10 +636,13 @@ void launch_residual(dgj_ctx* c, const ResArgs& a) {
 }
 
 ResArgs res_args(dgj_ctx* c) {
+  if (c->has_dirichlet && !c->d_bc_field) fail(DGJ_EINVAL, "Dirichlet boundary without ghost states (dgj_set_bc_field)");
   ResArgs a{};
   a.nbr = c->d_nbr;
   a.bc_kind = c->d_bc_kind;
   a.bc_state = c->d_bc_state;
+  a.bc_field = c->d_bc_field;
+  a.src = c->d_src;
   if (c->curved) {
     a.vg = c->d_vg;
     a.fg = c->d_fg;
@@ -725,11 +765,11 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
   if (c->pc_prec == DGJ_PC_F64)
     hipLaunchKernelGGL((k_pc_face<D, N, Q, double>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
                        c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (double*)c->d_Jp, e0, c->d_bc_kind,
-                       c->d_bc_state, c->curved ? c->d_fg : nullptr);
+                       c->d_bc_state, c->curved ? c->d_fg : nullptr, c->d_bc_field);
   else
     hipLaunchKernelGGL((k_pc_face<D, N, Q, float>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
                        c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (float*)c->d_Jp, e0, c->d_bc_kind,
-                       c->d_bc_state, c->curved ? c->d_fg : nullptr);
+                       c->d_bc_state, c->curved ? c->d_fg : nullptr, c->d_bc_field);
   // up to 16 accumulators of the NM x NM sub-block per thread; large blocks
   // are split into tiles of NTA * 16 entries
   constexpr int NTA0 = ((S::NM * S::NM / 16 + 63) / 64) * 64;
@@ -774,6 +814,7 @@ void free_pc(dgj_ctx* c) {
 // Build the BRJ blocks of elements [e0, e0+ne) (one instance) at state up.
 void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, long ne, const Phys& ph, double* Wt,
                          double* JmW, void* Dm) {
+  if (c->has_dirichlet && !c->d_bc_field) fail(DGJ_EINVAL, "Dirichlet boundary without ghost states (dgj_set_bc_field)");
   // chi_v = ||u^(v)||_2 sqrt(eps_hat) over the instance  (Eq. 31)
   hipLaunchKernelGGL(k_varsq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, up + e0 * c->NB, ne, c->NV,
                      c->NM, c->d_part);
@@ -781,13 +822,16 @@ void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, lon
   HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   double* chi = c->h_scal;   // pinned; the stream was synchronised above
+  double total = 0.0;
   for (int v = 0; v < c->NV; ++v) {
     double s = 0.0;
     for (int b = 0; b < RED_BLOCKS; ++b) s += part[(size_t)b * c->NV + v];
-    chi[v] = std::sqrt(s) * std::sqrt(EPS_HAT);
-    if (!(chi[v] > 0.0) || !std::isfinite(chi[v]))
-      fail(DGJ_EINVAL, "precond_build: variable %d of u_p is zero or non-finite", v);
+    chi[v] = s;
+    total += s;
   }
+  if (!(total > 0.0) || !std::isfinite(total)) fail(DGJ_EINVAL, "precond_build: u_p is zero or non-finite");
+  // a variable that is zero everywhere takes the norm of the whole state
+  for (int v = 0; v < c->NV; ++v) chi[v] = std::sqrt(chi[v] > 0.0 ? chi[v] : total) * std::sqrt(EPS_HAT);
   HIPCHK(hipMemcpyAsync(c->d_chi, chi, c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
 #define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm, e0, ne, ph); } else
   DGJ_FOR_SHAPES(X)
@@ -1221,7 +1265,9 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     const int NVh = D + 2;
     for (int b = 0; b < mesh->n_bc; ++b) {
       const int k = mesh->bc_kind[b];
-      if (k != DGJ_BC_FARFIELD && k != DGJ_BC_WALL) fail(DGJ_EINVAL, "boundary %d: unknown kind %d", b, k);
+      if (k != DGJ_BC_FARFIELD && k != DGJ_BC_WALL && k != DGJ_BC_DIRICHLET)
+        fail(DGJ_EINVAL, "boundary %d: unknown kind %d", b, k);
+      if (k == DGJ_BC_DIRICHLET) c->has_dirichlet = true;
       if (k == DGJ_BC_FARFIELD) {
         const double* U = mesh->bc_state + b * NVh;
         double ke = 0.0;
@@ -1370,6 +1416,8 @@ void dgj_destroy(dgj_ctx* c) {
   if (c->d_nbr) hipFree(c->d_nbr);
   if (c->d_bc_kind) hipFree(c->d_bc_kind);
   if (c->d_bc_state) hipFree(c->d_bc_state);
+  if (c->d_bc_field) hipFree(c->d_bc_field);
+  if (c->d_src) hipFree(c->d_src);
   void* bps[] = {c->d_inst, c->d_phs, c->d_epsv, c->d_dtav, c->d_active, c->d_ioff, c->d_hs, c->d_part2, c->d_kused};
   for (void* p : bps)
     if (p) hipFree(p);
@@ -1403,6 +1451,58 @@ int dgj_project_tgv(dgj_ctx* c, const double* noise, double amp, double* u) {
 #undef X
     fail(DGJ_EUNSUPPORTED, "unsupported shape");
     HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_project(dgj_ctx* c, const double* f, double* u) {
+  if (!c || !f || !u) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (c->n_inst > 0) fail(DGJ_EUNSUPPORTED, "project: single instances only");
+    double* rhs = c->curved ? c->d_t2 : u;
+    const long total = c->n_elem * c->NV * c->NM;
+    bool launched = false;
+#define X(d, n, q)                                                                                          \
+  if (c->dim == d && c->N == n && c->nq == q) {                                                              \
+    hipLaunchKernelGGL((k_project_rhs<d, n, q>), dim3(grid_for(total)), dim3(256), 0, c->stream, c->d_tab,   \
+                       c->curved ? c->d_vg : nullptr, c->n_elem, f, rhs);                                  \
+    launched = true;                                                                                       \
+  }
+    DGJ_FOR_SHAPES(X)
+#undef X
+    if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
+    if (c->curved)
+      hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_Minv, rhs, u, c->NM, c->NV,
+                         c->n_elem);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_set_source(dgj_ctx* c, const double* s) {
+  if (!c) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (c->n_inst > 0) fail(DGJ_EUNSUPPORTED, "set_source: single instances only");
+    if (!s) {
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (c->d_src) HIPCHK(hipFree(c->d_src));
+      c->d_src = nullptr;
+      return DGJ_OK;
+    }
+    if (!c->d_src) HIPCHK(hipMalloc(&c->d_src, c->n * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c->d_src, s, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return DGJ_OK;
+  });
+}
+
+int dgj_set_bc_field(dgj_ctx* c, const double* g) {
+  if (!c || !g) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!c->has_dirichlet) fail(DGJ_EINVAL, "set_bc_field: the mesh has no Dirichlet boundary");
+    const long nqf = c->dim == 2 ? c->nq : (long)c->nq * c->nq;
+    const size_t bytes = (size_t)c->n_elem * 2 * c->dim * c->NV * nqf * sizeof(double);
+    if (!c->d_bc_field) HIPCHK(hipMalloc(&c->d_bc_field, bytes));
+    HIPCHK(hipMemcpyAsync(c->d_bc_field, g, bytes, hipMemcpyDeviceToDevice, c->stream));
     return DGJ_OK;
   });
 }

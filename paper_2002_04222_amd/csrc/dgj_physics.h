@@ -361,7 +361,7 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, cons
 // by w = (1 + tanh(u_nb / (0.02 c_b)))/2;
 // no-slip wall: mirrored momentum (zero wall velocity), with the heat flux
 // through the wall zero (adiabatic), so the viscous energy fluxes vanish.
-enum { BC_FARFIELD = 0, BC_WALL = 1 };
+enum { BC_FARFIELD = 0, BC_WALL = 1, BC_DIRICHLET = 2 };
 
 template <int D>
 __device__ __forceinline__ void farfield_ghost(const Phys& ph, const double* Ui, const double* n, const double* Uo,
@@ -419,7 +419,11 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
                                               double (*S)[D + 2]) {
   constexpr int NV = D + 2;
   double Un[NV];
-  if (kind == BC_FARFIELD) {
+  if (kind == BC_DIRICHLET) {
+    // the given state at this face point (Uinf points at it)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = Uinf[v];
+  } else if (kind == BC_FARFIELD) {
     farfield_ghost<D>(ph, Uo, n, Uinf, Un);
   } else {
     Un[0] = Uo[0];

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
                           const double* __restrict__ beta, const double* __restrict__ tables, Phys ph, long n_elem,
                           const double* __restrict__ chi_dev, double* __restrict__ JmW, TJ* __restrict__ Jp,
                           long e0, const int* __restrict__ bc_kind, const double* __restrict__ bc_state,
-                          const double* __restrict__ fg) {
+                          const double* __restrict__ fg, const double* __restrict__ bc_field) {
   using S = Shape<D, N, Q>;
   constexpr int NV = S::NV, NQF = S::NQF, NF = S::NF;
   __shared__ double st[S::TAB];
@@ -240,6 +240,13 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
     const int bid = -en - 1;
     const int kind = bc_kind[bid];
     const double* Uinf = bc_state + bid * NV;
+    double UD[NV];
+    if (kind == BC_DIRICHLET) {
+      const double* g = bc_field + (e * NF + f) * (long)NV * NQF + p;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) UD[v] = g[v * NQF];
+      Uinf = UD;
+    }
     boundary_flux<D>(ph, kind, Uo, go, nrm, b, Uinf, H0, nullptr);
     for (int l = 0; l < NV; ++l) {
       const double chi = chi_dev[l];

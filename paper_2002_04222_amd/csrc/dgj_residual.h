@@ -464,7 +464,16 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
     face_flux<D>(ph, UL, UR, gL, gR, nrm, beta, H, Sf);
   } else {
     const int bid = -(int)en - 1;
-    boundary_flux<D>(ph, a.bc_kind[bid], UL, gL, nrm, beta, a.bc_state + bid * NV, H, Sf);
+    const int kind = a.bc_kind[bid];
+    double UD[NV];
+    const double* Ub = a.bc_state + bid * NV;
+    if (kind == BC_DIRICHLET) {
+      const double* g = a.bc_field + (e * K::NF + f) * (long)NV * NQF + p;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) UD[v] = g[v * NQF];
+      Ub = UD;
+    }
+    boundary_flux<D>(ph, kind, UL, gL, nrm, beta, Ub, H, Sf);
   }
   double* o = X + e * (long)K::XF + f * (D + 1) * NV * NQF;
 #pragma unroll
@@ -498,6 +507,7 @@ __global__ __launch_bounds__(256) void k_res_face(ResArgs a, TabK<N, Q> tk, cons
 
 // output of the residual kernels for unknown gi with R = (M^-1 L)_gi
 __device__ __forceinline__ void epilogue(const ResArgs& a, const ElemParams& ep, long gi, double R) {
+  if (a.src) R += a.src[gi];
   if (a.mode == RES_R) {
     a.out[gi] = R;
   } else {

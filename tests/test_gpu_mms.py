@@ -1,0 +1,166 @@
+"""The Dirichlet boundary, the source term and the projection of point
+values through the C ABI against the oracle (residual 1e-12 relative per
+variable, projection 1e-13, BRJ blocks 1e-6, steady pseudo-time steps with
+the same Newton/GMRES counts and 1e-9 in the state), and the manufactured
+Poiseuille case of Sec. 6.1 solved to steady state on the device at the
+designed order of accuracy P + 1."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+from oracle import solver as OS
+from oracle.dg import Disc, make_disc
+from oracle.physics import Gas, BC_DIRICHLET
+from tests.gpu_util import rel_err_per_var
+from tests.test_oracle_mms import mms_disc, mms_steady
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(cfg, mesh, kinds, states, **over):
+    from paper_2002_04222_amd import Context
+    return Context(mesh, cfg, bc_kind=kinds, bc_state=states, **over)
+
+
+@pytest.mark.parametrize("dim,P", [(2, 2), (2, 3), (2, 4), (2, 5), (3, 2), (3, 3)])
+def test_residual_parity_dirichlet_and_source(dim, P):
+    _case(f"dirichlet + source residual dim {dim} P {P}")
+    cfg = dataclasses.replace(W.mms_config(P, 3), dim=dim, ncells=(3,) * dim, lengths=(1.0, 1.3, 1.6)[:dim],
+                              Ma=0.3, Re=40.0)
+    mesh = cfg.mesh()
+    kinds, states = cfg.boundary()
+    nv, nqf = dim + 2, (P + 2) ** (dim - 1)
+    mean = W.DEFAULT_MEAN[dim]
+    rng = np.random.Generator(np.random.PCG64(17))
+    g = np.asarray(mean)[None, None, :, None] * (1.0 + 0.02 * rng.uniform(-1, 1, size=(mesh.n_elem, 2 * dim, nv, nqf)))
+    u = W.random_state(mesh.n_elem, dim, P, seed=18)
+    src = W.random_vector(mesh.n_elem, dim, P, seed=19)
+    ctx = _ctx(cfg, mesh, kinds, states)
+    ctx.set_bc_field(_dev(g))
+    ctx.set_source(_dev(src))
+    R = ctx.empty()
+    ctx.residual(_dev(u), R)
+    d = make_disc(cfg, mesh)
+    d.bc_kind, d.bc_state, d.bc_field, d.source = kinds, states, g, src
+    Ro = d.residual(u)
+    err = rel_err_per_var(_host(R), Ro)
+    print("rel err", err, flush=True)
+    assert err <= 1e-12
+    # removing the source removes exactly s
+    ctx.set_source(None)
+    R2 = ctx.empty()
+    ctx.residual(_dev(u), R2)
+    assert rel_err_per_var(_host(R2), Ro - src) <= 1e-12
+
+
+def test_projection_parity_boxes_and_curved():
+    _case("projection of point values")
+    cfg = W.mms_config(3, 4)
+    mesh = cfg.mesh()
+    inp = W.mms_inputs(cfg, mesh)
+    kinds, states = cfg.boundary()
+    ctx = _ctx(cfg, mesh, kinds, states)
+    u = ctx.empty()
+    ctx.project(_dev(inp["forcing"]), u)
+    d = make_disc(cfg, mesh)
+    assert rel_err_per_var(_host(u), d.project_values(inp["forcing"])) <= 1e-13
+    # curved annulus, random point values
+    ca = dataclasses.replace(W.config(4), dim=2, ncells=(3, 8), lengths=(1.0, 2 * np.pi), P=3, nq=5, r1=3.0)
+    ma = ca.mesh()
+    ka, sa = ca.boundary()
+    f = W.noise((ma.n_elem, 4, 25), 23) + 2.0
+    c2 = _ctx(ca, ma, ka, sa)
+    u2 = c2.empty()
+    c2.project(_dev(f), u2)
+    d2 = make_disc(ca, ma)
+    assert rel_err_per_var(_host(u2), d2.project_values(f)) <= 1e-13
+
+
+def test_brj_blocks_with_dirichlet_faces():
+    _case("BRJ blocks with Dirichlet faces")
+    cfg, d, inp = mms_disc(2, 3)
+    mesh = cfg.mesh()
+    kinds, states = cfg.boundary()
+    u = d.project_values(inp["initial"])          # the v-momentum is zero: exercises the chi fallback
+    ctx = _ctx(cfg, mesh, kinds, states)
+    ctx.set_bc_field(_dev(inp["bc_field"]))
+    ctx.precond_build(_dev(u), 0.3)
+    nb = d.nv * d.ref.nm
+    dinv = torch.empty((mesh.n_elem, nb, nb), dtype=torch.float64, device="cuda")
+    ctx.precond_diag_inverse(dinv)
+    pc = OS.BRJ(d, u, 0.3)
+    ref = np.linalg.inv(pc.D)
+    got = _host(dinv)
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def _gpu_steady(P, n, max_steps=30, stats=None):
+    cfg = W.mms_config(P, n)
+    mesh = cfg.mesh()
+    inp = W.mms_inputs(cfg, mesh)
+    kinds, states = cfg.boundary()
+    ctx = _ctx(cfg, mesh, kinds, states, pc_freeze=1, newton_rtol=1e-4)
+    ctx.set_bc_field(_dev(inp["bc_field"]))
+    s = ctx.empty()
+    ctx.project(_dev(inp["forcing"]), s)
+    ctx.set_source(s)
+    u = ctx.empty()
+    ctx.project(_dev(inp["initial"]), u)
+    R = ctx.empty()
+    ctx.residual(u, R)
+    r0 = float(torch.linalg.vector_norm(R))
+    dt0 = cfg.dt()
+    for i in range(max_steps):
+        st = ctx.sdirk_step(u, dt0 * 10.0 ** min(1.0, i / 9.0))
+        if stats is not None:
+            stats.append(st)
+        ctx.residual(u, R)
+        if float(torch.linalg.vector_norm(R)) < 1e-9 * r0:
+            break
+    d = make_disc(cfg, mesh)
+    Q = np.einsum('qm,evm->evq', d.ref.B, _host(u))
+    err = np.sqrt(np.einsum('eq,evq->v', d.geo.wJ, (Q - inp["exact"]) ** 2))
+    return _host(u), err, i + 1
+
+
+def test_steady_pseudo_time_parity():
+    _case("MMS steady pseudo-time steps P=2 4x4")
+    stats = []
+    ug, eg, ng = _gpu_steady(2, 4, stats=stats)
+    uo, eo, no = mms_steady(2, 4)
+    assert ng == no
+    assert np.linalg.norm(ug - uo) <= 1e-9 * np.linalg.norm(uo)
+    assert np.allclose(eg, eo, rtol=1e-4, atol=0)
+
+
+@pytest.mark.parametrize("P,levels", [(2, (3, 4, 8, 12, 16, 20)), (3, (3, 4, 8, 12)), (4, (3, 4)), (5, (2, 3))])
+def test_manufactured_poiseuille_order_on_device(P, levels):
+    _case(f"MMS order of accuracy P={P} levels {levels}")
+    errs = []
+    for n in levels:
+        _, e, steps = _gpu_steady(P, n)
+        errs.append(e)
+        print(f"P={P} n={n}: L2 errors {e} after {steps} steps", flush=True)
+    for k in range(1, len(levels)):
+        rate = np.log(errs[k - 1] / errs[k]) / np.log(levels[k] / levels[k - 1])
+        print(f"  rate {levels[k - 1]}->{levels[k]}: {rate}", flush=True)
+        assert np.all(rate[1:] > P + 1 - 0.35), rate
