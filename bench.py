@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--batch", action="store_true",
                     help="also time the batch of 64 independent 2D problems, batched against one by one")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--mms", action="store_true",
+                    help="also run the steady manufactured Poiseuille comparison: implicit SDIRK2 (CFL 500 -> 5000) "
+                         "against ERK2 at its largest stable CFL, both to steady state, P = 2, 3, 4")
+    ap.add_argument("--mms-n", type=int, default=8, help="elements per direction of the manufactured case")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cylinder-steps", action="store_true",
                     help="cylinder workload: also time implicit steps (warmup steps ramp dt from dt/100)")
@@ -353,6 +357,9 @@ def main():
     if args.batch:
         out["batch"] = bench_batch(args.batch_steps)
 
+    if args.mms:
+        out["mms_steady"] = [bench_mms(P, args.mms_n) for P in (2, 3, 4)]
+
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
@@ -403,22 +410,140 @@ def bench_explicit(cfg, mesh, u_start, u_impl, impl_ms, T, kinds, states):
         else:
             hi = mid
     cfl = lo
-    n_steps = int(math.ceil(T / (dt20 * cfl / cfg.cfl)))
-    dte = T / n_steps
-    v = u_start.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_steps):
-        ctx.sdirk_step(v, dte)
-    torch.cuda.synchronize()
-    ems = (time.perf_counter() - t0) * 1e3
-    diff = float(torch.linalg.vector_norm(v - u_impl) / torch.linalg.vector_norm(v))
+    for attempt in range(6):
+        n_steps = int(math.ceil(T / (dt20 * cfl / cfg.cfl)))
+        dte = T / n_steps
+        v = u_start.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            ctx.sdirk_step(v, dte)
+        torch.cuda.synchronize()
+        ems = (time.perf_counter() - t0) * 1e3
+        diff = float(torch.linalg.vector_norm(v - u_impl) / torch.linalg.vector_norm(v))
+        if math.isfinite(diff) and rate_norm(v) <= 2.0 * r0:
+            break
+        log(f"ERK2 at CFL {cfl:.4f} did not stay bounded over T; retrying at 0.8 x")
+        cfl *= 0.8
     ctx.close()
     log(f"ERK2: largest stable CFL {cfl:.4f}, {n_steps} steps over T = {T:.4g} in {ems:.1f} ms; "
         f"implicit {impl_ms:.1f} ms; end states differ by {diff:.2e}")
     return {"cfl_max_stable": cfl, "cfl_implicit": cfg.cfl, "T": T, "explicit_steps": n_steps,
             "explicit_ms": ems, "implicit_ms": impl_ms, "implicit_speedup": ems / impl_ms,
             "rel_l2_diff_end_states": diff}
+
+
+def bench_mms(P, n, drop=1e-8):
+    """The paper's steady comparison on the manufactured Poiseuille flow
+    (n x n elements on [0, 1]^2, Re 100, Ma 0.1, Dirichlet data from the exact
+    solution): implicit SDIRK2 with the CFL number growing from 500 to 5000
+    over the first ten steps and the blocks rebuilt every other step, against
+    ERK2 at its largest stable CFL (bisection as in bench_explicit), each run
+    from the uniform-velocity start until ||M^-1 L + s|| has dropped by
+    `drop`.  Newton stops at alpha = 1e-3 (steady target; at 1e-8 Newton
+    stalls at the rounding level of dt R once the state is nearly steady)."""
+    import math
+    import dataclasses
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2002_04222_amd import Context
+    cfg = W.mms_config(P, n)
+    mesh = cfg.mesh()
+    inp = W.mms_inputs(cfg, mesh)
+    kinds, states = cfg.boundary()
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    def setup(scheme, **over):
+        ctx = Context(mesh, dataclasses.replace(cfg, scheme=scheme), bc_kind=kinds, bc_state=states, **over)
+        ctx.set_bc_field(dev(inp["bc_field"]))
+        s = ctx.empty()
+        ctx.project(dev(inp["forcing"]), s)
+        ctx.set_source(s)
+        u = ctx.empty()
+        ctx.project(dev(inp["initial"]), u)
+        return ctx, u
+
+    R = None
+
+    def rnorm(ctx, u):
+        ctx.residual(u, R)
+        return float(torch.linalg.vector_norm(R))
+
+    ci, u = setup("sdirk2", pc_freeze=2, newton_rtol=1e-3)
+    R = ci.empty()
+    r0 = rnorm(ci, u)
+    dt_cfl = cfg.dt() / cfg.cfl             # dt per unit CFL
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, newton, gmres = 0, 0, 0
+    r = r0
+    while r > drop * r0 and steps < 60:
+        st = ci.sdirk_step(u, dt_cfl * 500.0 * 10.0 ** min(1.0, steps / 9.0))
+        steps += 1
+        newton += sum(st["newton_its"])
+        gmres += sum(sum(x) for x in st["gmres_its"])
+        r = rnorm(ci, u)
+    torch.cuda.synchronize()
+    impl_ms = (time.perf_counter() - t0) * 1e3
+    ci.close()
+    log(f"MMS P={P}: implicit steady in {steps} steps, {impl_ms:.0f} ms; ERK2 next")
+
+    ce, u0 = setup("erk2")
+    re0 = rnorm(ce, u0)
+
+    def stable(cfl, k=2000, every=100):
+        # on the way to a steady state ||M^-1 L + s|| decays; an unstable
+        # mode makes it grow again
+        v = u0.clone()
+        best = re0
+        for _ in range(k // every):
+            for _ in range(every):
+                ce.sdirk_step(v, dt_cfl * cfl)
+            rr = rnorm(ce, v)
+            if not math.isfinite(rr) or rr > 1.5 * best:
+                return False
+            best = min(best, rr)
+        return True
+
+    lo, hi = 0.005, 1.0
+    for _ in range(8):
+        mid = math.sqrt(lo * hi)
+        if stable(mid):
+            lo = mid
+        else:
+            hi = mid
+    cfl = lo
+    for attempt in range(6):
+        v = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        esteps = 0
+        r = re0
+        best = re0
+        ok = True
+        while r > drop * re0 and esteps < 3_000_000:
+            for _ in range(500):
+                ce.sdirk_step(v, dt_cfl * cfl)
+            esteps += 500
+            r = rnorm(ce, v)
+            if not math.isfinite(r) or r > 1.5 * best:
+                ok = False
+                break
+            best = min(best, r)
+        torch.cuda.synchronize()
+        expl_ms = (time.perf_counter() - t0) * 1e3
+        if ok:
+            break
+        log(f"MMS P={P}: ERK2 at CFL {cfl:.4f} grew after {esteps} steps; retrying at 0.8 x")
+        cfl *= 0.8
+    ce.close()
+    log(f"MMS P={P} {n}x{n}: implicit {steps} steps ({newton} Newton, {gmres} GMRES) {impl_ms:.0f} ms; "
+        f"ERK2 CFL {cfl:.4f} {esteps} steps {expl_ms:.0f} ms; speed-up {expl_ms / impl_ms:.1f}")
+    return {"P": P, "elements": mesh.n_elem, "implicit_steps": steps, "implicit_newton": newton,
+            "implicit_gmres": gmres, "implicit_ms": impl_ms, "erk2_cfl_max_stable": cfl, "erk2_steps": esteps,
+            "erk2_ms": expl_ms, "erk2_converged": ok, "implicit_speedup": expl_ms / impl_ms,
+            "residual_drop": drop}
 
 
 def bench_batch(steps):
