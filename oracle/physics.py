@@ -32,7 +32,7 @@ class Gas:
     visc_law: int = 0       # 0 constant, 1 Sutherland
     T_ref_K: float = 288.15
     flux_mode: int = 0      # 0 Navier-Stokes, 1 Euler, 2 scalar diffusion test
-    riemann: int = 0        # 0 Roe, 1 local Lax-Friedrichs
+    riemann: int = 0        # 0 Roe, 1 local Lax-Friedrichs, 2 HLL, 3 HLLC, 4 AUSM+
 
 
 def cabs(x):
@@ -175,12 +175,110 @@ def llf_flux(gas: Gas, UL, UR, n):
     return 0.5 * (FL + FR) - 0.5 * lam[..., None] * (UR - UL)
 
 
+def _normal_state(gas, U, n):
+    r, v, E, p = primitives(gas, U)
+    un = np.sum(v * n, axis=-1)
+    c = np.sqrt(gas.gamma * p / r)
+    return r, v, E, p, un, c
+
+
+def _wave_speeds(gas, UL, UR, n):
+    """Signal speeds S_L, S_R of the HLL family: the smaller (larger) of the
+    left (right) acoustic speed u_n -+ c and the Roe-average one (Einfeldt's
+    estimate)."""
+    rL, vL, EL, pL, uL, cL = _normal_state(gas, UL, n)
+    rR, vR, ER, pR, uR, cR = _normal_state(gas, UR, n)
+    sL, sR = np.sqrt(rL), np.sqrt(rR)
+    vt = (sL[..., None] * vL + sR[..., None] * vR) / (sL + sR)[..., None]
+    Ht = (sL * (EL + pL) / rL + sR * (ER + pR) / rR) / (sL + sR)
+    ct = np.sqrt((gas.gamma - 1.0) * (Ht - 0.5 * np.sum(vt * vt, axis=-1)))
+    ut = np.sum(vt * n, axis=-1)
+    return np.minimum(uL - cL, ut - ct), np.maximum(uR + cR, ut + ct)
+
+
+def hll_flux(gas: Gas, UL, UR, n):
+    """HLL flux (Harten, Lax and van Leer): one intermediate state between
+    the signal speeds S_L, S_R; upwind when both have one sign."""
+    SL, SR = _wave_speeds(gas, UL, UR, n)
+    FL = normal_flux(euler_flux(gas, UL), n)
+    FR = normal_flux(euler_flux(gas, UR), n)
+    mid = (SR[..., None] * FL - SL[..., None] * FR + (SL * SR)[..., None] * (UR - UL)) / (SR - SL)[..., None]
+    return np.where((SL >= 0.0)[..., None], FL, np.where((SR <= 0.0)[..., None], FR, mid))
+
+
+def hllc_flux(gas: Gas, UL, UR, n):
+    """HLLC flux (Toro, Spruce and Speares): HLL with the contact wave
+    restored; the two star states share the contact speed S* and the
+    pressure, and keep their side's tangential velocity."""
+    SL, SR = _wave_speeds(gas, UL, UR, n)
+    rL, vL, EL, pL, uL, _ = _normal_state(gas, UL, n)
+    rR, vR, ER, pR, uR, _ = _normal_state(gas, UR, n)
+    mL, mR = rL * (SL - uL), rR * (SR - uR)
+    Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR)
+
+    def star(r, v, E, p, u, S, m):
+        f = m / (S - Ss)
+        Us = np.empty(np.broadcast_shapes(v.shape[:-1] + (v.shape[-1] + 2,)), dtype=np.result_type(r, v))
+        Us[..., 0] = f
+        Us[..., 1:-1] = f[..., None] * (v + (Ss - u)[..., None] * n)
+        Us[..., -1] = f * (E / r + (Ss - u) * (Ss + p / m))
+        return Us
+    FL = normal_flux(euler_flux(gas, UL), n)
+    FR = normal_flux(euler_flux(gas, UR), n)
+    FsL = FL + SL[..., None] * (star(rL, vL, EL, pL, uL, SL, mL) - UL)
+    FsR = FR + SR[..., None] * (star(rR, vR, ER, pR, uR, SR, mR) - UR)
+    out = np.where((Ss >= 0.0)[..., None], FsL, FsR)
+    out = np.where((SL >= 0.0)[..., None], FL, out)
+    return np.where((SR <= 0.0)[..., None], FR, out)
+
+
+AUSM_BETA, AUSM_ALPHA = 1.0 / 8.0, 3.0 / 16.0
+
+
+def ausmp_flux(gas: Gas, UL, UR, n):
+    """AUSM+ flux (Liou): the interface Mach number and pressure from the
+    polynomial splittings M+-(M), P+-(M) of both sides (beta = 1/8,
+    alpha = 3/16), the convected quantities (rho, rho u, rho H) taken
+    upwind of the interface mass flux, and the interface sound speed the
+    mean of the two sides' (read here; Liou's critical-speed variant is one
+    of several)."""
+    rL, vL, EL, pL, uL, cL = _normal_state(gas, UL, n)
+    rR, vR, ER, pR, uR, cR = _normal_state(gas, UR, n)
+    a = 0.5 * (cL + cR)
+    ML, MR = uL / a, uR / a
+
+    def split(M, sgn):
+        big = np.abs(M) >= 1.0
+        Mb = 0.5 * (M + sgn * np.abs(M))
+        Pb = 0.5 * (1.0 + sgn * np.sign(M))
+        q = M * M - 1.0
+        Ms = sgn * 0.25 * (M + sgn) ** 2 + sgn * AUSM_BETA * q * q
+        Ps = 0.25 * (M + sgn) ** 2 * (2.0 - sgn * M) + sgn * AUSM_ALPHA * M * q * q
+        return np.where(big, Mb, Ms), np.where(big, Pb, Ps)
+    MpL, PpL = split(ML, 1.0)
+    MmR, PmR = split(MR, -1.0)
+    m = MpL + MmR
+    p = PpL * pL + PmR * pR
+
+    def phi(r, v, E, pp):
+        return np.concatenate([r[..., None], (r[..., None] * v), (E + pp)[..., None]], axis=-1)
+    mp, mm = 0.5 * (m + np.abs(m)), 0.5 * (m - np.abs(m))
+    F = a[..., None] * (mp[..., None] * phi(rL, vL, EL, pL) + mm[..., None] * phi(rR, vR, ER, pR))
+    F[..., 1:-1] = F[..., 1:-1] + p[..., None] * n
+    return F
+
+
+RIEMANN = {0: "roe", 1: "llf", 2: "hll", 3: "hllc", 4: "ausm+"}
+
+
 def riemann_flux(gas: Gas, UL, UR, n):
+    """The Riemann flux chosen by gas.riemann: 0 Roe, 1 local
+    Lax-Friedrichs, 2 HLL, 3 HLLC, 4 AUSM+ (the paper's solver offers these
+    among others, Sec. 4.3)."""
     if gas.flux_mode == 2:
         return np.zeros(np.broadcast_shapes(UL.shape, UR.shape), dtype=np.result_type(UL, UR))
-    if gas.riemann == 0:
-        return roe_flux(gas, UL, UR, n)
-    return llf_flux(gas, UL, UR, n)
+    fn = {0: roe_flux, 1: llf_flux, 2: hll_flux, 3: hllc_flux, 4: ausmp_flux}[gas.riemann]
+    return fn(gas, UL, UR, n)
 
 
 def ip_face_fluxes(gas: Gas, Uo, Un, go, gn, n, beta_p):
