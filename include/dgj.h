@@ -117,7 +117,8 @@ typedef struct {
   double T_ref_K;             /* Sutherland reference temperature, kelvin */
   int32_t visc_law;           /* 0 constant mu = 1/Re, 1 Sutherland */
   int32_t flux_mode;          /* 0 Navier-Stokes, 1 Euler, 2 scalar diffusion test */
-  int32_t riemann;            /* 0 Roe, 1 local Lax-Friedrichs */
+  int32_t riemann;            /* 0 Roe, 1 local Lax-Friedrichs, 2 HLL, 3 HLLC, 4 AUSM+ (Sec. 4.3 lists
+                                 these among its solver's fluxes) */
 } dgj_phys;
 
 /* Implicit solver options (Sec. 3.2, Sec. 4.2.2). */

@@ -1214,7 +1214,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     if (solver->gmres_restart < 1 || solver->gmres_restart > 60) fail(DGJ_EINVAL, "gmres_restart must be in 1..60");
     if (!scheme_known(solver->scheme)) fail(DGJ_EINVAL, "unknown scheme %d", solver->scheme);
     if (solver->pc_precision < 0 || solver->pc_precision > 2) fail(DGJ_EINVAL, "bad pc_precision");
-    if (phys->flux_mode < 0 || phys->flux_mode > 2 || phys->riemann < 0 || phys->riemann > 1)
+    if (phys->flux_mode < 0 || phys->flux_mode > 2 || phys->riemann < 0 || phys->riemann > 4)
       fail(DGJ_EINVAL, "bad flux options");
     c->dim = mesh->dim;
     c->P = mesh->P;

@@ -17,7 +17,7 @@ struct Phys {
   double gamma, Pr, Re, Ma, T_ref_K;
   int visc_law;    // 0 constant mu = 1/Re, 1 Sutherland
   int flux_mode;   // 0 Navier-Stokes, 1 Euler, 2 scalar diffusion test (G = grad U / Re, F = 0)
-  int riemann;     // 0 Roe, 1 local Lax-Friedrichs
+  int riemann;     // 0 Roe, 1 local Lax-Friedrichs, 2 HLL, 3 HLLC, 4 AUSM+
 };
 
 // ---------------------------------------------------------------- dual numbers
@@ -288,6 +288,154 @@ __device__ __forceinline__ void llf_flux(const Phys& ph, const double* UL, const
   for (int v = 0; v < NV; ++v) Fn[v] = 0.5 * (F[0][v] + F[1][v]) - 0.5 * lm * (UR[v] - UL[v]);
 }
 
+// side state along n: density, velocity, pressure, normal velocity, sound speed
+template <int D>
+struct SideState {
+  double r, v[D], p, E, un, c;
+};
+template <int D>
+__device__ __forceinline__ SideState<D> side_state(const Phys& ph, const double* U, const double* n) {
+  SideState<D> s;
+  s.r = U[0];
+  s.E = U[D + 1];
+  double ke = 0.0, un = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    s.v[c] = U[1 + c] / s.r;
+    ke += s.v[c] * U[1 + c];
+    un += s.v[c] * n[c];
+  }
+  s.p = (ph.gamma - 1.0) * (U[D + 1] - 0.5 * ke);
+  s.un = un;
+  s.c = sqrt(ph.gamma * s.p / s.r);
+  return s;
+}
+template <int D>
+__device__ __forceinline__ void phys_normal_flux(const double* U, const SideState<D>& s, const double* n, double* F) {
+  F[0] = s.r * s.un;
+#pragma unroll
+  for (int c = 0; c < D; ++c) F[1 + c] = U[1 + c] * s.un + s.p * n[c];
+  F[D + 1] = s.un * (U[D + 1] + s.p);
+}
+// Einfeldt's signal speeds: the smaller (larger) of the left (right)
+// acoustic speed and the Roe-average one
+template <int D>
+__device__ __forceinline__ void wave_speeds(const Phys& ph, const SideState<D>& L, const SideState<D>& R,
+                                            const double* n, double& SL, double& SR) {
+  const double sL = sqrt(L.r), sR = sqrt(R.r), is = 1.0 / (sL + sR);
+  double q2 = 0.0, ut = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double vt = (sL * L.v[c] + sR * R.v[c]) * is;
+    q2 += vt * vt;
+    ut += vt * n[c];
+  }
+  const double Ht = (sL * (L.E + L.p) / L.r + sR * (R.E + R.p) / R.r) * is;
+  const double ct = sqrt((ph.gamma - 1.0) * (Ht - 0.5 * q2));
+  SL = fmin(L.un - L.c, ut - ct);
+  SR = fmax(R.un + R.c, ut + ct);
+}
+
+// HLL (Harten, Lax, van Leer): one state between the signal speeds
+template <int D>
+__device__ __forceinline__ void hll_flux(const Phys& ph, const double* UL, const double* UR, const double* n,
+                                         double* Fn) {
+  constexpr int NV = D + 2;
+  const SideState<D> L = side_state<D>(ph, UL, n), R = side_state<D>(ph, UR, n);
+  double SL, SR;
+  wave_speeds<D>(ph, L, R, n, SL, SR);
+  double FL[NV], FR[NV];
+  phys_normal_flux<D>(UL, L, n, FL);
+  phys_normal_flux<D>(UR, R, n, FR);
+  if (SL >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fn[v] = FL[v];
+  } else if (SR <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fn[v] = FR[v];
+  } else {
+    const double id = 1.0 / (SR - SL);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fn[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
+  }
+}
+
+// HLLC (Toro, Spruce, Speares): HLL with the contact wave; the star states
+// share the contact speed S* and keep their side's tangential velocity
+template <int D>
+__device__ __forceinline__ void hllc_flux(const Phys& ph, const double* UL, const double* UR, const double* n,
+                                          double* Fn) {
+  constexpr int NV = D + 2;
+  const SideState<D> L = side_state<D>(ph, UL, n), R = side_state<D>(ph, UR, n);
+  double SL, SR;
+  wave_speeds<D>(ph, L, R, n, SL, SR);
+  const bool left = SL >= 0.0, right = SR <= 0.0;
+  const double mL = L.r * (SL - L.un), mR = R.r * (SR - R.un);
+  const double Ss = (R.p - L.p + mL * L.un - mR * R.un) / (mL - mR);
+  const bool useL = left || (!right && Ss >= 0.0);
+  const SideState<D>& K = useL ? L : R;
+  const double* UK = useL ? UL : UR;
+  const double SK = useL ? SL : SR, mK = useL ? mL : mR;
+  double F[NV];
+  phys_normal_flux<D>(UK, K, n, F);
+  if (left || right) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fn[v] = F[v];
+    return;
+  }
+  const double f = mK / (SK - Ss);
+  double Us[NV];
+  Us[0] = f;
+#pragma unroll
+  for (int c = 0; c < D; ++c) Us[1 + c] = f * (K.v[c] + (Ss - K.un) * n[c]);
+  Us[D + 1] = f * (K.E / K.r + (Ss - K.un) * (Ss + K.p / mK));
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Fn[v] = F[v] + SK * (Us[v] - UK[v]);
+}
+
+// AUSM+ (Liou): interface Mach number and pressure from the polynomial
+// splittings (beta = 1/8, alpha = 3/16), quantities convected upwind of
+// the interface mass flux, interface sound speed the mean of the sides'
+__device__ __forceinline__ void ausm_split(double M, double sgn, double& Ms, double& Ps) {
+  if (fabs_(M) >= 1.0) {
+    Ms = 0.5 * (M + sgn * fabs_(M));
+    Ps = 0.5 * (1.0 + sgn * (M > 0.0 ? 1.0 : (M < 0.0 ? -1.0 : 0.0)));
+  } else {
+    const double q = M * M - 1.0;
+    Ms = sgn * 0.25 * (M + sgn) * (M + sgn) + sgn * 0.125 * q * q;
+    Ps = 0.25 * (M + sgn) * (M + sgn) * (2.0 - sgn * M) + sgn * 0.1875 * M * q * q;
+  }
+}
+template <int D>
+__device__ __forceinline__ void ausmp_flux(const Phys& ph, const double* UL, const double* UR, const double* n,
+                                           double* Fn) {
+  const SideState<D> L = side_state<D>(ph, UL, n), R = side_state<D>(ph, UR, n);
+  const double a = 0.5 * (L.c + R.c);
+  double MpL, PpL, MmR, PmR;
+  ausm_split(L.un / a, 1.0, MpL, PpL);
+  ausm_split(R.un / a, -1.0, MmR, PmR);
+  const double m = MpL + MmR;
+  const double p = PpL * L.p + PmR * R.p;
+  const double mp = 0.5 * (m + fabs_(m)), mm = 0.5 * (m - fabs_(m));
+  Fn[0] = a * (mp * L.r + mm * R.r);
+#pragma unroll
+  for (int c = 0; c < D; ++c) Fn[1 + c] = a * (mp * UL[1 + c] + mm * UR[1 + c]) + p * n[c];
+  Fn[D + 1] = a * (mp * (L.E + L.p) + mm * (R.E + R.p));
+}
+
+// the Riemann flux chosen by ph.riemann (0 Roe, 1 LLF, 2 HLL, 3 HLLC, 4 AUSM+)
+template <int D>
+__device__ __forceinline__ void riemann_flux(const Phys& ph, const double* UL, const double* UR, const double* n,
+                                             double* Fn) {
+  switch (ph.riemann) {
+    case 0: roe_flux<D>(ph, UL, UR, n, Fn); break;
+    case 1: llf_flux<D>(ph, UL, UR, n, Fn); break;
+    case 2: hll_flux<D>(ph, UL, UR, n, Fn); break;
+    case 3: hllc_flux<D>(ph, UL, UR, n, Fn); break;
+    default: ausmp_flux<D>(ph, UL, UR, n, Fn); break;
+  }
+}
+
 // Numerical normal flux seen from side 'o' with outward normal n:
 //   H = Fhat(Uo, Un, n) - [ n.G(Ubar, {gU}) - beta n.G(Ubar, dU (x) n) ]
 //   S[j] = 1/2 n.G(Ubar, dU (x) e_j)
@@ -303,10 +451,8 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, cons
   if (ph.flux_mode == 2) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = 0.0;
-  } else if (ph.riemann == 0) {
-    roe_flux<D>(ph, Uo, Un, n, F);
   } else {
-    llf_flux<D>(ph, Uo, Un, n, F);
+    riemann_flux<D>(ph, Uo, Un, n, F);
   }
   if (ph.flux_mode == 1) {
 #pragma unroll
@@ -437,10 +583,8 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
     if (ph.flux_mode == 2) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) F[v] = 0.0;
-    } else if (ph.riemann == 0) {
-      roe_flux<D>(ph, Uo, Un, n, F);
     } else {
-      llf_flux<D>(ph, Uo, Un, n, F);
+      riemann_flux<D>(ph, Uo, Un, n, F);
     }
     H[D + 1] = F[D + 1];
     if (S) {
