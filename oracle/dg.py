@@ -47,7 +47,7 @@ class Disc:
     elem_h: Optional[np.ndarray]
     face_nbr: np.ndarray
     bc: Optional[Callable] = None   # extra boundary contribution hook (tests)
-    bc_kind: Optional[np.ndarray] = None    # per boundary id: BC_FARFIELD or BC_WALL
+    bc_kind: Optional[np.ndarray] = None    # per boundary id: one of the BC_* kinds of physics.py
     bc_state: Optional[np.ndarray] = None   # per boundary id: freestream conserved state [nv]
     geo_nodes: Optional[np.ndarray] = None  # curved elements: isoparametric nodes
     geo_order: int = 1

@@ -327,6 +327,21 @@ def face_flux_own(gas: Gas, Uo, Un, go, gn, n, beta_p):
 # Poiseuille case applies the exact solution weakly): the ghost state is a
 # given state at every face point.
 BC_FARFIELD, BC_WALL, BC_DIRICHLET = 0, 1, 2
+# The other kinds of its list, with readings that keep the number of
+# conditions equal to the number of incoming characteristics:
+#  slip wall / symmetry plane: the normal momentum mirrored; no heat flux
+#    and no tangential viscous traction through the face;
+#  isothermal no-slip wall: the velocity negated, the pressure kept and the
+#    ghost temperature the interior's mirrored about the wall temperature
+#    (that of the given state), so that their mean is the wall temperature
+#    and a fluid at rest sees a stationary contact (no mass flux) -- the
+#    viscous penalty then drives the wall temperature weakly;
+#  zero-order extrapolation: the ghost is the interior state;
+#  pressure outflow: the interior state with the given pressure where the
+#    outflow is subsonic (the interior state where supersonic);
+#  pressure inflow: the given density and velocity with the interior
+#    pressure where the inflow is subsonic (the given state where supersonic).
+BC_SLIP, BC_ISOTHERMAL, BC_EXTRAPOLATE, BC_PRESSURE_OUT, BC_PRESSURE_IN = 3, 4, 5, 6, 7
 
 
 FARFIELD_BLEND = 0.02   # half-width of the inflow/outflow blend in u_nb, relative to c_b
@@ -377,10 +392,53 @@ def wall_ghost(U):
     return G
 
 
+def ghost_state(gas: Gas, kind, U, n, Ub):
+    """Ghost state of the kinds other than far field and Dirichlet (see the
+    readings above); Ub is the boundary id's given state."""
+    g = gas.gamma
+    G = U.copy()
+    r, v, E, p = primitives(gas, U)
+    ke = 0.5 * r * np.sum(v * v, axis=-1)
+    if kind == BC_WALL:
+        return wall_ghost(U)
+    if kind == BC_SLIP:
+        mn = np.sum(U[..., 1:-1] * n, axis=-1)
+        G[..., 1:-1] = U[..., 1:-1] - 2.0 * mn[..., None] * n
+        return G
+    if kind == BC_ISOTHERMAL:
+        rb, vb, Eb, pb = primitives(gas, np.broadcast_to(Ub, U.shape))
+        Tw, T = pb / rb, p / r                              # temperatures up to the same factor
+        rg = r * T / (2.0 * Tw - T)                         # same pressure, mirrored temperature
+        G[..., 0] = rg
+        G[..., 1:-1] = -rg[..., None] * v
+        G[..., -1] = p / (g - 1.0) + 0.5 * rg * np.sum(v * v, axis=-1)
+        return G
+    if kind == BC_EXTRAPOLATE:
+        return G
+    if kind == BC_PRESSURE_OUT:
+        _, _, _, pb = primitives(gas, np.broadcast_to(Ub, U.shape))
+        c = np.sqrt(g * p / r)
+        sub = np.real(np.sum(v * n, axis=-1)) < np.real(c)
+        G[..., -1] = np.where(sub, pb / (g - 1.0) + ke, E)
+        return G
+    if kind == BC_PRESSURE_IN:
+        Ubb = np.broadcast_to(Ub, U.shape)
+        rb, vb, Eb, pb = primitives(gas, Ubb)
+        cb = np.sqrt(g * pb / rb)
+        sup = np.real(np.sum(vb * n, axis=-1)) <= -np.real(cb)
+        G = np.array(Ubb, dtype=np.result_type(U, Ubb))
+        G[..., -1] = np.where(sup, Eb, p / (g - 1.0) + 0.5 * rb * np.sum(vb * vb, axis=-1))
+        return G
+    raise ValueError(f"unknown boundary kind {kind}")
+
+
 def boundary_flux_own(gas: Gas, kind, Uo, go, n, beta_p, Uinf=None):
     """Boundary face flux (H^n, S) seen from the interior with outward normal
     n: ghost state per kind (Dirichlet: Uinf holds the ghost state of every
-    point), ghost gradient = interior gradient; at an
+    point; far field, isothermal wall and the pressure kinds read their
+    given state from Uinf), ghost gradient = interior gradient; at slip and
+    no-slip adiabatic walls no heat flux crosses, at a slip wall no
+    tangential traction either; at an
     adiabatic wall the heat flux through the wall is zero, so the energy
     components of the viscous face fluxes vanish (the work term vanishes with
     the zero wall velocity)."""
@@ -389,12 +447,18 @@ def boundary_flux_own(gas: Gas, kind, Uo, go, n, beta_p, Uinf=None):
     elif kind == BC_FARFIELD:
         Un = farfield_ghost(gas, Uo, n, Uinf)
     else:
-        Un = wall_ghost(Uo)
+        Un = ghost_state(gas, kind, Uo, n, Uinf)
     F = riemann_flux(gas, Uo, Un, n)
     Gn, S = ip_face_fluxes(gas, Uo, Un, go, go, n, beta_p)
-    if kind == BC_WALL:
+    if kind in (BC_WALL, BC_SLIP):
         Gn = Gn.copy()
         S = S.copy()
         Gn[..., -1] = 0.0
         S[..., -1] = 0.0
+    if kind == BC_SLIP:
+        # only the normal viscous traction remains
+        gm = np.sum(Gn[..., 1:-1] * n, axis=-1)
+        Gn[..., 1:-1] = gm[..., None] * n
+        sm = np.einsum('...jc,...c->...j', S[..., 1:-1], n)
+        S[..., 1:-1] = sm[..., None] * n[..., None, :]
     return F - Gn, S
