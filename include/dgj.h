@@ -62,9 +62,10 @@ enum { DGJ_PC_F64 = 0, DGJ_PC_F32 = 1, DGJ_PC_BF16 = 2 };
 typedef struct dgj_ctx dgj_ctx;
 
 /* Boundary condition kinds.  No formulas are given in the paper, which
- * only names the kinds its solver offers (Sec. 5); the ones built are
- * those of its cylinder case and the Dirichlet data of its manufactured
- * Poiseuille case (Sec. 6.1).  A boundary face takes the interior trace and
+ * only names the kinds its solver offers (Sec. 4.3): all of them are built,
+ * with the readings below (periodic faces are ordinary interior faces;
+ * symmetry and slip wall are one kind; time-dependent Dirichlet data are
+ * given by setting the field again between steps).  A boundary face takes the interior trace and
  * a ghost state with the interior gradient, and the interior face fluxes
  * (Riemann flux, interior-penalty viscous terms) apply:
  *  DGJ_BC_FARFIELD: 1D characteristic far field.  With u_n the outward
@@ -81,8 +82,21 @@ typedef struct dgj_ctx dgj_ctx;
  *    viscous flux and of the symmetric interior-penalty term are zero (no
  *    heat flux through the wall).
  *  DGJ_BC_DIRICHLET: the ghost state is a given state at every face point
- *    (dgj_set_bc_field), e.g. an exact solution applied weakly. */
-enum { DGJ_BC_FARFIELD = 0, DGJ_BC_WALL = 1, DGJ_BC_DIRICHLET = 2 };
+ *    (dgj_set_bc_field), e.g. an exact solution applied weakly.
+ *  DGJ_BC_SLIP: slip wall / symmetry plane.  Ghost = interior with the
+ *    normal momentum mirrored; no heat flux and no tangential viscous
+ *    traction (only the normal viscous traction) through the face.
+ *  DGJ_BC_ISOTHERMAL: no-slip wall at the temperature of the id's state.
+ *    Ghost: velocity negated, interior pressure, temperature mirrored
+ *    about the wall temperature (a fluid at rest sees a stationary contact).
+ *  DGJ_BC_EXTRAPOLATE: zero-order extrapolation, ghost = interior.
+ *  DGJ_BC_PRESSURE_OUT: ghost = interior with the id's pressure where the
+ *    outflow is subsonic, the interior state where supersonic.
+ *  DGJ_BC_PRESSURE_IN: ghost = the id's density and velocity with the
+ *    interior pressure where the inflow is subsonic, the id's state where
+ *    supersonic. */
+enum { DGJ_BC_FARFIELD = 0, DGJ_BC_WALL = 1, DGJ_BC_DIRICHLET = 2, DGJ_BC_SLIP = 3, DGJ_BC_ISOTHERMAL = 4,
+       DGJ_BC_EXTRAPOLATE = 5, DGJ_BC_PRESSURE_OUT = 6, DGJ_BC_PRESSURE_IN = 7 };
 
 /* Mesh of affine boxes (host arrays, copied by dgj_create). */
 typedef struct {
@@ -95,10 +109,10 @@ typedef struct {
   const int32_t *face_nbr;    /* host [n_elem][2*dim]: element across the face, or -(id+1)
                                  for a face on boundary id (0 <= id < n_bc) */
   int32_t n_bc;               /* number of boundary ids; 0 for periodic meshes */
-  const int32_t *bc_kind;     /* host [n_bc]: DGJ_BC_FARFIELD, DGJ_BC_WALL or DGJ_BC_DIRICHLET
-                                 (NULL if n_bc = 0) */
-  const double *bc_state;     /* host [n_bc][dim+2]: freestream conserved state of each far-field
-                                 id (rho > 0, p > 0); entries of other ids are not read */
+  const int32_t *bc_kind;     /* host [n_bc]: one of the DGJ_BC_* kinds (NULL if n_bc = 0) */
+  const double *bc_state;     /* host [n_bc][dim+2]: the given conserved state of each far-field,
+                                 isothermal-wall and pressure id (rho > 0, p > 0); entries of
+                                 the other ids are not read */
   int32_t geo_order;          /* curved elements: order g of the element maps (1..7) */
   const double *geo_nodes;    /* host [n_elem][(g+1)^dim][dim] or NULL (affine boxes).  When
                                  set, elements are isoparametric: x(xi) = sum_c X_c l_c(xi),

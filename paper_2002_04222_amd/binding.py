@@ -16,7 +16,8 @@ DGJ_OK = 0
 DGJ_BEULER, DGJ_SDIRK2, DGJ_SDIRK3, DGJ_SDIRK4, DGJ_BDF2, DGJ_ERK2 = 1, 2, 3, 4, 12, 20
 MAX_STAGES = 6
 DGJ_PC_F64, DGJ_PC_F32, DGJ_PC_BF16 = 0, 1, 2
-DGJ_BC_FARFIELD, DGJ_BC_WALL, DGJ_BC_DIRICHLET = 0, 1, 2
+(DGJ_BC_FARFIELD, DGJ_BC_WALL, DGJ_BC_DIRICHLET, DGJ_BC_SLIP, DGJ_BC_ISOTHERMAL, DGJ_BC_EXTRAPOLATE,
+ DGJ_BC_PRESSURE_OUT, DGJ_BC_PRESSURE_IN) = range(8)
 STATUS = {0: "OK", -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOTCONV", -5: "ENAN", -6: "ESINGULAR",
           -7: "EUNSUPPORTED"}
 

@@ -1265,15 +1265,14 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     const int NVh = D + 2;
     for (int b = 0; b < mesh->n_bc; ++b) {
       const int k = mesh->bc_kind[b];
-      if (k != DGJ_BC_FARFIELD && k != DGJ_BC_WALL && k != DGJ_BC_DIRICHLET)
-        fail(DGJ_EINVAL, "boundary %d: unknown kind %d", b, k);
+      if (k < DGJ_BC_FARFIELD || k > DGJ_BC_PRESSURE_IN) fail(DGJ_EINVAL, "boundary %d: unknown kind %d", b, k);
       if (k == DGJ_BC_DIRICHLET) c->has_dirichlet = true;
-      if (k == DGJ_BC_FARFIELD) {
+      if (k == DGJ_BC_FARFIELD || k == DGJ_BC_ISOTHERMAL || k == DGJ_BC_PRESSURE_OUT || k == DGJ_BC_PRESSURE_IN) {
         const double* U = mesh->bc_state + b * NVh;
         double ke = 0.0;
         for (int j = 0; j < D; ++j) ke += U[1 + j] * U[1 + j];
         const double p = (phys->gamma - 1.0) * (U[D + 1] - 0.5 * ke / U[0]);
-        if (!(U[0] > 0.0) || !(p > 0.0)) fail(DGJ_EINVAL, "boundary %d: freestream needs rho > 0 and p > 0", b);
+        if (!(U[0] > 0.0) || !(p > 0.0)) fail(DGJ_EINVAL, "boundary %d: the given state needs rho > 0 and p > 0", b);
       }
     }
     for (long e = 0; e < E; ++e) {

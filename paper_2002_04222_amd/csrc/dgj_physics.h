@@ -507,7 +507,8 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, cons
 // by w = (1 + tanh(u_nb / (0.02 c_b)))/2;
 // no-slip wall: mirrored momentum (zero wall velocity), with the heat flux
 // through the wall zero (adiabatic), so the viscous energy fluxes vanish.
-enum { BC_FARFIELD = 0, BC_WALL = 1, BC_DIRICHLET = 2 };
+enum { BC_FARFIELD = 0, BC_WALL = 1, BC_DIRICHLET = 2, BC_SLIP = 3, BC_ISOTHERMAL = 4, BC_EXTRAPOLATE = 5,
+       BC_PRESSURE_OUT = 6, BC_PRESSURE_IN = 7 };
 
 template <int D>
 __device__ __forceinline__ void farfield_ghost(const Phys& ph, const double* Ui, const double* n, const double* Uo,
@@ -558,6 +559,82 @@ __device__ __forceinline__ void farfield_ghost(const Phys& ph, const double* Ui,
   Ub[D + 1] = pb / (g - 1.0) + 0.5 * rb * kb;
 }
 
+// Ghost state of boundary kind `kind` for the interior state Uo at a face
+// point with outward normal n; Ub is the id's given state (Dirichlet: the
+// point's state).  Far field by characteristics; no-slip adiabatic wall:
+// momentum negated; slip wall: normal momentum mirrored; isothermal wall:
+// velocity negated, pressure kept, temperature mirrored about the given
+// state's; extrapolation: the interior; pressure outflow: the given
+// pressure where the outflow is subsonic; pressure inflow: the given
+// density and velocity with the interior pressure where the inflow is
+// subsonic, the given state where supersonic.
+template <int D>
+__device__ __forceinline__ void ghost_state(const Phys& ph, int kind, const double* Uo, const double* n,
+                                            const double* Ub, double* Un) {
+  constexpr int NV = D + 2;
+  const double g = ph.gamma;
+  if (kind == BC_DIRICHLET) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = Ub[v];
+    return;
+  }
+  if (kind == BC_FARFIELD) {
+    farfield_ghost<D>(ph, Uo, n, Ub, Un);
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Un[v] = Uo[v];
+  if (kind == BC_WALL) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) Un[1 + c] = -Uo[1 + c];
+    return;
+  }
+  if (kind == BC_EXTRAPOLATE) return;
+  const double r = Uo[0];
+  double ke = 0.0, un = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    ke += Uo[1 + c] * Uo[1 + c];
+    un += Uo[1 + c] * n[c];
+  }
+  ke *= 0.5 / r;
+  const double p = (g - 1.0) * (Uo[D + 1] - ke);
+  if (kind == BC_SLIP) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) Un[1 + c] = Uo[1 + c] - 2.0 * un * n[c];
+    return;
+  }
+  double keb = 0.0, unb = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    keb += Ub[1 + c] * Ub[1 + c];
+    unb += Ub[1 + c] * n[c];
+  }
+  keb *= 0.5 / Ub[0];
+  const double pb = (g - 1.0) * (Ub[D + 1] - keb);
+  if (kind == BC_ISOTHERMAL) {
+    const double Tw = pb / Ub[0], T = p / r;
+    const double rg = r * T / (2.0 * Tw - T);
+    double kg = 0.0;
+    Un[0] = rg;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double vc = Uo[1 + c] / r;
+      Un[1 + c] = -rg * vc;
+      kg += vc * vc;
+    }
+    Un[D + 1] = p / (g - 1.0) + 0.5 * rg * kg;
+  } else if (kind == BC_PRESSURE_OUT) {
+    const double c = sqrt(g * p / r);
+    if (un / r < c) Un[D + 1] = pb / (g - 1.0) + ke;
+  } else {   // BC_PRESSURE_IN
+    const double cb = sqrt(g * pb / Ub[0]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = Ub[v];
+    if (!(unb / Ub[0] <= -cb)) Un[D + 1] = p / (g - 1.0) + keb;
+  }
+}
+
 // boundary face flux seen from the interior (outward normal n)
 template <int D>
 __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const double* Uo, const double (*go)[D + 2],
@@ -565,20 +642,12 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
                                               double (*S)[D + 2]) {
   constexpr int NV = D + 2;
   double Un[NV];
-  if (kind == BC_DIRICHLET) {
-    // the given state at this face point (Uinf points at it)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Un[v] = Uinf[v];
-  } else if (kind == BC_FARFIELD) {
-    farfield_ghost<D>(ph, Uo, n, Uinf, Un);
-  } else {
-    Un[0] = Uo[0];
-#pragma unroll
-    for (int c = 0; c < D; ++c) Un[1 + c] = -Uo[1 + c];
-    Un[D + 1] = Uo[D + 1];
-  }
+  ghost_state<D>(ph, kind, Uo, n, Uinf, Un);
   face_flux<D>(ph, Uo, Un, go, go, n, beta, H, S);
-  if (kind == BC_WALL) {
+  if (kind == BC_WALL || kind == BC_SLIP) {
+    // no heat flux (and no work) through the wall: the energy components
+    // keep only the Riemann flux; a slip wall also takes no tangential
+    // viscous traction
     double F[NV];
     if (ph.flux_mode == 2) {
 #pragma unroll
@@ -590,6 +659,24 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
     if (S) {
 #pragma unroll
       for (int j = 0; j < D; ++j) S[j][D + 1] = 0.0;
+    }
+    if (kind == BC_SLIP) {
+      // viscous momentum flux G = F - H, keep its normal part
+      double gn = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) gn += (F[1 + c] - H[1 + c]) * n[c];
+#pragma unroll
+      for (int c = 0; c < D; ++c) H[1 + c] = F[1 + c] - gn * n[c];
+      if (S) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          double sn = 0.0;
+#pragma unroll
+          for (int c = 0; c < D; ++c) sn += S[j][1 + c] * n[c];
+#pragma unroll
+          for (int c = 0; c < D; ++c) S[j][1 + c] = sn * n[c];
+        }
+      }
     }
   }
 }

@@ -173,10 +173,11 @@ def test_bc_create_rejects_bad_ids_and_kinds():
     with pytest.raises(DgjError) as ei:
         _ctx(cfg, mesh, k[:2], st[:2])       # ids 2 and 3 undefined
     assert ei.value.code == -1
-    bad = k.copy()
-    bad[0] = 7
-    with pytest.raises(DgjError):
-        _ctx(cfg, mesh, bad, st)
+    for kind in (8, -1):                      # kinds 0..7 exist
+        bad = k.copy()
+        bad[0] = kind
+        with pytest.raises(DgjError):
+            _ctx(cfg, mesh, bad, st)
     neg = st.copy()
     neg[0, 0] = -1.0
     with pytest.raises(DgjError):
