@@ -51,6 +51,7 @@ class Disc:
     bc_state: Optional[np.ndarray] = None   # per boundary id: freestream conserved state [nv]
     geo_nodes: Optional[np.ndarray] = None  # curved elements: isoparametric nodes
     geo_order: int = 1
+    viscous: str = "ip"                     # viscous face terms: "ip" (Eq. 12) or "ldg"
     bc_field: Optional[np.ndarray] = None   # Dirichlet ghost states [E, 2d, nv, nqf] (faces of that kind)
     source: Optional[np.ndarray] = None     # modal source [E, nv, nm] added to M^-1 L
 
@@ -138,6 +139,8 @@ class Disc:
         """L(u) of Eq. 16 (the right-hand side before M^-1)."""
         gas, ref, d = self.gas, self.ref, self.dim
         u = np.asarray(u)
+        if self.viscous == "ldg":
+            return self.L_ldg(u)
         Q, gQ = self.vol_values(u)
         H = euler_flux(gas, Q) - viscous_flux(gas, Q, gQ)                  # [e, q, j, v]
         wq = self.geo.wJ                                                     # [e, q]
@@ -168,6 +171,91 @@ class Disc:
                 L += self.boundary_terms(u)
             else:
                 raise ValueError("mesh has boundary faces but no boundary condition")
+        return L
+
+    # -- LDG (the viscous option "ldg"; readings in physics.py) ------------------
+    def _boundary_data(self, u, e, f, bid, Qo):
+        """Per-point given states Uinf [k, p, v] of boundary faces (e, f)."""
+        out = np.zeros(Qo.shape)
+        for b in np.unique(bid):
+            k = bid == b
+            if int(self.bc_kind[b]) == BC_DIRICHLET:
+                out[k] = np.transpose(self.bc_field[e[k], f], (0, 2, 1))
+            else:
+                out[k] = self.bc_state[b]
+        return out
+
+    def ldg_lift(self, u):
+        """r[e, j, v, m] with M_e r_j = sum over the faces of the integral of
+        phi (u_hat - u^-) n_j: nonzero on faces where the element is the
+        right one (u_hat from the left) and on boundary faces (u_hat the mean
+        of interior and ghost states)."""
+        from .physics import boundary_ghost
+        ref, d = self.ref, self.dim
+        rhs = np.zeros((self.n_elem, d) + self.shape[1:], dtype=np.result_type(u, np.float64))
+        for axis in range(d):
+            eL, eR = self.interior_faces(axis)
+            fL, fR = 2 * axis + 1, 2 * axis
+            QL, _ = self.trace(u, eL, fL)
+            QR, _ = self.trace(u, eR, fR)
+            n = -self.geo.nf[fL][eL]                        # outward from the right element
+            wf = self.geo.wJf[fL][eL]
+            c = np.einsum('pm,kpv,kp,kpj->kjvm', ref.BF[fR], QL - QR, wf, n)
+            np.add.at(rhs, eR, c)
+        if self.bc_kind is not None:
+            for e, f, bid in self.boundary_faces():
+                Qo, _ = self.trace(u, e, f)
+                n = self.geo.nf[f][e]
+                Ub = self._boundary_data(u, e, f, bid, Qo)
+                Ug = np.zeros(Qo.shape, dtype=Qo.dtype)
+                for b in np.unique(bid):
+                    k = bid == b
+                    Ug[k] = boundary_ghost(self.gas, int(self.bc_kind[b]), Qo[k], n[k], Ub[k])
+                wf = self.geo.wJf[f][e]
+                c = np.einsum('pm,kpv,kp,kpj->kjvm', ref.BF[f], 0.5 * (Ug - Qo), wf, n)
+                np.add.at(rhs, e, c)
+        Minv = np.linalg.inv(self.M)
+        return np.einsum('emn,ejvn->ejvm', Minv, rhs)
+
+    def L_ldg(self, u):
+        from .physics import riemann_flux, ldg_viscous_flux_n, boundary_flux_own_ldg
+        gas, ref, d = self.gas, self.ref, self.dim
+        r = self.ldg_lift(u)
+        Q, gQ = self.vol_values(u)
+        gQ = gQ + np.einsum('qm,ejvm->eqjv', ref.B, r)
+        H = euler_flux(gas, Q) - viscous_flux(gas, Q, gQ)
+        wq = self.geo.wJ
+        L = np.zeros(u.shape, dtype=np.result_type(u, np.float64))
+        for k in range(d):
+            Hk = np.einsum('eqj,eqjv->eqv', self.geo.Gq[:, :, k, :], H)
+            L += np.einsum('qm,eqv->evm', ref.D[k], Hk * wq[:, :, None])
+        for axis in range(d):
+            eL, eR = self.interior_faces(axis)
+            fL, fR = 2 * axis + 1, 2 * axis
+            QL, _ = self.trace(u, eL, fL)
+            QR, gR = self.trace(u, eR, fR)
+            gR = gR + np.einsum('pm,kjvm->kpjv', ref.BF[fR], r[eR])
+            n = self.geo.nf[fL][eL]
+            beta = np.broadcast_to(self.beta_p(eL, eR, axis)[:, None], QL.shape[:-1])
+            Hn = riemann_flux(gas, QL, QR, n) - ldg_viscous_flux_n(gas, QL, gR, QL - QR, n, beta)
+            wf = self.geo.wJf[fL][eL]
+            np.add.at(L, eL, -np.einsum('pm,kpv->kvm', ref.BF[fL], Hn * wf[..., None]))
+            np.add.at(L, eR, np.einsum('pm,kpv->kvm', ref.BF[fR], Hn * wf[..., None]))
+        if np.any(self.face_nbr < 0):
+            if self.bc_kind is None:
+                raise ValueError("mesh has boundary faces but no boundary condition")
+            for e, f, bid in self.boundary_faces():
+                Qo, go = self.trace(u, e, f)
+                go = go + np.einsum('pm,kjvm->kpjv', ref.BF[f], r[e])
+                n = self.geo.nf[f][e]
+                beta = np.broadcast_to(self.boundary_beta(e, f)[:, None], Qo.shape[:-1])
+                Ub = self._boundary_data(u, e, f, bid, Qo)
+                Hb = np.zeros(Qo.shape, dtype=np.result_type(Qo, go))
+                for b in np.unique(bid):
+                    k = bid == b
+                    Hb[k] = boundary_flux_own_ldg(gas, int(self.bc_kind[b]), Qo[k], go[k], n[k], beta[k], Ub[k])
+                wf = self.geo.wJf[f][e]
+                np.add.at(L, e, -np.einsum('pm,kpv->kvm', ref.BF[f], Hb * wf[..., None]))
         return L
 
     def boundary_faces(self):
@@ -290,7 +378,7 @@ def make_disc(cfg, mesh, **gas_overrides) -> Disc:
     kw.update(gas_overrides)
     return Disc(gas=Gas(**kw), dim=mesh.dim, P=cfg.P, nq=cfg.nq, elem_origin=mesh.elem_origin,
                 elem_h=mesh.elem_h, face_nbr=mesh.face_nbr, geo_nodes=getattr(mesh, "geo_nodes", None),
-                geo_order=getattr(mesh, "geo_order", 1))
+                geo_order=getattr(mesh, "geo_order", 1), viscous=getattr(cfg, "viscous", "ip"))
 
 
 def conserved_from_primitive(gamma, rho, vel, p):

@@ -442,23 +442,63 @@ def boundary_flux_own(gas: Gas, kind, Uo, go, n, beta_p, Uinf=None):
     adiabatic wall the heat flux through the wall is zero, so the energy
     components of the viscous face fluxes vanish (the work term vanishes with
     the zero wall velocity)."""
-    if kind == BC_DIRICHLET:
-        Un = np.broadcast_to(Uinf, Uo.shape)
-    elif kind == BC_FARFIELD:
-        Un = farfield_ghost(gas, Uo, n, Uinf)
-    else:
-        Un = ghost_state(gas, kind, Uo, n, Uinf)
+    Un = boundary_ghost(gas, kind, Uo, n, Uinf)
     F = riemann_flux(gas, Uo, Un, n)
     Gn, S = ip_face_fluxes(gas, Uo, Un, go, go, n, beta_p)
+    Gn, S = wall_viscous_limits(kind, Gn, S, n)
+    return F - Gn, S
+
+
+def boundary_ghost(gas: Gas, kind, Uo, n, Uinf):
+    """The ghost state of any boundary kind."""
+    if kind == BC_DIRICHLET:
+        return np.broadcast_to(Uinf, Uo.shape)
+    if kind == BC_FARFIELD:
+        return farfield_ghost(gas, Uo, n, Uinf)
+    return ghost_state(gas, kind, Uo, n, Uinf)
+
+
+def wall_viscous_limits(kind, Gn, S, n):
+    """No heat flux (nor work) through slip and no-slip adiabatic walls; at a
+    slip wall only the normal viscous traction remains."""
     if kind in (BC_WALL, BC_SLIP):
         Gn = Gn.copy()
-        S = S.copy()
         Gn[..., -1] = 0.0
-        S[..., -1] = 0.0
+        if S is not None:
+            S = S.copy()
+            S[..., -1] = 0.0
     if kind == BC_SLIP:
-        # only the normal viscous traction remains
         gm = np.sum(Gn[..., 1:-1] * n, axis=-1)
         Gn[..., 1:-1] = gm[..., None] * n
-        sm = np.einsum('...jc,...c->...j', S[..., 1:-1], n)
-        S[..., 1:-1] = sm[..., None] * n[..., None, :]
-    return F - Gn, S
+        if S is not None:
+            sm = np.einsum('...jc,...c->...j', S[..., 1:-1], n)
+            S[..., 1:-1] = sm[..., None] * n[..., None, :]
+    return Gn, S
+
+
+# ---------------------------------------------------------------- LDG viscous fluxes
+# Local discontinuous Galerkin (Sec. 4.3 lists it beside IP; the paper gives
+# no formulas).  Reading: the auxiliary gradient is q = grad u + r, with the
+# lifting r of the face jumps defined by M r_j = sum over faces of the
+# integral of phi (u_hat - u^-) n_j; the switch takes u_hat from the face's
+# left element (the one that meets it with side 1) and the viscous flux's
+# gradient q_hat from the right one; a penalty beta_p n.G(u_hat, [u] (x) n)
+# on the jump; no symmetric term.  On a boundary face u_hat is the mean of
+# the interior and ghost states, q_hat the interior q.
+
+
+def ldg_viscous_flux_n(gas: Gas, Uhat, qhat, jump, n, beta_p):
+    """n.G(u_hat, q_hat) - beta_p n.G(u_hat, jump (x) n) with jump = u^- - u^+
+    seen from the side whose outward normal is n."""
+    Gn = normal_flux(viscous_flux(gas, Uhat, qhat), n)
+    J = n[..., :, None] * jump[..., None, :]
+    return Gn - beta_p[..., None] * normal_flux(viscous_flux(gas, Uhat, J), n)
+
+
+def boundary_flux_own_ldg(gas: Gas, kind, Uo, qo, n, beta_p, Uinf=None):
+    """LDG boundary face flux H^n seen from the interior (no symmetric term)."""
+    Un = boundary_ghost(gas, kind, Uo, n, Uinf)
+    F = riemann_flux(gas, Uo, Un, n)
+    Gn = ldg_viscous_flux_n(gas, 0.5 * (Uo + Un), qo, Uo - Un, n, beta_p)
+    Gn, _ = wall_viscous_limits(kind, Gn, None, n)
+    return F - Gn

@@ -189,3 +189,44 @@ def test_navier_stokes_truncation_3d():
     e = _truncation_errors(gas, 3, 3, (4, 8), field, (2 * np.pi,) * 3)
     # pre-asymptotic on these meshes (P - 1 = 2 is approached from below)
     assert np.log2(e[0] / e[1]) >= 1.2, e
+
+
+@pytest.mark.parametrize("dim,cells,P", [(2, (3, 3), 2), (2, (2, 3), 3), (3, (2, 2, 2), 1)])
+def test_ldg_diffusion_symmetric_negative(dim, cells, P):
+    """The LDG option (auxiliary gradient with lifted jumps, u_hat and q_hat
+    from opposite sides, jump penalty): with G = nu grad U the operator
+    -dL/du is symmetric and positive semi-definite with the constants as
+    its kernel, as the LDG primal form is; it differs from the IP operator."""
+    d = tiny_disc(dim=dim, cells=cells, P=P, Re=1.0, flux_mode=2)
+    n = int(np.prod(d.shape))
+    K = np.zeros((n, n))
+    Kip = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        Kip[:, i] = -d.L(e.reshape(d.shape)).ravel()
+    d.viscous = "ldg"
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        K[:, i] = -d.L(e.reshape(d.shape)).ravel()
+    s = np.abs(K).max()
+    assert np.abs(K - K.T).max() <= 1e-12 * s
+    ev = np.linalg.eigvalsh(0.5 * (K + K.T))
+    assert ev.min() >= -1e-11 * s
+    assert np.sum(np.abs(ev) <= 1e-10 * s) == d.nv
+    assert np.abs(K - Kip).max() > 1e-3 * s
+
+
+@pytest.mark.parametrize("dim,P", [(2, 3), (3, 2)])
+def test_ldg_navier_stokes_conservation_and_freestream(dim, P):
+    d = tiny_disc(dim=dim, cells=(3,) * dim, P=P, Ma=0.3, Re=30.0)
+    d.viscous = "ldg"
+    u = W.random_state(d.n_elem, dim, P, seed=9)
+    L = d.L(u)
+    for v in range(d.nv):
+        assert abs(L[:, v, 0].sum()) <= 1e-13 * np.abs(L[:, v, 0]).sum()
+    U = W.DEFAULT_MEAN[dim]
+    c = np.zeros(d.shape)
+    c[:, :, 0] = np.asarray(U) * 2 ** (dim / 2)
+    assert np.abs(d.L(c)).max() <= 1e-13 * np.abs(L).max()

@@ -58,23 +58,24 @@ def test_brj_blocks_exact_with_dirichlet_faces():
         assert np.abs(pc.D[e] - blk).max() <= 2e-6 * np.abs(blk).max()
 
 
-def mms_disc(P, n):
+def mms_disc(P, n, viscous="ip"):
     cfg = W.mms_config(P, n)
     mesh = cfg.mesh()
     inp = W.mms_inputs(cfg, mesh)
     d = make_disc(cfg, mesh)
+    d.viscous = viscous
     d.bc_kind, d.bc_state = cfg.boundary()
     d.bc_field = inp["bc_field"]
     d.source = d.project_values(inp["forcing"])
     return cfg, d, inp
 
 
-def mms_steady(P, n, stepper_opts=None):
+def mms_steady(P, n, stepper_opts=None, viscous="ip"):
     """Backward-Euler pseudo-time steps from the initial state with the
     CFL number growing from 500 to 5000 over ten steps (as the paper's
     steady runs), until ||M^-1 L + s|| has dropped by 1e-9.  Returns the
     solution, the L2 error per variable at the Gauss points and the steps."""
-    cfg, d, inp = mms_disc(P, n)
+    cfg, d, inp = mms_disc(P, n, viscous)
     u = d.project_values(inp["initial"])
     r0 = np.linalg.norm(d.residual(u))
     opts = stepper_opts or S.SolverOpts(scheme="beuler", pc_freeze=1, newton_rtol=1e-4)
@@ -89,9 +90,10 @@ def mms_steady(P, n, stepper_opts=None):
     return u, err, i + 1
 
 
+@pytest.mark.parametrize("viscous", ["ip", "ldg"])
 @pytest.mark.parametrize("P,levels", [(2, (3, 4, 8)), (3, (4, 8))])
-def test_manufactured_poiseuille_order_of_accuracy(P, levels):
-    errs = [mms_steady(P, n)[1] for n in levels]
+def test_manufactured_poiseuille_order_of_accuracy(P, levels, viscous):
+    errs = [mms_steady(P, n, viscous=viscous)[1] for n in levels]
     for k in range(1, len(levels)):
         rate = np.log(errs[k - 1] / errs[k]) / np.log(levels[k] / levels[k - 1])
         print(P, levels[k], errs[k], rate)

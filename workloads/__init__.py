@@ -176,7 +176,8 @@ class FlowConfig:
     gamma: float = 1.4
     Pr: float = 0.72
     flux_mode: int = 0        # 0 Navier-Stokes, 1 Euler, 2 scalar-diffusion test
-    riemann: int = 0          # 0 Roe, 1 local Lax-Friedrichs
+    riemann: int = 0          # 0 Roe, 1 LLF, 2 HLL, 3 HLLC, 4 AUSM+
+    viscous: str = "ip"       # viscous face terms: "ip" (interior penalty) or "ldg"
     visc_law: int = 0         # 0 constant mu = 1/Re, 1 Sutherland
     T_ref_K: float = 288.15
     scheme: str = "sdirk2"
