@@ -133,6 +133,14 @@ typedef struct {
   int32_t flux_mode;          /* 0 Navier-Stokes, 1 Euler, 2 scalar diffusion test */
   int32_t riemann;            /* 0 Roe, 1 local Lax-Friedrichs, 2 HLL, 3 HLLC, 4 AUSM+ (Sec. 4.3 lists
                                  these among its solver's fluxes) */
+  int32_t viscous;            /* viscous face terms (Sec. 4.3 names both): 0 interior penalty
+                                 (Eq. 12), 1 LDG -- auxiliary gradient q = grad u + the lifted
+                                 face jumps (u_hat from the face's left element, the element that
+                                 meets it with side 1, or the mean of interior and ghost states on
+                                 a boundary), viscous flux with q_hat from the right element and
+                                 a penalty on the jump, no symmetric term.  LDG runs on affine
+                                 boxes and single instances; its preconditioner blocks are the
+                                 interior-penalty ones. */
 } dgj_phys;
 
 /* Implicit solver options (Sec. 3.2, Sec. 4.2.2). */

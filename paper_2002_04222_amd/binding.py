@@ -38,7 +38,7 @@ class Mesh(C.Structure):
 class Phys(C.Structure):
     _fields_ = [("gamma", C.c_double), ("Pr", C.c_double), ("Re", C.c_double), ("Ma", C.c_double),
                 ("T_ref_K", C.c_double), ("visc_law", C.c_int32), ("flux_mode", C.c_int32),
-                ("riemann", C.c_int32)]
+                ("riemann", C.c_int32), ("viscous", C.c_int32)]
 
 
 class Solver(C.Structure):
@@ -149,6 +149,7 @@ def _fptr(t) -> Optional[int]:
 SCHEMES = {"beuler": DGJ_BEULER, "sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3, "sdirk4": DGJ_SDIRK4,
            "bdf2": DGJ_BDF2, "erk2": DGJ_ERK2}
 PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
+VISCOUS = {"ip": 0, "ldg": 1}
 
 
 def _mesh_struct(mesh, cfg, keep, bc_kind=None, bc_state=None):
@@ -179,7 +180,8 @@ def _mesh_struct(mesh, cfg, keep, bc_kind=None, bc_state=None):
 
 
 def _phys_struct(cfg):
-    return Phys(cfg.gamma, cfg.Pr, cfg.Re, cfg.Ma, cfg.T_ref_K, cfg.visc_law, cfg.flux_mode, cfg.riemann)
+    return Phys(cfg.gamma, cfg.Pr, cfg.Re, cfg.Ma, cfg.T_ref_K, cfg.visc_law, cfg.flux_mode, cfg.riemann,
+                VISCOUS[getattr(cfg, "viscous", "ip")])
 
 
 def _solver_struct(cfg):
@@ -273,7 +275,8 @@ class Context:
         self._keep = []
         m = _mesh_struct(mesh, cfg, self._keep, bc_kind, bc_state)
         g = lambda k: over.get(k, getattr(cfg, k))
-        ph = Phys(g("gamma"), g("Pr"), g("Re"), g("Ma"), g("T_ref_K"), g("visc_law"), g("flux_mode"), g("riemann"))
+        ph = Phys(g("gamma"), g("Pr"), g("Re"), g("Ma"), g("T_ref_K"), g("visc_law"), g("flux_mode"), g("riemann"),
+                  VISCOUS[over.get("viscous", getattr(cfg, "viscous", "ip"))])
         sv = Solver(SCHEMES[g("scheme")], g("newton_rtol"), g("newton_max"), g("gmres_restart"), g("gmres_rtol"),
                     g("gmres_max"), g("brj_sweeps"), g("brj_omega"), PRECISIONS[g("pc_precision")], g("pc_freeze"),
                     g("pc_refresh_its"))

@@ -121,6 +121,9 @@ struct ResArgs {
   const double* bc_field;
   // modal source [e][NV][NM] added to M^-1 L (null: none)
   const double* src;
+  // LDG: lifted jump gradient r_j at the volume points, rq[e][D][NV][NQ]
+  // (written by k_ldg_lift; null for the interior-penalty form)
+  double* ldg_r;
   // curved elements (all null for affine boxes): per-point metrics
   // vg[e][D*D+1][NQ], fg[e][NF][D*D+D+1][NQF] and the dense inverse mass
   // matrix minv[e][NM][NM]

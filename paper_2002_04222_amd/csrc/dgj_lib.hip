@@ -418,6 +418,8 @@ struct dgj_ctx {
   bool has_dirichlet = false;     // some boundary id has the Dirichlet kind
   double* d_bc_field = nullptr;   // Dirichlet ghost states [E][NF][NV][NQF] (dgj_set_bc_field)
   double* d_src = nullptr;        // modal source [E][NV][NM] added to M^-1 L (dgj_set_source)
+  bool ldg = false;               // LDG viscous face terms (else interior penalty)
+  double* d_rq = nullptr;         // LDG lifted jump gradients at the volume points [E][D][NV][NQ]
   double* d_origin = nullptr;
   double* d_tab = nullptr;
   std::vector<double> h_tab;   // tables + Lagrange weights, passed by value to the residual kernels
@@ -571,6 +573,8 @@ TabK<N, Q> tables_by_value(dgj_ctx* c) {
 template <int D, int N, int Q>
 void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
   const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
+  if (a.ldg_r)
+    hipLaunchKernelGGL((k_ldg_lift<D, N, Q>), dim3(c->n_elem), dim3(128), 0, c->stream, a, tk, a.ldg_r);
   for (int k = 0; k < 3; ++k) {
     const int nt = c->res_nt[k] > 0 ? c->res_nt[k] : default_nt<D, N, Q>(k);
     if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, tk, k, nt);
@@ -643,6 +647,7 @@ ResArgs res_args(dgj_ctx* c) {
   a.bc_state = c->d_bc_state;
   a.bc_field = c->d_bc_field;
   a.src = c->d_src;
+  a.ldg_r = c->ldg ? c->d_rq : nullptr;
   if (c->curved) {
     a.vg = c->d_vg;
     a.fg = c->d_fg;
@@ -1214,6 +1219,9 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     if (solver->gmres_restart < 1 || solver->gmres_restart > 60) fail(DGJ_EINVAL, "gmres_restart must be in 1..60");
     if (!scheme_known(solver->scheme)) fail(DGJ_EINVAL, "unknown scheme %d", solver->scheme);
     if (solver->pc_precision < 0 || solver->pc_precision > 2) fail(DGJ_EINVAL, "bad pc_precision");
+    if (phys->viscous < 0 || phys->viscous > 1) fail(DGJ_EINVAL, "viscous must be 0 (IP) or 1 (LDG)");
+    if (phys->viscous == 1 && mesh->geo_nodes) fail(DGJ_EUNSUPPORTED, "LDG is built for affine boxes only");
+    c->ldg = phys->viscous == 1;
     if (phys->flux_mode < 0 || phys->flux_mode > 2 || phys->riemann < 0 || phys->riemann > 4)
       fail(DGJ_EINVAL, "bad flux options");
     c->dim = mesh->dim;
@@ -1362,6 +1370,11 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       HIPCHK(hipMemsetAsync(c->d_inc2[m], 0, vb, c->stream));
     }
     if (c->sv.scheme == DGJ_BDF2) HIPCHK(hipMalloc(&c->d_uprev, vb));
+    if (c->ldg) {
+      long nqv = 1;
+      for (int a = 0; a < c->dim; ++a) nqv *= c->nq;
+      HIPCHK(hipMalloc(&c->d_rq, (size_t)E * c->dim * c->NV * nqv * sizeof(double)));
+    }
     if (curved) {
       // dense mass matrices and their inverses (Gauss-Jordan on the device)
       const size_t mm = (size_t)E * c->NM * c->NM;
@@ -1416,6 +1429,7 @@ void dgj_destroy(dgj_ctx* c) {
   if (c->d_bc_kind) hipFree(c->d_bc_kind);
   if (c->d_bc_state) hipFree(c->d_bc_state);
   if (c->d_bc_field) hipFree(c->d_bc_field);
+  if (c->d_rq) hipFree(c->d_rq);
   if (c->d_src) hipFree(c->d_src);
   void* bps[] = {c->d_inst, c->d_phs, c->d_epsv, c->d_dtav, c->d_active, c->d_ioff, c->d_hs, c->d_part2, c->d_kused};
   for (void* p : bps)

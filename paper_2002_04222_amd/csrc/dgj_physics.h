@@ -681,4 +681,85 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
   }
 }
 
+// LDG viscous normal flux n.G(u_hat, q_hat) - beta n.G(u_hat, jump (x) n)
+template <int D>
+__device__ __forceinline__ void ldg_viscous_n(const Phys& ph, const double* Uh, const double (*q)[D + 2],
+                                              const double* jump, const double* n, double beta, double* Gn) {
+  constexpr int NV = D + 2;
+  double G[D][NV], J[D][NV], Pn[NV];
+  viscous_flux<D, double, double>(ph, Uh, q, G);
+  dot_normal<D>(G, n, Gn);
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) J[j][v] = n[j] * jump[v];
+  viscous_flux<D, double, double>(ph, Uh, J, G);
+  dot_normal<D>(G, n, Pn);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Gn[v] -= beta * Pn[v];
+}
+
+// LDG interior face flux seen from the left element (the one that meets the
+// face with side 1, outward normal n): u_hat = U_L, q_hat = the right
+// element's auxiliary gradient qR, penalty on U_L - U_R; no symmetric term
+template <int D>
+__device__ __forceinline__ void face_flux_ldg(const Phys& ph, const double* UL, const double* UR,
+                                              const double (*qR)[D + 2], const double* n, double beta, double* H) {
+  constexpr int NV = D + 2;
+  double F[NV];
+  if (ph.flux_mode == 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.0;
+  } else {
+    riemann_flux<D>(ph, UL, UR, n, F);
+  }
+  if (ph.flux_mode == 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) H[v] = F[v];
+    return;
+  }
+  double jump[NV], Gn[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) jump[v] = UL[v] - UR[v];
+  ldg_viscous_n<D>(ph, UL, qR, jump, n, beta, Gn);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) H[v] = F[v] - Gn[v];
+}
+
+// LDG boundary face flux: u_hat the mean of interior and ghost states, q_hat
+// the interior auxiliary gradient, the same wall limits as the IP form
+template <int D>
+__device__ __forceinline__ void boundary_flux_ldg(const Phys& ph, int kind, const double* Uo,
+                                                  const double (*qo)[D + 2], const double* n, double beta,
+                                                  const double* Uinf, double* H) {
+  constexpr int NV = D + 2;
+  double Un[NV], F[NV];
+  ghost_state<D>(ph, kind, Uo, n, Uinf, Un);
+  if (ph.flux_mode == 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.0;
+  } else {
+    riemann_flux<D>(ph, Uo, Un, n, F);
+  }
+  if (ph.flux_mode == 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) H[v] = F[v];
+    return;
+  }
+  double Uh[NV], jump[NV], Gn[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) { Uh[v] = 0.5 * (Uo[v] + Un[v]); jump[v] = Uo[v] - Un[v]; }
+  ldg_viscous_n<D>(ph, Uh, qo, jump, n, beta, Gn);
+  if (kind == BC_WALL || kind == BC_SLIP) Gn[D + 1] = 0.0;
+  if (kind == BC_SLIP) {
+    double gn = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) gn += Gn[1 + c] * n[c];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Gn[1 + c] = gn * n[c];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) H[v] = F[v] - Gn[v];
+}
+
 }  // namespace dgj

@@ -181,6 +181,17 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
   }
   __syncthreads();
 
+  // LDG (affine boxes): the auxiliary gradient is grad u plus the lifted
+  // face jumps, so the traces and the volume flux below see q
+  if (!CV && a.ldg_r) {
+    const double* r = a.ldg_r + e * (long)D * NV * NQ;
+    for (int it = tid; it < D * NV * NQ; it += NT) {
+      const int j = it / (NV * NQ);
+      sQ[(1 + j) * NV * NQ + it % (NV * NQ)] += r[it] / dxi[j];
+    }
+    __syncthreads();
+  }
+
   // own face traces: value and physical gradient at the face points
   if constexpr (CV) {
     // curved: interpolate value and reference gradient, then grad = G^T grad_xi
@@ -418,6 +429,131 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
   }
 }
 
+// ---------------------------------------------------------------- LDG lifting
+// Lifted face jumps of the LDG auxiliary gradient at the volume points of
+// an affine box: rq[e][j][v][q] = r_j(x_q), M_e r_j = sum over the faces of
+// the integral of phi (u_hat - u^-) n_j.  u_hat comes from the face's left
+// element, so only the element's side-0 interior faces (u_hat = the
+// neighbour's trace) and its boundary faces (u_hat = the mean of interior
+// and ghost states) contribute.  With the orthonormal basis M_e = |J| I and
+// |J_f| / |J| = 2 / h_axis, so for face f of axis j and side s
+//   r_j(x_q) += (2/h_j) n_j sum_p K_f(q, p) w_p delta_p,
+// K_f(q, p) = sum_m phi_m(x_q) phi_m(x_p) = kE[a_j(q)][s] prod_t k1[a_t(q)][a_t(p)]
+// with the 1D kernels k1[a][b] = sum_i B[a][i] B[b][i] (Gauss points) and
+// kE[a][s] = sum_i B[a][i] phi_i(+-1).
+template <int D, int N, int Q>
+__global__ __launch_bounds__(256) void k_ldg_lift(ResArgs a, TabK<N, Q> tk, double* __restrict__ rq) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
+  __shared__ double sU[NB], sN[NB];
+  __shared__ double sD[NF * NV * NQF];
+  __shared__ double k1[Q][Q], kE[Q][2];
+  const long e = blockIdx.x;
+  if (e >= a.n_elem) return;
+  ElemParams ep;
+  if (!elem_params(a, e, ep)) return;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const double* g = a.geo + e * K::S::GEO;
+  for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
+  for (int i = tid; i < Q * Q; i += NT) {
+    const int x = i / Q, y = i % Q;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) s += tk.B[x][m] * tk.B[y][m];
+    k1[x][y] = s;
+  }
+  for (int i = tid; i < 2 * Q; i += NT) {
+    const int x = i / 2, sd = i % 2;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) s += tk.B[x][m] * tk.phiE[sd][m];
+    kE[x][sd] = s;
+  }
+  for (int f = 0; f < NF; ++f) {
+    const long en = a.nbr[e * NF + f];
+    const int ax = f >> 1, sd = f & 1;
+    const bool active = en < 0 || sd == 0;
+    __syncthreads();
+    if (active && en >= 0)
+      for (int i = tid; i < NB; i += NT) sN[i] = ep.in(en * NB + i);
+    __syncthreads();
+    for (int p = tid; p < NQF; p += NT) {
+      double* dj = sD + f * NV * NQF + p;
+      if (!active) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dj[v * NQF] = 0.0;
+        continue;
+      }
+      int t[2] = {0, 0};
+      tang_axes<D>(ax, t);
+      const int ap0 = p % Q, ap1 = p / Q;
+      double Uo[NV], Uo2[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) { Uo[v] = 0.0; Uo2[v] = 0.0; }
+      for (int m = 0; m < NM; ++m) {
+        int mi[3] = {0, 0, 0};
+        split<D, N>(m, mi);
+        double bt = tk.B[ap0][mi[t[0]]];
+        if (D == 3) bt *= tk.B[ap1][mi[t[1]]];
+        const double po = bt * tk.phiE[sd][mi[ax]];
+        const double pn = bt * tk.phiE[sd ^ 1][mi[ax]];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          Uo[v] += po * sU[v * NM + m];
+          if (en >= 0) Uo2[v] += pn * sN[v * NM + m];
+        }
+      }
+      if (en >= 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dj[v * NQF] = Uo2[v] - Uo[v];
+      } else {
+        const int bid = -(int)en - 1;
+        const int kind = a.bc_kind[bid];
+        double nrm[D], UD[NV], Ug[NV];
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (sd == 1 ? 1.0 : -1.0) : 0.0;
+        const double* Ub = a.bc_state + bid * NV;
+        if (kind == BC_DIRICHLET) {
+          const double* gb = a.bc_field + (e * NF + f) * (long)NV * NQF + p;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) UD[v] = gb[v * NQF];
+          Ub = UD;
+        }
+        ghost_state<D>(ep.ph, kind, Uo, nrm, Ub, Ug);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dj[v * NQF] = 0.5 * (Ug[v] - Uo[v]);
+      }
+    }
+  }
+  __syncthreads();
+  double* out = rq + e * (long)D * NV * NQ;
+  for (int it = tid; it < D * NV * NQ; it += NT) {
+    const int q = it % NQ, v = (it / NQ) % NV, j = it / (NV * NQ);
+    int aq[3] = {0, 0, 0};
+    {
+      int r = q;
+#pragma unroll
+      for (int k = 0; k < D; ++k) { aq[k] = r % Q; r /= Q; }
+    }
+    int t[2] = {0, 0};
+    tang_axes<D>(j, t);
+    double acc = 0.0;
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const double* dj = sD + (2 * j + sd) * NV * NQF + v * NQF;
+      double s = 0.0;
+      for (int p = 0; p < NQF; ++p) {
+        const int ap0 = p % Q, ap1 = p / Q;
+        double kk = k1[aq[t[0]]][ap0] * tk.w[ap0];
+        if (D == 3) kk *= k1[aq[t[1]]][ap1] * tk.w[ap1];
+        s += kk * dj[p];
+      }
+      acc += (sd == 1 ? 1.0 : -1.0) * kE[aq[j]][sd] * s;
+    }
+    out[it] = g[j] * acc;   // g[j] = d xi_j / d x_j = 2 / h_j
+  }
+}
+
 // ---------------------------------------------------------------- face fluxes
 // Flux of face f of element e at face point p, weighted by w^G |J^G|, into
 // X[e][f]: (H^n, S_j) in e's orientation (outward normal of face f).
@@ -452,7 +588,36 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
   }
   double H[NV], Sf[D][NV];
   const double beta = a.beta[e * K::NF + f];
-  if (en >= 0) {
+  if (a.ldg_r) {
+    // LDG: the traces' gradients are the auxiliary q; no symmetric term
+    if (en >= 0) {
+      const double* tR = trace + en * (long)K::TRACE + (f ^ 1) * (D + 1) * NV * NQF;
+      double UR[NV], qR[D][NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UR[v] = tR[v * NQF + p];
+#pragma unroll
+        for (int j = 0; j < D; ++j) qR[j][v] = tR[((1 + j) * NV + v) * NQF + p];
+      }
+      face_flux_ldg<D>(ph, UL, UR, qR, nrm, beta, H);
+    } else {
+      const int bid = -(int)en - 1;
+      const int kind = a.bc_kind[bid];
+      double UD[NV];
+      const double* Ub = a.bc_state + bid * NV;
+      if (kind == BC_DIRICHLET) {
+        const double* g = a.bc_field + (e * K::NF + f) * (long)NV * NQF + p;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) UD[v] = g[v * NQF];
+        Ub = UD;
+      }
+      boundary_flux_ldg<D>(ph, kind, UL, gL, nrm, beta, Ub, H);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sf[j][v] = 0.0;
+  } else if (en >= 0) {
     const double* tR = trace + en * (long)K::TRACE + (f ^ 1) * (D + 1) * NV * NQF;
     double UR[NV], gR[D][NV];
 #pragma unroll
