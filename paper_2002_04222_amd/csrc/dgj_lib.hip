@@ -549,6 +549,8 @@ int default_nt(int k) { return k == 1 ? 128 : (D == 2 ? 64 : (k == 0 ? 128 : 256
 template <int D, int N, int Q, bool CV>
 void launch_res_kernel(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int k, int nt) {
   using K = ResK<D, N, Q>;
+  // the kernels stride by blockDim; the lift's per-thread register arrays assume at least one wavefront
+  if (nt < 64 || nt > 256 || nt % 64) fail(DGJ_EINVAL, "residual workgroup size %d (64, 128, 192 or 256)", nt);
   if (k == 0) {
     hipLaunchKernelGGL((k_res_vol<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk, c->d_trace,
                        c->d_Lvol);

@@ -710,29 +710,62 @@ __global__ __launch_bounds__(256) void k_res_lift(ResArgs a, TabK<N, Q> tk, cons
     s_mine[tid] = mine;
   }
   __syncthreads();
-  // face data in the element's own orientation and scaling
-#pragma unroll 4
-  for (int it = tid; it < NF * (D + 1) * NV * NQF; it += NT) {
-    const int p = it % NQF;
-    const int v = (it / NQF) % NV;
-    const int k = (it / (NQF * NV)) % (D + 1);
-    const int f = it / (NQF * NV * (D + 1));
-    const bool mine = s_mine[f];
-    const double* Xs = X + s_src[f] * (long)K::XF + (s_fs[f] * (D + 1) * NV + v) * NQF + p;
-    // k = 0: -Hhat_own (the neighbour's flux has the opposite orientation);
-    // k >= 1: sum_j (d xi_{k-1} / d x_j) Shat_j
-    if (k == 0) {
-      const double x = Xs[0];
-      sA[it] = mine ? -x : x;
-    } else if constexpr (CV) {
-      constexpr int CF = D * D + D + 1;
-      const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
-      double s = 0.0;
+  // this thread's volume terms, loaded early (read after the face phases)
+  constexpr int LPT = (NB + 63) / 64;           // at most this many per thread (NT >= 64)
+  double lv[LPT];
 #pragma unroll
-      for (int j = 0; j < D; ++j) s += Gp[((k - 1) * D + j) * NQF] * Xs[(1 + j) * NV * NQF];
-      sA[it] = s;
-    } else {
-      sA[it] = Xs[k * NV * NQF] * g[k - 1];
+  for (int u = 0; u < LPT; ++u) {
+    const int i = tid + u * NT;
+    lv[u] = i < NB ? Lvol[e * NB + i] : 0.0;
+  }
+  // face data in the element's own orientation and scaling
+  constexpr int TOT = NF * (D + 1) * NV * NQF;
+  if constexpr (CV) {
+    for (int it = tid; it < TOT; it += NT) {
+      const int p = it % NQF;
+      const int v = (it / NQF) % NV;
+      const int k = (it / (NQF * NV)) % (D + 1);
+      const int f = it / (NQF * NV * (D + 1));
+      const bool mine = s_mine[f];
+      const double* Xs = X + s_src[f] * (long)K::XF + (s_fs[f] * (D + 1) * NV + v) * NQF + p;
+      // k = 0: -Hhat_own (the neighbour's flux has the opposite orientation);
+      // k >= 1: sum_j (d xi_{k-1} / d x_j) Shat_j
+      if (k == 0) {
+        const double x = Xs[0];
+        sA[it] = mine ? -x : x;
+      } else {
+        constexpr int CF = D * D + D + 1;
+        const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) s += Gp[((k - 1) * D + j) * NQF] * Xs[(1 + j) * NV * NQF];
+        sA[it] = s;
+      }
+    }
+  } else {
+    // affine boxes: each face's data is one contiguous run of X; issue a
+    // batch of independent loads per thread before any is used
+    constexpr int FB = (D + 1) * NV * NQF;
+    constexpr int UB = 8;
+    for (int base = 0; base < TOT; base += UB * NT) {
+      double x[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int it = base + u * NT + tid;
+        if (it < TOT) {
+          const int f = it / FB;
+          x[u] = X[s_src[f] * (long)K::XF + s_fs[f] * FB + it % FB];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int it = base + u * NT + tid;
+        if (it < TOT) {
+          const int f = it / FB;
+          const int k = (it % FB) / (NV * NQF);
+          sA[it] = (k == 0) ? (s_mine[f] ? -x[u] : x[u]) : x[u] * g[k - 1];
+        }
+      }
     }
   }
   __syncthreads();
@@ -765,11 +798,14 @@ __global__ __launch_bounds__(256) void k_res_lift(ResArgs a, TabK<N, Q> tk, cons
   const double invdetJ = g[D + 1];
   double* sL = sA;   // curved: L staged for the dense M^-1 (sA is no longer read)
   constexpr bool curved = CV;
-  for (int i = tid; i < NB; i += NT) {
+#pragma unroll
+  for (int u = 0; u < LPT; ++u) {
+    const int i = tid + u * NT;
+    if (i >= NB) break;
     const int m = i % NM, v = i / NM;
     int mi[3] = {0, 0, 0};
     split<D, N>(m, mi);
-    double L = Lvol[e * NB + i];
+    double L = lv[u];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int ax = f >> 1, s = f & 1;
