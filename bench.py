@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--P", type=int, default=None, help="polynomial order (default: the workload's; nq = P+2)")
     ap.add_argument("--pc", default=None, help="preconditioner storage f64|f32|bf16 (default: workload's)")
+    ap.add_argument("--brj-sweeps", type=int, default=None, help="BRJ sweeps J (default: the workload's, 7)")
     ap.add_argument("--pc-freeze", type=int, default=None,
                     help="steps a built preconditioner is kept (default: the workload's, 10 as in the paper)")
     ap.add_argument("--pc-refresh-its", type=int, default=None,
@@ -184,6 +185,9 @@ def main():
     if args.pc_freeze is not None:
         import dataclasses
         cfg = dataclasses.replace(cfg, pc_freeze=args.pc_freeze)
+    if args.brj_sweeps is not None:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, brj_sweeps=args.brj_sweeps)
     if args.pc_refresh_its is not None:
         import dataclasses
         cfg = dataclasses.replace(cfg, pc_refresh_its=args.pc_refresh_its)
