@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--learned", action="store_true",
                     help="also time the learned Newton guess against the paper's and the extrapolated one")
     ap.add_argument("--learned-train", type=int, default=20, help="plain steps recorded to train the MLP")
+    ap.add_argument("--learned-epochs", type=int, default=150, help="Adam passes over the recorded stages")
+    ap.add_argument("--learned-held", type=int, default=3, help="held-out steps timed with each guess")
     ap.add_argument("--batch", action="store_true",
                     help="also time the batch of 64 independent 2D problems, batched against one by one")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -356,7 +358,7 @@ def main():
         out["explicit_erk2"] = bench_explicit(cfg, mesh, u_start, u, wall * 1e3, args.steps * dt, kinds, states)
 
     if args.learned:
-        out["learned"] = bench_learned(cfg, make, args.learned_train, min(args.steps, 3))
+        out["learned"] = bench_learned(cfg, make, args.learned_train, args.learned_held, args.learned_epochs)
 
     if args.batch:
         out["batch"] = bench_batch(args.batch_steps)
@@ -614,7 +616,7 @@ def bench_batch(steps):
             "autotuned_workgroups_per_group": tuned}
 
 
-def bench_learned(cfg, make, n_train, held):
+def bench_learned(cfg, make, n_train, held, epochs=150):
     """The learned-guess form: record n_train plain steps, fit the per-element
     MLP on the recorded stages (in the library), then from one saved state
     time `held` steps with each Newton initial guess (the paper's S_m, the
@@ -638,19 +640,27 @@ def bench_learned(cfg, make, n_train, held):
     for k in range(n_train):
         ctx.set_record(S_rec[k], I_rec[k])
         ctx.sdirk_step(u, dt)
+        if (k + 1) % 10 == 0:
+            log(f"learned: recorded {k + 1} of {n_train} steps")
     ctx.set_record(None, None)
     torch.cuda.synchronize()
     rec_s = time.perf_counter() - t
     nb = ctx.shape[1] * ctx.shape[2]
     ctx.mlp_create(256, W.mlp_init(2 * nb, 256, nb, seed=8))
     t = time.perf_counter()
-    loss = ctx.mlp_fit(S_rec, I_rec, n_train, 150, 1e-3)
+    # in chunks of passes (the optimiser's state carries over between calls)
+    done = 0
+    while done < epochs:
+        k = min(5, epochs - done)
+        loss = ctx.mlp_fit(S_rec, I_rec, n_train, k, 1e-3)
+        done += k
+        log(f"learned: {done} of {epochs} passes, loss {loss:.3e}")
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t
     del S_rec, I_rec
     log(f"learned: recorded {n_train} steps in {rec_s:.1f} s, fit loss {loss:.3e} in {fit_s:.1f} s")
     u_save = u.clone()
-    inc_save = torch.empty((2, 3, n), dtype=torch.float64, device="cuda")
+    inc_save = torch.empty((2, stages, n), dtype=torch.float64, device="cuda")
     ctx.guess_state(inc_out=inc_save)
     res = {}
     for mode in ("paper", "extrapolated", "learned"):
@@ -672,7 +682,8 @@ def bench_learned(cfg, make, n_train, held):
         log(f"guess {mode}: {ms:.1f} ms/step, newton {its}")
     ctx.set_guess("paper")
     base = res["paper"]["u"]
-    out = {"train_steps": n_train, "fit_loss": loss, "record_s": rec_s, "fit_s": fit_s, "held_out_steps": held}
+    out = {"train_steps": n_train, "epochs": epochs, "fit_loss": loss, "record_s": rec_s, "fit_s": fit_s,
+           "held_out_steps": held}
     for mode, r in res.items():
         out[mode] = {"ms_per_step": r["ms_per_step"], "newton_its": r["newton_its"],
                      "guess_used": r["used"],
