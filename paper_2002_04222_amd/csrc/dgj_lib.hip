@@ -777,12 +777,10 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
     hipLaunchKernelGGL((k_pc_face<D, N, Q, float>), dim3((nf + 127) / 128), dim3(128), 0, c->stream, up, c->d_nbr,
                        c->d_geo, c->d_beta, c->d_tab, ph, ne, c->d_chi, JmW, (float*)c->d_Jp, e0, c->d_bc_kind,
                        c->d_bc_state, c->curved ? c->d_fg : nullptr, c->d_bc_field);
-  // up to 16 accumulators of the NM x NM sub-block per thread; large blocks
-  // are split into tiles of NTA * 16 entries
-  constexpr int NTA0 = ((S::NM * S::NM / 16 + 63) / 64) * 64;
-  constexpr int NTA = NTA0 < 64 ? 64 : (NTA0 > 256 ? 256 : NTA0);
-  const long nblk = ne * S::NV * S::NV * AssembleTiles<D, N, Q, NTA>::NTILE;
-  hipLaunchKernelGGL((k_pc_assemble<D, N, Q, NTA, double>), dim3(nblk), dim3(NTA), 0, c->stream, Wt, JmW, c->d_geo,
+  // sum-factorised assembly, one workgroup per (element, k, l) sub-block
+  using AS = AssembleSF<D, N, Q>;
+  const long nblk = ne * S::NV * S::NV;
+  hipLaunchKernelGGL((k_pc_assemble_sf<D, N, Q>), dim3(nblk), dim3(AS::NT), 0, c->stream, Wt, JmW, c->d_geo,
                      c->d_tab, dt_a, ne, (double*)Dm, e0, c->curved ? c->d_M : nullptr);
 }
 

@@ -283,136 +283,204 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
 }
 
 // ---------------------------------------------------------------- block assembly
-// One workgroup per (element, k, l, tile): a tile of NT*NO entries of the
-// NM x NM sub-block A_kl of A_e (a thread keeps NO <= 16 accumulators in
-// registers), then D = I - dt_a / |J| A (boxes) or D = M_e - dt_a A
-// (curved, mass[e][NM][NM]; its inverse is (M_e - dt_a A_e)^-1 =
-// D_e^-1 M_e^-1) written column-major into Dm[e][col][row].
-template <int D, int N, int Q, int NT>
-struct AssembleTiles {
-  static constexpr int NM2 = Shape<D, N, Q>::NM * Shape<D, N, Q>::NM;
-  static constexpr int NO = (NM2 + NT - 1) / NT < 16 ? (NM2 + NT - 1) / NT : 16;
-  static constexpr int NTILE = (NM2 + NT * NO - 1) / (NT * NO);
+// Sum-factorised assembly: one workgroup per (element, k, l) computes the
+// whole NM x NM sub-block A_kl.  The volume term
+//   A_kl[m][n] = sum_j sum_b sum_q f_j(q, m) W_jb(q) g_b(q, n),
+// f_j = d phi_m / d xi_j, g_0 = phi_n, g_{1+i} = d phi_n / d xi_i, is
+// contracted one tensor direction at a time (the 1D factors are B or its
+// derivative Dq per direction); terms that continue with the same 1D
+// factors are merged after each direction, so the cost per sub-block is
+// about N^(2d) Q instead of the dense N^(2d) Q^d.  The partial sums of each
+// direction j go straight into the output block (coalesced over rows), so
+// no per-thread accumulators are kept.  The own-side face term of face f
+// (normal axis a, side s) factorises as phi_s(m_a) phi_s(n_a) times a
+// contraction over the tangential face points; the last pass adds it and
+// writes D = I - dt_a / |J| A (boxes) or D = M_e - dt_a A (curved) column-
+// major into Dm[e][col][row].
+template <int D, int N, int Q>
+struct AssembleSF {
+  using S = Shape<D, N, Q>;
+  static constexpr int NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF;
+  static constexpr int NM2 = NM * NM;
+  static constexpr int NTR = ((NM2 / 16 + 63) / 64) * 64;
+  static constexpr int NT = NTR < 64 ? 64 : (NTR > 512 ? 512 : NTR);
+  static constexpr int SW = D * (D + 1) * NQ;                                 // W_jb(q)
+  static constexpr int S1 = (D == 3) ? 3 * N * N * Q * Q : 2 * N * N * Q;     // after the first direction
+  static constexpr int S2 = (D == 3) ? 2 * N * N * N * N * Q : 0;             // after the second (3D)
+  static constexpr int FF = NF * ((D == 3) ? N * N * N * N : N * N);          // face blocks
+  static constexpr int FG = (D == 3) ? N * N * Q : 0;                         // face scratch
+  static constexpr int WORK = (S1 + S2) > (FF + FG) ? (S1 + S2) : (FF + FG);
 };
 
-template <int D, int N, int Q, int NT, typename TD>
-__global__ __launch_bounds__(NT) void k_pc_assemble(const double* __restrict__ Wt, const double* __restrict__ JmW,
-                                                     const double* __restrict__ geo, const double* __restrict__ tables,
-                                                     double dt_a, long n_elem, TD* __restrict__ Dm, long e0,
-                                                     const double* __restrict__ mass) {
+template <int D, int N, int Q>
+__global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
+    const double* __restrict__ Wt, const double* __restrict__ JmW, const double* __restrict__ geo,
+    const double* __restrict__ tables, double dt_a, long n_elem, double* __restrict__ Dm, long e0,
+    const double* __restrict__ mass) {
   using S = Shape<D, N, Q>;
-  using AT = AssembleTiles<D, N, Q, NT>;
+  using A = AssembleSF<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF, NB = S::NB;
   constexpr int PER_Q = D * (D + 1) * NV * NV;
-  constexpr int NO = AT::NO, NTILE = AT::NTILE;
+  constexpr int NT = A::NT;
   __shared__ double st[S::TAB];
-  __shared__ double Z[NM];
-  __shared__ double wv[D + 1];
+  __shared__ double sW[A::SW];
+  __shared__ double wk[A::WORK];
+  __shared__ double sJ[NF * NQF];
   Tab tb = load_tables<N, Q>(tables, st);
   const long blk = blockIdx.x;
-  if (blk / (NV * NV * NTILE) >= n_elem) return;
-  const long e = e0 + blk / (NV * NV * NTILE);
-  const int kl = (blk / NTILE) % (NV * NV);
-  const int tile = blk % NTILE;
+  if (blk / (NV * NV) >= n_elem) return;
+  const long e = e0 + blk / (NV * NV);
+  const int kl = blk % (NV * NV);
   const int k = kl / NV, l = kl % NV;
-  double acc[NO];
-#pragma unroll
-  for (int o = 0; o < NO; ++o) acc[o] = 0.0;
-  __syncthreads();
   const int tid = threadIdx.x;
-  for (int q = 0; q < NQ; ++q) {
-    int aq[3] = {0, 0, 0};
-    {
-      int r = q;
+  for (int i = tid; i < A::SW; i += NT) {
+    const int q = i % NQ, jb = i / NQ;
+    sW[i] = Wt[(e * NQ + q) * (long)PER_Q + (jb * NV + k) * NV + l];
+  }
+  for (int i = tid; i < NF * NQF; i += NT) sJ[i] = JmW[(e * NF * NQF + i) * (long)NV * NV + k * NV + l];
+  const double* B = tb.B;     // B[q * N + m]
+  const double* Dq = tb.Dq;
+  // output sub-block: entry (m, n) of A_kl at Dm[e][l NM + n][k NM + m]
+  double* out = Dm + (e * NB + l * NM) * (long)NB + k * NM;
+  __syncthreads();
+  for (int j = 0; j < D; ++j) {
+    const double* F1 = (j == 0) ? Dq : B;
+    const double* F2 = (j == 1) ? Dq : B;
+    const double* W0 = sW + (j * (D + 1)) * NQ;
+    if constexpr (D == 3) {
+      const double* F3 = (j == 2) ? Dq : B;
+      double* s1a = wk;                          // [m1][n1][q2 q3]: g = (B|Dq, B, B)
+      double* s1b = wk + N * N * Q * Q;          // (B, Dq, B)
+      double* s1c = wk + 2 * N * N * Q * Q;      // (B, B, Dq)
+      double* s2b = wk + A::S1;                  // [m1][n1][m2][n2][q3]: g3 = B
+      double* s2d = s2b + N * N * N * N * Q;     // g3 = Dq
+      for (int it = tid; it < N * N * Q * Q; it += NT) {
+        const int r = it % (Q * Q), n1 = (it / (Q * Q)) % N, m1 = it / (Q * Q * N);
+        double a = 0.0, b = 0.0, c = 0.0;
 #pragma unroll
-      for (int x = 0; x < D; ++x) { aq[x] = r % Q; r /= Q; }
-    }
-    const double* wq = Wt + (e * NQ + q) * (long)PER_Q;
-    for (int j = 0; j < D; ++j) {
-      if (tid <= D) wv[tid] = wq[((j * (D + 1) + tid) * NV + k) * NV + l];
-      __syncthreads();
-      for (int n = tid; n < NM; n += NT) {
-        int ni[3] = {0, 0, 0};
-        split<D, N>(n, ni);
-        double bv[D], dv[D];
-#pragma unroll
-        for (int x = 0; x < D; ++x) { bv[x] = tb.B[aq[x] * N + ni[x]]; dv[x] = tb.Dq[aq[x] * N + ni[x]]; }
-        double psi0 = 1.0;
-#pragma unroll
-        for (int x = 0; x < D; ++x) psi0 *= bv[x];
-        double z = wv[0] * psi0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-          double t = 1.0;
-#pragma unroll
-          for (int x = 0; x < D; ++x) t *= (x == i) ? dv[x] : bv[x];
-          z += wv[1 + i] * t;
+        for (int q1 = 0; q1 < Q; ++q1) {
+          const double f = F1[q1 * N + m1];
+          const int q = q1 + Q * r;
+          a += f * (B[q1 * N + n1] * W0[q] + Dq[q1 * N + n1] * W0[NQ + q]);
+          b += f * B[q1 * N + n1] * W0[2 * NQ + q];
+          c += f * B[q1 * N + n1] * W0[3 * NQ + q];
         }
-        Z[n] = z;
+        s1a[it] = a;
+        s1b[it] = b;
+        s1c[it] = c;
       }
       __syncthreads();
+      for (int it = tid; it < N * N * N * N * Q; it += NT) {
+        const int q3 = it % Q, n2 = (it / Q) % N, m2 = (it / (Q * N)) % N, mn1 = it / (Q * N * N);
+        double b3 = 0.0, d3 = 0.0;
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        int oi = tile * NT * NO + tid + o * NT;
-        if (oi < NM * NM) {
-          int m = oi / NM, n = oi % NM;
-          int mi[3] = {0, 0, 0};
-          split<D, N>(m, mi);
-          double t = 1.0;
-#pragma unroll
-          for (int x = 0; x < D; ++x) t *= (x == j) ? tb.Dq[aq[x] * N + mi[x]] : tb.B[aq[x] * N + mi[x]];
-          acc[o] += t * Z[n];
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const double f = F2[q2 * N + m2];
+          const int o = mn1 * Q * Q + q2 + Q * q3;
+          b3 += f * (B[q2 * N + n2] * s1a[o] + Dq[q2 * N + n2] * s1b[o]);
+          d3 += f * B[q2 * N + n2] * s1c[o];
         }
+        s2b[it] = b3;
+        s2d[it] = d3;
+      }
+      __syncthreads();
+      for (int oi = tid; oi < NM * NM; oi += NT) {
+        const int m = oi % NM, n = oi / NM;
+        const int m1 = m % N, m2 = (m / N) % N, m3 = m / (N * N);
+        const int n1 = n % N, n2 = (n / N) % N, n3 = n / (N * N);
+        const int base = (((m1 * N + n1) * N + m2) * N + n2) * Q;
+        double t = 0.0;
+#pragma unroll
+        for (int q3 = 0; q3 < Q; ++q3)
+          t += F3[q3 * N + m3] * (B[q3 * N + n3] * s2b[base + q3] + Dq[q3 * N + n3] * s2d[base + q3]);
+        double* o = out + (long)n * NB + m;
+        *o = (j == 0) ? t : *o + t;
+      }
+      __syncthreads();
+    } else {
+      double* s1a = wk;                // [m1][n1][q2]: g = (B|Dq, B)
+      double* s1b = wk + N * N * Q;    // (B, Dq)
+      for (int it = tid; it < N * N * Q; it += NT) {
+        const int q2 = it % Q, n1 = (it / Q) % N, m1 = it / (Q * N);
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+          const double f = F1[q1 * N + m1];
+          const int q = q1 + Q * q2;
+          a += f * (B[q1 * N + n1] * W0[q] + Dq[q1 * N + n1] * W0[NQ + q]);
+          b += f * B[q1 * N + n1] * W0[2 * NQ + q];
+        }
+        s1a[it] = a;
+        s1b[it] = b;
+      }
+      __syncthreads();
+      for (int oi = tid; oi < NM * NM; oi += NT) {
+        const int m = oi % NM, n = oi / NM;
+        const int m1 = m % N, m2 = m / N, n1 = n % N, n2 = n / N;
+        const int base = (m1 * N + n1) * Q;
+        double t = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2)
+          t += F2[q2 * N + m2] * (B[q2 * N + n2] * s1a[base + q2] + Dq[q2 * N + n2] * s1b[base + q2]);
+        double* o = out + (long)n * NB + m;
+        *o = (j == 0) ? t : *o + t;
       }
       __syncthreads();
     }
   }
-  // own-side face term
+  // own-side face terms: tangential contraction per face, then the normal factors
+  constexpr int FB = (D == 3) ? N * N * N * N : N * N;
+  double* ff = wk;
   for (int f = 0; f < NF; ++f) {
-    const int ax = f >> 1, s = f & 1;
-    int tax[2] = {0, 0};
-    tang_axes<D>(ax, tax);
-    for (int p = 0; p < NQF; ++p) {
-      int bq[3] = {0, 0, 0};
-      bq[tax[0]] = p % Q;
-      if (D == 3) bq[tax[1]] = p / Q;
-      const double jw = JmW[((e * NF + f) * NQF + p) * NV * NV + k * NV + l];
-      for (int n = tid; n < NM; n += NT) {
-        int ni[3] = {0, 0, 0};
-        split<D, N>(n, ni);
-        double t = 1.0;
+    const double* jw = sJ + f * NQF;
+    if constexpr (D == 3) {
+      double* g = wk + A::FF;                  // [mt0][nt0][p1]
+      for (int it = tid; it < N * N * Q; it += NT) {
+        const int p1 = it % Q, n0 = (it / Q) % N, m0 = it / (Q * N);
+        double t = 0.0;
 #pragma unroll
-        for (int x = 0; x < D; ++x) t *= (x == ax) ? tb.phiE[s * N + ni[x]] : tb.B[bq[x] * N + ni[x]];
-        Z[n] = t * jw;
+        for (int p0 = 0; p0 < Q; ++p0) t += B[p0 * N + m0] * B[p0 * N + n0] * jw[p0 + Q * p1];
+        g[it] = t;
       }
       __syncthreads();
+      for (int it = tid; it < FB; it += NT) {
+        const int n1 = it % N, m1 = (it / N) % N, mn0 = it / (N * N);
+        double t = 0.0;
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        int oi = tile * NT * NO + tid + o * NT;
-        if (oi < NM * NM) {
-          int m = oi / NM, n = oi % NM;
-          int mi[3] = {0, 0, 0};
-          split<D, N>(m, mi);
-          double t = 1.0;
-#pragma unroll
-          for (int x = 0; x < D; ++x) t *= (x == ax) ? tb.phiE[s * N + mi[x]] : tb.B[bq[x] * N + mi[x]];
-          acc[o] -= t * Z[n];
-        }
+        for (int p1 = 0; p1 < Q; ++p1) t += B[p1 * N + m1] * B[p1 * N + n1] * g[mn0 * Q + p1];
+        ff[f * FB + it] = t;                   // [mt0][nt0][mt1][nt1]
       }
       __syncthreads();
+    } else {
+      for (int it = tid; it < FB; it += NT) {
+        const int n0 = it % N, m0 = it / N;
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) t += B[p * N + m0] * B[p * N + n0] * jw[p];
+        ff[f * FB + it] = t;                   // [mt][nt]
+      }
     }
   }
+  __syncthreads();
   const double sc = mass ? dt_a : dt_a * geo[e * S::GEO + D + 1];
+  for (int oi = tid; oi < NM * NM; oi += NT) {
+    const int m = oi % NM, n = oi / NM;
+    int mi[3] = {0, 0, 0}, ni[3] = {0, 0, 0};
+    split<D, N>(m, mi);
+    split<D, N>(n, ni);
+    double fsum = 0.0;
 #pragma unroll
-  for (int o = 0; o < NO; ++o) {
-    int oi = tile * NT * NO + tid + o * NT;
-    if (oi < NM * NM) {
-      int m = oi / NM, n = oi % NM;
-      int row = k * NM + m, col = l * NM + n;
-      const double dg = mass ? ((k == l) ? mass[(e * NM + m) * (long)NM + n] : 0.0) : ((row == col) ? 1.0 : 0.0);
-      double val = dg - sc * acc[o];
-      Dm[(e * NB + col) * (long)NB + row] = (TD)val;
+    for (int f = 0; f < NF; ++f) {
+      const int ax = f >> 1, sd = f & 1;
+      int t[2] = {0, 0};
+      tang_axes<D>(ax, t);
+      const double nf = tb.phiE[sd * N + mi[ax]] * tb.phiE[sd * N + ni[ax]];
+      const int fi = (D == 3) ? ((mi[t[0]] * N + ni[t[0]]) * N + mi[t[1]]) * N + ni[t[1]] : mi[t[0]] * N + ni[t[0]];
+      fsum += nf * ff[f * FB + fi];
     }
+    double* o = out + (long)n * NB + m;
+    const double dg = mass ? ((k == l) ? mass[(e * NM + m) * (long)NM + n] : 0.0) : ((k == l && m == n) ? 1.0 : 0.0);
+    *o = dg - sc * (*o - fsum);
   }
 }
 
