@@ -75,3 +75,36 @@ def test_batch_rejects_boundaries_and_curved_instances():
     _raises(EUNSUPPORTED, lambda: Batch([cfgs[0], ann]))
     # the batched stepper runs the SDIRK2/3 tables only
     _raises(EUNSUPPORTED, lambda: Batch([dataclasses.replace(c, scheme="sdirk4") for c in cfgs]))
+
+
+def test_dirichlet_and_source_errors():
+    """A Dirichlet mesh needs its ghost states before any residual or build;
+    the field cannot be set on a mesh without Dirichlet faces; a source can
+    be set and removed."""
+    _case("Dirichlet / source errors")
+    from paper_2002_04222_amd import Context
+    cfg = W.mms_config(2, 3)
+    mesh = cfg.mesh()
+    k, st = cfg.boundary()
+    ctx = Context(mesh, cfg, bc_kind=k, bc_state=st)
+    u = ctx.empty()
+    inp = W.mms_inputs(cfg, mesh)
+    ctx.project(torch.tensor(inp["initial"], device="cuda"), u)
+    R = ctx.empty()
+    _raises(EINVAL, lambda: ctx.residual(u, R))            # no ghost states yet
+    _raises(EINVAL, lambda: ctx.precond_build(u, 0.1))
+    ctx.set_bc_field(torch.tensor(inp["bc_field"], device="cuda"))
+    ctx.residual(u, R)
+    s = torch.ones_like(R)
+    ctx.set_source(s)
+    R2 = ctx.empty()
+    ctx.residual(u, R2)
+    ctx.set_source(None)
+    R3 = ctx.empty()
+    ctx.residual(u, R3)
+    torch.cuda.synchronize()
+    assert torch.allclose(R2 - 1.0, R, rtol=0, atol=1e-12 * max(1.0, float(R.abs().max())))
+    assert torch.equal(R3, R)
+    cfg2, mesh2, _ = setup(2, (3, 3), 2)
+    c2 = Context(mesh2, cfg2)
+    _raises(EINVAL, lambda: c2.set_bc_field(torch.zeros(9 * 4 * 4 * 4, dtype=torch.float64, device="cuda")))
