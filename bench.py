@@ -64,7 +64,8 @@ def parse():
     ap.add_argument("--no-explicit", action="store_true",
                     help="skip the explicit ERK2 comparison (its largest stable CFL and its time to reach the "
                          "same physical time as the timed implicit steps)")
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernel-reps", type=int, default=100,
+                    help="back-to-back residual evaluations per timing repeat (median of 5 repeats)")
     ap.add_argument("--mode", default="full", choices=["full", "sweep", "copy", "residual"],
                     help="sweep: only build the preconditioner and apply it (for counter runs); "
                          "copy: a plain 1 GiB device copy (counter calibration); "
@@ -244,16 +245,20 @@ def main():
 
     # ---- residual kernel throughput (inputs resident, back-to-back launches)
     R = ctx.empty()
-    for _ in range(5):
+    for _ in range(10):
         ctx.residual(u, R)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.kernel_reps):
-        ctx.residual(u, R)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    res_ms = ev0.elapsed_time(ev1) / args.kernel_reps
-    log(f"residual kernel {res_ms:.4f} ms")
+    times = []
+    for _ in range(5):
+        ev0.record(stream)
+        for _ in range(args.kernel_reps):
+            ctx.residual(u, R)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / args.kernel_reps)
+    res_ms = sorted(times)[2]
+    log(f"residual kernel {res_ms:.4f} ms (median of 5 x {args.kernel_reps}; "
+        f"{min(times):.4f}-{max(times):.4f})")
 
     if cfg.geometry == "annulus" and not args.cylinder_steps:
         line = cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream)
@@ -296,13 +301,16 @@ def main():
     o = ctx.empty()
     for _ in range(3):
         ctx.precond_apply(q, o)
-    reps = max(5, args.kernel_reps // 5)
-    ev0.record(stream)
-    for _ in range(reps):
-        ctx.precond_apply(q, o)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    sweep_ms = ev0.elapsed_time(ev1) / (reps * cfg.brj_sweeps)
+    reps = max(5, args.kernel_reps // 10)
+    times = []
+    for _ in range(3):
+        ev0.record(stream)
+        for _ in range(reps):
+            ctx.precond_apply(q, o)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / (reps * cfg.brj_sweeps))
+    sweep_ms = sorted(times)[1]
     sb = sweep_bytes(ctx, cfg, cfg.pc_precision)
     achieved = sb / (sweep_ms * 1e-3) / 1e9
     log(f"BRJ sweep {sweep_ms:.4f} ms, {achieved:.0f} GB/s")
