@@ -8,8 +8,12 @@
  *   N(u) = u - S - dt a M^-1 L(u)                  (Sec. 3.2, Eq. 20)
  *   J v ~ (N(u + eps v) - N(u)) / eps              (Sec. 4.2.2, Eq. 25-26)
  *   P^-1 q by block-relaxed Jacobi BRJ(J)          (Sec. 4.2.2, Eq. 27-31)
- * and advances u by SDIRK steps with Newton (Eq. 21-23) and restarted
- * right-preconditioned GMRES (Eq. 24).
+ * and advances u by implicit Runge-Kutta (SDIRK2/3/4, backward Euler), BDF2
+ * or explicit ERK2 steps (Sec. 3.2, Sec. 4.3, Appendix A), the implicit ones
+ * with Newton (Eq. 21-23) and restarted right-preconditioned GMRES (Eq. 24).
+ * Viscous face terms by interior penalty (Eq. 12) or LDG; Roe, LLF, HLL,
+ * HLLC or AUSM+ Riemann fluxes; the boundary kinds of Sec. 4.3; affine boxes
+ * or curved isoparametric elements (Sec. 3.1).
  *
  * Conventions for every entry point below:
  *  - Array arguments are DEVICE pointers (on the device current when the
@@ -19,7 +23,8 @@
  *    (rho, rho u_1..rho u_d, E); modes of the orthonormal tensor Legendre
  *    basis phi_i(xi) = sqrt((2i+1)/2) P_i(xi) on [-1,1]^d, mode index
  *    i + n (j + n k), x fastest, n = P + 1.  n_unknowns = n_elem (d+2) n^d.
- *  - Elements are affine boxes; faces are f = 2*axis + side (side 0 at
+ *  - Elements are affine boxes or isoparametric maps of the reference
+ *    cube (dgj_mesh.geo_nodes); faces are f = 2*axis + side (side 0 at
  *    xi_axis = -1).  face_nbr[e][f] is the element across face f, which
  *    meets it with its face 2*axis + (1 - side), face points aligned, or
  *    marks a boundary face (dgj_mesh).
