@@ -693,10 +693,10 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
   constexpr int NV = S::NV, NM = S::NM, NQF = S::NQF, NMF = S::NMF, NF = S::NF, NB = S::NB;
   __shared__ double st[S::TAB];
   __shared__ double sr[NB];
-  __shared__ double sacc[NB];
-  __shared__ double tvf[NV * NMF];
-  __shared__ double tpt[NV * NQF];
-  __shared__ double flx[NV * NQF];
+  __shared__ double tvf[NF * NV * NMF];
+  __shared__ double tpt[NF * NV * NQF];
+  __shared__ double flx[NF * NV * NQF];
+  __shared__ long snb[NF];
   Tab tb = load_tables<N, Q>(tables, st);
   const long e = blockIdx.x;
   if (e >= n_elem) return;
@@ -707,42 +707,48 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
   }
   const int tid = threadIdx.x;
   const double* g = geo + e * S::GEO;
-  for (int i = tid; i < NB; i += NT) { sr[i] = q[e * NB + i]; sacc[i] = 0.0; }
+  for (int i = tid; i < NB; i += NT) sr[i] = q[e * NB + i];
+  if (tid < NF) snb[tid] = nbr[e * NF + tid];
   __syncthreads();
   if (!first) {
-    for (int f = 0; f < NF; ++f) {
-      const int ax = f >> 1, s = f & 1;
-      const long en = nbr[e * NF + f];
-      if (en < 0) continue;   // boundary face: no neighbour block
-      const int sg = 1 - s;
-      int tax[2] = {0, 0};
-      tang_axes<D>(ax, tax);
-      for (int it = tid; it < NV * NMF; it += NT) {
-        int tm = it % NMF, v = it / NMF;
-        double sv = 0.0;
+    // all faces at once (boundary faces have no neighbour block and add 0):
+    // neighbour trace in face modes, at the face points, times the stored
+    // flux Jacobian and weight, lifted back onto this element's modes
+    for (int it = tid; it < NF * NV * NMF; it += NT) {
+      const int tm = it % NMF, v = (it / NMF) % NV, f = it / (NMF * NV);
+      const long en = snb[f];
+      double sv = 0.0;
+      if (en >= 0) {
+        const int ax = f >> 1, sg = 1 - (f & 1);
 #pragma unroll
         for (int ia = 0; ia < N; ++ia) sv += tb.phiE[sg * N + ia] * qold[en * NB + v * NM + mode_of<D, N>(ax, ia, tm)];
-        tvf[it] = sv;
       }
-      __syncthreads();
-      for (int it = tid; it < NV * NQF; it += NT) {
-        int p = it % NQF, v = it / NQF;
-        int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
-        double val = 0.0;
+      tvf[it] = sv;
+    }
+    __syncthreads();
+    for (int it = tid; it < NF * NV * NQF; it += NT) {
+      const int p = it % NQF, f = it / (NQF * NV);
+      const int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
+      const double* tv = tvf + (it / NQF) * NMF;
+      double val = 0.0;
+      if (snb[f] >= 0)
         for (int tm = 0; tm < NMF; ++tm) {
-          int j0 = tm % N, j1 = (D == 3) ? tm / N : 0;
-          double bb = tb.B[b0 * N + j0] * ((D == 3) ? tb.B[b1 * N + j1] : 1.0);
-          val += bb * tvf[v * NMF + tm];
+          const int j0 = tm % N, j1 = (D == 3) ? tm / N : 0;
+          val += tb.B[b0 * N + j0] * ((D == 3) ? tb.B[b1 * N + j1] : 1.0) * tv[tm];
         }
-        tpt[v * NQF + p] = val;
-      }
-      __syncthreads();
-      for (int it = tid; it < NV * NQF; it += NT) {
-        int p = it % NQF, k = it / NQF;
+      tpt[it] = val;
+    }
+    __syncthreads();
+    for (int it = tid; it < NF * NV * NQF; it += NT) {
+      const int p = it % NQF, k = (it / NQF) % NV, f = it / (NQF * NV);
+      double val = 0.0;
+      if (snb[f] >= 0) {
+        const int ax = f >> 1;
         const TJ* J = Jp + ((e * NF + f) * NQF + p) * NV * NV + k * NV;
+        const double* tp = tpt + f * NV * NQF + p;
         double sacc2 = 0.0;
 #pragma unroll
-        for (int l = 0; l < NV; ++l) sacc2 += jp_ld<TJ>(J + l) * tpt[l * NQF + p];
+        for (int l = 0; l < NV; ++l) sacc2 += jp_ld<TJ>(J + l) * tp[l * NQF];
         double wf;
         if (fg) {
           wf = fg[((e * NF + f) * (long)(D * D + D + 1) + D * D + D) * NQF + p];
@@ -750,27 +756,36 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
           wf = g[D + 2 + ax] * tb.w[p % Q];
           if (D == 3) wf *= tb.w[p / Q];
         }
-        flx[k * NQF + p] = sacc2 * wf;
+        val = sacc2 * wf;
       }
-      __syncthreads();
-      for (int it = tid; it < NB; it += NT) {
-        int m = it % NM, v = it / NM;
-        int mi[3] = {0, 0, 0};
-        split<D, N>(m, mi);
-        int j0 = mi[tax[0]], j1 = (D == 3) ? mi[tax[1]] : 0;
+      flx[it] = val;
+    }
+    __syncthreads();
+    // r = q - (L+U) qold, (L+U) qold = -dt_a / |J| sacc (curved: times M_e),
+    // sacc = -sum_f phi_s(m_ax) sum_p B B flx
+    const double sc = fg ? dt_a : dt_a * g[D + 1];
+    for (int it = tid; it < NB; it += NT) {
+      const int m = it % NM, v = it / NM;
+      int mi[3] = {0, 0, 0};
+      split<D, N>(m, mi);
+      double sacc = 0.0;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        if (snb[f] < 0) continue;
+        const int ax = f >> 1, s = f & 1;
+        int tax[2] = {0, 0};
+        tang_axes<D>(ax, tax);
+        const int j0 = mi[tax[0]], j1 = (D == 3) ? mi[tax[1]] : 0;
+        const double* fl = flx + (f * NV + v) * NQF;
         double s2 = 0.0;
         for (int p = 0; p < NQF; ++p) {
-          int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
-          double bb = tb.B[b0 * N + j0] * ((D == 3) ? tb.B[b1 * N + j1] : 1.0);
-          s2 += bb * flx[v * NQF + p];
+          const int b0 = p % Q, b1 = (D == 3) ? p / Q : 0;
+          s2 += tb.B[b0 * N + j0] * ((D == 3) ? tb.B[b1 * N + j1] : 1.0) * fl[p];
         }
-        sacc[it] -= tb.phiE[s * N + mi[ax]] * s2;
+        sacc -= tb.phiE[s * N + mi[ax]] * s2;
       }
-      __syncthreads();
+      sr[it] = sr[it] + sc * sacc;
     }
-    // r = q - (L+U) qold, (L+U) qold = -dt_a / |J| sacc (curved: times M_e)
-    const double sc = fg ? dt_a : dt_a * g[D + 1];
-    for (int i = tid; i < NB; i += NT) sr[i] = sr[i] + sc * sacc[i];
     __syncthreads();
   }
   using A = typename AccT<T>::type;
