@@ -21,7 +21,8 @@
     variable v (||u||_2 sqrt(eps_hat) for a variable that is zero
     everywhere, where the paper's rule gives no step).  D_e is inverted explicitly with LU and partial pivoting.
   * GMRES (Sec. 3.2): restarted right-preconditioned GMRES(m) of Saad and
-    Schultz with modified Gram-Schmidt and Givens rotations, x0 = 0,
+    Schultz with modified Gram-Schmidt (or classical Gram-Schmidt twice) and
+    Givens rotations, x0 = 0,
     stopping when the residual has dropped by the factor rtol (5e-2) or
     after gmres_max iterations in total.  x = x0 + P^-1 V y (the
     preconditioner is linear: a fixed number of sweeps from q^0 = 0).
@@ -206,9 +207,13 @@ class BRJ:
 
 
 # ------------------------------------------------------------------ GMRES
-def gmres(matvec, precond, b, restart=30, rtol=5e-2, maxit=300):
+def gmres(matvec, precond, b, restart=30, rtol=5e-2, maxit=300, ortho="mgs"):
     """Right-preconditioned restarted GMRES(m); returns (x, iterations,
-    converged, residual history)."""
+    converged, residual history).  ortho: "mgs" (modified Gram-Schmidt, one
+    projection at a time) or "cgs2" (classical Gram-Schmidt applied twice:
+    all projections of a pass from the same vector, the second pass
+    removing what rounding left of the first; the Hessenberg column is the
+    sum of both passes' coefficients)."""
     x = np.zeros_like(b)
     beta0 = l2(b)
     hist = [beta0]
@@ -234,9 +239,15 @@ def gmres(matvec, precond, b, restart=30, rtol=5e-2, maxit=300):
             z = precond(V[k])
             w = matvec(z)
             total += 1
-            for i in range(k + 1):
-                H[i, k] = float(np.sum(w * V[i]))
-                w = w - H[i, k] * V[i]
+            if ortho == "cgs2":
+                for _ in range(2):
+                    h = np.array([float(np.sum(w * V[i])) for i in range(k + 1)])
+                    w = w - sum(h[i] * V[i] for i in range(k + 1))
+                    H[:k + 1, k] += h
+            else:
+                for i in range(k + 1):
+                    H[i, k] = float(np.sum(w * V[i]))
+                    w = w - H[i, k] * V[i]
             H[k + 1, k] = l2(w)
             breakdown = H[k + 1, k] == 0.0
             V.append(w / H[k + 1, k] if not breakdown else np.zeros_like(w))
@@ -280,6 +291,7 @@ class SolverOpts:
     brj_omega: float = 1.0
     pc_freeze: int = 10
     pc_refresh_its: int = 30      # rebuild before a stage when the last Newton step's GMRES took more (0: never)
+    ortho: str = "mgs"            # GMRES orthogonalisation: "mgs" or "cgs2"
     use_pc: bool = True
 
 
@@ -312,7 +324,8 @@ def newton_solve(disc, S, dt_a, pc, opts: SolverOpts, guess=None):
         eps = jfnk_eps(u)
         Nu = N
         mv = lambda q, u=u, Nu=Nu, eps=eps: jfnk_matvec(disc, u, Nu, S, dt_a, q, eps)
-        delta, its, ok, _ = gmres(mv, precond, -N, opts.gmres_restart, opts.gmres_rtol, opts.gmres_max)
+        delta, its, ok, _ = gmres(mv, precond, -N, opts.gmres_restart, opts.gmres_rtol, opts.gmres_max,
+                                  opts.ortho)
         st.gmres_its.append(its)
         u = u + delta
         N = disc.stage_residual(u, S, dt_a)

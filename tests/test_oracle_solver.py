@@ -253,23 +253,24 @@ def test_brj_apply_equals_dense_iteration():
         assert np.abs(x - y).max() <= 1e-12 * np.abs(x).max()
 
 
-def test_gmres_solves_dense_system():
+@pytest.mark.parametrize("ortho", ["mgs", "cgs2"])
+def test_gmres_solves_dense_system(ortho):
     """P11b: with a tight tolerance and no restart GMRES returns the solution
-    of the linear system."""
+    of the linear system, with either orthogonalisation."""
     rng = np.random.default_rng(5)
     n = 40
     A = np.eye(n) * 4 + rng.normal(size=(n, n)) * 0.3
     b = rng.normal(size=n)
     M = np.diag(1.0 / np.diag(A))
-    x, its, ok, hist = S.gmres(lambda v: A @ v, lambda v: M @ v, b, restart=n, rtol=1e-13, maxit=n)
+    x, its, ok, hist = S.gmres(lambda v: A @ v, lambda v: M @ v, b, restart=n, rtol=1e-13, maxit=n, ortho=ortho)
     assert ok
     assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
     # restarted variant converges to the same solution
-    x2, its2, ok2, _ = S.gmres(lambda v: A @ v, lambda v: M @ v, b, restart=5, rtol=1e-11, maxit=400)
+    x2, its2, ok2, _ = S.gmres(lambda v: A @ v, lambda v: M @ v, b, restart=5, rtol=1e-11, maxit=400, ortho=ortho)
     assert ok2 and its2 > 5
     assert np.allclose(x2, np.linalg.solve(A, b), rtol=1e-8, atol=1e-10)
     # residual estimate equals the true residual at exit
-    x3, its3, ok3, hist3 = S.gmres(lambda v: A @ v, lambda v: M @ v, b, restart=30, rtol=5e-2)
+    x3, its3, ok3, hist3 = S.gmres(lambda v: A @ v, lambda v: M @ v, b, restart=30, rtol=5e-2, ortho=ortho)
     assert np.isclose(np.linalg.norm(b - A @ x3), hist3[-1], rtol=1e-8)
     assert hist3[-1] <= 5e-2 * np.linalg.norm(b)
 
@@ -365,3 +366,24 @@ def test_erk2_step_is_second_order_taylor_polynomial():
     ref = (u0.ravel() + Kd @ u0.ravel() + 0.5 * Kd @ (Kd @ u0.ravel())).reshape(u0.shape)
     assert np.abs(u1 - ref).max() <= 1e-13 * np.abs(ref).max()
     assert st.pc is None and all(x.newton_its == 0 for x in stats)
+
+
+
+def test_cgs2_basis_orthonormal_where_single_cgs_is_not():
+    """The second classical pass restores orthogonality that one pass loses
+    on an ill-conditioned Krylov sequence (Giraud-Langou-Rozloznik): the
+    basis GMRES builds with "cgs2" stays orthonormal to rounding."""
+    rng = np.random.default_rng(7)
+    n = 60
+    U, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    A = U @ np.diag(np.logspace(0, 12, n)) @ U.T
+    b = rng.normal(size=n)
+    basis = []
+
+    def mv(v):
+        basis.append(v)
+        return A @ v
+    S.gmres(mv, lambda v: v, b, restart=25, rtol=1e-30, maxit=25, ortho="cgs2")
+    Vb = np.array(basis).T
+    G = Vb.T @ Vb
+    assert np.abs(G - np.eye(G.shape[0])).max() < 1e-14      # one classical pass: ~2e-10 here
