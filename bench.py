@@ -45,7 +45,11 @@ def parse():
     ap.add_argument("--pc-refresh-its", type=int, default=None,
                     help="GMRES count of a Newton step above which the next stage rebuilds the blocks "
                          "(default: the workload's; 0 = fixed freeze only)")
-    ap.add_argument("--forms", action="store_true", help="also time the f32 and bf16 preconditioner forms")
+    ap.add_argument("--ortho", default=None, choices=["mgs", "cgs2"],
+                    help="GMRES orthogonalisation (default: the workload's, modified Gram-Schmidt)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision forms (FP64 / FP32 / BF16 blocks: 3 steps each from the start "
+                         "state, their sweep's roofline, speed-up and state difference against FP64)")
     ap.add_argument("--learned", action="store_true",
                     help="also time the learned Newton guess against the paper's and the extrapolated one")
     ap.add_argument("--learned-train", type=int, default=20, help="plain steps recorded to train the MLP")
@@ -179,21 +183,12 @@ def main():
     from paper_2002_04222_amd import Context
 
     cfg = W.config(args.workload)
+    import dataclasses
     if args.P is not None:
-        import dataclasses
         cfg = dataclasses.replace(cfg, P=args.P, nq=args.P + 2, name=cfg.name.rsplit("-p", 1)[0] + f"-p{args.P}")
-    if args.pc:
-        import dataclasses
-        cfg = dataclasses.replace(cfg, pc_precision=args.pc)
-    if args.pc_freeze is not None:
-        import dataclasses
-        cfg = dataclasses.replace(cfg, pc_freeze=args.pc_freeze)
-    if args.brj_sweeps is not None:
-        import dataclasses
-        cfg = dataclasses.replace(cfg, brj_sweeps=args.brj_sweeps)
-    if args.pc_refresh_its is not None:
-        import dataclasses
-        cfg = dataclasses.replace(cfg, pc_refresh_its=args.pc_refresh_its)
+    over = {"pc_precision": args.pc, "pc_freeze": args.pc_freeze, "brj_sweeps": args.brj_sweeps,
+            "pc_refresh_its": args.pc_refresh_its, "ortho": args.ortho}
+    cfg = dataclasses.replace(cfg, **{k: v for k, v in over.items() if v is not None and v != ""})
     mesh = cfg.mesh()
     dt = cfg.dt()
     log(f"workload {cfg.name}: {mesh.n_elem} elements, P={cfg.P}, dt={dt:.4f}, pc={cfg.pc_precision}")
@@ -323,8 +318,8 @@ def main():
         "config": {"workload": cfg.name, "elements": mesh.n_elem, "P": cfg.P, "nq": cfg.nq, "dim": cfg.dim,
                    "dofs_per_var": cfg.dofs(), "unknowns": ctx.n_unknowns, "scheme": cfg.scheme,
                    "cfl": cfg.cfl, "dt": dt, "Re": cfg.Re, "Ma": cfg.Ma, "newton_rtol": cfg.newton_rtol,
-                   "gmres": f"GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol}", "brj_sweeps": cfg.brj_sweeps,
-                   "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze,
+                   "gmres": f"GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol}, {cfg.ortho}",
+                   "brj_sweeps": cfg.brj_sweeps, "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze,
                    "pc_refresh_its": cfg.pc_refresh_its},
         "roofline": {"bound": "hbm", "kernel": "k_brj_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -338,7 +333,7 @@ def main():
         "gmres_its": [s["gmres_its"] for s in stats],
     }
 
-    if args.forms:
+    if not args.no_forms and cfg.geometry != "annulus":
         base_u = None
         forms = {}
         for prec in ("f64", "f32", "bf16"):
@@ -354,10 +349,23 @@ def main():
             uh = u2.cpu().numpy()
             if base_u is None:
                 base_u = uh
+            # the form's sweep: same launches as in its steps, its own block bytes
+            qf, of = c2.empty(), c2.empty()
+            qf.copy_(q)
+            c2.precond_apply(qf, of)
+            ev0.record(stream)
+            for _ in range(5):
+                c2.precond_apply(qf, of)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            sw_ms = ev0.elapsed_time(ev1) / (5 * cfg.brj_sweeps)
+            sw_gbs = sweep_bytes(c2, cfg, prec) / (sw_ms * 1e-3) / 1e9
             forms[prec] = {"ms_per_step": ms, "newton_its": its,
-                           "rel_diff_vs_f64": float(np.linalg.norm(uh - base_u) / np.linalg.norm(base_u))}
+                           "rel_diff_vs_f64": float(np.linalg.norm(uh - base_u) / np.linalg.norm(base_u)),
+                           "sweep_ms": sw_ms, "sweep_GBps": sw_gbs, "sweep_frac_hbm": sw_gbs / HBM_PEAK_GBS,
+                           "sweep_traffic": measured_traffic(prec) if args.workload == 2 else None}
             c2.close()
-            log(f"form {prec}: {ms:.1f} ms/step")
+            log(f"form {prec}: {ms:.1f} ms/step, sweep {sw_ms:.4f} ms {sw_gbs:.0f} GB/s")
         for prec in forms:
             forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
         out["forms"] = forms

@@ -166,6 +166,10 @@ typedef struct {
                                  than this, and retry a failed stage once from S_m with blocks
                                  rebuilt at S_m (0: the paper's fixed freeze only); not in the
                                  paper, which keeps the blocks for pc_freeze steps */
+  int32_t ortho;              /* GMRES orthogonalisation: 0 modified Gram-Schmidt (one projection
+                                 at a time), 1 classical Gram-Schmidt applied twice (all
+                                 projections of a pass at once: two batched reductions per
+                                 iteration instead of k + 1; single instances only) */
 } dgj_solver;
 
 /* Per-step statistics filled by dgj_sdirk_step. */
@@ -266,8 +270,9 @@ int dgj_mass_inverse(dgj_ctx *ctx, double *out);
 int dgj_precond_diag_inverse(dgj_ctx *ctx, double *out);
 
 /* Solve J x = b approximately by restarted right-preconditioned GMRES
- * (MGS Arnoldi, Givens rotations, x0 = 0) with the Jacobian-free J at
- * (u, N_u, S, dt_a) and eps as in dgj_jfnk_matvec; uses the built
+ * (Arnoldi by the solver's ortho choice, Givens rotations, x0 = 0) with
+ * the Jacobian-free J at (u, N_u, S, dt_a) and eps as in dgj_jfnk_matvec;
+ * uses the built
  * preconditioner if any.  *iters receives the iteration count. */
 int dgj_gmres(dgj_ctx *ctx, const double *u, const double *N_u, const double *S, double dt_a, double eps,
               const double *b, double *x, int32_t *iters);

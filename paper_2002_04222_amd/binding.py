@@ -45,7 +45,7 @@ class Solver(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("newton_rtol", C.c_double), ("newton_max", C.c_int32),
                 ("gmres_restart", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_max", C.c_int32),
                 ("brj_sweeps", C.c_int32), ("brj_omega", C.c_double), ("pc_precision", C.c_int32),
-                ("pc_freeze", C.c_int32), ("pc_refresh_its", C.c_int32)]
+                ("pc_freeze", C.c_int32), ("pc_refresh_its", C.c_int32), ("ortho", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -150,6 +150,7 @@ SCHEMES = {"beuler": DGJ_BEULER, "sdirk2": DGJ_SDIRK2, "sdirk3": DGJ_SDIRK3, "sd
            "bdf2": DGJ_BDF2, "erk2": DGJ_ERK2}
 PRECISIONS = {"f64": DGJ_PC_F64, "f32": DGJ_PC_F32, "bf16": DGJ_PC_BF16}
 VISCOUS = {"ip": 0, "ldg": 1}
+ORTHO = {"mgs": 0, "cgs2": 1}
 
 
 def _mesh_struct(mesh, cfg, keep, bc_kind=None, bc_state=None):
@@ -187,7 +188,7 @@ def _phys_struct(cfg):
 def _solver_struct(cfg):
     return Solver(SCHEMES[cfg.scheme], cfg.newton_rtol, cfg.newton_max, cfg.gmres_restart, cfg.gmres_rtol,
                   cfg.gmres_max, cfg.brj_sweeps, cfg.brj_omega, PRECISIONS[cfg.pc_precision], cfg.pc_freeze,
-                  cfg.pc_refresh_its)
+                  cfg.pc_refresh_its, ORTHO[getattr(cfg, "ortho", "mgs")])
 
 
 class Batch:
@@ -279,7 +280,7 @@ class Context:
                   VISCOUS[over.get("viscous", getattr(cfg, "viscous", "ip"))])
         sv = Solver(SCHEMES[g("scheme")], g("newton_rtol"), g("newton_max"), g("gmres_restart"), g("gmres_rtol"),
                     g("gmres_max"), g("brj_sweeps"), g("brj_omega"), PRECISIONS[g("pc_precision")], g("pc_freeze"),
-                    g("pc_refresh_its"))
+                    g("pc_refresh_its"), ORTHO[over.get("ortho", getattr(cfg, "ortho", "mgs"))])
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

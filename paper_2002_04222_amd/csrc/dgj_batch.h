@@ -470,6 +470,7 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
     b->loc.assign(n, -1);
     if (solver->scheme != DGJ_SDIRK2 && solver->scheme != DGJ_SDIRK3)
       throw Status{DGJ_EUNSUPPORTED, "batch: scheme must be SDIRK2 or SDIRK3"};
+    if (solver->ortho != 0) throw Status{DGJ_EUNSUPPORTED, "batch: modified Gram-Schmidt only"};
     for (int i = 0; i < n; ++i)
       if (phys[i].viscous != 0) throw Status{DGJ_EUNSUPPORTED, "batch: interior-penalty viscous terms only"};
     for (int i = 0; i < n; ++i) {

@@ -149,6 +149,37 @@ __global__ void k_reduce_final(const double* __restrict__ part, int np, double* 
   if (threadIdx.x == 0) out[0] = op == 1 ? sqrt(s) : s;
 }
 
+// partial dot products of w with k vectors at once: part[i][block] over the
+// same grid-stride partition as k_dot_partial (blockIdx.y = i)
+__global__ void k_multidot_partial(const double* __restrict__ w, const double* const* __restrict__ V, long n,
+                                   double* part) {
+  __shared__ double red[16];
+  const double* v = V[blockIdx.y];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    s += w[i] * v[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+// fixed-order sums of np partials per vector (one block per vector)
+__global__ void k_reduce_multi(const double* __restrict__ part, int np, double* out) {
+  __shared__ double red[16];
+  const double* p = part + (long)blockIdx.x * np;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += p[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+// w -= sum_{i<k} h[i] V[i]
+__global__ void k_multi_axpy(double* __restrict__ w, const double* const* __restrict__ V,
+                             const double* __restrict__ h, int k, long n) {
+  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += h[i] * V[i][j];
+    w[j] -= s;
+  }
+}
+
 // per-variable sums of squares of a state: part[b][v]
 __global__ void k_varsq_partial(const double* __restrict__ u, long n_elem, int nv, int nm, double* part) {
   __shared__ double red[16];
@@ -427,9 +458,12 @@ struct dgj_ctx {
   // reductions
   double* d_part = nullptr;    // [RED_BLOCKS * 8]
   double* d_scal = nullptr;    // scalars [64]
-  double* h_scal = nullptr;    // pinned host mirror
+  double* h_scal = nullptr;    // pinned host mirror [128]
   // solver workspaces
   std::vector<double*> V;      // restart+1 Krylov vectors
+  double** d_Vptr = nullptr;    // the same pointers on the device (classical Gram-Schmidt)
+  double* d_partm = nullptr;    // multi-dot partials [restart+1][RED_BLOCKS]
+  double* d_h2 = nullptr;       // second-pass projection coefficients [64]
   double *d_z = nullptr, *d_w = nullptr, *d_t1 = nullptr, *d_t2 = nullptr;
   double *d_ubar = nullptr, *d_N = nullptr, *d_S = nullptr, *d_b = nullptr, *d_x = nullptr, *d_un = nullptr;
   double* d_E[DGJ_MAX_STAGES] = {};   // stage derivatives (the scheme's stage count allocated)
@@ -1051,15 +1085,31 @@ GmresOut gmres(dgj_ctx* c, const double* u, const double* Nu, const double* S, d
       double* w = c->V[k + 1];
       matvec(c, u, Nu, S, dt_a, c->d_z, eps, w);
       r.its++;
-      for (int i = 0; i <= k; ++i) {
-        dot_dev(c, w, c->V[i], c->d_scal + i, 0);
-        hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(c->n)), dim3(256), 0, c->stream, w, c->V[i], c->d_scal + i, -1.0,
-                           c->n);
+      if (c->sv.ortho == 1) {
+        // classical Gram-Schmidt twice: h = V^T w, w -= V h, per pass
+        for (int pass = 0; pass < 2; ++pass) {
+          double* h = pass == 0 ? c->d_scal : c->d_h2;
+          hipLaunchKernelGGL(k_multidot_partial, dim3(RED_BLOCKS, k + 1), dim3(RED_THREADS), 0, c->stream, w,
+                             (const double* const*)c->d_Vptr, c->n, c->d_partm);
+          hipLaunchKernelGGL(k_reduce_multi, dim3(k + 1), dim3(RED_THREADS), 0, c->stream, c->d_partm, RED_BLOCKS, h);
+          hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(c->n)), dim3(256), 0, c->stream, w,
+                             (const double* const*)c->d_Vptr, h, k + 1, c->n);
+        }
+      } else {
+        for (int i = 0; i <= k; ++i) {
+          dot_dev(c, w, c->V[i], c->d_scal + i, 0);
+          hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(c->n)), dim3(256), 0, c->stream, w, c->V[i], c->d_scal + i,
+                             -1.0, c->n);
+        }
       }
       dot_dev(c, w, w, c->d_scal + k + 1, 1);
       HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      if (c->sv.ortho == 1)
+        HIPCHK(hipMemcpyAsync(c->h_scal + 64, c->d_h2, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
       for (int i = 0; i <= k + 1; ++i) Hc(i, k) = c->h_scal[i];
+      if (c->sv.ortho == 1)
+        for (int i = 0; i <= k; ++i) Hc(i, k) += c->h_scal[64 + i];
       if (!std::isfinite(Hc(k + 1, k))) fail(DGJ_ENAN, "gmres: non-finite Krylov vector");
       const bool breakdown = Hc(k + 1, k) == 0.0;
       if (!breakdown)
@@ -1222,6 +1272,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       fail(DGJ_EUNSUPPORTED, "dim %d, P %d, nq %d not built (nq = P+2, P <= %d)", mesh->dim, mesh->P, mesh->nq,
            mesh->dim == 2 ? 5 : 4);
     if (solver->gmres_restart < 1 || solver->gmres_restart > 60) fail(DGJ_EINVAL, "gmres_restart must be in 1..60");
+    if (solver->ortho < 0 || solver->ortho > 1) fail(DGJ_EINVAL, "ortho must be 0 (MGS) or 1 (CGS2)");
     if (!scheme_known(solver->scheme)) fail(DGJ_EINVAL, "unknown scheme %d", solver->scheme);
     if (solver->pc_precision < 0 || solver->pc_precision > 2) fail(DGJ_EINVAL, "bad pc_precision");
     if (phys->viscous < 0 || phys->viscous > 1) fail(DGJ_EINVAL, "viscous must be 0 (IP) or 1 (LDG)");
@@ -1353,12 +1404,18 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     HIPCHK(hipMemcpy(c->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&c->d_part, RED_BLOCKS * 8 * sizeof(double)));
     HIPCHK(hipMalloc(&c->d_scal, 64 * sizeof(double)));
-    HIPCHK(hipHostMalloc(&c->h_scal, 64 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&c->h_scal, 128 * sizeof(double), hipHostMallocDefault));   // [64] scalars + [64] second pass
     HIPCHK(hipMalloc(&c->d_chi, 8 * sizeof(double)));
     HIPCHK(hipMalloc(&c->d_status, E * sizeof(int)));
     const size_t vb = c->n * sizeof(double);
     c->V.assign(c->sv.gmres_restart + 1, nullptr);
     for (auto& p : c->V) HIPCHK(hipMalloc(&p, vb));
+    if (c->sv.ortho == 1) {
+      HIPCHK(hipMalloc(&c->d_Vptr, c->V.size() * sizeof(double*)));
+      HIPCHK(hipMemcpy(c->d_Vptr, c->V.data(), c->V.size() * sizeof(double*), hipMemcpyHostToDevice));
+      HIPCHK(hipMalloc(&c->d_partm, c->V.size() * RED_BLOCKS * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_h2, 64 * sizeof(double)));
+    }
     double** bufs[] = {&c->d_z, &c->d_w, &c->d_t1, &c->d_t2, &c->d_ubar, &c->d_N, &c->d_S, &c->d_b, &c->d_x,
                        &c->d_un, &c->d_pa, &c->d_pb, &c->d_g2};
     for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
@@ -1434,6 +1491,9 @@ void dgj_destroy(dgj_ctx* c) {
   if (c->d_bc_kind) hipFree(c->d_bc_kind);
   if (c->d_bc_state) hipFree(c->d_bc_state);
   if (c->d_bc_field) hipFree(c->d_bc_field);
+  if (c->d_Vptr) hipFree(c->d_Vptr);
+  if (c->d_partm) hipFree(c->d_partm);
+  if (c->d_h2) hipFree(c->d_h2);
   if (c->d_rq) hipFree(c->d_rq);
   if (c->d_src) hipFree(c->d_src);
   void* bps[] = {c->d_inst, c->d_phs, c->d_epsv, c->d_dtav, c->d_active, c->d_ioff, c->d_hs, c->d_part2, c->d_kused};

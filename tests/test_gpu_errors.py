@@ -75,6 +75,8 @@ def test_batch_rejects_boundaries_and_curved_instances():
     _raises(EUNSUPPORTED, lambda: Batch([cfgs[0], ann]))
     # the batched stepper runs the SDIRK2/3 tables only
     _raises(EUNSUPPORTED, lambda: Batch([dataclasses.replace(c, scheme="sdirk4") for c in cfgs]))
+    # and modified Gram-Schmidt only
+    _raises(EUNSUPPORTED, lambda: Batch([dataclasses.replace(c, ortho="cgs2") for c in cfgs]))
 
 
 def test_dirichlet_and_source_errors():

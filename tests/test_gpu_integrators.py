@@ -106,3 +106,15 @@ def test_bdf2_reset_history_restarts_with_backward_euler():
     uo, sto = stepper.step(u1, 0.1)
     assert st["newton_its"] == [s.newton_its for s in sto]
     assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
+
+
+@pytest.mark.parametrize("dim,cells,P,scheme", [(2, (4, 3), 3, "sdirk3"), (3, (3, 3, 3), 2, "sdirk2")])
+def test_cgs2_gmres_steps(dim, cells, P, scheme):
+    """GMRES with classical Gram-Schmidt applied twice: the same counts as the
+    oracle's CGS2 GMRES and its state to 1e-10."""
+    _case(f"cgs2 {dim}D {cells} P={P} {scheme}")
+    cfg, mesh, disc = setup(dim, cells, P, Ma=0.3, Re=40.0, scheme=scheme)
+    ctx = _ctx(cfg, mesh, ortho="cgs2")
+    u0 = W.random_state(mesh.n_elem, dim, P, seed=47)
+    stepper = OS.make_stepper(disc, OS.SolverOpts(scheme=scheme, ortho="cgs2"))
+    _run(ctx, stepper, _dev(u0), u0, [0.1, 0.1], 1e-10)

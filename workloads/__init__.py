@@ -194,6 +194,7 @@ class FlowConfig:
     brj_omega: float = 1.0
     pc_freeze: int = 10
     pc_refresh_its: int = 30
+    ortho: str = "mgs"        # GMRES orthogonalisation: "mgs" or "cgs2"
     pc_precision: str = "f64"
     geometry: str = "box"     # "box" (periodic affine boxes), "annulus" (curved O-grid, walls + far
                               # field) or "channel" (affine boxes, Dirichlet on every side)
