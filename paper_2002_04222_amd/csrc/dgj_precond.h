@@ -490,9 +490,10 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
 // held in LDS: the panel is eliminated on all rows (row swaps applied to the
 // panel only), then the other columns take the panel's row swaps and the
 // rank-KB update x <- x(non-pivot rows) + Panel * x(pivot rows); finally the
-// columns are unscrambled in reverse order of the swaps.  One thread per row.
-// status[e] = 1 if a zero pivot was met.
-template <typename T, int KB>
+// columns are unscrambled in reverse order of the swaps.  One thread per row
+// in the panel phase; RPL >= ceil(nb / 64) rows per lane and CB columns per
+// wave in the trailing update.  status[e] = 1 if a zero pivot was met.
+template <typename T, int KB, int RPL, int CB>
 __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restrict__ status) {
   extern __shared__ unsigned char smraw[];
   T* Pan = reinterpret_cast<T*>(smraw);                       // [nb][KB+1]
@@ -576,44 +577,57 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
         int tmp = perm[k]; perm[k] = perm[p]; perm[p] = tmp;
       }
     __syncthreads();
-    // Trailing update, one column per wave at a time (columns are
+    // Trailing update, CB columns per wave at a time (columns are
     // independent, so no workgroup barrier): with the panel's composed row
     // permutation perm, x(r) <- [r not a pivot row] x(perm[r]) +
-    // sum_t Panel[r][t] x(perm[k0+t]).  Each wave reads the whole column
-    // (pivot entries broadcast by shuffles) before it writes any of it.
+    // sum_t Panel[r][t] x(perm[k0+t]).  Each wave reads its columns whole
+    // (pivot entries broadcast by shuffles) before it writes any of them;
+    // every panel value read from LDS serves CB columns.
     {
-      constexpr int RPL = 16;                 // rows per lane, nb <= 1024
-      const int nrow = (nb + 63) >> 6;
-      int prm[RPL];
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int row = lane + 64 * i;
-        prm[i] = (i < nrow && row < nb) ? perm[row] : 0;
-      }
+      const int nrow = (nb + 63) >> 6;        // <= RPL
       const int ppv = lane < kb ? perm[k0 + lane] : 0;
-      for (int j = wid; j < nb; j += nw) {
-        if (j >= k0 && j < k0 + kb) continue;
-        T* col = Ae + (long)j * nb;
-        const T pvl = lane < kb ? col[ppv] : (T)0;
-        T acc[RPL];
+      const int ncol = nb - kb;               // the columns outside the panel
+      for (int j0 = wid * CB; j0 < ncol; j0 += nw * CB) {
+        T* col[CB];
+        bool ok[CB];
+        T pvl[CB];
+        T acc[CB][RPL];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const int row = lane + 64 * i;
-          const bool piv_row = row >= k0 && row < k0 + kb;
-          acc[i] = (i < nrow && row < nb && !piv_row) ? col[prm[i]] : (T)0;
-        }
-        for (int t = 0; t < kb; ++t) {
-          const T pt = __shfl(pvl, t, 64);
+        for (int c = 0; c < CB; ++c) {
+          const int jj = j0 + c;
+          ok[c] = jj < ncol;
+          const int j = jj < k0 ? jj : jj + kb;
+          col[c] = Ae + (long)(ok[c] ? j : 0) * nb;
+          pvl[c] = (ok[c] && lane < kb) ? col[c][ppv] : (T)0;
 #pragma unroll
           for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            if (i < nrow && row < nb) acc[i] += Pan[row * (KB + 1) + t] * pt;
+            const bool piv_row = row >= k0 && row < k0 + kb;
+            acc[c][i] = (ok[c] && i < nrow && row < nb && !piv_row) ? col[c][perm[row]] : (T)0;
+          }
+        }
+        for (int t = 0; t < kb; ++t) {
+          T pt[CB];
+#pragma unroll
+          for (int c = 0; c < CB; ++c) pt[c] = __shfl(pvl[c], t, 64);
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (i < nrow && row < nb) {
+              const T pn = Pan[row * (KB + 1) + t];
+#pragma unroll
+              for (int c = 0; c < CB; ++c) acc[c][i] += pn * pt[c];
+            }
           }
         }
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const int row = lane + 64 * i;
-          if (i < nrow && row < nb) col[row] = acc[i];
+        for (int c = 0; c < CB; ++c) {
+          if (!ok[c]) continue;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (i < nrow && row < nb) col[c][row] = acc[c][i];
+          }
         }
       }
     }
