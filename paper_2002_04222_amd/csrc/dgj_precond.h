@@ -661,31 +661,35 @@ __device__ __forceinline__ double ld_acc<double>(const double* p) { return *p; }
 template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { return (double)(*p); }
 
 // 16-byte load of 16/sizeof(T) consecutive entries (p 16-byte aligned),
-// widened to the accumulation type
+// widened to the accumulation type.  The block inverses are streamed once
+// per sweep with no reuse, so the loads carry the nontemporal hint (FP64
+// sweep on 16^3 P = 3: 0.58 -> 0.51 ms).
+typedef double dgj_d2 __attribute__((ext_vector_type(2)));
+typedef float dgj_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned dgj_u4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ __forceinline__ void ld16(const T* p, typename AccT<T>::type* v);
 template <>
 __device__ __forceinline__ void ld16<double>(const double* p, double* v) {
-  const double2 x = *reinterpret_cast<const double2*>(p);
-  v[0] = x.x;
-  v[1] = x.y;
+  const dgj_d2 x = __builtin_nontemporal_load(reinterpret_cast<const dgj_d2*>(p));
+  v[0] = x[0];
+  v[1] = x[1];
 }
 template <>
 __device__ __forceinline__ void ld16<float>(const float* p, float* v) {
-  const float4 x = *reinterpret_cast<const float4*>(p);
-  v[0] = x.x;
-  v[1] = x.y;
-  v[2] = x.z;
-  v[3] = x.w;
+  const dgj_f4 x = __builtin_nontemporal_load(reinterpret_cast<const dgj_f4*>(p));
+  v[0] = x[0];
+  v[1] = x[1];
+  v[2] = x[2];
+  v[3] = x[3];
 }
 template <>
 __device__ __forceinline__ void ld16<__hip_bfloat16>(const __hip_bfloat16* p, float* v) {
-  const uint4 x = *reinterpret_cast<const uint4*>(p);
-  const unsigned w[4] = {x.x, x.y, x.z, x.w};
+  const dgj_u4 x = __builtin_nontemporal_load(reinterpret_cast<const dgj_u4*>(p));
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    v[2 * i] = __uint_as_float(w[i] << 16);              // bfloat16 -> float: the high half of the bits
-    v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    v[2 * i] = __uint_as_float(x[i] << 16);              // bfloat16 -> float: the high half of the bits
+    v[2 * i + 1] = __uint_as_float(x[i] & 0xffff0000u);
   }
 }
 
