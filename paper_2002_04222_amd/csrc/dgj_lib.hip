@@ -245,24 +245,25 @@ __global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y
     y[i] = (float)x[i];
 }
 template <typename T>
-__global__ void k_dinv_export(const T* __restrict__ Dinv, int nb, long n_elem, double* __restrict__ out) {
-  // out row-major [e][row][col] from column-major [e][col][row]
+__global__ void k_dinv_export(const T* __restrict__ Dinv, int nb, int ld, long n_elem, double* __restrict__ out) {
+  // out row-major [e][row][col] from column-major [e][col][row], columns ld apart
   long total = n_elem * (long)nb * nb;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
     long e = i / ((long)nb * nb);
     long rc = i % ((long)nb * nb);
     int row = rc / nb, col = rc % nb;
-    out[i] = (double)to_f<T>(Dinv[(e * nb + col) * (long)nb + row]);
+    out[i] = (double)to_f<T>(Dinv[(e * nb + col) * (long)ld + row]);
   }
 }
 template <>
-__global__ void k_dinv_export<double>(const double* __restrict__ Dinv, int nb, long n_elem, double* __restrict__ out) {
+__global__ void k_dinv_export<double>(const double* __restrict__ Dinv, int nb, int ld, long n_elem,
+                                      double* __restrict__ out) {
   long total = n_elem * (long)nb * nb;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
     long e = i / ((long)nb * nb);
     long rc = i % ((long)nb * nb);
     int row = rc / nb, col = rc % nb;
-    out[i] = Dinv[(e * nb + col) * (long)nb + row];
+    out[i] = Dinv[(e * nb + col) * (long)ld + row];
   }
 }
 
@@ -797,7 +798,7 @@ void precond_apply(dgj_ctx* c, const double* q, double* out) {
 
 template <int D, int N, int Q>
 void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* JmW, void* Dm, long e0, long ne,
-                 const Phys& ph) {
+                 const Phys& ph, int ld) {
   using S = Shape<D, N, Q>;
   constexpr int NTV = 64;
   hipLaunchKernelGGL((k_pc_volume<D, N, Q, NTV>), dim3(ne), dim3(NTV), 0, c->stream, up, c->d_geo, c->d_tab, ph, ne,
@@ -815,15 +816,15 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
   using AS = AssembleSF<D, N, Q>;
   const long nblk = ne * S::NV * S::NV;
   hipLaunchKernelGGL((k_pc_assemble_sf<D, N, Q>), dim3(nblk), dim3(AS::NT), 0, c->stream, Wt, JmW, c->d_geo,
-                     c->d_tab, dt_a, ne, (double*)Dm, e0, c->curved ? c->d_M : nullptr);
+                     c->d_tab, dt_a, ne, (double*)Dm, e0, c->curved ? c->d_M : nullptr, ld);
 }
 
 template <typename T, int KB>
-void invert(dgj_ctx* c, T* A, long e0, long ne, int nb, int threads) {
+void invert(dgj_ctx* c, T* A, long e0, long ne, int nb, int ld, int threads) {
   size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int);
   auto go = [&](auto kern) {
     HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * nb, nb, ne,
+    hipLaunchKernelGGL(kern, dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * ld, nb, ld, ne,
                        c->d_status + e0);
   };
   // rows per lane of the trailing update cover nb; columns per wave as the
@@ -842,7 +843,7 @@ void invert(dgj_ctx* c, T* A, long e0, long ne, int nb, int threads) {
 // columns up to 512 (320 x 320: 63.6 -> 31.1 ms for 4,096 blocks), 1024
 // threads and the widest panel that fits LDS above (each panel streams the
 // trailing columns once; 625 x 625: 30 columns).
-void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb) {
+void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb, int ld) {
   int dev = 0, lim = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -850,11 +851,11 @@ void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb) {
   auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 32 * 8 + 32 * 4; };
   const int threads = nb <= 256 ? ((nb + 63) / 64) * 64 : (nb <= 512 ? 512 : 1024);
   const int want = nb <= 256 ? 16 : (nb <= 512 ? 24 : 32);
-  if (want >= 32 && lds(32) <= L) invert<double, 32>(c, A, e0, ne, nb, threads);
-  else if (want >= 30 && lds(30) <= L) invert<double, 30>(c, A, e0, ne, nb, threads);
-  else if (want >= 24 && lds(24) <= L) invert<double, 24>(c, A, e0, ne, nb, threads);
-  else if (lds(16) <= L) invert<double, 16>(c, A, e0, ne, nb, threads);
-  else if (lds(8) <= L) invert<double, 8>(c, A, e0, ne, nb, threads);
+  if (want >= 32 && lds(32) <= L) invert<double, 32>(c, A, e0, ne, nb, ld, threads);
+  else if (want >= 30 && lds(30) <= L) invert<double, 30>(c, A, e0, ne, nb, ld, threads);
+  else if (want >= 24 && lds(24) <= L) invert<double, 24>(c, A, e0, ne, nb, ld, threads);
+  else if (lds(16) <= L) invert<double, 16>(c, A, e0, ne, nb, ld, threads);
+  else if (lds(8) <= L) invert<double, 8>(c, A, e0, ne, nb, ld, threads);
   else fail(DGJ_EUNSUPPORTED, "block size %d too large for the in-LDS inversion", nb);
 }
 
@@ -866,9 +867,10 @@ void free_pc(dgj_ctx* c) {
   c->pc_ready = false;
 }
 
-// Build the BRJ blocks of elements [e0, e0+ne) (one instance) at state up.
+// Build the BRJ blocks of elements [e0, e0+ne) (one instance) at state up
+// into Dm (FP64, columns ld apart).
 void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, long ne, const Phys& ph, double* Wt,
-                         double* JmW, void* Dm) {
+                         double* JmW, void* Dm, int ld) {
   if (c->has_dirichlet && !c->d_bc_field) fail(DGJ_EINVAL, "Dirichlet boundary without ghost states (dgj_set_bc_field)");
   // chi_v = ||u^(v)||_2 sqrt(eps_hat) over the instance  (Eq. 31)
   hipLaunchKernelGGL(k_varsq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, up + e0 * c->NB, ne, c->NV,
@@ -888,11 +890,16 @@ void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, lon
   // a variable that is zero everywhere takes the norm of the whole state
   for (int v = 0; v < c->NV; ++v) chi[v] = std::sqrt(chi[v] > 0.0 ? chi[v] : total) * std::sqrt(EPS_HAT);
   HIPCHK(hipMemcpyAsync(c->d_chi, chi, c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
-#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm, e0, ne, ph); } else
+#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm, e0, ne, ph, ld); } else
   DGJ_FOR_SHAPES(X)
 #undef X
   fail(DGJ_EUNSUPPORTED, "unsupported shape");
-  invert_blocks(c, (double*)Dm, e0, ne, c->NB);
+  invert_blocks(c, (double*)Dm, e0, ne, c->NB, ld);
+}
+
+int stored_ld_of(const dgj_ctx* c, int prec) {
+  return prec == DGJ_PC_F64 ? stored_ld<double>(c->NB) : (prec == DGJ_PC_F32 ? stored_ld<float>(c->NB)
+                                                                               : stored_ld<__hip_bfloat16>(c->NB));
 }
 
 void precond_alloc(dgj_ctx* c) {
@@ -900,7 +907,7 @@ void precond_alloc(dgj_ctx* c) {
   if (!c->d_Dinv || c->pc_prec != prec) {
     free_pc(c);
     size_t es = prec == DGJ_PC_F64 ? 8 : (prec == DGJ_PC_F32 ? 4 : 2);
-    HIPCHK(hipMalloc(&c->d_Dinv, (size_t)c->n_elem * c->NB * c->NB * es));
+    HIPCHK(hipMalloc(&c->d_Dinv, (size_t)c->n_elem * c->NB * stored_ld_of(c, prec) * es));
     size_t js = prec == DGJ_PC_F64 ? 8 : 4;
     HIPCHK(hipMalloc(&c->d_Jp, (size_t)c->n_elem * 2 * c->dim * (size_t)std::pow(c->nq, c->dim - 1) * c->NV * c->NV * js));
     c->pc_prec = prec;
@@ -922,6 +929,9 @@ void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& i
   const size_t blk = (size_t)c->n_elem * c->NB * c->NB;
   // blocks are assembled and inverted in FP64 (LU-based inversion in double,
   // as the paper's dgetrf/dgetri), then stored in the chosen precision
+  // FP64 blocks are built in place with the stored column stride; the
+  // reduced-precision forms from an FP64 copy with columns nb apart
+  const int ld = prec == DGJ_PC_F64 ? stored_ld_of(c, prec) : c->NB;
   if (prec == DGJ_PC_F64) Dm = c->d_Dinv;
   else HIPCHK(hipMalloc(&Dm, blk * sizeof(double)));
   try {
@@ -929,7 +939,7 @@ void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& i
       const int i = insts[k];
       const long e0 = c->inst_e0[i], ne = c->inst_e0[i + 1] - e0;
       const Phys ph = c->n_inst > 0 ? c->h_phs[i] : c->ph;
-      precond_build_range(c, up, dta[k], e0, ne, ph, Wt, JmW, Dm);
+      precond_build_range(c, up, dta[k], e0, ne, ph, Wt, JmW, Dm, ld);
     }
   } catch (...) {
     // the build scratch is released before the error propagates
@@ -1465,7 +1475,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
 #undef X
       if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
       HIPCHK(hipMemcpyAsync(c->d_Minv, c->d_M, mm * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      invert_blocks(c, c->d_Minv, 0, E, c->NM);
+      invert_blocks(c, c->d_Minv, 0, E, c->NM, c->NM);
       std::vector<int> st(E);
       HIPCHK(hipMemcpyAsync(st.data(), c->d_status, E * sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1671,13 +1681,13 @@ int dgj_precond_diag_inverse(dgj_ctx* c, double* out) {
     long total = c->n_elem * (long)c->NB * c->NB;
     if (c->pc_prec == DGJ_PC_F64)
       hipLaunchKernelGGL(k_dinv_export<double>, dim3(grid_for(total)), dim3(256), 0, c->stream,
-                         (const double*)c->d_Dinv, c->NB, c->n_elem, out);
+                         (const double*)c->d_Dinv, c->NB, stored_ld_of(c, c->pc_prec), c->n_elem, out);
     else if (c->pc_prec == DGJ_PC_F32)
       hipLaunchKernelGGL(k_dinv_export<float>, dim3(grid_for(total)), dim3(256), 0, c->stream,
-                         (const float*)c->d_Dinv, c->NB, c->n_elem, out);
+                         (const float*)c->d_Dinv, c->NB, stored_ld_of(c, c->pc_prec), c->n_elem, out);
     else
       hipLaunchKernelGGL(k_dinv_export<__hip_bfloat16>, dim3(grid_for(total)), dim3(256), 0, c->stream,
-                         (const __hip_bfloat16*)c->d_Dinv, c->NB, c->n_elem, out);
+                         (const __hip_bfloat16*)c->d_Dinv, c->NB, stored_ld_of(c, c->pc_prec), c->n_elem, out);
     HIPCHK(hipGetLastError());
     return DGJ_OK;
   });

@@ -316,7 +316,7 @@ template <int D, int N, int Q>
 __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
     const double* __restrict__ Wt, const double* __restrict__ JmW, const double* __restrict__ geo,
     const double* __restrict__ tables, double dt_a, long n_elem, double* __restrict__ Dm, long e0,
-    const double* __restrict__ mass) {
+    const double* __restrict__ mass, int ld) {
   using S = Shape<D, N, Q>;
   using A = AssembleSF<D, N, Q>;
   constexpr int NV = S::NV, NM = S::NM, NQ = S::NQ, NQF = S::NQF, NF = S::NF, NB = S::NB;
@@ -341,7 +341,8 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
   const double* B = tb.B;     // B[q * N + m]
   const double* Dq = tb.Dq;
   // output sub-block: entry (m, n) of A_kl at Dm[e][l NM + n][k NM + m]
-  double* out = Dm + (e * NB + l * NM) * (long)NB + k * NM;
+  // (columns ld apart, ld >= nb)
+  double* out = Dm + e * (long)NB * ld + (long)(l * NM) * ld + k * NM;
   __syncthreads();
   for (int j = 0; j < D; ++j) {
     const double* F1 = (j == 0) ? Dq : B;
@@ -393,7 +394,7 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
 #pragma unroll
         for (int q3 = 0; q3 < Q; ++q3)
           t += F3[q3 * N + m3] * (B[q3 * N + n3] * s2b[base + q3] + Dq[q3 * N + n3] * s2d[base + q3]);
-        double* o = out + (long)n * NB + m;
+        double* o = out + (long)n * ld + m;
         *o = (j == 0) ? t : *o + t;
       }
       __syncthreads();
@@ -422,7 +423,7 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
 #pragma unroll
         for (int q2 = 0; q2 < Q; ++q2)
           t += F2[q2 * N + m2] * (B[q2 * N + n2] * s1a[base + q2] + Dq[q2 * N + n2] * s1b[base + q2]);
-        double* o = out + (long)n * NB + m;
+        double* o = out + (long)n * ld + m;
         *o = (j == 0) ? t : *o + t;
       }
       __syncthreads();
@@ -478,14 +479,15 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
       const int fi = (D == 3) ? ((mi[t[0]] * N + ni[t[0]]) * N + mi[t[1]]) * N + ni[t[1]] : mi[t[0]] * N + ni[t[0]];
       fsum += nf * ff[f * FB + fi];
     }
-    double* o = out + (long)n * NB + m;
+    double* o = out + (long)n * ld + m;
     const double dg = mass ? ((k == l) ? mass[(e * NM + m) * (long)NM + n] : 0.0) : ((k == l && m == n) ? 1.0 : 0.0);
     *o = dg - sc * (*o - fsum);
   }
 }
 
 // ---------------------------------------------------------------- blocked Gauss-Jordan inverse
-// In-place inversion of each nb x nb block (column-major) by Gauss-Jordan
+// In-place inversion of each nb x nb block (column-major, columns ld apart,
+// blocks nb ld apart) by Gauss-Jordan
 // elimination with partial pivoting, processed in column panels of width KB
 // held in LDS: the panel is eliminated on all rows (row swaps applied to the
 // panel only), then the other columns take the panel's row swaps and the
@@ -494,7 +496,7 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
 // in the panel phase; RPL >= ceil(nb / 64) rows per lane and CB columns per
 // wave in the trailing update.  status[e] = 1 if a zero pivot was met.
 template <typename T, int KB, int RPL, int CB>
-__global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restrict__ status) {
+__global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int* __restrict__ status) {
   extern __shared__ unsigned char smraw[];
   T* Pan = reinterpret_cast<T*>(smraw);                       // [nb][KB+1]
   int* piv = reinterpret_cast<int*>(Pan + (size_t)nb * (KB + 1));
@@ -503,7 +505,7 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
   int* redi = reinterpret_cast<int*>(redv + 32);               // [32]
   const long e = blockIdx.x;
   if (e >= n_elem) return;
-  T* Ae = A + e * (long)nb * nb;
+  T* Ae = A + e * (long)nb * ld;
   const int r = threadIdx.x;
   const int nw = (blockDim.x + 63) / 64;
   const int lane = r & 63, wid = r >> 6;
@@ -511,7 +513,7 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
   for (int k0 = 0; k0 < nb; k0 += KB) {
     const int kb = (nb - k0) < KB ? (nb - k0) : KB;
     if (r < nb)
-      for (int c = 0; c < kb; ++c) Pan[r * (KB + 1) + c] = Ae[(long)(k0 + c) * nb + r];
+      for (int c = 0; c < kb; ++c) Pan[r * (KB + 1) + c] = Ae[(long)(k0 + c) * ld + r];
     __syncthreads();
     for (int t = 0; t < kb; ++t) {
       const int k = k0 + t;
@@ -567,7 +569,7 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
     }
     // write the panel back; composed row permutation of this panel
     if (r < nb) {
-      for (int c = 0; c < kb; ++c) Ae[(long)(k0 + c) * nb + r] = Pan[r * (KB + 1) + c];
+      for (int c = 0; c < kb; ++c) Ae[(long)(k0 + c) * ld + r] = Pan[r * (KB + 1) + c];
       perm[r] = r;
     }
     __syncthreads();
@@ -597,7 +599,7 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
           const int jj = j0 + c;
           ok[c] = jj < ncol;
           const int j = jj < k0 ? jj : jj + kb;
-          col[c] = Ae + (long)(ok[c] ? j : 0) * nb;
+          col[c] = Ae + (long)(ok[c] ? j : 0) * ld;
           pvl[c] = (ok[c] && lane < kb) ? col[c][ppv] : (T)0;
 #pragma unroll
           for (int i = 0; i < RPL; ++i) {
@@ -637,9 +639,9 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, long n_elem, int* __restr
   for (int k = nb - 1; k >= 0; --k) {
     const int p = piv[k];
     if (p != k && r < nb) {
-      T a0 = Ae[(long)k * nb + r], a1 = Ae[(long)p * nb + r];
-      Ae[(long)k * nb + r] = a1;
-      Ae[(long)p * nb + r] = a0;
+      T a0 = Ae[(long)k * ld + r], a1 = Ae[(long)p * ld + r];
+      Ae[(long)k * ld + r] = a1;
+      Ae[(long)p * ld + r] = a0;
     }
     __syncthreads();
   }
@@ -659,6 +661,13 @@ template <>
 __device__ __forceinline__ double ld_acc<double>(const double* p) { return *p; }
 
 template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { return (double)(*p); }
+
+// Column stride of the stored block inverses: FP64 blocks of odd size get one
+// padding row, so that every column starts on a 16-byte boundary and the
+// sweep reads them with 16-byte loads (3D P = 2 and 4: nb = 135, 625).
+template <typename T> __host__ __device__ constexpr int stored_ld(int nb) {
+  return sizeof(T) == 8 ? nb + (nb & 1) : nb;
+}
 
 // 16-byte load of 16/sizeof(T) consecutive entries (p 16-byte aligned),
 // widened to the accumulation type.  The block inverses are streamed once
@@ -807,15 +816,17 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
     __syncthreads();
   }
   using A = typename AccT<T>::type;
-  const T* De = Dinv + e * (long)NB * NB;
+  constexpr int LD = stored_ld<T>(NB);                     // column stride of the stored blocks
+  const T* De = Dinv + e * (long)NB * LD;
   constexpr int VW = 16 / (int)sizeof(T);                 // rows per 16-byte load
-  if constexpr (NB % VW == 0 && (NB * (int)sizeof(T)) % 16 == 0) {
+  if constexpr (LD % VW == 0 && (LD * (int)sizeof(T)) % 16 == 0) {
     // every thread busy: VW rows by one 16-byte load per column, the
     // columns split into SEG segments, partial sums added in LDS in a fixed
-    // order
-    constexpr int NR = NB / VW;
+    // order; the padding rows of an odd FP64 block (row nb) are summed and
+    // dropped
+    constexpr int NR = LD / VW;
     constexpr int SEG = NT / NR >= 1 ? NT / NR : 1;
-    __shared__ A part[SEG * NB];
+    __shared__ A part[SEG * LD];
     for (int t = tid; t < SEG * NR; t += NT) {
       const int rg = t % NR, sg = t / NR;
       const int c0 = sg * NB / SEG, c1 = (sg + 1) * NB / SEG;
@@ -825,19 +836,19 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
 #pragma unroll 4
       for (int c = c0; c < c1; ++c) {
         A v[VW];
-        ld16<T>(De + (long)c * NB + rg * VW, v);
+        ld16<T>(De + (long)c * LD + rg * VW, v);
         const A x = (A)sr[c];
 #pragma unroll
         for (int i = 0; i < VW; ++i) acc[i] += v[i] * x;
       }
 #pragma unroll
-      for (int i = 0; i < VW; ++i) part[sg * NB + rg * VW + i] = acc[i];
+      for (int i = 0; i < VW; ++i) part[sg * LD + rg * VW + i] = acc[i];
     }
     __syncthreads();
     for (int row = tid; row < NB; row += NT) {
       A acc = (A)0;
 #pragma unroll
-      for (int sg = 0; sg < SEG; ++sg) acc += part[sg * NB + row];
+      for (int sg = 0; sg < SEG; ++sg) acc += part[sg * LD + row];
       double res = omega * (double)acc;
       if (!first && omega != 1.0) res += (1.0 - omega) * qold[e * NB + row];
       out[e * NB + row] = res;
@@ -845,7 +856,7 @@ __global__ __launch_bounds__(NT) void k_brj_sweep(const double* __restrict__ q, 
   } else {
     for (int row = tid; row < NB; row += NT) {
       A acc = (A)0;
-      for (int c = 0; c < NB; ++c) acc += ld_acc<T>(De + (long)c * NB + row) * (A)sr[c];
+      for (int c = 0; c < NB; ++c) acc += ld_acc<T>(De + (long)c * LD + row) * (A)sr[c];
       double res = omega * (double)acc;
       if (!first && omega != 1.0) res += (1.0 - omega) * qold[e * NB + row];
       out[e * NB + row] = res;
