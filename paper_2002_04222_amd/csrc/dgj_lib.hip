@@ -821,34 +821,26 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
 
 template <typename T, int KB>
 void invert(dgj_ctx* c, T* A, long e0, long ne, int nb, int ld, int threads) {
-  size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int);
-  auto go = [&](auto kern) {
-    HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * ld, nb, ld, ne,
-                       c->d_status + e0);
-  };
-  // rows per lane of the trailing update cover nb; columns per wave as the
-  // accumulators fit 128 registers
-  if (nb <= 64) go(k_gj_invert<T, KB, 1, 4>);
-  else if (nb <= 128) go(k_gj_invert<T, KB, 2, 4>);
-  else if (nb <= 256) go(k_gj_invert<T, KB, 4, 4>);
-  else if (nb <= 512) go(k_gj_invert<T, KB, 8, 4>);
-  else if (nb <= 1024) go(k_gj_invert<T, KB, 16, 2>);
-  else fail(DGJ_EUNSUPPORTED, "block size %d above 1024", nb);
+  size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int) +
+               (2 * KB + 1) * sizeof(int);
+  if (nb > 1024) fail(DGJ_EUNSUPPORTED, "block size %d above 1024", nb);
+  HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * ld, nb, ld, ne,
+                     c->d_status + e0);
 }
 
 // In-place inversion of ne blocks of size nb.  Workgroup size and panel
 // width as measured fastest on MI355X: one wave per 64 rows and 16-column
 // panels up to nb = 256 (several blocks share a CU), 512 threads and 24
-// columns up to 512 (320 x 320: 63.6 -> 31.1 ms for 4,096 blocks), 1024
-// threads and the widest panel that fits LDS above (each panel streams the
-// trailing columns once; 625 x 625: 30 columns).
+// columns up to 512 (320 x 320: 28.7 ms for 4,096 blocks), 1024 threads and
+// the widest panel that fits LDS above (each panel streams the trailing
+// columns once; 625 x 625: 30 columns).
 void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb, int ld) {
   int dev = 0, lim = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   const size_t L = (size_t)lim;
-  auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 32 * 8 + 32 * 4; };
+  auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 32 * 8 + 32 * 4 + (2 * kb + 1) * 4; };
   const int threads = nb <= 256 ? ((nb + 63) / 64) * 64 : (nb <= 512 ? 512 : 1024);
   const int want = nb <= 256 ? 16 : (nb <= 512 ? 24 : 32);
   if (want >= 32 && lds(32) <= L) invert<double, 32>(c, A, e0, ne, nb, ld, threads);

@@ -487,22 +487,24 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
 
 // ---------------------------------------------------------------- blocked Gauss-Jordan inverse
 // In-place inversion of each nb x nb block (column-major, columns ld apart,
-// blocks nb ld apart) by Gauss-Jordan
-// elimination with partial pivoting, processed in column panels of width KB
-// held in LDS: the panel is eliminated on all rows (row swaps applied to the
-// panel only), then the other columns take the panel's row swaps and the
-// rank-KB update x <- x(non-pivot rows) + Panel * x(pivot rows); finally the
-// columns are unscrambled in reverse order of the swaps.  One thread per row
-// in the panel phase; RPL >= ceil(nb / 64) rows per lane and CB columns per
-// wave in the trailing update.  status[e] = 1 if a zero pivot was met.
-template <typename T, int KB, int RPL, int CB>
+// blocks nb ld apart) by Gauss-Jordan elimination with partial pivoting,
+// processed in column panels of width KB held in LDS: the panel is eliminated
+// on all rows (row swaps applied to the panel only, one thread per row), then
+// the other columns take the panel's row swaps and the rank-KB update
+// x <- x(non-pivot rows) + Panel * x(pivot rows) on FP64 MFMA; finally the
+// columns are unscrambled in reverse order of the swaps.  status[e] = 1 if a
+// zero pivot was met.
+template <typename T, int KB>
 __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int* __restrict__ status) {
+  static_assert(sizeof(T) == 8, "the trailing update runs on FP64 MFMA");
   extern __shared__ unsigned char smraw[];
   T* Pan = reinterpret_cast<T*>(smraw);                       // [nb][KB+1]
   int* piv = reinterpret_cast<int*>(Pan + (size_t)nb * (KB + 1));
   int* perm = piv + nb;
   T* redv = reinterpret_cast<T*>(perm + nb);                   // [32]
   int* redi = reinterpret_cast<int*>(redv + 32);               // [32]
+  int* srow = redi + 32;                                       // [2 KB] rows the panel's swaps touch
+  int* nsrow = srow + 2 * KB;                                  // [1] their number
   const long e = blockIdx.x;
   if (e >= n_elem) return;
   T* Ae = A + e * (long)nb * ld;
@@ -573,64 +575,95 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int*
       perm[r] = r;
     }
     __syncthreads();
-    if (r == 0)
+    if (r == 0) {
       for (int t = 0; t < kb; ++t) {
         int k = k0 + t, p = piv[k];
         int tmp = perm[k]; perm[k] = perm[p]; perm[p] = tmp;
       }
+      // every row a swap moved: the pivot range and the rows below it that
+      // were exchanged with it (rows below only ever receive pivot-range rows)
+      int ns = 0;
+      for (int t = 0; t < kb; ++t) srow[ns++] = k0 + t;
+      for (int t = 0; t < kb; ++t) {
+        const int p = piv[k0 + t];
+        if (p >= k0 + kb) {
+          bool seen = false;
+          for (int i = kb; i < ns; ++i) seen = seen || srow[i] == p;
+          if (!seen) srow[ns++] = p;
+        }
+      }
+      *nsrow = ns;
+    }
     __syncthreads();
-    // Trailing update, CB columns per wave at a time (columns are
-    // independent, so no workgroup barrier): with the panel's composed row
-    // permutation perm, x(r) <- [r not a pivot row] x(perm[r]) +
-    // sum_t Panel[r][t] x(perm[k0+t]).  Each wave reads its columns whole
-    // (pivot entries broadcast by shuffles) before it writes any of them;
-    // every panel value read from LDS serves CB columns.
-    {
-      const int nrow = (nb + 63) >> 6;        // <= RPL
-      const int ppv = lane < kb ? perm[k0 + lane] : 0;
-      const int ncol = nb - kb;               // the columns outside the panel
-      for (int j0 = wid * CB; j0 < ncol; j0 += nw * CB) {
-        T* col[CB];
-        bool ok[CB];
-        T pvl[CB];
-        T acc[CB][RPL];
+    // FP64 MFMA trailing update over tiles of 16 columns, one tile per wave
+    // at a time: (a) the panel's row swaps are applied to the tile's
+    // columns in memory (each touched row's source read before any write),
+    // so that (c) reads x'(r) = x(perm[r]); (b) the pivot rows x'(k0 + t)
+    // of the 16 columns are held as the A operand; (c) per 16-row tile,
+    // x(r) <- [r not a pivot row] x'(r) + sum_t Panel[r][t] x'(k0 + t) by
+    // v_mfma_f64_16x16x4 (lane l: A[l%16][l/16], B[l/16][l%16], D[l/16 + 4v][l%16]).
+    typedef double dgj_d4 __attribute__((ext_vector_type(4)));
+    constexpr int NK = (KB + 3) / 4;
+    const int ns = *nsrow;
+    const int ncol = nb - kb;
+    const int ntile = (ncol + 15) >> 4;
+    const int nrt = (nb + 15) >> 4;
+    const int li = lane & 15, lq = lane >> 4;
+    for (int jt = wid; jt < ntile; jt += nw) {
+      double tmp[16];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int jj = j0 + c;
-          ok[c] = jj < ncol;
-          const int j = jj < k0 ? jj : jj + kb;
-          col[c] = Ae + (long)(ok[c] ? j : 0) * ld;
-          pvl[c] = (ok[c] && lane < kb) ? col[c][ppv] : (T)0;
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) {
-            const int row = lane + 64 * i;
-            const bool piv_row = row >= k0 && row < k0 + kb;
-            acc[c][i] = (ok[c] && i < nrow && row < nb && !piv_row) ? col[c][perm[row]] : (T)0;
-          }
+      for (int i = 0; i < 16; ++i) {
+        const int idx = lane + 64 * i;
+        tmp[i] = 0.0;
+        if (idx < 16 * ns) {
+          const int c = idx / ns, sidx = idx - c * ns;
+          const int jj = jt * 16 + c;
+          if (jj < ncol) tmp[i] = Ae[(long)(jj < k0 ? jj : jj + kb) * ld + perm[srow[sidx]]];
         }
-        for (int t = 0; t < kb; ++t) {
-          T pt[CB];
+      }
 #pragma unroll
-          for (int c = 0; c < CB; ++c) pt[c] = __shfl(pvl[c], t, 64);
+      for (int i = 0; i < 16; ++i) {
+        const int idx = lane + 64 * i;
+        if (idx < 16 * ns) {
+          const int c = idx / ns, sidx = idx - c * ns;
+          const int jj = jt * 16 + c;
+          if (jj < ncol) Ae[(long)(jj < k0 ? jj : jj + kb) * ld + srow[sidx]] = tmp[i];
+        }
+      }
+      __threadfence_block();
+      const int jjA = jt * 16 + li;
+      const bool okA = jjA < ncol;
+      const T* colA = Ae + (long)(okA ? (jjA < k0 ? jjA : jjA + kb) : 0) * ld;
+      double a[NK];
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) {
-            const int row = lane + 64 * i;
-            if (i < nrow && row < nb) {
-              const T pn = Pan[row * (KB + 1) + t];
+      for (int kk = 0; kk < NK; ++kk) {
+        const int t = 4 * kk + lq;
+        a[kk] = (okA && t < kb) ? colA[k0 + t] : 0.0;
+      }
+      T* colD[4];
+      bool okD[4];
 #pragma unroll
-              for (int c = 0; c < CB; ++c) acc[c][i] += pn * pt[c];
-            }
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int jj = jt * 16 + lq + 4 * v;
+        okD[v] = jj < ncol;
+        colD[v] = Ae + (long)(okD[v] ? (jj < k0 ? jj : jj + kb) : 0) * ld;
+      }
+      for (int rt = 0; rt < nrt; ++rt) {
+        const int n = rt * 16 + li;
+        const bool rowok = n < nb;
+        const bool piv_row = n >= k0 && n < k0 + kb;
+        dgj_d4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = (okD[v] && rowok && !piv_row) ? colD[v][n] : 0.0;
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) {
+          const int t = 4 * kk + lq;
+          const double bv = (rowok && t < kb) ? Pan[n * (KB + 1) + t] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bv, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          if (!ok[c]) continue;
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) {
-            const int row = lane + 64 * i;
-            if (i < nrow && row < nb) col[c][row] = acc[c][i];
-          }
-        }
+        for (int v = 0; v < 4; ++v)
+          if (okD[v] && rowok) colD[v][n] = acc[v];
       }
     }
     __syncthreads();
