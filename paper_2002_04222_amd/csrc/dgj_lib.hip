@@ -236,13 +236,18 @@ __global__ void k_sub_div(double* __restrict__ y, const double* __restrict__ x, 
     y[i] = (x[i] - z[i]) / a;
 }
 
-__global__ void k_f64_to_bf16(const double* __restrict__ x, __hip_bfloat16* __restrict__ y, long n) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    y[i] = __float2bfloat16((float)x[i]);
-}
-__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, long n) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    y[i] = (float)x[i];
+// FP64 blocks with columns nb apart -> stored blocks with columns ld apart
+// (padding rows zero), converted to FP32 or BF16
+__device__ __forceinline__ void cvt_store(float* y, double v) { *y = (float)v; }
+__device__ __forceinline__ void cvt_store(__hip_bfloat16* y, double v) { *y = __float2bfloat16((float)v); }
+template <typename T>
+__global__ void k_blocks_from_f64(const double* __restrict__ x, T* __restrict__ y, int nb, int ld, long n_elem) {
+  const long total = n_elem * (long)nb * ld;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long col = i / ld;                     // e nb + c
+    const int row = (int)(i - col * ld);
+    cvt_store(y + i, row < nb ? x[col * nb + row] : 0.0);
+  }
 }
 template <typename T>
 __global__ void k_dinv_export(const T* __restrict__ Dinv, int nb, int ld, long n_elem, double* __restrict__ out) {
@@ -941,12 +946,14 @@ void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& i
     if (prec != DGJ_PC_F64) (void)hipFree(Dm);
     throw;
   }
+  const long stored = (long)c->n_elem * c->NB * stored_ld_of(c, prec);
   if (prec == DGJ_PC_F32)
-    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const double*)Dm,
-                       (float*)c->d_Dinv, (long)blk);
+    hipLaunchKernelGGL(k_blocks_from_f64<float>, dim3(grid_for(stored)), dim3(256), 0, c->stream, (const double*)Dm,
+                       (float*)c->d_Dinv, c->NB, stored_ld_of(c, prec), (long)c->n_elem);
   else if (prec == DGJ_PC_BF16)
-    hipLaunchKernelGGL(k_f64_to_bf16, dim3(grid_for((long)blk)), dim3(256), 0, c->stream, (const double*)Dm,
-                       (__hip_bfloat16*)c->d_Dinv, (long)blk);
+    hipLaunchKernelGGL(k_blocks_from_f64<__hip_bfloat16>, dim3(grid_for(stored)), dim3(256), 0, c->stream,
+                       (const double*)Dm, (__hip_bfloat16*)c->d_Dinv, c->NB, stored_ld_of(c, prec),
+                       (long)c->n_elem);
   HIPCHK(hipGetLastError());
   std::vector<int> st(c->n_elem);
   HIPCHK(hipMemcpyAsync(st.data(), c->d_status, c->n_elem * sizeof(int), hipMemcpyDeviceToHost, c->stream));

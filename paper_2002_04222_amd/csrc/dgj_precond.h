@@ -695,11 +695,12 @@ __device__ __forceinline__ double ld_acc<double>(const double* p) { return *p; }
 
 template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { return (double)(*p); }
 
-// Column stride of the stored block inverses: FP64 blocks of odd size get one
-// padding row, so that every column starts on a 16-byte boundary and the
-// sweep reads them with 16-byte loads (3D P = 2 and 4: nb = 135, 625).
+// Column stride of the stored block inverses: nb rounded up to a whole
+// number of 16-byte groups, so that every column starts on a 16-byte boundary
+// and the sweep reads them with 16-byte loads (padding rows are zero or
+// unused; e.g. 3D P = 4: nb = 625 -> 626 FP64, 628 FP32, 632 BF16).
 template <typename T> __host__ __device__ constexpr int stored_ld(int nb) {
-  return sizeof(T) == 8 ? nb + (nb & 1) : nb;
+  return (nb + (16 / (int)sizeof(T)) - 1) / (16 / (int)sizeof(T)) * (16 / (int)sizeof(T));
 }
 
 // 16-byte load of 16/sizeof(T) consecutive entries (p 16-byte aligned),

@@ -134,15 +134,22 @@ def test_precond_parity(dim, cells, P):
     assert np.abs(_host(o) - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
+# block sizes 320 (3D P = 3), 135 (3D P = 2: padded to 136 / 136 rows) and
+# 36 (2D P = 2: padded to 40 rows in BF16)
+@pytest.mark.parametrize("dim,cells,P", [(3, (2, 2, 2), 3), (3, (2, 2, 3), 2), (2, (3, 3), 2)])
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("bf16", 3e-2)])
-def test_precond_reduced_precision(prec, tol):
-    _case(f"precond {prec}")
-    cfg, mesh, disc = setup(3, (2, 2, 2), 3, Ma=0.3, Re=40.0, pc_precision=prec)
+def test_precond_reduced_precision(prec, tol, dim, cells, P):
+    _case(f"precond {prec} dim={dim} P={P}")
+    cfg, mesh, disc = setup(dim, cells, P, Ma=0.3, Re=40.0, pc_precision=prec)
     ctx = _ctx(cfg, mesh)
-    u = W.random_state(mesh.n_elem, 3, 3, seed=23)
+    u = W.random_state(mesh.n_elem, dim, P, seed=23)
     ctx.precond_build(_dev(u), 0.1)
     pc = OS.BRJ(disc, u, 0.1)
-    q = W.random_vector(mesh.n_elem, 3, 3, seed=24)
+    nb = disc.nv * disc.ref.nm
+    out = torch.empty((mesh.n_elem, nb, nb), dtype=torch.float64, device="cuda")
+    ctx.precond_diag_inverse(out)
+    assert np.abs(_host(out) - pc.Dinv).max() <= tol * np.abs(pc.Dinv).max()
+    q = W.random_vector(mesh.n_elem, dim, P, seed=24)
     o = ctx.empty()
     ctx.precond_apply(_dev(q), o)
     ref = pc.apply(q)
