@@ -12,14 +12,16 @@ torch = pytest.importorskip("torch")
 import workloads as W
 
 
-@pytest.mark.parametrize("graphs", [False, True])
-def test_batch_matches_solo_runs(graphs):
+@pytest.mark.parametrize("graphs,prec", [(False, "f64"), (True, "f64"), (False, "bf16")])
+def test_batch_matches_solo_runs(graphs, prec):
     """With graphs the captured Krylov steps are replayed many times (every
     iteration of every Newton step of both steps), each checked through the
-    final states against eager single-instance runs."""
-    print(f"[case] batch of 6 mixed-order instances vs solo, graphs={graphs}", flush=True)
+    final states against eager single-instance runs.  BF16 blocks of the
+    P = 2 instances (nb = 36) are stored with 40-row columns."""
+    print(f"[case] batch of 6 mixed-order instances vs solo, graphs={graphs}, blocks {prec}", flush=True)
     from paper_2002_04222_amd import Batch, Context
-    cfgs = W.batch_configs(6, seed=11, nmin=3, nmax=6, pmin=1, pmax=3)
+    cfgs = [dataclasses.replace(c, pc_precision=prec)
+            for c in W.batch_configs(6, seed=11, nmin=3, nmax=6, pmin=1, pmax=3)]
     batch = Batch(cfgs)
     batch.set_graphs(graphs)
     u = batch.empty()
