@@ -162,7 +162,7 @@ void arnoldi_launch(Batch& B, int gi, int k) {
 void drop_graphs(Batch& B) {
   for (auto& v : B.gexec)
     for (auto& x : v)
-      if (x) { hipGraphExecDestroy(x); x = nullptr; }
+      if (x) { (void)hipGraphExecDestroy(x); x = nullptr; }
 }
 
 void set_active(dgj_ctx* c, std::vector<int>& h) {
@@ -582,14 +582,14 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
 
 void dgj_batch_destroy(dgj_batch* b) {
   if (!b) return;
-  if (b->own) hipStreamSynchronize(b->own);
+  if (b->own) (void)hipStreamSynchronize(b->own);
   drop_graphs(*b);
   for (auto* c : b->g) dgj_destroy(c);
   for (double* p : b->h_slots)
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   for (int* p : b->h_act)
-    if (p) hipHostFree(p);
-  if (b->own) hipStreamDestroy(b->own);
+    if (p) (void)hipHostFree(p);
+  if (b->own) (void)hipStreamDestroy(b->own);
   delete b;
 }
 

@@ -857,8 +857,8 @@ void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb, int ld) {
 }
 
 void free_pc(dgj_ctx* c) {
-  if (c->d_Dinv) hipFree(c->d_Dinv);
-  if (c->d_Jp) hipFree(c->d_Jp);
+  if (c->d_Dinv) (void)hipFree(c->d_Dinv);
+  if (c->d_Jp) (void)hipFree(c->d_Jp);
   c->d_Dinv = nullptr;
   c->d_Jp = nullptr;
   c->pc_ready = false;
@@ -958,9 +958,9 @@ void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& i
   std::vector<int> st(c->n_elem);
   HIPCHK(hipMemcpyAsync(st.data(), c->d_status, c->n_elem * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  hipFree(Wt);
-  hipFree(JmW);
-  if (prec != DGJ_PC_F64) hipFree(Dm);
+  (void)hipFree(Wt);
+  (void)hipFree(JmW);
+  if (prec != DGJ_PC_F64) (void)hipFree(Dm);
   for (int i : insts)
     for (long e = c->inst_e0[i]; e < c->inst_e0[i + 1]; ++e)
       if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
@@ -979,7 +979,7 @@ void precond_build(dgj_ctx* c, const double* up, double dt_a) {
 void mlp_free_acts(dgj_ctx::Mlp& M) {
   void* ps[] = {M.Xb, M.H1b, M.H2b, M.dYb, M.dZb, M.H1, M.H2, M.Y, M.dY, M.dH, M.dZ};
   for (void* p : ps)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   M.Xb = M.H1b = M.H2b = M.dYb = M.dZb = nullptr;
   M.H1 = M.H2 = M.Y = M.dY = M.dH = M.dZ = nullptr;
   M.cap = 0;
@@ -989,7 +989,7 @@ void mlp_free(dgj_ctx::Mlp& M) {
   mlp_free_acts(M);
   void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt};
   for (void* p : ps)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   M = dgj_ctx::Mlp();
 }
 
@@ -1494,8 +1494,8 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
 
 void dgj_destroy(dgj_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
   free_pc(c);
   mlp_free(c->mlp);
   double* ptrs[] = {c->d_vg, c->d_fg, c->d_M, c->d_Minv, c->d_Mq, c->d_trace, c->d_X, c->d_Lvol, c->d_geo,
@@ -1503,26 +1503,26 @@ void dgj_destroy(dgj_ctx* c) {
                     c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_pa, c->d_pb,
                     c->d_g2, c->d_uprev};
   for (double* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   for (int m = 0; m < DGJ_MAX_STAGES; ++m)
     for (double* p : {c->d_E[m], c->d_inc[m], c->d_inc2[m]})
-      if (p) hipFree(p);
-  if (c->d_nbr) hipFree(c->d_nbr);
-  if (c->d_bc_kind) hipFree(c->d_bc_kind);
-  if (c->d_bc_state) hipFree(c->d_bc_state);
-  if (c->d_bc_field) hipFree(c->d_bc_field);
-  if (c->d_Vptr) hipFree(c->d_Vptr);
-  if (c->d_partm) hipFree(c->d_partm);
-  if (c->d_h2) hipFree(c->d_h2);
-  if (c->d_rq) hipFree(c->d_rq);
-  if (c->d_src) hipFree(c->d_src);
+      if (p) (void)hipFree(p);
+  if (c->d_nbr) (void)hipFree(c->d_nbr);
+  if (c->d_bc_kind) (void)hipFree(c->d_bc_kind);
+  if (c->d_bc_state) (void)hipFree(c->d_bc_state);
+  if (c->d_bc_field) (void)hipFree(c->d_bc_field);
+  if (c->d_Vptr) (void)hipFree(c->d_Vptr);
+  if (c->d_partm) (void)hipFree(c->d_partm);
+  if (c->d_h2) (void)hipFree(c->d_h2);
+  if (c->d_rq) (void)hipFree(c->d_rq);
+  if (c->d_src) (void)hipFree(c->d_src);
   void* bps[] = {c->d_inst, c->d_phs, c->d_epsv, c->d_dtav, c->d_active, c->d_ioff, c->d_hs, c->d_part2, c->d_kused};
   for (void* p : bps)
-    if (p) hipFree(p);
-  if (c->d_status) hipFree(c->d_status);
-  if (c->h_scal) hipHostFree(c->h_scal);
+    if (p) (void)hipFree(p);
+  if (c->d_status) (void)hipFree(c->d_status);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
   for (double* p : c->V)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete c;
 }
 
