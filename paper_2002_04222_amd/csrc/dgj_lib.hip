@@ -522,6 +522,8 @@ struct dgj_ctx {
     float *H1 = nullptr, *H2 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ = nullptr;
     double *s_inc = nullptr, *s_out = nullptr, *loss_part = nullptr;
     float *feat = nullptr, *pred = nullptr, *tgt = nullptr;
+    float* splitk = nullptr;   // split-K partial sums of the weight-gradient products
+    long splitk_n = 0;
   } mlp;
 };
 
@@ -987,7 +989,7 @@ void mlp_free_acts(dgj_ctx::Mlp& M) {
 
 void mlp_free(dgj_ctx::Mlp& M) {
   mlp_free_acts(M);
-  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt};
+  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt, M.splitk};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   M = dgj_ctx::Mlp();
@@ -1014,8 +1016,31 @@ void mlp_reserve(dgj_ctx* c, long R) {
 
 void gemm(dgj_ctx* c, const uint16_t* A, long a_i, long a_k, const uint16_t* B, long b_k, long b_j, int Mr, int Nc,
           int K, const float* bias, int act, float* Cf, uint16_t* Cb, long c_ld) {
-  GemmArgs g{A, a_i, a_k, B, b_k, b_j, Mr, Nc, K, bias, act, Cf, Cb, c_ld};
+  GemmArgs g{A, a_i, a_k, B, b_k, b_j, Mr, Nc, K, bias, act, Cf, Cb, c_ld, 0, nullptr};
   dim3 grid((Nc + 63) / 64, (Mr + 63) / 64);
+  const long tiles = (long)grid.x * grid.y;
+  if (tiles < 128 && K >= 2048) {
+    // few output tiles over a long K (the weight gradients, K = rows): split
+    // K over up to 16 workgroups per tile, partials summed in a fixed order
+    int S = std::min(16, K / 256);
+    const int chunk = ((K + S - 1) / S + 15) / 16 * 16;
+    S = (K + chunk - 1) / chunk;
+    const long need = (long)S * Mr * Nc;
+    auto& M = c->mlp;
+    if (need > M.splitk_n) {
+      if (M.splitk) HIPCHK(hipFree(M.splitk));
+      M.splitk = nullptr;
+      M.splitk_n = 0;
+      HIPCHK(hipMalloc(&M.splitk, need * sizeof(float)));
+      M.splitk_n = need;
+    }
+    g.k_chunk = chunk;
+    g.part = M.splitk;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(grid.x, grid.y, S), dim3(256), 0, c->stream, g);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((long)Mr * Nc)), dim3(256), 0, c->stream, M.splitk, S, Mr, Nc,
+                       bias, act, Cf, Cb, c_ld);
+    return;
+  }
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, c->stream, g);
 }
 

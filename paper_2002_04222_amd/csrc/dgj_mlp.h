@@ -33,6 +33,8 @@ struct GemmArgs {
   float* Cf;           // C(i,j) = Cf[i*c_ld + j] or null
   uint16_t* Cb;        // bf16 copy with the same layout, or null
   long c_ld;
+  int k_chunk;         // split K: workgroup z sums k in [z k_chunk, (z+1) k_chunk) (0: all of K)
+  float* part;         // split K: raw partial sums part[z][i][j] (M x N each) instead of the epilogue
 };
 
 // 64x64 output tile per workgroup of 4 wavefronts, 32x32 per wavefront as
@@ -49,7 +51,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  const int kb0 = g.k_chunk > 0 ? (int)blockIdx.z * g.k_chunk : 0;
+  const int kb1 = g.k_chunk > 0 ? min(g.K, kb0 + g.k_chunk) : g.K;
+  for (int k0 = kb0; k0 < kb1; k0 += 16) {
     bf16x4_t av[2], bv[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -58,8 +62,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int k = k0 + kq + t;
-        av[s][t] = (i < g.M && k < g.K) ? (short)g.A[(long)i * g.a_i + (long)k * g.a_k] : (short)0;
-        bv[s][t] = (j < g.N && k < g.K) ? (short)g.B[(long)k * g.b_k + (long)j * g.b_j] : (short)0;
+        av[s][t] = (i < g.M && k < kb1) ? (short)g.A[(long)i * g.a_i + (long)k * g.a_k] : (short)0;
+        bv[s][t] = (j < g.N && k < kb1) ? (short)g.B[(long)k * g.b_k + (long)j * g.b_j] : (short)0;
       }
     }
 #pragma unroll
@@ -77,12 +81,31 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         const int j = tj + b * 16 + r16;
         if (i < g.M && j < g.N) {
           float v = acc[a][b][r];
+          if (g.part) {
+            g.part[((long)blockIdx.z * g.M + i) * g.N + j] = v;
+            continue;
+          }
           if (g.bias) v += g.bias[j];
           if (g.act == 1) v = tanhf(v);
           if (g.Cf) g.Cf[(long)i * g.c_ld + j] = v;
           if (g.Cb) g.Cb[(long)i * g.c_ld + j] = f2bf(v);
         }
       }
+}
+
+// sum of the split-K partials in a fixed order, then the GEMM epilogue
+__global__ void k_splitk_reduce(const float* __restrict__ part, int S, int M, int N, const float* __restrict__ bias,
+                                int act, float* __restrict__ Cf, uint16_t* __restrict__ Cb, long c_ld) {
+  const long total = (long)M * N;
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (long)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    for (int z = 0; z < S; ++z) v += part[(long)z * total + q];
+    const long i = q / N, j = q - i * N;
+    if (bias) v += bias[j];
+    if (act == 1) v = tanhf(v);
+    if (Cf) Cf[i * c_ld + j] = v;
+    if (Cb) Cb[i * c_ld + j] = f2bf(v);
+  }
 }
 
 __global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, long n) {
