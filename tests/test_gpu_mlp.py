@@ -30,8 +30,10 @@ def _small():
     return cfg, cfg.mesh()
 
 
-def test_mlp_forward_and_gradient_match_oracle():
-    _case("mlp forward/grad vs oracle")
+# 2500 rows: the weight-gradient products are split over K (rows)
+@pytest.mark.parametrize("R", [300, 2500])
+def test_mlp_forward_and_gradient_match_oracle(R):
+    _case(f"mlp forward/grad vs oracle, {R} rows")
     cfg, mesh = _small()
     ctx = _ctx(cfg, mesh)
     H = 64
@@ -40,7 +42,6 @@ def test_mlp_forward_and_gradient_match_oracle():
     ctx.mlp_create(H, th)
     assert ctx.mlp_n_params == OM.n_params(2 * nb, H, nb)
     rng = np.random.default_rng(4)
-    R = 300
     X = rng.normal(size=(R, 2 * nb)).astype(np.float32) * 0.5
     T = rng.normal(size=(R, nb)).astype(np.float32) * 0.3
     Xd = torch.tensor(X, device="cuda")
