@@ -151,14 +151,20 @@ class BRJ:
             wq = disc.geo.wJ[el]
             # physical derivatives of the basis at the points: sum_k dxi_k/dx_j D_k B
             Dx = np.einsum('eqkj,kqm->ejqm', disc.geo.Gq[el], np.stack(ref.D))                # [e,j,q,m]
-            A[el] += np.einsum('ejqm,eq,eqjkl,qn->ekmln', Dx, wq, dHdQ, ref.B)
-            A[el] += np.einsum('ejqm,eq,eqjikl,eiqn->ekmln', Dx, wq, dHdG, Dx)
+            # sum over j, q of (w Dx)[j,q,m] T[q,j,k,l,n], with the point
+            # factor T = dH_j/dQ B (first term) + sum_i dH_j/d(grad_i Q) Dx_i
+            # (second term), taken as one matrix product per element
+            T = np.einsum('eqjkl,qn->eqjkln', dHdQ, ref.B) + np.einsum('eqjikl,eiqn->eqjkln', dHdG, Dx)
+            WDx = np.einsum('ejqm,eq->emqj', Dx, wq)
+            ne, nq = WDx.shape[0], WDx.shape[2]
+            A[el] += np.matmul(WDx.reshape(ne, nm, nq * d), T.reshape(ne, nq * d, nv * nv * nm)).reshape(
+                ne, nm, nv, nv, nm).transpose(0, 2, 1, 3, 4)
         # own-side face term (third term of Eq. 30) and stored neighbour Jacobians
         self.face_jp = {}
         for elems, f, nbrs, fn, sign in face_sides(disc):
             Jm, Jp = face_fd_jacobians(disc, u_p, self.chi, elems, f, nbrs, fn, sign)
             wf = disc.geo.wJf[f][elems]
-            A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f])
+            A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f], optimize=True)
             self.face_jp[f] = (elems, nbrs, fn, wf, Jp)
         # boundary faces: the boundary condition is inside the flux that is
         # differenced (Eq. 31), so only the own-side Jacobian exists
@@ -173,7 +179,7 @@ class BRJ:
                     H1, _ = disc.boundary_flux(u_p, elems, f, bid, Qo + dq, go)
                     Jm[..., l] = (H1 - H0) / self.chi[l]
                 wf = disc.geo.wJf[f][elems]
-                A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f])
+                A[elems] -= np.einsum('pm,kp,kpvl,pn->kvmln', ref.BF[f], wf, Jm, ref.BF[f], optimize=True)
         self.A_diag = A.reshape(E, nb, nb)
         Minv = np.linalg.inv(disc.M)                                       # [E, nm, nm]
         MinvA = np.einsum('emn,eknlo->ekmlo', Minv, A).reshape(E, nb, nb)
