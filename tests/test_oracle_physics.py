@@ -55,6 +55,18 @@ def test_poiseuille_forcing_matches_appendix_b():
     assert np.abs(div[:, 1] - f[:, 1]).max() <= 1e-9 * scale[1]
 
 
+def _mu_closed_form(gas, T):
+    """Viscosity and dmu/dT written out by hand: constant 1/Re, or
+    Sutherland's law mu = (1/Re) T^(3/2) (1 + s) / (T + s), s = 110 K / T_ref
+    (nondimensional T = 1 at the reference state, where mu = 1/Re)."""
+    if gas.visc_law == 0:
+        return 1.0 / gas.Re + 0.0 * T, 0.0 * T
+    s = 110.0 / gas.T_ref_K
+    mu = T ** 1.5 * (1.0 + s) / (T + s) / gas.Re
+    dmu = (1.0 + s) / gas.Re * np.sqrt(T) * (0.5 * T + 1.5 * s) / (T + s) ** 2
+    return mu, dmu
+
+
 def _special(kind, axis, dim, gas, a=0.3, k=2.0):
     p0 = 1.0 / (gas.gamma * gas.Ma ** 2)
 
@@ -84,8 +96,13 @@ def _special(kind, axis, dim, gas, a=0.3, k=2.0):
         mu = 1.0 / gas.Re
         out = np.zeros(s.shape + (dim + 2,))
         if kind == "heat":
-            kap = mu / (gas.Ma ** 2 * gas.Pr * (gas.gamma - 1))
-            out[..., dim + 1] = kap * a * k ** 2 * np.sin(k * s)      # -(kappa T'')
+            # -(kappa(T) T')' = -(kappa' T'^2 + kappa T''), kappa = mu / (Ma^2 Pr (gamma - 1))
+            T = 1.0 + a * np.sin(k * s)
+            dT = a * k * np.cos(k * s)
+            d2T = -a * k ** 2 * np.sin(k * s)
+            mu_T, dmu_T = _mu_closed_form(gas, T)
+            c = 1.0 / (gas.Ma ** 2 * gas.Pr * (gas.gamma - 1))
+            out[..., dim + 1] = -c * (dmu_T * dT * dT + mu_T * d2T)
         elif kind == "long":
             u = a * np.sin(k * s)
             ux = a * k * np.cos(k * s)
@@ -105,10 +122,14 @@ def _special(kind, axis, dim, gas, a=0.3, k=2.0):
     return field, exact_div
 
 
+@pytest.mark.parametrize("visc_law", [0, 1])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("kind", ["heat", "long", "shear"])
-def test_special_state_rates(kind, dim):
-    gas = Gas(Re=7.0, Ma=0.3, Pr=0.72)
+def test_special_state_rates(kind, dim, visc_law):
+    """Sutherland's law (visc_law 1) is pinned by the heat-conduction state,
+    whose temperature varies (kappa(T) differentiated by hand), and by the
+    two velocity states at T = 1, where it must reduce to mu = 1/Re."""
+    gas = Gas(Re=7.0, Ma=0.3, Pr=0.72, visc_law=visc_law)
     rng = np.random.default_rng(1)
     x = rng.uniform(0, 3, size=(50, dim))
     for axis in range(dim):
