@@ -188,9 +188,12 @@ typedef struct {
                                               (0 if not evaluated) */
 } dgj_step_stats;
 
-/* Create a context on the current device; hip_stream may be NULL (default
+/* Create a context on the current device for the discretisation of Sec. 3.1
+ * (Eq. 9-13: mesh, basis, quadrature, gas of Sec. 2) and the implicit solver
+ * of Sec. 3.2 and 4.2.2 (options above); hip_stream may be NULL (default
  * stream).  Copies the mesh and options; allocates the library's device
- * workspaces (freed by dgj_destroy). */
+ * workspaces (freed by dgj_destroy); the preconditioner's blocks and build
+ * scratch are allocated by the first dgj_precond_build or step and kept. */
 int dgj_create(const dgj_mesh *mesh, const dgj_phys *phys, const dgj_solver *solver, void *hip_stream,
                dgj_ctx **out);
 void dgj_destroy(dgj_ctx *ctx);
@@ -239,6 +242,12 @@ int dgj_precond_build(dgj_ctx *ctx, const double *u_p, double dt_a);
 /* out = P^-1 q by brj_sweeps sweeps of Eq. 28 from q^0 = 0.  Requires a
  * built preconditioner.  out must not alias q. */
 int dgj_precond_apply(dgj_ctx *ctx, const double *q, double *out);
+
+/* Change the storage precision of the BRJ blocks (DGJ_PC_F64 / F32 / BF16;
+ * Sec. 4.2.2 stores them in single precision) for the following builds; the
+ * held preconditioner is released, so the next step or dgj_precond_apply
+ * needs a build first. */
+int dgj_set_pc_precision(dgj_ctx *ctx, int32_t pc_precision);
 
 /* L2 projection onto the modes of values given at the volume Gauss points:
  * f[e][v][q] (device, q = q0 + nq (q1 + nq q2), x fastest) -> u[e][v][m],
@@ -370,6 +379,10 @@ int dgj_mlp_train_step(dgj_ctx *ctx, const float *X, const float *T, int64_t row
  * small problems at once. */
 typedef struct dgj_batch dgj_batch;
 int dgj_batch_create(int32_t n, const dgj_mesh *meshes, const dgj_phys *phys, const dgj_solver *solver,
+                     void *hip_stream, dgj_batch **out);
+/* The same call under the name the interface sketch of the batching form
+ * uses. */
+int dgj_create_batch(int32_t n, const dgj_mesh *meshes, const dgj_phys *phys, const dgj_solver *solver,
                      void *hip_stream, dgj_batch **out);
 void dgj_batch_destroy(dgj_batch *batch);
 const char *dgj_batch_last_error(const dgj_batch *batch);

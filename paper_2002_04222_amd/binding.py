@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_newton": ([vp, vp, dp, vp, i32p, i32p], C.c_int),
         "dgj_sdirk_step": ([vp, vp, dp, C.POINTER(StepStats)], C.c_int),
         "dgj_set_guess": ([vp, C.c_int32], C.c_int),
+        "dgj_set_pc_precision": ([vp, C.c_int32], C.c_int),
         "dgj_project": ([vp, vp, vp], C.c_int),
         "dgj_set_source": ([vp, vp], C.c_int),
         "dgj_set_bc_field": ([vp, vp], C.c_int),
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "dgj_mlp_grad": ([vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double)], C.c_int),
         "dgj_mlp_train_step": ([vp, vp, vp, C.c_int64, dp, C.POINTER(C.c_double)], C.c_int),
         "dgj_batch_create": ([C.c_int32, C.POINTER(Mesh), C.POINTER(Phys), C.POINTER(Solver), vp, C.POINTER(vp)],
+                             C.c_int),
+        "dgj_create_batch": ([C.c_int32, C.POINTER(Mesh), C.POINTER(Phys), C.POINTER(Solver), vp, C.POINTER(vp)],
                              C.c_int),
         "dgj_batch_destroy": ([vp], None),
         "dgj_batch_set_graphs": ([vp, C.c_int32], C.c_int),
@@ -382,6 +385,9 @@ class Context:
 
     # ---- Newton initial guess and the learned predictor
     GUESS = {"paper": 0, "extrapolated": 1, "learned": 2}
+
+    def set_pc_precision(self, prec):
+        self._check(self.lib.dgj_set_pc_precision(self.h, PRECISIONS[prec] if isinstance(prec, str) else int(prec)))
 
     def set_guess(self, mode):
         self._check(self.lib.dgj_set_guess(self.h, self.GUESS[mode] if isinstance(mode, str) else int(mode)))

@@ -580,6 +580,11 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
   return DGJ_OK;
 }
 
+int dgj_create_batch(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, const dgj_solver* solver,
+                     void* hip_stream, dgj_batch** out) {
+  return dgj_batch_create(n, meshes, phys, solver, hip_stream, out);
+}
+
 void dgj_batch_destroy(dgj_batch* b) {
   if (!b) return;
   if (b->own) (void)hipStreamSynchronize(b->own);

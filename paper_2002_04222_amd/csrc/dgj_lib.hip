@@ -28,6 +28,10 @@ namespace {
 
 constexpr int RED_BLOCKS = 512;
 constexpr int RED_THREADS = 256;
+// elements per preconditioner-build launch: bounds the build scratch the
+// context keeps (at 3D P = 4: 2.1 GB of quadrature-point Jacobians, and
+// 12.8 GB of FP64 staging for the reduced-precision forms)
+constexpr long PC_CHUNK = 4096;
 const double EPS_HAT = std::ldexp(1.0, -52);
 
 // ---------------------------------------------------------------- basis tables (host)
@@ -480,6 +484,8 @@ struct dgj_ctx {
   double pc_dta = 0.0;
   int pc_prec = 0;
   void* d_Dinv = nullptr;      // double / float / bf16
+  double *d_pcWt = nullptr, *d_pcJmW = nullptr, *d_pcD64 = nullptr;   // build scratch of pc_chunk elements
+  long pc_chunk = 0;
   void* d_Jp = nullptr;        // double / float
   double* d_chi = nullptr;
   int* d_status = nullptr;
@@ -827,13 +833,12 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
 }
 
 template <typename T, int KB>
-void invert(dgj_ctx* c, T* A, long e0, long ne, int nb, int ld, int threads) {
+void invert(dgj_ctx* c, T* A, int* status, long ne, int nb, int ld, int threads) {
   size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int) +
                (2 * KB + 1) * sizeof(int);
   if (nb > 1024) fail(DGJ_EUNSUPPORTED, "block size %d above 1024", nb);
   HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(ne), dim3(threads), lds, c->stream, A + e0 * (long)nb * ld, nb, ld, ne,
-                     c->d_status + e0);
+  hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(ne), dim3(threads), lds, c->stream, A, nb, ld, ne, status);
 }
 
 // In-place inversion of ne blocks of size nb.  Workgroup size and panel
@@ -842,7 +847,8 @@ void invert(dgj_ctx* c, T* A, long e0, long ne, int nb, int ld, int threads) {
 // columns up to 512 (320 x 320: 28.7 ms for 4,096 blocks), 1024 threads and
 // the widest panel that fits LDS above (each panel streams the trailing
 // columns once; 625 x 625: 30 columns).
-void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb, int ld) {
+// A: the first of the ne blocks; status: its slot of the per-block flags.
+void invert_blocks(dgj_ctx* c, double* A, int* status, long ne, int nb, int ld) {
   int dev = 0, lim = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -850,26 +856,31 @@ void invert_blocks(dgj_ctx* c, double* A, long e0, long ne, int nb, int ld) {
   auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 32 * 8 + 32 * 4 + (2 * kb + 1) * 4; };
   const int threads = nb <= 256 ? ((nb + 63) / 64) * 64 : (nb <= 512 ? 512 : 1024);
   const int want = nb <= 256 ? 16 : (nb <= 512 ? 24 : 32);
-  if (want >= 32 && lds(32) <= L) invert<double, 32>(c, A, e0, ne, nb, ld, threads);
-  else if (want >= 30 && lds(30) <= L) invert<double, 30>(c, A, e0, ne, nb, ld, threads);
-  else if (want >= 24 && lds(24) <= L) invert<double, 24>(c, A, e0, ne, nb, ld, threads);
-  else if (lds(16) <= L) invert<double, 16>(c, A, e0, ne, nb, ld, threads);
-  else if (lds(8) <= L) invert<double, 8>(c, A, e0, ne, nb, ld, threads);
+  if (want >= 32 && lds(32) <= L) invert<double, 32>(c, A, status, ne, nb, ld, threads);
+  else if (want >= 30 && lds(30) <= L) invert<double, 30>(c, A, status, ne, nb, ld, threads);
+  else if (want >= 24 && lds(24) <= L) invert<double, 24>(c, A, status, ne, nb, ld, threads);
+  else if (lds(16) <= L) invert<double, 16>(c, A, status, ne, nb, ld, threads);
+  else if (lds(8) <= L) invert<double, 8>(c, A, status, ne, nb, ld, threads);
   else fail(DGJ_EUNSUPPORTED, "block size %d too large for the in-LDS inversion", nb);
 }
 
 void free_pc(dgj_ctx* c) {
-  if (c->d_Dinv) (void)hipFree(c->d_Dinv);
-  if (c->d_Jp) (void)hipFree(c->d_Jp);
+  for (void* p : {(void*)c->d_Dinv, (void*)c->d_Jp, (void*)c->d_pcWt, (void*)c->d_pcJmW, (void*)c->d_pcD64})
+    if (p) (void)hipFree(p);
   c->d_Dinv = nullptr;
   c->d_Jp = nullptr;
+  c->d_pcWt = c->d_pcJmW = c->d_pcD64 = nullptr;
   c->pc_ready = false;
+}
+
+int stored_ld_of(const dgj_ctx* c, int prec) {
+  return prec == DGJ_PC_F64 ? stored_ld<double>(c->NB) : (prec == DGJ_PC_F32 ? stored_ld<float>(c->NB)
+                                                                               : stored_ld<__hip_bfloat16>(c->NB));
 }
 
 // Build the BRJ blocks of elements [e0, e0+ne) (one instance) at state up
 // into Dm (FP64, columns ld apart).
-void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, long ne, const Phys& ph, double* Wt,
-                         double* JmW, void* Dm, int ld) {
+void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, long ne, const Phys& ph) {
   if (c->has_dirichlet && !c->d_bc_field) fail(DGJ_EINVAL, "Dirichlet boundary without ghost states (dgj_set_bc_field)");
   // chi_v = ||u^(v)||_2 sqrt(eps_hat) over the instance  (Eq. 31)
   hipLaunchKernelGGL(k_varsq_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, up + e0 * c->NB, ne, c->NV,
@@ -889,80 +900,69 @@ void precond_build_range(dgj_ctx* c, const double* up, double dt_a, long e0, lon
   // a variable that is zero everywhere takes the norm of the whole state
   for (int v = 0; v < c->NV; ++v) chi[v] = std::sqrt(chi[v] > 0.0 ? chi[v] : total) * std::sqrt(EPS_HAT);
   HIPCHK(hipMemcpyAsync(c->d_chi, chi, c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
-#define X(d, n, q) if (c->dim == d && c->N == n && c->nq == q) { build_shape<d, n, q>(c, up, dt_a, Wt, JmW, Dm, e0, ne, ph, ld); } else
-  DGJ_FOR_SHAPES(X)
+  // blocks are assembled and inverted in FP64 (LU-based inversion in double,
+  // as the paper's dgetrf/dgetri), then stored in the chosen precision: FP64
+  // blocks in place with the stored column stride, the reduced-precision
+  // forms through an FP64 staging chunk with columns nb apart.  At most
+  // pc_chunk elements at a time, through the build scratch the context keeps.
+  const int prec = c->pc_prec;
+  const int lds = stored_ld_of(c, prec);
+  const int ld = prec == DGJ_PC_F64 ? lds : c->NB;
+  for (long cs = e0; cs < e0 + ne; cs += c->pc_chunk) {
+    const long n = std::min<long>(c->pc_chunk, e0 + ne - cs);
+    double* Dm = prec == DGJ_PC_F64 ? (double*)c->d_Dinv + cs * (long)c->NB * lds : c->d_pcD64;
+#define X(d, n_, q) if (c->dim == d && c->N == n_ && c->nq == q) { build_shape<d, n_, q>(c, up, dt_a, c->d_pcWt, c->d_pcJmW, Dm, cs, n, ph, ld); } else
+    DGJ_FOR_SHAPES(X)
 #undef X
-  fail(DGJ_EUNSUPPORTED, "unsupported shape");
-  invert_blocks(c, (double*)Dm, e0, ne, c->NB, ld);
+    fail(DGJ_EUNSUPPORTED, "unsupported shape");
+    invert_blocks(c, Dm, c->d_status + cs, n, c->NB, ld);
+    const long stored = n * c->NB * (long)lds;
+    if (prec == DGJ_PC_F32)
+      hipLaunchKernelGGL(k_blocks_from_f64<float>, dim3(grid_for(stored)), dim3(256), 0, c->stream, Dm,
+                         (float*)c->d_Dinv + cs * (long)c->NB * lds, c->NB, lds, n);
+    else if (prec == DGJ_PC_BF16)
+      hipLaunchKernelGGL(k_blocks_from_f64<__hip_bfloat16>, dim3(grid_for(stored)), dim3(256), 0, c->stream, Dm,
+                         (__hip_bfloat16*)c->d_Dinv + cs * (long)c->NB * lds, c->NB, lds, n);
+    HIPCHK(hipGetLastError());
+  }
 }
 
-int stored_ld_of(const dgj_ctx* c, int prec) {
-  return prec == DGJ_PC_F64 ? stored_ld<double>(c->NB) : (prec == DGJ_PC_F32 ? stored_ld<float>(c->NB)
-                                                                               : stored_ld<__hip_bfloat16>(c->NB));
-}
-
+// The stored blocks, face Jacobians and the build scratch (quadrature-point
+// Jacobians, own-side face Jacobians, FP64 staging of the reduced-precision
+// forms) of at most pc_chunk elements, allocated by the first build and kept:
+// later builds, including the refresh rules' rebuilds inside a step,
+// allocate nothing.
 void precond_alloc(dgj_ctx* c) {
   const int prec = c->sv.pc_precision;
   if (!c->d_Dinv || c->pc_prec != prec) {
     free_pc(c);
+    c->pc_prec = prec;
     size_t es = prec == DGJ_PC_F64 ? 8 : (prec == DGJ_PC_F32 ? 4 : 2);
     HIPCHK(hipMalloc(&c->d_Dinv, (size_t)c->n_elem * c->NB * stored_ld_of(c, prec) * es));
     size_t js = prec == DGJ_PC_F64 ? 8 : 4;
-    HIPCHK(hipMalloc(&c->d_Jp, (size_t)c->n_elem * 2 * c->dim * (size_t)std::pow(c->nq, c->dim - 1) * c->NV * c->NV * js));
-    c->pc_prec = prec;
+    const long nqf = (long)std::pow(c->nq, c->dim - 1), nqv = (long)std::pow(c->nq, c->dim);
+    HIPCHK(hipMalloc(&c->d_Jp, (size_t)c->n_elem * 2 * c->dim * nqf * c->NV * c->NV * js));
+    c->pc_chunk = std::min<long>(c->n_elem, PC_CHUNK);
+    HIPCHK(hipMalloc(&c->d_pcWt, (size_t)c->pc_chunk * nqv * c->dim * (c->dim + 1) * c->NV * c->NV * sizeof(double)));
+    HIPCHK(hipMalloc(&c->d_pcJmW, (size_t)c->pc_chunk * 2 * c->dim * nqf * c->NV * c->NV * sizeof(double)));
+    if (prec != DGJ_PC_F64) HIPCHK(hipMalloc(&c->d_pcD64, (size_t)c->pc_chunk * c->NB * c->NB * sizeof(double)));
   }
 }
 
 // Build the preconditioner of the given instances (all: n_inst == 0 or list
 // empty) at state up with per-instance dt a^mm.
 void precond_build_insts(dgj_ctx* c, const double* up, const std::vector<int>& insts, const std::vector<double>& dta) {
-  const int prec = c->sv.pc_precision;
   precond_alloc(c);
   c->pc_ready = false;
-  const long nq_vol = (long)std::pow(c->nq, c->dim);
-  const long nqf = (long)std::pow(c->nq, c->dim - 1);
-  double *Wt = nullptr, *JmW = nullptr;
-  void* Dm = nullptr;
-  HIPCHK(hipMalloc(&Wt, (size_t)c->n_elem * nq_vol * c->dim * (c->dim + 1) * c->NV * c->NV * sizeof(double)));
-  HIPCHK(hipMalloc(&JmW, (size_t)c->n_elem * 2 * c->dim * nqf * c->NV * c->NV * sizeof(double)));
-  const size_t blk = (size_t)c->n_elem * c->NB * c->NB;
-  // blocks are assembled and inverted in FP64 (LU-based inversion in double,
-  // as the paper's dgetrf/dgetri), then stored in the chosen precision
-  // FP64 blocks are built in place with the stored column stride; the
-  // reduced-precision forms from an FP64 copy with columns nb apart
-  const int ld = prec == DGJ_PC_F64 ? stored_ld_of(c, prec) : c->NB;
-  if (prec == DGJ_PC_F64) Dm = c->d_Dinv;
-  else HIPCHK(hipMalloc(&Dm, blk * sizeof(double)));
-  try {
-    for (size_t k = 0; k < insts.size(); ++k) {
-      const int i = insts[k];
-      const long e0 = c->inst_e0[i], ne = c->inst_e0[i + 1] - e0;
-      const Phys ph = c->n_inst > 0 ? c->h_phs[i] : c->ph;
-      precond_build_range(c, up, dta[k], e0, ne, ph, Wt, JmW, Dm, ld);
-    }
-  } catch (...) {
-    // the build scratch is released before the error propagates
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(Wt);
-    (void)hipFree(JmW);
-    if (prec != DGJ_PC_F64) (void)hipFree(Dm);
-    throw;
+  for (size_t k = 0; k < insts.size(); ++k) {
+    const int i = insts[k];
+    const long e0 = c->inst_e0[i], ne = c->inst_e0[i + 1] - e0;
+    const Phys ph = c->n_inst > 0 ? c->h_phs[i] : c->ph;
+    precond_build_range(c, up, dta[k], e0, ne, ph);
   }
-  const long stored = (long)c->n_elem * c->NB * stored_ld_of(c, prec);
-  if (prec == DGJ_PC_F32)
-    hipLaunchKernelGGL(k_blocks_from_f64<float>, dim3(grid_for(stored)), dim3(256), 0, c->stream, (const double*)Dm,
-                       (float*)c->d_Dinv, c->NB, stored_ld_of(c, prec), (long)c->n_elem);
-  else if (prec == DGJ_PC_BF16)
-    hipLaunchKernelGGL(k_blocks_from_f64<__hip_bfloat16>, dim3(grid_for(stored)), dim3(256), 0, c->stream,
-                       (const double*)Dm, (__hip_bfloat16*)c->d_Dinv, c->NB, stored_ld_of(c, prec),
-                       (long)c->n_elem);
-  HIPCHK(hipGetLastError());
   std::vector<int> st(c->n_elem);
   HIPCHK(hipMemcpyAsync(st.data(), c->d_status, c->n_elem * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  (void)hipFree(Wt);
-  (void)hipFree(JmW);
-  if (prec != DGJ_PC_F64) (void)hipFree(Dm);
   for (int i : insts)
     for (long e = c->inst_e0[i]; e < c->inst_e0[i + 1]; ++e)
       if (st[e]) fail(DGJ_ESINGULAR, "precond_build: zero pivot in block of element %ld", e);
@@ -1027,13 +1027,7 @@ void gemm(dgj_ctx* c, const uint16_t* A, long a_i, long a_k, const uint16_t* B, 
     S = (K + chunk - 1) / chunk;
     const long need = (long)S * Mr * Nc;
     auto& M = c->mlp;
-    if (need > M.splitk_n) {
-      if (M.splitk) HIPCHK(hipFree(M.splitk));
-      M.splitk = nullptr;
-      M.splitk_n = 0;
-      HIPCHK(hipMalloc(&M.splitk, need * sizeof(float)));
-      M.splitk_n = need;
-    }
+    if (need > M.splitk_n) fail(DGJ_EINVAL, "split-K scratch of %ld floats too small for %ld", M.splitk_n, need);
     g.k_chunk = chunk;
     g.part = M.splitk;
     hipLaunchKernelGGL(k_gemm_bf16, dim3(grid.x, grid.y, S), dim3(256), 0, c->stream, g);
@@ -1499,7 +1493,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
 #undef X
       if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
       HIPCHK(hipMemcpyAsync(c->d_Minv, c->d_M, mm * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      invert_blocks(c, c->d_Minv, 0, E, c->NM, c->NM);
+      invert_blocks(c, c->d_Minv, c->d_status, E, c->NM, c->NM);
       std::vector<int> st(E);
       HIPCHK(hipMemcpyAsync(st.data(), c->d_status, E * sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1684,6 +1678,17 @@ int dgj_precond_apply(dgj_ctx* c, const double* q, double* out) {
     if (!c->pc_ready) fail(DGJ_EINVAL, "precond_apply: no preconditioner built");
     precond_apply(c, q, out);
     HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_set_pc_precision(dgj_ctx* c, int32_t prec) {
+  if (!c || prec < DGJ_PC_F64 || prec > DGJ_PC_BF16) return DGJ_EINVAL;
+  if (c->n_inst > 0) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    free_pc(c);
+    c->sv.pc_precision = prec;
     return DGJ_OK;
   });
 }
@@ -1923,6 +1928,11 @@ int dgj_mlp_create(dgj_ctx* c, int32_t hidden, const float* params_host) {
     HIPCHK(hipMalloc(&M.tgt, (size_t)c->n_elem * M.n_out * 4));
     HIPCHK(hipMalloc(&M.loss_part, RED_BLOCKS * sizeof(double)));
     HIPCHK(hipMalloc(&M.feat, (size_t)c->n_elem * M.n_in * 4));
+    // split-K partial sums of the weight-gradient products (at most 16
+    // K-slices of the largest weight matrix), sized once here so that the
+    // products inside a step never allocate
+    M.splitk_n = 16L * std::max({(long)M.n_in * M.H, (long)M.H * M.H, (long)M.H * M.n_out});
+    HIPCHK(hipMalloc(&M.splitk, M.splitk_n * sizeof(float)));
     std::vector<float> zero(M.np, 0.0f);
     HIPCHK(hipMemcpy(M.w, params_host ? params_host : zero.data(), M.np * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(M.m, zero.data(), M.np * 4, hipMemcpyHostToDevice));

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(NT) void k_pc_volume(const double* __restrict__ u, 
         gU[j][v] = s;
       }
     }
-    double* out = Wt + (e * NQ + q) * (long)PER_Q;
+    double* out = Wt + ((long)blockIdx.x * NQ + q) * PER_Q;   // Wt holds the launch's elements
     // dH/dQ via duals, one flux direction at a time to bound register use
     Dual<NV> Ud[NV];
 #pragma unroll
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
   }
   const double b = beta[e * NF + f];
   const long base = ((e * NF + f) * NQF + p) * NV * NV;
+  const long lbase = gid * (long)(NV * NV);   // JmW holds the launch's elements
   double H0[NV], H1[NV];
   if (en < 0) {
     // boundary face: the condition is inside the differenced flux (Eq. 31);
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
       Uo[l] = save;
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        JmW[base + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
+        JmW[lbase + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
         Jp[base + k * NV + l] = (TJ)0.0;
       }
     }
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
     face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H1, nullptr);
     Uo[l] = save;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) JmW[base + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
+    for (int k = 0; k < NV; ++k) JmW[lbase + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
     save = Un[l];
     Un[l] = save + chi;
     face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H1, nullptr);
@@ -329,20 +330,21 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
   Tab tb = load_tables<N, Q>(tables, st);
   const long blk = blockIdx.x;
   if (blk / (NV * NV) >= n_elem) return;
-  const long e = e0 + blk / (NV * NV);
+  const long le = blk / (NV * NV);   // Wt, JmW and Dm hold the launch's elements
+  const long e = e0 + le;
   const int kl = blk % (NV * NV);
   const int k = kl / NV, l = kl % NV;
   const int tid = threadIdx.x;
   for (int i = tid; i < A::SW; i += NT) {
     const int q = i % NQ, jb = i / NQ;
-    sW[i] = Wt[(e * NQ + q) * (long)PER_Q + (jb * NV + k) * NV + l];
+    sW[i] = Wt[(le * NQ + q) * (long)PER_Q + (jb * NV + k) * NV + l];
   }
-  for (int i = tid; i < NF * NQF; i += NT) sJ[i] = JmW[(e * NF * NQF + i) * (long)NV * NV + k * NV + l];
+  for (int i = tid; i < NF * NQF; i += NT) sJ[i] = JmW[(le * NF * NQF + i) * (long)NV * NV + k * NV + l];
   const double* B = tb.B;     // B[q * N + m]
   const double* Dq = tb.Dq;
   // output sub-block: entry (m, n) of A_kl at Dm[e][l NM + n][k NM + m]
   // (columns ld apart, ld >= nb)
-  double* out = Dm + e * (long)NB * ld + (long)(l * NM) * ld + k * NM;
+  double* out = Dm + le * (long)NB * ld + (long)(l * NM) * ld + k * NM;
   __syncthreads();
   for (int j = 0; j < D; ++j) {
     const double* F1 = (j == 0) ? Dq : B;
