@@ -1,7 +1,7 @@
 """Parity of the HIP path with the oracle on meshes with boundary faces:
 1D characteristic far field and adiabatic no-slip walls (ghost states with
 the interior gradient).  Tolerances as for the periodic parity tests:
-residual 1e-12 relative per variable, matvec 1e-6, SDIRK steps 1e-10.
+residual 1e-12 relative per variable, matvec 1e-6, SDIRK steps 1e-12 per variable.
 BRJ blocks 5e-6 and applies 1e-5: where a far-field face lies in the
 inflow/outflow blend (|u_nb| below ~0.02 c_b) the forward difference of Eq.
 31 divides the rounding of u_nb = (R+ + R-)/2 (|R+-| ~ 2c/(gamma-1)),
@@ -22,7 +22,7 @@ import workloads as W
 from oracle import solver as OS
 from oracle.dg import Disc
 from oracle.physics import Gas, BC_FARFIELD, BC_WALL
-from tests.gpu_util import rel_err_per_var
+from tests.gpu_util import assert_step, rel_err_per_var
 
 
 def _case(msg):
@@ -158,12 +158,12 @@ def test_bc_sdirk_step_parity(scheme):
     du = _dev(u0)
     stepper = OS.SDIRK(disc, OS.SolverOpts(scheme=scheme))
     uo = u0
-    for _ in range(2):
+    for k in range(2):
         s = ctx.sdirk_step(du, 0.1)
         uo, so = stepper.step(uo, 0.1)
         assert s["newton_its"] == [x.newton_its for x in so]
         assert s["gmres_its"] == [x.gmres_its for x in so]
-        assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
+        assert_step(_host(du), uo, f"walls + far field {scheme} step {k}")
 
 
 def test_bc_create_rejects_bad_ids_and_kinds():

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_bench_json_contract():
     print("[case] bench.py --workload 1 --steps 2", flush=True)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "1", "--steps", "2",
-                        "--warmup", "1", "--no-forms", "--no-explicit", "--no-cpu-baseline", "--kernel-reps", "10"],
+                        "--warmup", "1", "--no-forms", "--no-explicit", "--no-cpu-baseline", "--no-learned",
+                        "--kernel-reps", "10"],
                        capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.strip().splitlines() if l.startswith("{")]
@@ -32,5 +33,9 @@ def test_bench_json_contract():
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert 0.0 < rf["frac"] <= 1.0 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-12
-    # counters are recorded for the 16^3 workload only
+    # counters are recorded for the benchmark workloads only
     assert rf["traffic"] is None
+    rr = d["residual_roofline"]
+    assert rr["bound"] == "alu" and rr["unit"] == "TFLOP/s" and rr["peak"] == 78.6
+    assert 0.0 < rr["frac"] <= 1.0 and rr["algorithmic_flops"] > 0 and rr["compulsory_bytes"] > 0
+    assert d["value"] == pytest.approx(d["residual_kernel"]["dofs_per_s"])

@@ -2,7 +2,7 @@
 1e-12 relative per variable (2D P = 1..5, 3D P = 1..4, Navier-Stokes and
 the diffusion test operator, with Dirichlet and wall/far-field
 boundaries), the Jacobian-free matvec 1e-6, implicit steps with the same
-Newton/GMRES counts and 1e-10 in the state, and the manufactured Poiseuille
+Newton/GMRES counts and 1e-12 per variable in the state, and the manufactured Poiseuille
 case at the designed order on the device."""
 import dataclasses
 import sys
@@ -18,7 +18,7 @@ import workloads as W
 from oracle import solver as OS
 from oracle.dg import Disc, make_disc
 from oracle.physics import Gas, BC_FARFIELD, BC_WALL, BC_SLIP, BC_ISOTHERMAL
-from tests.gpu_util import rel_err_per_var, setup
+from tests.gpu_util import assert_step, rel_err_per_var, setup
 
 
 def _dev(a):
@@ -94,12 +94,12 @@ def test_matvec_and_step_parity():
     du = _dev(u)
     stepper = OS.make_stepper(disc, OS.SolverOpts(scheme="sdirk2"))
     uo = u
-    for _ in range(2):
+    for k in range(2):
         st = ctx.sdirk_step(du, 0.1)
         uo, sto = stepper.step(uo, 0.1)
         assert st["newton_its"] == [s.newton_its for s in sto]
         assert st["gmres_its"] == [s.gmres_its for s in sto]
-        assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
+        assert_step(_host(du), uo, f"LDG step {k}")
 
 
 def test_ldg_rejected_where_not_built():
@@ -148,7 +148,8 @@ def test_ldg_steady_parity_and_order():
     from tests.test_oracle_mms import mms_steady
     eg, ug = _gpu_steady_ldg(2, 4)
     uo, eo, _ = mms_steady(2, 4, viscous="ldg")
-    assert np.linalg.norm(ug - uo) <= 1e-9 * np.linalg.norm(uo)
+    # v vanishes in the exact solution: the momentum components share one scale
+    assert_step(ug, uo, "LDG MMS steady state", vector_scale=True)
     for P, levels in ((2, (4, 8, 16)), (3, (3, 4, 8))):
         errs = [_gpu_steady_ldg(P, n)[0] for n in levels]
         for k in range(1, len(levels)):

@@ -4,8 +4,8 @@ Tolerances: residual and stage residual 1e-12 relative per variable (FP64
 with a different summation order); the Jacobian-free matvec 1e-6 (the
 forward difference amplifies rounding by ~1/sqrt(eps_hat)); preconditioner
 blocks and apply 1e-6 (forward-difference face Jacobians, Eq. 31); SDIRK
-steps 1e-10 relative in the state (Newton contracts early differences;
-both runs meet the same Newton tolerance)."""
+steps 1e-12 relative per variable in the state (Newton contracts early
+differences; both runs take identical Newton and GMRES counts)."""
 import sys
 
 import numpy as np
@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 import workloads as W
 from oracle import solver as OS
 from oracle.dg import initial_state
-from tests.gpu_util import rel_err_per_var, setup
+from tests.gpu_util import assert_step, rel_err_per_var, setup
 
 
 def _ctx(cfg, mesh, **over):
@@ -63,6 +63,43 @@ def test_residual_parity(dim, cells, P, mode, riemann):
     detJ = disc.detJ[:, None]
     tot = (Rg[:, :, 0] * detJ).sum(0)
     assert np.all(np.abs(tot) <= 1e-13 * np.abs(Rg[:, :, 0] * detJ).sum(0) + 1e-300)
+
+
+@pytest.mark.parametrize("dim,cells,P", [(2, (3, 2), 3), (3, (2, 2, 3), 2)])
+def test_residual_parity_sutherland(dim, cells, P):
+    """Sutherland's viscosity law (visc_law 1): a state whose temperature
+    varies by a few percent, so mu(T) varies over the mesh."""
+    _case(f"residual Sutherland dim={dim} cells={cells} P={P}")
+    cfg, mesh, disc = setup(dim, cells, P, Ma=0.3, Re=40.0, visc_law=1)
+    assert disc.gas.visc_law == 1
+    ctx = _ctx(cfg, mesh)
+    u = W.random_state(mesh.n_elem, dim, P, seed=150 + P, amp=0.1)
+    R = ctx.empty()
+    ctx.residual(_dev(u), R)
+    assert rel_err_per_var(_host(R), disc.residual(u)) <= 1e-12
+
+
+def test_precond_and_step_parity_sutherland():
+    _case("precond + SDIRK2 steps Sutherland 2D P=2")
+    cfg, mesh, disc = setup(2, (4, 3), 2, Ma=0.3, Re=40.0, visc_law=1, scheme="sdirk2")
+    ctx = _ctx(cfg, mesh)
+    u = W.random_state(mesh.n_elem, 2, 2, seed=161, amp=0.1)
+    ctx.precond_build(_dev(u), 0.1)
+    pc = OS.BRJ(disc, u, 0.1)
+    nb = disc.nv * disc.ref.nm
+    out = torch.empty((mesh.n_elem, nb, nb), dtype=torch.float64, device="cuda")
+    ctx.precond_diag_inverse(out)
+    assert np.abs(_host(out) - pc.Dinv).max() <= 1e-6 * np.abs(pc.Dinv).max()
+    ctx2 = _ctx(cfg, mesh)
+    du = _dev(u)
+    stepper = OS.SDIRK(disc, OS.SolverOpts(scheme="sdirk2"))
+    uo = u
+    for k in range(2):
+        st = ctx2.sdirk_step(du, 0.1)
+        uo, sto = stepper.step(uo, 0.1)
+        assert st["newton_its"] == [s.newton_its for s in sto]
+        assert st["gmres_its"] == [s.gmres_its for s in sto]
+        assert_step(_host(du), uo, f"Sutherland SDIRK2 step {k}")
 
 
 def test_residual_parity_nonuniform_sizes():
@@ -176,7 +213,7 @@ def test_gmres_and_newton_parity():
     nit, git = ctx.newton(_dev(un), dt_a, du)
     uo, st = OS.newton_solve(disc, un, dt_a, pc, OS.SolverOpts())
     assert nit == st.newton_its and git == st.gmres_its
-    assert np.abs(_host(du) - uo).max() <= 1e-10 * np.abs(uo).max()
+    assert_step(_host(du), uo, "newton 2D P=2")
 
 
 def test_project_tgv_parity():
@@ -208,7 +245,7 @@ def test_sdirk_step_parity_small(scheme):
         uo, sto = stepper.step(uo, dt)
         assert st["newton_its"] == [s.newton_its for s in sto]
         assert st["gmres_its"] == [s.gmres_its for s in sto]
-        assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
+        assert_step(_host(du), uo, f"{scheme} 4x3 P=2 step {k}")
 
 
 def test_sdirk_step_parity_tgv2d_workload():
@@ -226,10 +263,10 @@ def test_sdirk_step_parity_tgv2d_workload():
     st = ctx.sdirk_step(u, cfg.dt())
     uo, sto = OS.SDIRK(disc, OS.SolverOpts(scheme=cfg.scheme)).step(u0, cfg.dt())
     ug = _host(u)
-    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
-    print("tgv2d step rel err", rel, st["newton_its"], st["gmres_its"], flush=True)
+    print("tgv2d step counts", st["newton_its"], st["gmres_its"], flush=True)
     assert st["newton_its"] == [s.newton_its for s in sto]
-    assert rel <= 1e-10
+    assert st["gmres_its"] == [s.gmres_its for s in sto]
+    assert_step(ug, uo, "tgv2d 8x8 P=2 SDIRK2 CFL 20")
 
 
 def test_residual_bitwise_repeatable_and_full_workload():
@@ -288,5 +325,5 @@ def test_sdirk_step_parity_with_preconditioner_refresh():
         uo, sto = stepper.step(uo, 0.2)
         assert st["newton_its"] == [s.newton_its for s in sto]
         assert st["gmres_its"] == [s.gmres_its for s in sto]
-        assert np.linalg.norm(_host(du) - uo) <= 1e-10 * np.linalg.norm(uo)
+        assert_step(_host(du), uo, f"sdirk3 refresh step {k}")
     assert builds >= 2
