@@ -1,19 +1,26 @@
 """Benchmark of the implicit DG hot path on one MI355X.
 
-Workload (default): 3D Taylor-Green vortex on the periodic cube [0, 2 pi]^3,
-16^3 affine hexahedra, P = 3 (4^3 modes, 5^3 Gauss points), 5 conserved
-variables in FP64, Re 1600, Ma 0.1, SDIRK3 at CFL 20, GMRES(30) with rtol
-5e-2, BRJ(7), Newton tolerance 1e-8, preconditioner frozen for 10 steps.
+Workload (default): flow past a cylinder on a curved O-grid annulus, r in
+[0.5, 10], 32 radial x 64 angular x 8 spanwise hexahedra (span pi), P = 4
+(5^3 modes, 6^3 Gauss points), quadratic isoparametric maps, no-slip wall and
+far field, Re 3900, Ma 0.2, 5 conserved variables in FP64 (10.24 M
+unknowns), SDIRK2 at CFL 20 on the smallest element, GMRES(30) with rtol
+5e-2, BRJ(7), Newton tolerance 1e-8, preconditioner frozen for 10 steps (the
+paper's settings).  The fluid starts at rest and the far field sets it
+moving; the warm-up steps ramp dt from dt/100 up to dt.
 
 A timed "step" is one implicit SDIRK step (every stage: Newton, GMRES,
 Jacobian-free matvecs, BRJ sweeps); the timed region starts with a
 preconditioner build, as the first step of each freeze window does.
 
-Printed JSON line: value = DG residual DOFs/s delivered by the timed steps
-(per-variable DoF N_e (P+1)^d times residual evaluations, over the timed
-wall time), ms_per_step = implicit-step time, plus the residual kernel's own
-throughput, the dominant kernel's roofline figures and the CPU oracle
-baseline.
+Printed JSON line: value = DG residual DOFs/s of the residual evaluation
+(per-variable DoF N_e (P+1)^d per evaluation, back-to-back evaluations with
+the state resident in HBM), ms_per_step = implicit-step time; the dominant
+kernel's roofline (the BRJ sweep), the residual's own roofline, the DOF/s
+the timed steps deliver, the precision forms (FP64 / FP32 / BF16 blocks) on
+this workload and on the 16^3 P = 3 Taylor-Green cube, the learned Newton
+guess on the 2D Taylor-Green workload, the explicit ERK2 comparison, and the
+CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -35,8 +42,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=4)
     ap.add_argument("--P", type=int, default=None, help="polynomial order (default: the workload's; nq = P+2)")
     ap.add_argument("--pc", default=None, help="preconditioner storage f64|f32|bf16 (default: workload's)")
     ap.add_argument("--brj-sweeps", type=int, default=None, help="BRJ sweeps J (default: the workload's, 7)")
@@ -48,13 +55,17 @@ def parse():
     ap.add_argument("--ortho", default=None, choices=["mgs", "cgs2"],
                     help="GMRES orthogonalisation (default: the workload's, modified Gram-Schmidt)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision forms (FP64 / FP32 / BF16 blocks: 3 steps each from the start "
-                         "state, their sweep's roofline, speed-up and state difference against FP64)")
-    ap.add_argument("--learned", action="store_true",
-                    help="also time the learned Newton guess against the paper's and the extrapolated one")
-    ap.add_argument("--learned-train", type=int, default=20, help="plain steps recorded to train the MLP")
+                    help="skip the precision forms (FP64 / FP32 / BF16 blocks from the same state, on this "
+                         "workload and on the 16^3 P = 3 Taylor-Green cube: their sweep's roofline, speed-up "
+                         "and state difference against FP64)")
+    ap.add_argument("--form-steps", type=int, default=2, help="steps per precision form")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned Newton guess (trained and timed on the 2D Taylor-Green workload)")
+    ap.add_argument("--learned-workload", type=int, default=1,
+                    help="workload the learned guess is trained and timed on")
+    ap.add_argument("--learned-train", type=int, default=40, help="plain steps recorded to train the MLP")
     ap.add_argument("--learned-epochs", type=int, default=150, help="Adam passes over the recorded stages")
-    ap.add_argument("--learned-held", type=int, default=3, help="held-out steps timed with each guess")
+    ap.add_argument("--learned-held", type=int, default=5, help="held-out steps timed with each guess")
     ap.add_argument("--batch", action="store_true",
                     help="also time the batch of 64 independent 2D problems, batched against one by one")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -63,8 +74,6 @@ def parse():
                          "against ERK2 at its largest stable CFL, both to steady state, P = 2, 3, 4")
     ap.add_argument("--mms-n", type=int, default=8, help="elements per direction of the manufactured case")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cylinder-steps", action="store_true",
-                    help="cylinder workload: also time implicit steps (warmup steps ramp dt from dt/100)")
     ap.add_argument("--no-explicit", action="store_true",
                     help="skip the explicit ERK2 comparison (its largest stable CFL and its time to reach the "
                          "same physical time as the timed implicit steps)")
@@ -81,32 +90,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The CPU oracle on the host cores: full residual evaluations of the
-    same workload until about budget_s seconds have passed (for the
-    cylinder workload: on every 128th element and its face neighbours)."""
-    import numpy as np
-    import workloads as W
-    from oracle.dg import make_disc, initial_state, restricted_disc
-    from oracle.physics import Gas
-    mesh = cfg.mesh()
-    if cfg.geometry == "annulus":
-        kinds, states = cfg.boundary()
-        gas = Gas(gamma=cfg.gamma, Pr=cfg.Pr, Re=cfg.Re, Ma=cfg.Ma, visc_law=cfg.visc_law, T_ref_K=cfg.T_ref_K,
-                  flux_mode=cfg.flux_mode, riemann=cfg.riemann)
-        sample = list(range(0, mesh.n_elem, 128))
-        disc, keep, _ = restricted_disc(gas, mesh.dim, cfg.P, cfg.nq, mesh.face_nbr, sample,
-                                        geo_nodes=mesh.geo_nodes, geo_order=mesh.geo_order, bc_kind=kinds,
-                                        bc_state=states)
-        u0 = W.freestream_state(cfg, mesh.n_elem)[keep]
-        dofs = len(keep) * (cfg.P + 1) ** cfg.dim
-        what = (f"residual R(u) = M^-1 L(u) on {len(keep)} elements of the same workload: every 128th "
-                f"element and its face neighbours (outer faces closed by far field), all counted")
-    else:
-        disc = make_disc(cfg, mesh)
-        u0 = initial_state(disc, W.noise(disc.shape, cfg.seed), cfg.noise_amp)
-        dofs = cfg.dofs()
-        what = "full residual evaluations R(u) = M^-1 L(u) of the same workload (u = projected initial state)"
+def _oracle_residual_rate(disc, u0, dofs, budget_s):
+    """Full oracle residual evaluations until budget_s has passed: (DOF/s,
+    evaluations, wall s, threads used = CPU time / wall)."""
     disc.residual(u0)          # metrics and mass matrices outside the timed loop
     n = 0
     r0 = resource.getrusage(resource.RUSAGE_SELF)
@@ -119,10 +105,69 @@ def cpu_baseline(cfg, budget_s=20.0):
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {"value": dofs * n / wall, "unit": "DOF/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": f"{n} x {what} in {wall:.1f} s wall, {cpu:.1f} s CPU; "
-                      f"host has {os.cpu_count()} logical CPUs"}
+    return dofs * n / wall, n, wall, cpu / wall
+
+
+def cpu_baseline(cfg, budget_s=12.0):
+    """The CPU oracle on the host cores, as it stands: residual evaluations of
+    the same workload (for the cylinder: every 256th element and its face
+    neighbours) for about budget_s seconds with the BLAS thread pools limited
+    to one thread and then left at their default (all host cores), and one
+    full SDIRK2 step of the 2D Taylor-Green workload (8x8, P = 2, CFL 20,
+    Newton alpha 1e-8) in both settings."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle.dg import make_disc, initial_state, restricted_disc
+    from oracle.physics import Gas
+    from oracle import solver as OS
+    mesh = cfg.mesh()
+    if cfg.geometry == "annulus":
+        kinds, states = cfg.boundary()
+        gas = Gas(gamma=cfg.gamma, Pr=cfg.Pr, Re=cfg.Re, Ma=cfg.Ma, visc_law=cfg.visc_law, T_ref_K=cfg.T_ref_K,
+                  flux_mode=cfg.flux_mode, riemann=cfg.riemann)
+        sample = list(range(0, mesh.n_elem, 256))
+        disc, keep, _ = restricted_disc(gas, mesh.dim, cfg.P, cfg.nq, mesh.face_nbr, sample,
+                                        geo_nodes=mesh.geo_nodes, geo_order=mesh.geo_order, bc_kind=kinds,
+                                        bc_state=states)
+        u0 = W.freestream_state(cfg, mesh.n_elem)[keep]
+        dofs = len(keep) * (cfg.P + 1) ** cfg.dim
+        what = (f"residual R(u) = M^-1 L(u) on {len(keep)} elements of the same workload: every 256th "
+                f"element and its face neighbours (outer faces closed by far field), all counted")
+    else:
+        disc = make_disc(cfg, mesh)
+        u0 = initial_state(disc, W.noise(disc.shape, cfg.seed), cfg.noise_amp)
+        dofs = cfg.dofs()
+        what = "full residual evaluations R(u) = M^-1 L(u) of the same workload (u = projected initial state)"
+    res = {}
+    for label, lim in (("one_thread", 1), ("all_cores", None)):
+        with threadpool_limits(limits=lim):
+            rate, n, wall, thr = _oracle_residual_rate(disc, u0, dofs, budget_s)
+        res[label] = {"value": rate, "unit": "DOF/s", "cores": max(1, round(thr)), "threads_used": thr,
+                      "sample": f"{n} x {what} in {wall:.1f} s wall"}
+    # a full implicit step of the 2D Taylor-Green workload
+    c1 = W.config(1)
+    m1 = c1.mesh()
+    d1 = make_disc(c1, m1)
+    u1 = initial_state(d1, W.noise(d1.shape, c1.seed), c1.noise_amp)
+    steps = {}
+    for label, lim in (("one_thread", 1), ("all_cores", None)):
+        with threadpool_limits(limits=lim):
+            r0 = resource.getrusage(resource.RUSAGE_SELF)
+            t0 = time.perf_counter()
+            _, sto = OS.SDIRK(d1, OS.SolverOpts(scheme=c1.scheme)).step(u1, c1.dt())
+            wall = time.perf_counter() - t0
+            r1 = resource.getrusage(resource.RUSAGE_SELF)
+        cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+        steps[label] = {"s_per_step": wall, "threads_used": cpu / wall,
+                        "newton_its": [x.newton_its for x in sto]}
+    allc = res["all_cores"]
+    return {"value": allc["value"], "unit": "DOF/s", "cores": allc["cores"], "kind": "oracle",
+            "sample": allc["sample"] + f"; BLAS pools at their default on a host of {os.cpu_count()} "
+                                       f"logical CPUs",
+            "one_thread": res["one_thread"],
+            "oracle_step_tgv2d-8x8-p2": steps,
+            "host_logical_cpus": os.cpu_count()}
 
 
 def sweep_bytes(ctx, cfg, prec):
@@ -147,28 +192,131 @@ def sweep_bytes(ctx, cfg, prec):
     return (first + (J - 1) * other + extra) / J
 
 
-def measured_traffic(prec):
-    """HBM bytes per BRJ sweep launch from the committed counter runs, or None
-    when the sweep's source (the apply section of its header, which holds the
-    sweep kernel and its load helpers) has changed since they were taken."""
+def _source_hash(rel_path, marker=None):
+    """sha256 (16 hex digits) of a source file, from `marker` to the end."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_brj_sweep_tgv3d-16c-p3_traffic.md")
-    src = os.path.join(ROOT, "paper_2002_04222_amd", "csrc", "dgj_precond.h")
-    try:
-        rec = None
-        for line in open(path):
-            if line.startswith("TRAFFIC "):
-                rec = json.loads(line[len("TRAFFIC "):])
-        text = open(src).read()
-        marker = "// ---------------------------------------------------------------- apply"
+    text = open(os.path.join(ROOT, rel_path)).read()
+    if marker is not None:
         if marker not in text:
             return None
-        h = hashlib.sha256(text[text.index(marker):].encode()).hexdigest()[:16]
-        if rec is None or rec.get("sweep_section_sha256_16") != h:
-            return None
-        return rec.get(prec)
+        text = text[text.index(marker):]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def _profile_record(name, tag):
+    """The last `tag {json}` line of profiles/<name>, or None."""
+    rec = None
+    try:
+        for line in open(os.path.join(ROOT, "profiles", name)):
+            if line.startswith(tag + " "):
+                rec = json.loads(line[len(tag) + 1:])
     except OSError:
         return None
+    return rec
+
+
+SWEEP_MARKER = "// ---------------------------------------------------------------- apply"
+RESIDUAL_SOURCES = ("paper_2002_04222_amd/csrc/dgj_residual.h", "paper_2002_04222_amd/csrc/dgj_physics.h")
+
+
+def measured_traffic(prec, workload="tgv3d-16c-p3"):
+    """HBM bytes per BRJ sweep launch from the committed counter runs of the
+    workload, or None when the sweep's source (the apply section of its
+    header, which holds the sweep kernel and its load helpers) has changed
+    since they were taken."""
+    try:
+        rec = _profile_record(f"k_brj_sweep_{workload}_traffic.md", "TRAFFIC")
+        h = _source_hash("paper_2002_04222_amd/csrc/dgj_precond.h", SWEEP_MARKER)
+    except OSError:
+        return None
+    if rec is None or h is None or rec.get("sweep_section_sha256_16") != h:
+        return None
+    return rec.get(prec)
+
+
+def residual_counters(workload):
+    """Counted HBM bytes and FP64 operations of one residual evaluation from
+    the committed counter runs, or None when the residual kernels' sources
+    have changed since they were taken."""
+    rec = _profile_record(f"residual_{workload}_counters.md", "COUNTERS")
+    if rec is None:
+        return None
+    try:
+        h = "".join(_source_hash(p) for p in RESIDUAL_SOURCES)
+    except OSError:
+        return None
+    if rec.get("residual_sources_sha256_16") != h:
+        return None
+    return rec
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def residual_algorithmic(cfg, n_elem):
+    """Algorithmic FP64 flops and compulsory HBM bytes of one residual
+    evaluation (sum factorisation, each face flux once):
+      per element and variable: the backward transform and its transpose,
+        2 x 2 (Q n^d + Q^2 n^(d-1) + ... + Q^d n), and the collocation
+        gradient and its transpose, 2 x 2 d Q^(d+1);
+      per element: 250 flops per volume point (Euler and viscous fluxes),
+        900 per face point of its d own faces (Riemann flux and the
+        interior-penalty terms);
+      curved elements add the metric products of the gradients and fluxes,
+        2 x 2 d^2 (d+2) per volume point, and the dense inverse mass matrix,
+        2 (d+2) n^(2d);
+    bytes: the state in and R out (16 per unknown) and, on curved elements,
+    the stored per-point metrics and inverse mass matrices."""
+    d, n, Q = cfg.dim, cfg.P + 1, cfg.nq
+    nv = d + 2
+    tr = 2 * sum(Q ** k * n ** (d - k + 1) for k in range(1, d + 1))
+    per_var = 2 * tr + 2 * (2 * d * Q ** (d + 1))
+    per_elem = nv * per_var + 250 * Q ** d + 900 * d * Q ** (d - 1)
+    nm, nq, nqf = n ** d, Q ** d, Q ** (d - 1)
+    byts = 16.0 * n_elem * nv * nm
+    if cfg.geometry == "annulus":
+        per_elem += 4 * d * d * nv * nq + 2 * nv * nm * nm
+        byts += 8.0 * n_elem * ((d * d + 1) * nq + 2 * d * (d * d + d + 1) * nqf + nm * nm)
+    return per_elem * n_elem, byts
+
+
+def residual_roofline(cfg, n_elem, res_ms):
+    flops, byts = residual_algorithmic(cfg, n_elem)
+    t = res_ms * 1e-3
+    out = {"bound": "alu", "kernel": "residual (k_res_vol + k_res_face + k_res_lift)",
+           "achieved": flops / t / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": flops / t / 1e12 / FP64_PEAK_TFLOPS, "algorithmic_flops": flops,
+           "compulsory_bytes": byts, "hbm_GBps_compulsory": byts / t / 1e9,
+           "hbm_frac_compulsory": byts / t / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": res_ms,
+           "counted": None}
+    rec = residual_counters(cfg.name)
+    if rec is not None:
+        out["counted"] = {k: rec[k] for k in ("traffic_bytes", "fp64_flops") if k in rec}
+        if "traffic_bytes" in rec:
+            out["counted"]["traffic_over_compulsory"] = rec["traffic_bytes"] / byts
+        if "fp64_flops" in rec:
+            out["counted"]["fp64_TFLOPs"] = rec["fp64_flops"] / t / 1e12
+            out["counted"]["fp64_frac"] = rec["fp64_flops"] / t / 1e12 / FP64_PEAK_TFLOPS
+    return out
+
+
+def time_apply(ctx, q, o, stream, reps, J):
+    """Median over 3 repeats of (reps back-to-back BRJ applies) / (reps J):
+    the average sweep launch (plus, on curved meshes, 1/J of the apply's one
+    mass-matrix product), with HIP events on the context's stream."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        ctx.precond_apply(q, o)
+    times = []
+    for _ in range(3):
+        ev0.record(stream)
+        for _ in range(reps):
+            ctx.precond_apply(q, o)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / (reps * J))
+    return sorted(times)[1]
 
 
 def main():
@@ -191,20 +339,21 @@ def main():
     cfg = dataclasses.replace(cfg, **{k: v for k, v in over.items() if v is not None and v != ""})
     mesh = cfg.mesh()
     dt = cfg.dt()
+    curved = cfg.geometry == "annulus"
     log(f"workload {cfg.name}: {mesh.n_elem} elements, P={cfg.P}, dt={dt:.4f}, pc={cfg.pc_precision}")
-
     kinds, states = cfg.boundary()
 
-    def make(prec):
-        ctx = Context(mesh, cfg, pc_precision=prec, bc_kind=kinds, bc_state=states)
+    def make(prec, c=cfg, m=mesh):
+        k, st = c.boundary()
+        ctx = Context(m, c, pc_precision=prec, bc_kind=k, bc_state=st)
         u = ctx.empty()
-        if cfg.geometry == "annulus":
+        if c.geometry == "annulus":
             # fluid at rest plus seeded noise; the far field sets it moving
-            u.copy_(torch.tensor(W.freestream_state(cfg, mesh.n_elem, at_rest=True), dtype=torch.float64,
+            u.copy_(torch.tensor(W.freestream_state(c, m.n_elem, at_rest=True), dtype=torch.float64,
                                  device="cuda"))
         else:
-            noise = torch.tensor(W.noise(ctx.shape, cfg.seed), dtype=torch.float64, device="cuda")
-            ctx.project_tgv(noise, cfg.noise_amp, u)
+            noise = torch.tensor(W.noise(ctx.shape, c.seed), dtype=torch.float64, device="cuda")
+            ctx.project_tgv(noise, c.noise_amp, u)
         return ctx, u
 
     if args.mode == "copy":
@@ -215,7 +364,10 @@ def main():
         torch.cuda.synchronize()
         log("copied 3 x 1 GiB")
         return
+    t_setup = time.perf_counter()
     ctx, u = make(cfg.pc_precision)
+    torch.cuda.synchronize()
+    log(f"context created in {time.perf_counter() - t_setup:.1f} s")
     stream = torch.cuda.current_stream()
     if args.mode == "residual":
         R = ctx.empty()
@@ -238,7 +390,7 @@ def main():
     tuned, tune_ms = ctx.autotune(u, reps=10)
     log(f"autotuned residual workgroups (volume, face, lift): {tuned}")
 
-    # ---- residual kernel throughput (inputs resident, back-to-back launches)
+    # ---- residual throughput (the metric): inputs resident, back-to-back launches
     R = ctx.empty()
     for _ in range(10):
         ctx.residual(u, R)
@@ -252,20 +404,30 @@ def main():
         torch.cuda.synchronize()
         times.append(ev0.elapsed_time(ev1) / args.kernel_reps)
     res_ms = sorted(times)[2]
-    log(f"residual kernel {res_ms:.4f} ms (median of 5 x {args.kernel_reps}; "
-        f"{min(times):.4f}-{max(times):.4f})")
+    log(f"residual {res_ms:.4f} ms (median of 5 x {args.kernel_reps}; {min(times):.4f}-{max(times):.4f})")
+    # Jacobian-free matvec (one residual at u + eps v plus the eps reduction)
+    dt_a = dt * _lam(cfg.scheme)
+    Nu = ctx.empty()
+    ctx.stage_residual(u, u, dt_a, Nu)
+    v = torch.tensor(W.random_vector(mesh.n_elem, cfg.dim, cfg.P, seed=5), dtype=torch.float64, device="cuda")
+    Jv = ctx.empty()
+    for _ in range(3):
+        ctx.jfnk_matvec(u, Nu, u, dt_a, v, 0.0, Jv)
+    reps_mv = max(10, args.kernel_reps // 2)
+    ev0.record(stream)
+    for _ in range(reps_mv):
+        ctx.jfnk_matvec(u, Nu, u, dt_a, v, 0.0, Jv)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / reps_mv
+    del Nu, v, Jv
+    log(f"matvec {mv_ms:.4f} ms (includes the eps reduction)")
 
-    if cfg.geometry == "annulus" and not args.cylinder_steps:
-        line = cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream)
-        line["residual_kernel"]["workgroups"] = dict(zip(("volume", "face", "lift"), tuned))
-        print(json.dumps(line), flush=True)
-        return
-
-    # ---- warmup steps (the cylinder starts impulsively: its warmup steps ramp
+    # ---- warmup steps (the cylinder starts from rest: its warmup steps ramp
     # dt geometrically from dt/100 up to dt)
     for i in range(args.warmup):
         dti = dt
-        if cfg.geometry == "annulus":
+        if curved:
             dti = dt * 0.01 ** (1.0 - i / max(1, args.warmup - 1)) if args.warmup > 1 else dt * 0.01
         st = ctx.sdirk_step(u, dti)     # rebuilds the preconditioner when dt a^mm changes
         log(f"warmup step {i} (dt {dti:.4g}): newton {st['newton_its']} gmres {st['gmres_its']} "
@@ -276,7 +438,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tb0 = time.perf_counter()
-    ctx.precond_build(u, dt * _lam(cfg.scheme))
+    ctx.precond_build(u, dt_a)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - tb0) * 1e3
     stats = []
@@ -289,92 +451,60 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    value = cfg.dofs() * evals / wall
 
     # ---- dominant kernel: BRJ sweep (block-inverse GEMV + off-diagonal product)
     q = R.clone()
     o = ctx.empty()
-    for _ in range(3):
-        ctx.precond_apply(q, o)
-    reps = max(5, args.kernel_reps // 10)
-    times = []
-    for _ in range(3):
-        ev0.record(stream)
-        for _ in range(reps):
-            ctx.precond_apply(q, o)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        times.append(ev0.elapsed_time(ev1) / (reps * cfg.brj_sweeps))
-    sweep_ms = sorted(times)[1]
+    sweep_ms = time_apply(ctx, q, o, stream, max(3, args.kernel_reps // 20), cfg.brj_sweeps)
     sb = sweep_bytes(ctx, cfg, cfg.pc_precision)
     achieved = sb / (sweep_ms * 1e-3) / 1e9
     log(f"BRJ sweep {sweep_ms:.4f} ms, {achieved:.0f} GB/s")
 
     out = {
         "metric": "DG residual DOFs/s + implicit-step time, mixed/learned vs plain FP64 @1e-8",
-        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "value": cfg.dofs() / (res_ms * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg.name, "elements": mesh.n_elem, "P": cfg.P, "nq": cfg.nq, "dim": cfg.dim,
                    "dofs_per_var": cfg.dofs(), "unknowns": ctx.n_unknowns, "scheme": cfg.scheme,
                    "cfl": cfg.cfl, "dt": dt, "Re": cfg.Re, "Ma": cfg.Ma, "newton_rtol": cfg.newton_rtol,
                    "gmres": f"GMRES({cfg.gmres_restart}) rtol {cfg.gmres_rtol}, {cfg.ortho}",
                    "brj_sweeps": cfg.brj_sweeps, "pc_precision": cfg.pc_precision, "pc_freeze": cfg.pc_freeze,
-                   "pc_refresh_its": cfg.pc_refresh_its},
+                   "pc_refresh_its": cfg.pc_refresh_its,
+                   "geometry": "curved isoparametric O-grid, no-slip wall + far field" if curved
+                   else "periodic affine boxes"},
         "roofline": {"bound": "hbm", "kernel": "k_brj_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(cfg.pc_precision) if args.workload == 2 else None,
+                     "traffic": measured_traffic(cfg.pc_precision, cfg.name),
                      "bytes_per_launch": sb, "avg_launch_ms": sweep_ms},
+        "residual_roofline": residual_roofline(cfg, mesh.n_elem, res_ms),
         "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3),
+                            "unknowns_per_s": ctx.n_unknowns / (res_ms * 1e-3),
                             "workgroups": dict(zip(("volume", "face", "lift"), tuned))},
+        "matvec": {"ms": mv_ms, "dofs_per_s": cfg.dofs() / (mv_ms * 1e-3)},
+        "delivered_residual_dofs_per_s": cfg.dofs() * evals / wall,
         "pc_build_ms": build_ms,
         "residual_evals": evals,
         "newton_its": [s["newton_its"] for s in stats],
         "gmres_its": [s["gmres_its"] for s in stats],
     }
 
-    if not args.no_forms and cfg.geometry != "annulus":
-        base_u = None
-        forms = {}
-        for prec in ("f64", "f32", "bf16"):
-            c2, u2 = make(prec)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            its = []
-            for i in range(min(args.steps, 3)):
-                st = c2.sdirk_step(u2, dt)
-                its.append(st["newton_its"])
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t) * 1e3 / min(args.steps, 3)
-            uh = u2.cpu().numpy()
-            if base_u is None:
-                base_u = uh
-            # the form's sweep: same launches as in its steps, its own block bytes
-            qf, of = c2.empty(), c2.empty()
-            qf.copy_(q)
-            c2.precond_apply(qf, of)
-            ev0.record(stream)
-            for _ in range(5):
-                c2.precond_apply(qf, of)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            sw_ms = ev0.elapsed_time(ev1) / (5 * cfg.brj_sweeps)
-            sw_gbs = sweep_bytes(c2, cfg, prec) / (sw_ms * 1e-3) / 1e9
-            forms[prec] = {"ms_per_step": ms, "newton_its": its,
-                           "rel_diff_vs_f64": float(np.linalg.norm(uh - base_u) / np.linalg.norm(base_u)),
-                           "sweep_ms": sw_ms, "sweep_GBps": sw_gbs, "sweep_frac_hbm": sw_gbs / HBM_PEAK_GBS,
-                           "sweep_traffic": measured_traffic(prec) if args.workload == 2 else None}
-            c2.close()
-            log(f"form {prec}: {ms:.1f} ms/step, sweep {sw_ms:.4f} ms {sw_gbs:.0f} GB/s")
-        for prec in forms:
-            forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
-        out["forms"] = forms
+    if not args.no_forms:
+        out["forms"] = bench_forms(ctx, u, cfg, dt, stream, args.form_steps)
+        ctx.close()
+        del ctx, q, o, R
+        torch.cuda.empty_cache()
+        if args.workload != 2:
+            out["forms_tgv3d-16c-p3"] = bench_forms_tgv(args)
 
     if not args.no_explicit:
         out["explicit_erk2"] = bench_explicit(cfg, mesh, u_start, u, wall * 1e3, args.steps * dt, kinds, states)
+    del u_start
 
-    if args.learned:
-        out["learned"] = bench_learned(cfg, make, args.learned_train, args.learned_held, args.learned_epochs)
+    if not args.no_learned:
+        lcfg = W.config(args.learned_workload)
+        out["learned"] = bench_learned(lcfg, lambda prec: make(prec, lcfg, lcfg.mesh()), args.learned_train,
+                                       args.learned_held, args.learned_epochs)
 
     if args.batch:
         out["batch"] = bench_batch(args.batch_steps)
@@ -386,6 +516,100 @@ def main():
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
+
+
+def bench_forms(ctx, u_end, cfg, dt, stream, nsteps):
+    """The precision forms on this workload's context: from the state after
+    the timed steps, the blocks built and stored in FP64, FP32 and BF16 in
+    turn, then nsteps steps each; steps (build excluded), the build, the
+    sweep's rate on the form's block bytes, and the state difference against
+    the FP64 form (device against device; the tests compare each form's step
+    with the FP64 oracle)."""
+    import torch
+    dt_a = dt * _lam(cfg.scheme)
+    forms = {}
+    base = None
+    for prec in ("f64", "f32", "bf16"):
+        ctx.set_pc_precision(prec)
+        uu = u_end.clone()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ctx.precond_build(uu, dt_a)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - tb) * 1e3
+        t = time.perf_counter()
+        its, gits = [], []
+        for _ in range(nsteps):
+            st = ctx.sdirk_step(uu, dt)
+            its.append(st["newton_its"])
+            gits.append(st["gmres_its"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / nsteps
+        if base is None:
+            base = uu.clone()
+        q, o = ctx.empty(), ctx.empty()
+        q.copy_(u_end)
+        sw_ms = time_apply(ctx, q, o, stream, 3, cfg.brj_sweeps)
+        sw_gbs = sweep_bytes(ctx, cfg, prec) / (sw_ms * 1e-3) / 1e9
+        forms[prec] = {"ms_per_step": ms, "build_ms": bms, "newton_its": its, "gmres_its": gits,
+                       "rel_diff_vs_f64_device": float(torch.linalg.vector_norm(uu - base) /
+                                                       torch.linalg.vector_norm(base)),
+                       "sweep_ms": sw_ms, "sweep_GBps": sw_gbs, "sweep_frac_hbm": sw_gbs / HBM_PEAK_GBS,
+                       "sweep_traffic": measured_traffic(prec, cfg.name)}
+        del q, o, uu
+        log(f"form {prec}: build {bms:.1f} ms, {ms:.1f} ms/step, newton {its}, sweep {sw_ms:.4f} ms "
+            f"{sw_gbs:.0f} GB/s")
+    for prec in forms:
+        forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
+    ctx.set_pc_precision(cfg.pc_precision)
+    return forms
+
+
+def bench_forms_tgv(args):
+    """The precision forms on the 16^3 P = 3 Taylor-Green cube (SDIRK3 at
+    CFL 20): 3 steps with each storage precision from the projected start."""
+    import dataclasses
+    import torch
+    import workloads as W
+    from paper_2002_04222_amd import Context
+    cfg = W.config(2)
+    mesh = cfg.mesh()
+    dt = cfg.dt()
+    forms = {}
+    base = None
+    q = None
+    stream = torch.cuda.current_stream()
+    for prec in ("f64", "f32", "bf16"):
+        ctx = Context(mesh, cfg, pc_precision=prec)
+        u = ctx.empty()
+        ctx.project_tgv(torch.tensor(W.noise(ctx.shape, cfg.seed), dtype=torch.float64, device="cuda"),
+                        cfg.noise_amp, u)
+        if q is None:
+            q = ctx.empty()
+            ctx.residual(u, q)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for _ in range(3):
+            its.append(ctx.sdirk_step(u, dt)["newton_its"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / 3
+        if base is None:
+            base = u.clone()
+        o = ctx.empty()
+        sw_ms = time_apply(ctx, q, o, stream, 5, cfg.brj_sweeps)
+        sw_gbs = sweep_bytes(ctx, cfg, prec) / (sw_ms * 1e-3) / 1e9
+        forms[prec] = {"ms_per_step": ms, "newton_its": its,
+                       "rel_diff_vs_f64_device": float(torch.linalg.vector_norm(u - base) /
+                                                       torch.linalg.vector_norm(base)),
+                       "sweep_ms": sw_ms, "sweep_GBps": sw_gbs, "sweep_frac_hbm": sw_gbs / HBM_PEAK_GBS,
+                       "sweep_traffic": measured_traffic(prec, cfg.name)}
+        ctx.close()
+        log(f"tgv3d form {prec}: {ms:.1f} ms/step (3 steps incl. the first build), sweep {sw_ms:.4f} ms "
+            f"{sw_gbs:.0f} GB/s")
+    for prec in forms:
+        forms[prec]["speedup_vs_f64"] = forms["f64"]["ms_per_step"] / forms[prec]["ms_per_step"]
+    return forms
 
 
 def bench_explicit(cfg, mesh, u_start, u_impl, impl_ms, T, kinds, states):
@@ -707,56 +931,6 @@ def bench_learned(cfg, make, n_train, held, epochs=150):
                      "speedup_vs_paper_guess": res["paper"]["ms_per_step"] / r["ms_per_step"],
                      "rel_diff_vs_paper_guess": float(torch.linalg.norm(r["u"] - base) / torch.linalg.norm(base))}
     ctx.close()
-    return out
-
-
-def cylinder_line(args, cfg, mesh, ctx, u, R, res_ms, stream):
-    """The curved cylinder workload: residual and Jacobian-free matvec
-    throughput.  Implicit steps are timed only with --cylinder-steps: at
-    P=4 the FP64 BRJ blocks (625 x 625, 51 GB) do not fit on chip and their
-    explicit inversion streams the blocks many times over."""
-    import torch
-    import workloads as W
-    dt_a = cfg.dt() * _lam(cfg.scheme)
-    Nu = ctx.empty()
-    ctx.stage_residual(u, u, dt_a, Nu)
-    v = torch.tensor(W.random_vector(mesh.n_elem, cfg.dim, cfg.P, seed=5), dtype=torch.float64, device="cuda")
-    Jv = ctx.empty()
-    for _ in range(3):
-        ctx.jfnk_matvec(u, Nu, u, dt_a, v, 0.0, Jv)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.kernel_reps):
-        ctx.jfnk_matvec(u, Nu, u, dt_a, v, 0.0, Jv)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    mv_ms = ev0.elapsed_time(ev1) / args.kernel_reps
-    log(f"matvec {mv_ms:.4f} ms (includes the eps reduction)")
-    E, n = mesh.n_elem, ctx.n_unknowns
-    nm, nq, nqf = (cfg.P + 1) ** cfg.dim, cfg.nq ** cfg.dim, cfg.nq ** (cfg.dim - 1)
-    d = cfg.dim
-    # compulsory bytes of one residual: state in, R out, volume and face
-    # metrics, dense M^-1
-    rb = 8 * (2 * n + E * (d * d + 1) * nq + E * 2 * d * (d * d + d + 1) * nqf + E * nm * nm)
-    ach = rb / (res_ms * 1e-3) / 1e9
-    out = {
-        "metric": "DG residual DOFs/s + implicit-step time, mixed/learned vs plain FP64 @1e-8",
-        "value": cfg.dofs() / (res_ms * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": 0,
-        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": cfg.name, "elements": E, "P": cfg.P, "nq": cfg.nq, "dim": d,
-                   "dofs_per_var": cfg.dofs(), "unknowns": n, "Re": cfg.Re, "Ma": cfg.Ma,
-                   "geometry": "curved isoparametric O-grid, no-slip wall + far field"},
-        "roofline": {"bound": "hbm", "kernel": "residual (k_res_vol + k_res_face + k_res_lift)", "achieved": ach,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": rb, "avg_launch_ms": res_ms},
-        "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3)},
-        "matvec": {"ms": mv_ms, "dofs_per_s": cfg.dofs() / (mv_ms * 1e-3)},
-        "note": "value = residual evaluations' DOF/s; implicit steps not timed on this workload",
-    }
-    if not args.no_cpu_baseline:
-        log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(cfg)
     return out
 
 
