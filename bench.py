@@ -19,8 +19,8 @@ the state resident in HBM), ms_per_step = implicit-step time; the dominant
 kernel's roofline (the BRJ sweep), the residual's own roofline, the DOF/s
 the timed steps deliver, the precision forms (FP64 / FP32 / BF16 blocks) on
 this workload and on the 16^3 P = 3 Taylor-Green cube, the learned Newton
-guess on the 2D Taylor-Green workload, the explicit ERK2 comparison, and the
-CPU oracle baseline.
+guess on the 2D Taylor-Green workload, and the CPU oracle baseline (the
+explicit ERK2 comparison with --explicit).
 """
 from __future__ import annotations
 
@@ -74,9 +74,9 @@ def parse():
                          "against ERK2 at its largest stable CFL, both to steady state, P = 2, 3, 4")
     ap.add_argument("--mms-n", type=int, default=8, help="elements per direction of the manufactured case")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-explicit", action="store_true",
-                    help="skip the explicit ERK2 comparison (its largest stable CFL and its time to reach the "
-                         "same physical time as the timed implicit steps)")
+    ap.add_argument("--explicit", action="store_true",
+                    help="also run the explicit ERK2 comparison (its largest stable CFL and its time to reach the "
+                         "same physical time as the timed implicit steps; 2-3 minutes on the cylinder)")
     ap.add_argument("--kernel-reps", type=int, default=100,
                     help="back-to-back residual evaluations per timing repeat (median of 5 repeats)")
     ap.add_argument("--mode", default="full", choices=["full", "sweep", "copy", "residual"],
@@ -497,7 +497,7 @@ def main():
         if args.workload != 2:
             out["forms_tgv3d-16c-p3"] = bench_forms_tgv(args)
 
-    if not args.no_explicit:
+    if args.explicit:
         out["explicit_erk2"] = bench_explicit(cfg, mesh, u_start, u, wall * 1e3, args.steps * dt, kinds, states)
     del u_start
 

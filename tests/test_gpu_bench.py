@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_bench_json_contract():
     print("[case] bench.py --workload 1 --steps 2", flush=True)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "1", "--steps", "2",
-                        "--warmup", "1", "--no-forms", "--no-explicit", "--no-cpu-baseline", "--no-learned",
+                        "--warmup", "1", "--no-forms", "--no-cpu-baseline", "--no-learned",
                         "--kernel-reps", "10"],
                        capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
