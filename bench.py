@@ -283,7 +283,7 @@ def residual_algorithmic(cfg, n_elem):
 def residual_roofline(cfg, n_elem, res_ms):
     flops, byts = residual_algorithmic(cfg, n_elem)
     t = res_ms * 1e-3
-    out = {"bound": "alu", "kernel": "residual (k_res_vol + k_res_face + k_res_lift)",
+    out = {"bound": "alu", "kernel": "k_res_fused",
            "achieved": flops / t / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
            "frac": flops / t / 1e12 / FP64_PEAK_TFLOPS, "algorithmic_flops": flops,
            "compulsory_bytes": byts, "hbm_GBps_compulsory": byts / t / 1e9,
@@ -386,25 +386,35 @@ def main():
             f"algorithmic bytes per sweep")
         return
 
-    # ---- workgroup sizes of the residual kernels by the autotuner
-    tuned, tune_ms = ctx.autotune(u, reps=10)
-    log(f"autotuned residual workgroups (volume, face, lift): {tuned}")
-
-    # ---- residual throughput (the metric): inputs resident, back-to-back launches
+    # ---- residual throughput (the metric): inputs resident, back-to-back
+    # launches; the fused kernel (the library's default), and for comparison
+    # the three-kernel path with the per-point traces and face fluxes staged
+    # in HBM; each with its workgroup sizes by the autotuner
     R = ctx.empty()
-    for _ in range(10):
-        ctx.residual(u, R)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(5):
-        ev0.record(stream)
-        for _ in range(args.kernel_reps):
+
+    def time_residual():
+        for _ in range(10):
             ctx.residual(u, R)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        times.append(ev0.elapsed_time(ev1) / args.kernel_reps)
-    res_ms = sorted(times)[2]
-    log(f"residual {res_ms:.4f} ms (median of 5 x {args.kernel_reps}; {min(times):.4f}-{max(times):.4f})")
+        times = []
+        for _ in range(5):
+            ev0.record(stream)
+            for _ in range(args.kernel_reps):
+                ctx.residual(u, R)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1) / args.kernel_reps)
+        return sorted(times)[2], min(times), max(times)
+
+    ctx.set_residual_kernels(False)
+    tuned3, _ = ctx.autotune(u, reps=10)
+    res3_ms, _, _ = time_residual()
+    log(f"three-kernel residual {res3_ms:.4f} ms (workgroups volume, face, lift {tuned3})")
+    ctx.set_residual_kernels(True)
+    tuned, tune_ms = ctx.autotune(u, reps=10)
+    res_ms, tmin, tmax = time_residual()
+    log(f"fused residual {res_ms:.4f} ms (median of 5 x {args.kernel_reps}; {tmin:.4f}-{tmax:.4f}; "
+        f"workgroup {tuned[0]})")
     # Jacobian-free matvec (one residual at u + eps v plus the eps reduction)
     dt_a = dt * _lam(cfg.scheme)
     Nu = ctx.empty()
@@ -478,9 +488,11 @@ def main():
                      "traffic": measured_traffic(cfg.pc_precision, cfg.name),
                      "bytes_per_launch": sb, "avg_launch_ms": sweep_ms},
         "residual_roofline": residual_roofline(cfg, mesh.n_elem, res_ms),
-        "residual_kernel": {"ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3),
-                            "unknowns_per_s": ctx.n_unknowns / (res_ms * 1e-3),
-                            "workgroups": dict(zip(("volume", "face", "lift"), tuned))},
+        "residual_kernel": {"kernel": "k_res_fused", "ms": res_ms, "dofs_per_s": cfg.dofs() / (res_ms * 1e-3),
+                            "unknowns_per_s": ctx.n_unknowns / (res_ms * 1e-3), "workgroup": tuned[0],
+                            "three_kernel_ms": res3_ms,
+                            "three_kernel_workgroups": dict(zip(("volume", "face", "lift"), tuned3)),
+                            "speedup_vs_three_kernel": res3_ms / res_ms},
         "matvec": {"ms": mv_ms, "dofs_per_s": cfg.dofs() / (mv_ms * 1e-3)},
         "delivered_residual_dofs_per_s": cfg.dofs() * evals / wall,
         "pc_build_ms": build_ms,

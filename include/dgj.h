@@ -210,18 +210,31 @@ const char *dgj_last_error(const dgj_ctx *ctx);
  * NULL.  u: output state. */
 int dgj_project_tgv(dgj_ctx *ctx, const double *noise, double noise_amp, double *u);
 
-/* R = M^-1 L(u)  (Eq. 13). */
+/* R = M^-1 L(u)  (Eq. 13).  The interior-penalty residual is evaluated by
+ * one fused kernel (one workgroup per element: volume terms, the modal face
+ * traces of the element and of its neighbours, the face fluxes in each
+ * face's canonical orientation -- every interior face by both of its
+ * elements, with bitwise the same result, so element sums still cancel
+ * exactly -- lifting and M^-1), the LDG residual by a volume, a face-flux and
+ * a lift kernel with the traces and face fluxes staged in the context's
+ * scratch. */
 int dgj_residual(dgj_ctx *ctx, const double *u, double *R);
-/* Autotuner of the residual's workgroup shapes (not in the paper; the
- * residual is evaluated by a volume, a face-flux and a lift kernel).  Times
- * each kernel alone at state u with workgroups of 64, 128 and 256 threads,
- * reps launches each (its other inputs left in place by one evaluation),
- * and keeps the fastest for every later evaluation on this context.
- * chosen: host [3] (volume, face, lift) or NULL; times_ms: host [3][3]
- * ([kernel][64, 128, 256]) or NULL.  Results are unchanged (the kernels
- * sum in the same order for every workgroup size) except on curved meshes,
- * where the M^-1 product's partial sums follow the workgroup size.
- * Synchronises the stream.  Not for batch groups (dgj_batch_autotune). */
+/* Evaluate the interior-penalty residual with the fused kernel (1, the
+ * default) or with the three kernels (0), for comparisons: the two agree to
+ * rounding (different summation orders of the traces). */
+int dgj_set_residual_kernels(dgj_ctx *ctx, int32_t fused);
+/* Autotuner of the residual's workgroup shapes (not in the paper).  Fused
+ * kernel: times it at state u with every workgroup size from the smallest
+ * multiple of 64 with a thread per face point up to 256, reps launches
+ * each, and keeps the fastest; chosen = {size, 0, 0}, times_ms[i] = the i-th
+ * size's time.  Three kernels (LDG): times each kernel alone with
+ * workgroups of 64, 128 and 256 threads (its other inputs left in place by
+ * one evaluation) and keeps the fastest per kernel; chosen: (volume, face,
+ * lift), times_ms [kernel][64, 128, 256].  chosen: host [3] or NULL;
+ * times_ms: host [3][3] or NULL.  Results are unchanged (the kernels sum in
+ * the same order for every workgroup size) except on curved meshes, where
+ * the M^-1 product's partial sums follow the workgroup size.  Synchronises
+ * the stream.  Not for batch groups (dgj_batch_autotune). */
 int dgj_autotune(dgj_ctx *ctx, const double *u, int32_t reps, int32_t *chosen, double *times_ms);
 
 /* N = u - S - dt_a M^-1 L(u)  (Eq. 20), dt_a = dt a^mm. */

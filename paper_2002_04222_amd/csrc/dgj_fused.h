@@ -1,0 +1,456 @@
+// Fused DG residual R(u) = M^-1 L(u) of arxiv 2002.04222 (Sec. 3.1, Eq. 13)
+// for the interior-penalty form: one workgroup per element, one kernel, and
+// nothing in HBM but the state read (the element's own coefficients, and its
+// face neighbours' through the L2) and the result written.
+//
+// Phases, separated by workgroup barriers, on LDS:
+//   volume  sum-factorised values and reference gradients at the Gauss
+//           points, pointwise H_j = F_j - G_j, transposed contraction with
+//           the derivative bases -> sL (as the three-kernel path).
+//   traces  modal face traces of both sides of every face: the value
+//           sum_i phi_i(+-1) u and the normal derivative sum_i phi_i'(+-1) u
+//           over the normal index (n^(d-1) coefficients each per variable),
+//           computed from the modal coefficients of the element and of its
+//           neighbour by the same code; then, tangentially, values and
+//           reference gradients at the face points.
+//   fluxes  one thread per face point: Riemann flux and interior-penalty
+//           terms (Eq. 12) in the face's canonical orientation (left = the
+//           element that meets it with side 1, its normal and weights), so
+//           that the two elements of an interior face compute bitwise the
+//           same flux and the element sums cancel exactly, as when each face
+//           is computed once; boundary faces in the element's orientation.
+//   lift    -phi H_own + grad phi . S over the 2d faces, sum-factorised to
+//           face modes and expanded along the normal index, added to sL;
+//           times 1/|J| (orthonormal basis on affine elements) or the dense
+//           M_e^-1 (curved elements), then the R / N / Jv epilogue.
+// Each interior face flux is evaluated by both of its elements (twice the
+// face arithmetic of the three-kernel path), which replaces the round trips
+// of the per-point traces and face fluxes through HBM.
+#pragma once
+#include "dgj_residual.h"
+
+namespace dgj {
+
+template <int D, int N, int Q>
+struct FusedK {
+  using K = ResK<D, N, Q>;
+  static constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NMF = K::NMF, NF = K::NF, NB = K::NB;
+  static constexpr int VOL = K::T1 + K::T2 + K::QG;                    // volume phase (W + sQ)
+  static constexpr int TR = 2 * NF * 2 * NV * NMF;                     // modal traces [side][f][kind][v][tm]
+  static constexpr int SA = (D == 3) ? 2 * NF * 3 * NV * Q * N : 0;    // first tangential stage [side][f][c][v][a][j]
+  static constexpr int AF = NF * (D + 1) * NV * NQF;                   // weighted face data [f][k][v][p]
+  static constexpr int Y = (D == 3) ? NF * NV * Q * 3 * N : 0;         // lift, first stage [f][v][a][c][j]
+  static constexpr int FM = NF * 2 * NV * NMF;                         // face modes [f][c][v][tm]
+  static constexpr int FACE = TR + SA;
+  static constexpr int LIFT = AF + Y + FM;
+  static constexpr int U1 = VOL > FACE ? VOL : FACE;
+  static constexpr int U = U1 > LIFT ? U1 : LIFT;
+  static constexpr int NPTS = NF * NQF;   // face points: one thread each in the flux phase
+};
+
+// smallest workgroup of the fused kernel: a multiple of 64 with a thread per face point
+template <int D, int N, int Q>
+constexpr int fused_min_threads() { return ((FusedK<D, N, Q>::NPTS + 63) / 64) * 64; }
+
+template <int D, int N, int Q, bool CV>
+__global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
+  using F = FusedK<D, N, Q>;
+  using K = ResK<D, N, Q>;
+  constexpr int NV = F::NV, NM = F::NM, NQF = F::NQF, NMF = F::NMF, NF = F::NF, NB = F::NB;
+  constexpr int CF = D * D + D + 1;
+  constexpr int GEO = K::S::GEO;
+  __shared__ double sU[NB];
+  __shared__ double sL[NB];
+  __shared__ double WS[F::U];
+  __shared__ double sE[4 * N];         // phi(-1), phi(+1), phi'(-1), phi'(+1)
+  __shared__ double sB[Q * N], sD[Q * N], sW[Q];
+  __shared__ long s_nb[NF];
+  const long e = blockIdx.x;
+  if (e >= a.n_elem) return;
+  ElemParams ep;
+  if (!elem_params(a, e, ep)) return;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  const double* g = a.geo + e * GEO;
+  double dxi[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dxi[j] = g[j];
+  const double detJ = g[D];
+  for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
+  if (tid < NF) s_nb[tid] = a.nbr[e * NF + tid];
+  if (tid < 2 * N) {
+    sE[tid] = tk.phiE[tid / N][tid % N];
+    sE[2 * N + tid] = tk.dphiE[tid / N][tid % N];
+  }
+  for (int i = tid; i < Q * N; i += NT) {
+    sB[i] = tk.B[i / N][i % N];
+    sD[i] = tk.Dq[i / N][i % N];
+  }
+  if (tid < Q) sW[tid] = tk.w[tid];
+  __syncthreads();
+
+  // ---- volume terms -> sL
+  {
+    double* W = WS;
+    double* sQ = WS + K::T1 + K::T2;
+    res_vol_forward<D, N, Q>(tk, sU, W, sQ);
+    __syncthreads();
+    res_vol_flux<D, N, Q, CV>(a, tk, ep, e, dxi, detJ, sQ);
+    __syncthreads();
+    res_vol_transpose<D, N, Q>(tk, sQ, W, sL);
+    __syncthreads();
+  }
+
+  // ---- modal face traces of both sides: TR[side][f][kind][v][tm]
+  double* TR = WS;
+  double* SA = WS + F::TR;
+  for (int it = tid; it < 2 * NF * NV * NMF; it += NT) {
+    const int tm = it % NMF;
+    const int v = (it / NMF) % NV;
+    const int f = (it / (NMF * NV)) % NF;
+    const int side = it / (NMF * NV * NF);
+    const long en = s_nb[f];
+    const int ax = f >> 1;
+    // side 0: this element on face f; side 1: the neighbour on its face f^1
+    const int ss = (f & 1) ^ side;
+    double tv = 0.0, tn = 0.0;
+    if (side == 0 || en >= 0) {
+      for (int ia = 0; ia < N; ++ia) {
+        const int m = mode_of<D, N>(ax, ia, tm);
+        const double x = side == 0 ? sU[v * NM + m] : ep.in(en * NB + v * NM + m);
+        tv += sE[ss * N + ia] * x;
+        tn += sE[2 * N + ss * N + ia] * x;
+      }
+    }
+    TR[((side * NF + f) * 2 + 0) * NV * NMF + v * NMF + tm] = tv;
+    TR[((side * NF + f) * 2 + 1) * NV * NMF + v * NMF + tm] = tn;
+  }
+  __syncthreads();
+  if constexpr (D == 3) {
+    // first tangential direction t0: SA[side][f][c][v][a][j], c = 0: B tv,
+    // 1: Dq tv, 2: B tn (tm = i + N j, i along t0)
+    for (int it = tid; it < 2 * NF * NV * N; it += NT) {
+      const int j = it % N;
+      const int v = (it / N) % NV;
+      const int sf = it / (N * NV);           // side * NF + f
+      const double* tv = TR + (sf * 2 + 0) * NV * NMF + v * NMF + N * j;
+      const double* tn = TR + (sf * 2 + 1) * NV * NMF + v * NMF + N * j;
+      double xv[N], xn[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) { xv[i] = tv[i]; xn[i] = tn[i]; }
+      double* o = SA + (sf * 3 * NV + v) * Q * N + j;
+#pragma unroll
+      for (int aa = 0; aa < Q; ++aa) {
+        double b0 = 0.0, d0 = 0.0, bn = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          b0 += tk.B[aa][i] * xv[i];
+          d0 += tk.Dq[aa][i] * xv[i];
+          bn += tk.B[aa][i] * xn[i];
+        }
+        o[aa * N] = b0;
+        o[NV * Q * N + aa * N] = d0;
+        o[2 * NV * Q * N + aa * N] = bn;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- face points: both sides' values and physical gradients, the face
+  // flux, and the weighted data the lift contracts: AF[f][k][v][p] with
+  // k = 0: -w H_own, k >= 1: sum_j (d xi_{k-1} / d x_j) w S_j (curved) or
+  // w S_{k-1} dxi_{k-1} (boxes)
+  double Af[D + 1][NV];
+  const bool pt = tid < F::NPTS;
+  const int f = pt ? tid / NQF : 0;
+  const int p = pt ? tid % NQF : 0;
+  if (pt) {
+    const int ax = f >> 1, s = f & 1;
+    int t[2] = {0, 0};
+    tang_axes<D>(ax, t);
+    const int pa = p % Q, pb = (D == 3) ? p / Q : 0;
+    const long en = s_nb[f];
+    double Us[2][NV], Gs[2][D][NV];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 1 && en < 0) break;
+      const long ee = side == 0 ? e : en;
+      const int ff = side == 0 ? f : (f ^ 1);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double val = 0.0, dt0 = 0.0, dt1 = 0.0, dn = 0.0;
+        if constexpr (D == 3) {
+          const double* o = SA + ((side * NF + f) * 3 * NV + v) * Q * N + pa * N;
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            const double bj = sB[pb * N + j];
+            val += bj * o[j];
+            dt0 += bj * o[NV * Q * N + j];
+            dt1 += sD[pb * N + j] * o[j];
+            dn += bj * o[2 * NV * Q * N + j];
+          }
+        } else {
+          const double* tv = TR + ((side * NF + f) * 2 + 0) * NV * NMF + v * NMF;
+          const double* tn = TR + ((side * NF + f) * 2 + 1) * NV * NMF + v * NMF;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            val += sB[pa * N + i] * tv[i];
+            dt0 += sD[pa * N + i] * tv[i];
+            dn += sB[pa * N + i] * tn[i];
+          }
+        }
+        double gr[D];
+        gr[ax] = dn;
+        gr[t[0]] = dt0;
+        if (D == 3) gr[t[1]] = dt1;
+        Us[side][v] = val;
+        if constexpr (CV) {
+          const double* Gp = a.fg + (ee * NF + ff) * (long)CF * NQF + p;
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            double sg = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) sg += Gp[(k * D + j) * NQF] * gr[k];
+            Gs[side][j][v] = sg;
+          }
+        } else {
+          const double* ge = a.geo + ee * GEO;
+#pragma unroll
+          for (int j = 0; j < D; ++j) Gs[side][j][v] = gr[j] * ge[j];
+        }
+      }
+    }
+    double H[NV], Sf[D][NV], nrm[D], wf;
+    if (en >= 0) {
+      // canonical orientation: the side-1 element's normal, weights and penalty
+      const long e1 = s ? e : en;
+      const int f1 = s ? f : (f ^ 1);
+      if constexpr (CV) {
+        const double* Gp = a.fg + (e1 * NF + f1) * (long)CF * NQF + p;
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm[j] = Gp[(D * D + j) * NQF];
+        wf = Gp[(D * D + D) * NQF];
+      } else {
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? 1.0 : 0.0;
+        wf = a.geo[e1 * GEO + D + 2 + ax] * sW[pa];
+        if (D == 3) wf *= sW[pb];
+      }
+      const double beta = a.beta[e1 * NF + f1];
+      // left = the side-1 data: this element's when s = 1 (selected lane by
+      // lane, so that both elements pass bitwise the same arguments)
+      double UL[NV], UR[NV], GL[D][NV], GR[D][NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UL[v] = s ? Us[0][v] : Us[1][v];
+        UR[v] = s ? Us[1][v] : Us[0][v];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          GL[j][v] = s ? Gs[0][j][v] : Gs[1][j][v];
+          GR[j][v] = s ? Gs[1][j][v] : Gs[0][j][v];
+        }
+      }
+      face_flux<D>(ep.ph, UL, UR, GL, GR, nrm, beta, H, Sf);
+      if (!s) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) H[v] = -H[v];
+      }
+    } else {
+      const int bid = -(int)en - 1;
+      const int kind = a.bc_kind[bid];
+      if constexpr (CV) {
+        const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm[j] = Gp[(D * D + j) * NQF];
+        wf = Gp[(D * D + D) * NQF];
+      } else {
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
+        wf = g[D + 2 + ax] * sW[pa];
+        if (D == 3) wf *= sW[pb];
+      }
+      double UD[NV];
+      const double* Ub = a.bc_state + bid * NV;
+      if (kind == BC_DIRICHLET) {
+        const double* gb = a.bc_field + (e * NF + f) * (long)NV * NQF + p;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) UD[v] = gb[v * NQF];
+        Ub = UD;
+      }
+      boundary_flux<D>(ep.ph, kind, Us[0], Gs[0], nrm, a.beta[e * NF + f], Ub, H, Sf);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Af[0][v] = -H[v];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (CV) {
+          const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
+          double sg = 0.0;
+#pragma unroll
+          for (int j = 0; j < D; ++j) sg += Gp[(k * D + j) * NQF] * Sf[j][v];
+          Af[1 + k][v] = sg;
+        } else {
+          Af[1 + k][v] = Sf[k][v] * dxi[k];
+        }
+      }
+    // face weight: w^G |J^G| at the point (boxes: |J^G| times the tensor Gauss weight)
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Af[k][v] *= wf;
+  }
+  __syncthreads();   // traces and first-stage data are dead from here
+  double* AF = WS;
+  double* Yb = WS + F::AF;
+  double* FMb = WS + F::AF + F::Y;
+  if (pt) {
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) AF[((f * (D + 1) + k) * NV + v) * NQF + p] = Af[k][v];
+  }
+  __syncthreads();
+
+  // ---- lift: tangential contraction to face modes FM[f][c][v][tm]
+  // (c = 0 multiplies phi(+-1), c = 1 phi'(+-1) of the normal index)
+  if constexpr (D == 3) {
+    for (int it = tid; it < NF * NV * Q; it += NT) {
+      const int aa = it % Q;
+      const int v = (it / Q) % NV;
+      const int ff = it / (Q * NV);
+      const int ax = ff >> 1;
+      int t[2] = {0, 0};
+      tang_axes<D>(ax, t);
+      const double* A0 = AF + ((ff * (D + 1) + 0) * NV + v) * NQF + aa;
+      const double* At0 = AF + ((ff * (D + 1) + 1 + t[0]) * NV + v) * NQF + aa;
+      const double* At1 = AF + ((ff * (D + 1) + 1 + t[1]) * NV + v) * NQF + aa;
+      const double* Aax = AF + ((ff * (D + 1) + 1 + ax) * NV + v) * NQF + aa;
+      double x0[Q], xt0[Q], xt1[Q], xax[Q];
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        x0[b] = A0[b * Q];
+        xt0[b] = At0[b * Q];
+        xt1[b] = At1[b * Q];
+        xax[b] = Aax[b * Q];
+      }
+      double* o = Yb + ((ff * NV + v) * Q + aa) * 3 * N;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+          y0 += tk.B[b][j] * x0[b] + tk.Dq[b][j] * xt1[b];
+          y1 += tk.B[b][j] * xt0[b];
+          y2 += tk.B[b][j] * xax[b];
+        }
+        o[j] = y0;
+        o[N + j] = y1;
+        o[2 * N + j] = y2;
+      }
+    }
+    __syncthreads();
+    for (int it = tid; it < NF * NV * N; it += NT) {
+      const int j1 = it % N;
+      const int v = (it / N) % NV;
+      const int ff = it / (N * NV);
+      double y0[Q], y1[Q], y2[Q];
+#pragma unroll
+      for (int aa = 0; aa < Q; ++aa) {
+        const double* o = Yb + ((ff * NV + v) * Q + aa) * 3 * N + j1;
+        y0[aa] = o[0];
+        y1[aa] = o[N];
+        y2[aa] = o[2 * N];
+      }
+#pragma unroll
+      for (int j0 = 0; j0 < N; ++j0) {
+        double f0 = 0.0, f1 = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < Q; ++aa) {
+          f0 += tk.B[aa][j0] * y0[aa] + tk.Dq[aa][j0] * y1[aa];
+          f1 += tk.B[aa][j0] * y2[aa];
+        }
+        FMb[((ff * 2 + 0) * NV + v) * NMF + j0 + N * j1] = f0;
+        FMb[((ff * 2 + 1) * NV + v) * NMF + j0 + N * j1] = f1;
+      }
+    }
+  } else {
+    for (int it = tid; it < NF * NV; it += NT) {
+      const int v = it % NV;
+      const int ff = it / NV;
+      const int ax = ff >> 1;
+      const int t0 = 1 - ax;
+      const double* A0 = AF + ((ff * (D + 1) + 0) * NV + v) * NQF;
+      const double* At0 = AF + ((ff * (D + 1) + 1 + t0) * NV + v) * NQF;
+      const double* Aax = AF + ((ff * (D + 1) + 1 + ax) * NV + v) * NQF;
+#pragma unroll
+      for (int j0 = 0; j0 < N; ++j0) {
+        double f0 = 0.0, f1 = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < Q; ++aa) {
+          f0 += tk.B[aa][j0] * A0[aa] + tk.Dq[aa][j0] * At0[aa];
+          f1 += tk.B[aa][j0] * Aax[aa];
+        }
+        FMb[((ff * 2 + 0) * NV + v) * NMF + j0] = f0;
+        FMb[((ff * 2 + 1) * NV + v) * NMF + j0] = f1;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- expansion along the normal index, mass inverse, epilogue
+  const double invdetJ = g[D + 1];
+  for (int i = tid; i < NB; i += NT) {
+    const int m = i % NM, v = i / NM;
+    int mi[3] = {0, 0, 0};
+    split<D, N>(m, mi);
+    double Lm = sL[i];
+#pragma unroll
+    for (int ff = 0; ff < NF; ++ff) {
+      const int ax = ff >> 1, s = ff & 1;
+      int t[2] = {0, 0};
+      tang_axes<D>(ax, t);
+      const int tm = mi[t[0]] + ((D == 3) ? N * mi[t[1]] : 0);
+      Lm += sE[s * N + mi[ax]] * FMb[((ff * 2 + 0) * NV + v) * NMF + tm] +
+            sE[2 * N + s * N + mi[ax]] * FMb[((ff * 2 + 1) * NV + v) * NMF + tm];
+    }
+    if constexpr (CV) sL[i] = Lm;
+    else epilogue(a, ep, e * NB + i, Lm * invdetJ);
+  }
+  if constexpr (CV) {
+    __syncthreads();
+    // R[v][m] = sum_n M^-1[m][n] L[v][n], M^-1 streamed once per element by
+    // NS groups of MP threads (coalesced over m), partial sums in LDS
+    constexpr int MP = ((NM + 63) / 64) * 64;
+    constexpr int NSC = F::U / NB;
+    static_assert(NSC >= 1, "LDS staging of the mass-matrix product");
+    const int NS = NT / MP < 1 ? 1 : (NT / MP > NSC ? NSC : NT / MP);
+    double* part = WS;
+    const double* Mi = a.minv + e * (long)NM * NM;
+    for (int t = tid; t < NS * MP; t += NT) {
+      const int m = t % MP, h = t / MP;
+      if (m >= NM) continue;
+      double R[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] = 0.0;
+#pragma unroll 4
+      for (int n = h; n < NM; n += NS) {
+        const double w = Mi[(long)n * NM + m];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[v] += w * sL[v * NM + n];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) part[(h * NV + v) * NM + m] = R[v];
+    }
+    __syncthreads();
+    for (int i = tid; i < NB; i += NT) {
+      const int m = i % NM, v = i / NM;
+      double R = 0.0;
+      for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
+      epilogue(a, ep, e * NB + i, R);
+    }
+  }
+}
+
+}  // namespace dgj

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <functional>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -20,6 +21,7 @@
 #include "dgj_precond.h"
 #include "dgj_geometry.h"
 #include "dgj_residual.h"
+#include "dgj_fused.h"
 #include "dgj_mlp.h"
 
 using namespace dgj;
@@ -491,6 +493,8 @@ struct dgj_ctx {
   int* d_status = nullptr;
   int residual_evals = 0;
   int res_nt[3] = {0, 0, 0};       // block sizes of the volume, face and lift kernels (0: default)
+  int fused_nt = 0;                // block size of the fused residual kernel (0: default)
+  bool fused = true;               // interior-penalty residual by the fused kernel (else the three kernels)
   int last_gmres_max = 0;          // largest GMRES count of the last Newton solve since the last build
   // initial guess of the stage solves
   int guess_mode = 0;              // 0 S_m, 1 extrapolated, 2 learned (with fallback)
@@ -620,9 +624,30 @@ TabK<N, Q> tables_by_value(dgj_ctx* c) {
   return tk;
 }
 
+template <int D, int N, int Q, bool CV>
+void launch_fused(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int nt) {
+  if (nt < fused_min_threads<D, N, Q>() || nt > 256 || nt % 64)
+    fail(DGJ_EINVAL, "fused residual workgroup size %d (multiples of 64 from %d to 256)", nt,
+         fused_min_threads<D, N, Q>());
+  hipLaunchKernelGGL((k_res_fused<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk);
+}
+
+template <int D, int N, int Q>
+int default_fused_nt() { return fused_min_threads<D, N, Q>() > 128 ? 256 : (D == 2 ? 64 : 128); }
+
+// the fused kernel evaluates the interior-penalty residual; LDG (its lifted
+// auxiliary gradient) runs through the three kernels
+bool use_fused(const dgj_ctx* c, const ResArgs& a) { return c->fused && !a.ldg_r; }
+
 template <int D, int N, int Q>
 void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
   const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
+  if (use_fused(c, a)) {
+    const int nt = c->fused_nt > 0 ? c->fused_nt : default_fused_nt<D, N, Q>();
+    if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt);
+    else launch_fused<D, N, Q, false>(c, a, tk, nt);
+    return;
+  }
   if (a.ldg_r)
     hipLaunchKernelGGL((k_ldg_lift<D, N, Q>), dim3(c->n_elem), dim3(128), 0, c->stream, a, tk, a.ldg_r);
   for (int k = 0; k < 3; ++k) {
@@ -634,9 +659,12 @@ void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
 
 ResArgs res_args(dgj_ctx* c);
 
-// Autotuner: time each residual kernel alone with block sizes 64, 128 and
-// 256 at the state u (the other kernels' inputs left in place by one full
-// evaluation) and keep the fastest per kernel.
+// Autotuner.  Fused residual: time the kernel with every workgroup size
+// from its minimum (a thread per face point) to 256 in steps of 64 and keep
+// the fastest (chosen = {size, 0, 0}).  Three-kernel path (LDG): time each
+// kernel alone with block sizes 64, 128 and 256 at the state u (the other
+// kernels' inputs left in place by one full evaluation) and keep the
+// fastest per kernel.
 template <int D, int N, int Q>
 void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* times) {
   ResArgs a = res_args(c);
@@ -648,6 +676,31 @@ void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* 
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  if (use_fused(c, a)) {
+    float best = 0.0f;
+    int bnt = 0, ci = 0;
+    for (int nt = fused_min_threads<D, N, Q>(); nt <= 256; nt += 64, ++ci) {
+      auto run = [&]() {
+        if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt);
+        else launch_fused<D, N, Q, false>(c, a, tk, nt);
+      };
+      run();
+      HIPCHK(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) run();
+      HIPCHK(hipEventRecord(e1, c->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (times && ci < 9) times[ci] = ms;
+      if (bnt == 0 || ms < best) { best = ms; bnt = nt; }
+    }
+    c->fused_nt = bnt;
+    if (chosen) { chosen[0] = bnt; chosen[1] = 0; chosen[2] = 0; }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    return;
+  }
   const int cand[3] = {64, 128, 256};
   for (int k = 0; k < 3; ++k) {
     float best = 0.0f;
@@ -787,16 +840,18 @@ void sweep_shape(dgj_ctx* c, const double* q, const double* qold, double* out, d
   else sweep_t<D, N, Q, __hip_bfloat16, float>(c, q, qold, out, dt_a, first);
 }
 
-void precond_apply(dgj_ctx* c, const double* q, double* out) {
+// P^-1 q through the iterate buffers pa, pb and (curved meshes) the mass
+// product buffer mq, each of n unknowns
+void precond_apply_bufs(dgj_ctx* c, const double* q, double* out, double* pa, double* pb, double* mq) {
   const int J = std::max(1, c->sv.brj_sweeps);
   if (c->curved) {
     // curved elements store (M_e - dt a A_e)^-1: the sweeps take M q
-    hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_M, q, c->d_Mq, c->NM, c->NV,
+    hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_M, q, mq, c->NM, c->NV,
                        c->n_elem);
-    q = c->d_Mq;
+    q = mq;
   }
   // ping-pong so the last sweep lands in out
-  double* bufs[2] = {c->d_pa, c->d_pb};
+  double* bufs[2] = {pa, pb};
   const double* prev = nullptr;
   for (int j = 0; j < J; ++j) {
     double* dst = (j == J - 1) ? out : bufs[j & 1];
@@ -808,6 +863,8 @@ void precond_apply(dgj_ctx* c, const double* q, double* out) {
     prev = dst;
   }
 }
+
+void precond_apply(dgj_ctx* c, const double* q, double* out) { precond_apply_bufs(c, q, out, c->d_pa, c->d_pb, c->d_Mq); }
 
 template <int D, int N, int Q>
 void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* JmW, void* Dm, long e0, long ne,
@@ -1680,6 +1737,12 @@ int dgj_precond_apply(dgj_ctx* c, const double* q, double* out) {
     HIPCHK(hipGetLastError());
     return DGJ_OK;
   });
+}
+
+int dgj_set_residual_kernels(dgj_ctx* c, int32_t fused) {
+  if (!c || fused < 0 || fused > 1) return DGJ_EINVAL;
+  c->fused = fused == 1;
+  return DGJ_OK;
 }
 
 int dgj_set_pc_precision(dgj_ctx* c, int32_t prec) {

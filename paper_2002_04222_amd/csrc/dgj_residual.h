@@ -45,31 +45,18 @@ struct ResK {
   static constexpr int QG = (D + 1) * NV * NQ;
 };
 
-// ---------------------------------------------------------------- volume + traces
-// Block size (runtime, a multiple of 64, at most 256) is chosen per shape by
-// the autotuner; every loop strides by blockDim.x.
-template <int D, int N, int Q, bool CV>
-__global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
-                                                double* __restrict__ Lvol) {
+// ---------------------------------------------------------------- volume phases
+// Sum-factorised backward transform and reference gradients at the Gauss
+// points: sQ[0][v][q] values, sQ[1+j][v][q] d/dxi_j (W: scratch of
+// ResK::T1 + T2 doubles).  Every loop strides by blockDim.x.
+template <int D, int N, int Q>
+__device__ __forceinline__ void res_vol_forward(const TabK<N, Q>& tk, const double* __restrict__ sU,
+                                                double* __restrict__ W, double* __restrict__ sQ) {
   using K = ResK<D, N, Q>;
-  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
-  __shared__ double sU[NB];
-  __shared__ double W[K::T1 + K::T2];
-  __shared__ double sQ[K::QG];
-  const long e = blockIdx.x;
-  if (e >= a.n_elem) return;
-  ElemParams ep;
-  if (!elem_params(a, e, ep)) return;
+  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
-  const double* g = a.geo + e * K::S::GEO;
-  double dxi[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) dxi[j] = g[j];
-  const double detJ = g[D];
-  for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
-  __syncthreads();
-
+  (void)NM;
   if constexpr (D == 3) {
     double* T1 = W;                  // [2][v][a0][i1 + N i2]
     double* T2 = W + K::T1;          // [3][v][i2][a0 + Q a1]
@@ -179,85 +166,19 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
       }
     }
   }
-  __syncthreads();
+}
 
-  // LDG (affine boxes): the auxiliary gradient is grad u plus the lifted
-  // face jumps, so the traces and the volume flux below see q
-  if (!CV && a.ldg_r) {
-    const double* r = a.ldg_r + e * (long)D * NV * NQ;
-    for (int it = tid; it < D * NV * NQ; it += NT) {
-      const int j = it / (NV * NQ);
-      sQ[(1 + j) * NV * NQ + it % (NV * NQ)] += r[it] / dxi[j];
-    }
-    __syncthreads();
-  }
-
-  // own face traces: value and physical gradient at the face points
-  if constexpr (CV) {
-    // curved: interpolate value and reference gradient, then grad = G^T grad_xi
-    constexpr int CF = D * D + D + 1;
-    double* tr = trace + e * (long)K::TRACE;
-    const double* fge = a.fg + e * (long)NF * CF * NQF;
-    for (int it = tid; it < NF * NV * NQF; it += NT) {
-      const int p = it % NQF;
-      const int v = (it / NQF) % NV;
-      const int f = it / (NQF * NV);
-      const int ax = f >> 1, s = f & 1;
-      int qstride = 1, base = 0;
-      {
-        int t[2] = {0, 0};
-        tang_axes<D>(ax, t);
-        int st[3] = {1, Q, Q * Q};
-        qstride = st[ax];
-        base = (p % Q) * st[t[0]];
-        if (D == 3) base += (p / Q) * st[t[1]];
-      }
-      double rv[D + 1];
-#pragma unroll
-      for (int c = 0; c <= D; ++c) {
-        const double* y = sQ + c * NV * NQ + v * NQ + base;
-        double acc = 0.0;
-#pragma unroll
-        for (int aa = 0; aa < Q; ++aa) acc += tk.lag[s][aa] * y[aa * qstride];
-        rv[c] = acc;
-      }
-      const double* Gp = fge + f * CF * NQF + p;
-      tr[((f * (D + 1)) * NV + v) * NQF + p] = rv[0];
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        double gj = 0.0;
-#pragma unroll
-        for (int kk = 0; kk < D; ++kk) gj += Gp[(kk * D + j) * NQF] * rv[1 + kk];
-        tr[((f * (D + 1) + 1 + j) * NV + v) * NQF + p] = gj;
-      }
-    }
-  } else {
-    double* tr = trace + e * (long)K::TRACE;
-    for (int it = tid; it < K::TRACE; it += NT) {
-      const int p = it % NQF;
-      const int v = (it / NQF) % NV;
-      const int c = (it / (NQF * NV)) % (D + 1);
-      const int f = it / (NQF * NV * (D + 1));
-      const int ax = f >> 1, s = f & 1;
-      // volume point index of (a along ax, tangential p)
-      int qstride = 1, base = 0;
-      {
-        int t[2] = {0, 0};
-        tang_axes<D>(ax, t);
-        int st[3] = {1, Q, Q * Q};
-        qstride = st[ax];
-        base = (p % Q) * st[t[0]];
-        if (D == 3) base += (p / Q) * st[t[1]];
-      }
-      const double* y = sQ + c * NV * NQ + v * NQ + base;
-      double acc = 0.0;
-#pragma unroll
-      for (int aa = 0; aa < Q; ++aa) acc += tk.lag[s][aa] * y[aa * qstride];
-      tr[it] = (c == 0) ? acc : acc * dxi[c - 1];
-    }
-  }
-  __syncthreads();   // the flux loop below overwrites the gradients read above
-
+// Pointwise volume flux H_j = F_j - G_j scaled by w|J| dxi_j (boxes) or the
+// contravariant w|J| sum_j (d xi_k / d x_j) H_j (curved), written over the
+// gradient slots of sQ.
+template <int D, int N, int Q, bool CV>
+__device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q>& tk, const ElemParams& ep, long e,
+                                             const double* dxi, double detJ, double* __restrict__ sQ) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  (void)NM;
   // pointwise volume flux, scaled by w |J| dxi_j (overwrites the gradients);
   // curved: the contravariant flux w|J| sum_j (d xi_k/d x_j) H_j
   if constexpr (CV) {
@@ -317,10 +238,17 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
 #pragma unroll
       for (int v = 0; v < NV; ++v) sQ[(1 + j) * NV * NQ + v * NQ + q] = (F[j][v] - G[j][v]) * (wq * dxi[j]);
   }
-  __syncthreads();
+}
 
-  // transposed contraction with the derivative bases
-  double* out = Lvol + e * (long)NB;
+// Transposed contraction with the derivative bases: out[v][m] =
+// sum_j sum_q d(phi_m)/d(xi_j) H_j (W: scratch of ResK::T1 + T2 doubles).
+template <int D, int N, int Q>
+__device__ __forceinline__ void res_vol_transpose(const TabK<N, Q>& tk, const double* __restrict__ sQ,
+                                                  double* __restrict__ W, double* __restrict__ out) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
   if constexpr (D == 3) {
     const double* Hx = sQ + NV * NQ;
     const double* Hy = sQ + 2 * NV * NQ;
@@ -427,6 +355,119 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
       }
     }
   }
+}
+
+// ---------------------------------------------------------------- volume + traces
+// Block size (runtime, a multiple of 64, at most 256) is chosen per shape by
+// the autotuner; every loop strides by blockDim.x.
+template <int D, int N, int Q, bool CV>
+__global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
+                                                double* __restrict__ Lvol) {
+  using K = ResK<D, N, Q>;
+  constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
+  __shared__ double sU[NB];
+  __shared__ double W[K::T1 + K::T2];
+  __shared__ double sQ[K::QG];
+  const long e = blockIdx.x;
+  if (e >= a.n_elem) return;
+  ElemParams ep;
+  if (!elem_params(a, e, ep)) return;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  const double* g = a.geo + e * K::S::GEO;
+  double dxi[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) dxi[j] = g[j];
+  const double detJ = g[D];
+  for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
+  __syncthreads();
+
+  res_vol_forward<D, N, Q>(tk, sU, W, sQ);
+  __syncthreads();
+
+  // LDG (affine boxes): the auxiliary gradient is grad u plus the lifted
+  // face jumps, so the traces and the volume flux below see q
+  if (!CV && a.ldg_r) {
+    const double* r = a.ldg_r + e * (long)D * NV * NQ;
+    for (int it = tid; it < D * NV * NQ; it += NT) {
+      const int j = it / (NV * NQ);
+      sQ[(1 + j) * NV * NQ + it % (NV * NQ)] += r[it] / dxi[j];
+    }
+    __syncthreads();
+  }
+
+  // own face traces: value and physical gradient at the face points
+  if constexpr (CV) {
+    // curved: interpolate value and reference gradient, then grad = G^T grad_xi
+    constexpr int CF = D * D + D + 1;
+    double* tr = trace + e * (long)K::TRACE;
+    const double* fge = a.fg + e * (long)NF * CF * NQF;
+    for (int it = tid; it < NF * NV * NQF; it += NT) {
+      const int p = it % NQF;
+      const int v = (it / NQF) % NV;
+      const int f = it / (NQF * NV);
+      const int ax = f >> 1, s = f & 1;
+      int qstride = 1, base = 0;
+      {
+        int t[2] = {0, 0};
+        tang_axes<D>(ax, t);
+        int st[3] = {1, Q, Q * Q};
+        qstride = st[ax];
+        base = (p % Q) * st[t[0]];
+        if (D == 3) base += (p / Q) * st[t[1]];
+      }
+      double rv[D + 1];
+#pragma unroll
+      for (int c = 0; c <= D; ++c) {
+        const double* y = sQ + c * NV * NQ + v * NQ + base;
+        double acc = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < Q; ++aa) acc += tk.lag[s][aa] * y[aa * qstride];
+        rv[c] = acc;
+      }
+      const double* Gp = fge + f * CF * NQF + p;
+      tr[((f * (D + 1)) * NV + v) * NQF + p] = rv[0];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double gj = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) gj += Gp[(kk * D + j) * NQF] * rv[1 + kk];
+        tr[((f * (D + 1) + 1 + j) * NV + v) * NQF + p] = gj;
+      }
+    }
+  } else {
+    double* tr = trace + e * (long)K::TRACE;
+    for (int it = tid; it < K::TRACE; it += NT) {
+      const int p = it % NQF;
+      const int v = (it / NQF) % NV;
+      const int c = (it / (NQF * NV)) % (D + 1);
+      const int f = it / (NQF * NV * (D + 1));
+      const int ax = f >> 1, s = f & 1;
+      // volume point index of (a along ax, tangential p)
+      int qstride = 1, base = 0;
+      {
+        int t[2] = {0, 0};
+        tang_axes<D>(ax, t);
+        int st[3] = {1, Q, Q * Q};
+        qstride = st[ax];
+        base = (p % Q) * st[t[0]];
+        if (D == 3) base += (p / Q) * st[t[1]];
+      }
+      const double* y = sQ + c * NV * NQ + v * NQ + base;
+      double acc = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < Q; ++aa) acc += tk.lag[s][aa] * y[aa * qstride];
+      tr[it] = (c == 0) ? acc : acc * dxi[c - 1];
+    }
+  }
+  __syncthreads();   // the flux loop below overwrites the gradients read above
+
+  // pointwise volume flux (overwrites the gradients)
+  res_vol_flux<D, N, Q, CV>(a, tk, ep, e, dxi, detJ, sQ);
+  __syncthreads();
+
+  // transposed contraction with the derivative bases
+  res_vol_transpose<D, N, Q>(tk, sQ, W, Lvol + e * (long)NB);
 }
 
 // ---------------------------------------------------------------- LDG lifting
