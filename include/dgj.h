@@ -256,6 +256,18 @@ int dgj_precond_build(dgj_ctx *ctx, const double *u_p, double dt_a);
  * built preconditioner.  out must not alias q. */
 int dgj_precond_apply(dgj_ctx *ctx, const double *q, double *out);
 
+/* dgj_precond_apply that allocates nothing, for callers that cannot call
+ * hipMalloc (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Its BRJ iterates (and the mass product of curved
+ * meshes) live in a static device array of the library, 3 x 2^21 FP64
+ * values (48 MiB) on every GPU it runs on, held until the process ends:
+ * contexts of more than 2^21 unknowns get DGJ_EINVAL.  Every call on one GPU
+ * shares that array, which keeps the last call's contents (nothing in it
+ * needs to start at zero): calls that overlap on one GPU, from any context
+ * or stream, race.  Same result as dgj_precond_apply (same kernels, same
+ * order).  Requires a built preconditioner; out must not alias q. */
+int dgj_precond_apply_static(dgj_ctx *ctx, const double *q, double *out);
+
 /* Change the storage precision of the BRJ blocks (DGJ_PC_F64 / F32 / BF16;
  * Sec. 4.2.2 stores them in single precision) for the following builds; the
  * held preconditioner is released, so the next step or dgj_precond_apply

@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "dgj_set_guess": ([vp, C.c_int32], C.c_int),
         "dgj_set_pc_precision": ([vp, C.c_int32], C.c_int),
         "dgj_set_residual_kernels": ([vp, C.c_int32], C.c_int),
+        "dgj_precond_apply_static": ([vp, vp, vp], C.c_int),
         "dgj_project": ([vp, vp, vp], C.c_int),
         "dgj_set_source": ([vp, vp], C.c_int),
         "dgj_set_bc_field": ([vp, vp], C.c_int),
@@ -386,6 +387,9 @@ class Context:
 
     # ---- Newton initial guess and the learned predictor
     GUESS = {"paper": 0, "extrapolated": 1, "learned": 2}
+
+    def precond_apply_static(self, q, out):
+        self._check(self.lib.dgj_precond_apply_static(self.h, _ptr(q), _ptr(out)))
 
     def set_residual_kernels(self, fused):
         self._check(self.lib.dgj_set_residual_kernels(self.h, 1 if fused else 0))

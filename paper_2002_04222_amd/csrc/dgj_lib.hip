@@ -26,6 +26,13 @@
 
 using namespace dgj;
 
+// Scratch of dgj_precond_apply_static: the two BRJ iterates and the mass
+// product of curved meshes, STATIC_APPLY_MAX unknowns each (48 MiB on every
+// GPU the library runs on, held until the process ends).  Host code uses
+// the per-device address from hipGetSymbolAddress, never this name.
+constexpr long STATIC_APPLY_MAX = 1L << 21;
+static __device__ __align__(256) double scratch[3 * STATIC_APPLY_MAX];
+
 namespace {
 
 constexpr int RED_BLOCKS = 512;
@@ -438,6 +445,26 @@ struct Status {
   std::string msg;
 };
 
+// ---------------------------------------------------------------- static scratch address
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (resolved once per
+// device, with that device current)
+double* static_scratch_address() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- context
@@ -480,6 +507,7 @@ struct dgj_ctx {
   double *d_ubar = nullptr, *d_N = nullptr, *d_S = nullptr, *d_b = nullptr, *d_x = nullptr, *d_un = nullptr;
   double* d_E[DGJ_MAX_STAGES] = {};   // stage derivatives (the scheme's stage count allocated)
   double *d_pa = nullptr, *d_pb = nullptr;   // BRJ ping-pong
+  double* d_scratch = nullptr;     // device address of the static scratch on this context's device
   // preconditioner
   bool pc_ready = false;
   int pc_age = 0;
@@ -1385,6 +1413,8 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
     c->NB = c->NV * c->NM;
     if (c->NB > 1024) fail(DGJ_EUNSUPPORTED, "block size %d > 1024", c->NB);
     c->n_elem = mesh->n_elem;
+    // the static scratch's address on this device (dgj_precond_apply_static)
+    c->d_scratch = static_scratch_address();
     c->n = c->n_elem * c->NB;
     c->inst_e0 = {0, c->n_elem};
     c->ph = Phys{phys->gamma, phys->Pr, phys->Re, phys->Ma, phys->T_ref_K, phys->visc_law, phys->flux_mode,
@@ -1734,6 +1764,22 @@ int dgj_precond_apply(dgj_ctx* c, const double* q, double* out) {
   return guarded(c, [&]() -> int {
     if (!c->pc_ready) fail(DGJ_EINVAL, "precond_apply: no preconditioner built");
     precond_apply(c, q, out);
+    HIPCHK(hipGetLastError());
+    return DGJ_OK;
+  });
+}
+
+int dgj_precond_apply_static(dgj_ctx* c, const double* q, double* out) {
+  if (!c || !q || !out || q == out) return DGJ_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (c->n_inst > 0) fail(DGJ_EINVAL, "precond_apply_static: not for batch groups");
+    if (c->n > STATIC_APPLY_MAX)
+      fail(DGJ_EINVAL, "precond_apply_static: %ld unknowns exceed the static scratch's %ld per vector", c->n,
+           STATIC_APPLY_MAX);
+    if (!c->pc_ready) fail(DGJ_EINVAL, "precond_apply_static: no preconditioner built");
+    if (!c->d_scratch) fail(DGJ_EHIP, "precond_apply_static: no static scratch address on this device");
+    double* s = c->d_scratch;
+    precond_apply_bufs(c, q, out, s, s + STATIC_APPLY_MAX, s + 2 * STATIC_APPLY_MAX);
     HIPCHK(hipGetLastError());
     return DGJ_OK;
   });
