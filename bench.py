@@ -79,6 +79,8 @@ def parse():
                          "same physical time as the timed implicit steps; 2-3 minutes on the cylinder)")
     ap.add_argument("--kernel-reps", type=int, default=100,
                     help="back-to-back residual evaluations per timing repeat (median of 5 repeats)")
+    ap.add_argument("--three-kernel", action="store_true",
+                    help="--mode residual: evaluate with the three-kernel path instead of the fused kernel")
     ap.add_argument("--mode", default="full", choices=["full", "sweep", "copy", "residual"],
                     help="sweep: only build the preconditioner and apply it (for counter runs); "
                          "copy: a plain 1 GiB device copy (counter calibration); "
@@ -371,10 +373,12 @@ def main():
     stream = torch.cuda.current_stream()
     if args.mode == "residual":
         R = ctx.empty()
+        ctx.set_residual_kernels(not args.three_kernel)
+        tuned, _ = ctx.autotune(u, reps=5)
         for _ in range(20):
             ctx.residual(u, R)
         torch.cuda.synchronize()
-        log("20 residual evaluations")
+        log(f"20 residual evaluations ({'three kernels' if args.three_kernel else 'fused kernel'}, tile {tuned})")
         return
     if args.mode == "sweep":
         ctx.precond_build(u, dt * _lam(cfg.scheme))

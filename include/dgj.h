@@ -224,10 +224,12 @@ int dgj_residual(dgj_ctx *ctx, const double *u, double *R);
  * rounding (different summation orders of the traces). */
 int dgj_set_residual_kernels(dgj_ctx *ctx, int32_t fused);
 /* Autotuner of the residual's workgroup shapes (not in the paper).  Fused
- * kernel: times it at state u with every workgroup size from the smallest
- * multiple of 64 with a thread per face point up to 256, reps launches
- * each, and keeps the fastest; chosen = {size, 0, 0}, times_ms[i] = the i-th
- * size's time.  Three kernels (LDG): times each kernel alone with
+ * kernel: times it at state u, reps launches each, with every tile of
+ * elements per workgroup (2D: 1, 2, 4, 8; 3D: 1) and workgroup size (64,
+ * 128, 256; 3D also 192), taken in that order, that gives each element at
+ * least a thread per face point in whole half-wavefronts (3D: wavefronts),
+ * and keeps the fastest; chosen = {size, elements per workgroup, 0},
+ * times_ms[i] = the i-th tile's time.  Three kernels (LDG): times each kernel alone with
  * workgroups of 64, 128 and 256 threads (its other inputs left in place by
  * one evaluation) and keeps the fastest per kernel; chosen: (volume, face,
  * lift), times_ms [kernel][64, 128, 256].  chosen: host [3] or NULL;

@@ -114,9 +114,9 @@ struct Batch {
   bool use_graphs = true;
   hipStream_t own = nullptr;
   hipStream_t caller = nullptr;
-  std::vector<std::vector<hipGraphExec_t>> gexec;   // [group][k]
+  std::vector<hipGraphExec_t> gexec;               // [k]: Krylov step k of every group, one graph
   std::vector<double*> h_slots;                    // pinned [group][n_inst*64]
-  std::vector<int*> h_act;                         // pinned [group][n_inst]
+  std::vector<int*> h_act;                         // pinned [group][2 n_inst]: normalisation mask, step mask
 };
 
 // one Arnoldi step of group c: z = P^-1 V_k, V_{k+1} = J z, MGS against V_0..V_k, ||V_{k+1}||
@@ -140,29 +140,50 @@ void arnoldi_body(dgj_ctx* c, int k) {
                      c->d_active, c->d_hs, k + 1, 1);
 }
 
-void arnoldi_launch(Batch& B, int gi, int k) {
-  dgj_ctx* c = B.g[gi];
-  if (!B.use_graphs) {
+// Krylov step k of every order group, all on the batch's stream: for k >= 1
+// normalise V[k] (mask h_act[gi][0..n): the instances whose step k-1 had no
+// breakdown), then with the step mask h_act[gi][n..2n) the Arnoldi step and
+// the copy of the new Hessenberg column to the pinned host slots.  The masks
+// are read from pinned host memory when the step runs, so one captured graph
+// per k serves every replay.
+void krylov_step_body(Batch& B, int k) {
+  for (size_t gi = 0; gi < B.g.size(); ++gi) {
+    dgj_ctx* c = B.g[gi];
+    const size_t mb = (size_t)c->n_inst * sizeof(int);
+    if (k >= 1) {
+      HIPCHK(hipMemcpyAsync(c->d_active, B.h_act[gi], mb, hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_div_seg, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->V[k], c->V[k], c->d_hs, k,
+                         c->d_inst, c->NB, c->d_active, c->n);
+    }
+    HIPCHK(hipMemcpyAsync(c->d_active, B.h_act[gi] + c->n_inst, mb, hipMemcpyHostToDevice, c->stream));
     arnoldi_body(c, k);
+    HIPCHK(hipMemcpyAsync(B.h_slots[gi], c->d_hs, (size_t)c->n_inst * 64 * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+  }
+}
+
+// one launch per Krylov step over all order groups: the step's graph
+// (captured on first use) or, without graphs, the same launches directly
+void krylov_step(Batch& B, int k) {
+  if (!B.use_graphs) {
+    krylov_step_body(B, k);
     return;
   }
-  auto& ge = B.gexec[gi];
-  if ((int)ge.size() <= k) ge.resize(k + 1, nullptr);
-  if (!ge[k]) {
+  if ((int)B.gexec.size() <= k) B.gexec.resize(k + 1, nullptr);
+  if (!B.gexec[k]) {
     hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    arnoldi_body(c, k);
-    HIPCHK(hipStreamEndCapture(c->stream, &graph));
-    HIPCHK(hipGraphInstantiate(&ge[k], graph, nullptr, nullptr, 0));
+    HIPCHK(hipStreamBeginCapture(B.own, hipStreamCaptureModeThreadLocal));
+    krylov_step_body(B, k);
+    HIPCHK(hipStreamEndCapture(B.own, &graph));
+    HIPCHK(hipGraphInstantiate(&B.gexec[k], graph, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(graph));
   }
-  HIPCHK(hipGraphLaunch(ge[k], c->stream));
+  HIPCHK(hipGraphLaunch(B.gexec[k], B.own));
 }
 
 void drop_graphs(Batch& B) {
-  for (auto& v : B.gexec)
-    for (auto& x : v)
-      if (x) { (void)hipGraphExecDestroy(x); x = nullptr; }
+  for (auto& x : B.gexec)
+    if (x) { (void)hipGraphExecDestroy(x); x = nullptr; }
 }
 
 void set_active(dgj_ctx* c, std::vector<int>& h) {
@@ -262,24 +283,27 @@ void batch_gmres(Batch& B, std::vector<std::vector<IG>>& ig) {
     }
     first = false;
     if (!any) break;
-    // Arnoldi steps in lockstep: one replayed graph per group, one host sync per step
+    // Arnoldi steps in lockstep: one launch (a replayed graph) per step over
+    // all order groups, one host sync per step
     for (int k = 0; k < m; ++k) {
       std::vector<int> live(G, 0);
       for (int gi = 0; gi < G; ++gi) {
-        for (int i = 0; i < B.g[gi]->n_inst; ++i) live[gi] |= B.act[gi][i];
-        if (!live[gi]) continue;
-        arnoldi_launch(B, gi, k);
         dgj_ctx* c = B.g[gi];
-        HIPCHK(hipMemcpyAsync(B.h_slots[gi], c->d_hs, (size_t)c->n_inst * 64 * sizeof(double), hipMemcpyDeviceToHost,
-                              c->stream));
+        int* a2 = B.h_act[gi] + c->n_inst;   // this step's mask
+        for (int i = 0; i < c->n_inst; ++i) {
+          a2[i] = B.act[gi][i];
+          live[gi] |= B.act[gi][i];
+        }
       }
+      krylov_step(B, k);
       HIPCHK(hipStreamSynchronize(B.own));
       bool running = false;
       for (int gi = 0; gi < G; ++gi) {
-        if (!live[gi]) continue;
         dgj_ctx* c = B.g[gi];
+        int* a = B.h_act[gi];   // next step's normalisation mask
+        for (int ii = 0; ii < c->n_inst; ++ii) a[ii] = 0;
+        if (!live[gi]) continue;
         const double* h = B.h_slots[gi];
-        int* a = B.h_act[gi];
         for (int ii = 0; ii < c->n_inst; ++ii) {
           a[ii] = B.act[gi][ii];
           if (!a[ii]) continue;
@@ -308,19 +332,13 @@ void batch_gmres(Batch& B, std::vector<std::vector<IG>>& ig) {
             s.stop = true;
           }
         }
-        // normalise the new vector for the instances without breakdown
-        HIPCHK(hipMemcpyAsync(c->d_active, a, c->n_inst * sizeof(int), hipMemcpyHostToDevice, c->stream));
-        hipLaunchKernelGGL(k_div_seg, SEGL(c), c->V[k + 1], c->V[k + 1], c->d_hs, k + 1, c->d_inst, c->NB, c->d_active,
-                           c->n);
+        // the new vector is normalised at the start of the next step (for
+        // the instances without breakdown, mask a); stopped instances leave
         for (int ii = 0; ii < c->n_inst; ++ii) {
           if (!B.act[gi][ii]) continue;
           if (ig[gi][ii].stop) B.act[gi][ii] = 0;
           running |= (bool)B.act[gi][ii];
         }
-        // next step's mask (pinned copy is reused only after the next sync)
-        int* a2 = B.h_act[gi] + c->n_inst;
-        for (int ii = 0; ii < c->n_inst; ++ii) a2[ii] = B.act[gi][ii];
-        HIPCHK(hipMemcpyAsync(c->d_active, a2, c->n_inst * sizeof(int), hipMemcpyHostToDevice, c->stream));
       }
       if (!running) break;
     }
@@ -552,7 +570,6 @@ int dgj_batch_create(int32_t n, const dgj_mesh* meshes, const dgj_phys* phys, co
       HIPCHK(hipHostMalloc(&ha, (size_t)ni * 2 * sizeof(int), hipHostMallocDefault));
       b->h_slots.push_back(hs);
       b->h_act.push_back(ha);
-      b->gexec.emplace_back();
       b->goff.push_back(pos);
       pos += c->n;
     }

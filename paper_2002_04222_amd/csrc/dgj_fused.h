@@ -31,6 +31,15 @@
 
 namespace dgj {
 
+// tangential axes of the face normal to axis ax (the first is the faster
+// one in face-point and face-mode indices), without a runtime-indexed array
+template <int D>
+__device__ __forceinline__ int tang0(int ax) { return D == 3 ? (ax == 0 ? 1 : 0) : 1 - ax; }
+template <int D>
+__device__ __forceinline__ int tang1(int ax) { return D == 3 ? (ax == 2 ? 1 : 2) : 0; }
+template <int N>
+__device__ __forceinline__ int npow(int x) { return x == 0 ? 1 : (x == 1 ? N : N * N); }
+
 template <int D, int N, int Q>
 struct FusedK {
   using K = ResK<D, N, Q>;
@@ -46,31 +55,48 @@ struct FusedK {
   static constexpr int U1 = VOL > FACE ? VOL : FACE;
   static constexpr int U = U1 > LIFT ? U1 : LIFT;
   static constexpr int NPTS = NF * NQF;   // face points: one thread each in the flux phase
+  // workgroups of 256 threads per CU the register budget is set for: as many
+  // as the LDS holds (at most 3)
+  static constexpr int LDS_BYTES = 8 * (2 * NB + U) + 8 * (4 * N + 2 * Q * N + Q) + 8 * NF;
+  static constexpr int MINB = (160 * 1024 / LDS_BYTES) >= 3 ? 3 : ((160 * 1024 / LDS_BYTES) >= 2 ? 2 : 1);
 };
 
-// smallest workgroup of the fused kernel: a multiple of 64 with a thread per face point
+// smallest number of threads per element: a thread per face point, in
+// whole half-wavefronts (2D) or wavefronts (3D)
 template <int D, int N, int Q>
-constexpr int fused_min_threads() { return ((FusedK<D, N, Q>::NPTS + 63) / 64) * 64; }
+constexpr int fused_min_threads() {
+  return D == 2 ? ((FusedK<D, N, Q>::NPTS + 31) / 32) * 32 : ((FusedK<D, N, Q>::NPTS + 63) / 64) * 64;
+}
 
-template <int D, int N, int Q, bool CV>
-__global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
+// EPW elements per workgroup, blockDim.x / EPW threads per element (the
+// workgroup-size and elements-per-workgroup tile the autotuner chooses; the
+// arithmetic of each element does not depend on it)
+template <int D, int N, int Q, bool CV, int EPW>
+__global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
   using F = FusedK<D, N, Q>;
   using K = ResK<D, N, Q>;
   constexpr int NV = F::NV, NM = F::NM, NQF = F::NQF, NMF = F::NMF, NF = F::NF, NB = F::NB;
   constexpr int CF = D * D + D + 1;
   constexpr int GEO = K::S::GEO;
-  __shared__ double sU[NB];
-  __shared__ double sL[NB];
-  __shared__ double WS[F::U];
+  __shared__ double sUa[EPW][NB];
+  __shared__ double sLa[EPW][NB];
+  __shared__ double WSa[EPW][F::U];
   __shared__ double sE[4 * N];         // phi(-1), phi(+1), phi'(-1), phi'(+1)
   __shared__ double sB[Q * N], sD[Q * N], sW[Q];
-  __shared__ long s_nb[NF];
-  const long e = blockIdx.x;
-  if (e >= a.n_elem) return;
+  __shared__ long s_nba[EPW][NF];
+  const int NT = blockDim.x / EPW;                 // threads of this element
+  const int sub = threadIdx.x / NT;
+  const int tid = threadIdx.x - sub * NT;
+  const long e_raw = (long)blockIdx.x * EPW + sub;
+  // an element past the end or of an inactive instance computes on a valid
+  // index (every load in bounds, every barrier reached) and writes nothing
+  const long e = e_raw < a.n_elem ? e_raw : a.n_elem - 1;
   ElemParams ep;
-  if (!elem_params(a, e, ep)) return;
-  const int tid = threadIdx.x;
-  const int NT = blockDim.x;
+  const bool ok = elem_params(a, e, ep) && e_raw < a.n_elem;
+  double* sU = sUa[sub];
+  double* sL = sLa[sub];
+  double* WS = WSa[sub];
+  long* s_nb = s_nba[sub];
   const double* g = a.geo + e * GEO;
   double dxi[D];
 #pragma unroll
@@ -78,26 +104,26 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
   const double detJ = g[D];
   for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
   if (tid < NF) s_nb[tid] = a.nbr[e * NF + tid];
-  if (tid < 2 * N) {
-    sE[tid] = tk.phiE[tid / N][tid % N];
-    sE[2 * N + tid] = tk.dphiE[tid / N][tid % N];
+  if (threadIdx.x < 2 * N) {
+    sE[threadIdx.x] = tk.phiE[threadIdx.x / N][threadIdx.x % N];
+    sE[2 * N + threadIdx.x] = tk.dphiE[threadIdx.x / N][threadIdx.x % N];
   }
-  for (int i = tid; i < Q * N; i += NT) {
+  for (int i = threadIdx.x; i < Q * N; i += blockDim.x) {
     sB[i] = tk.B[i / N][i % N];
     sD[i] = tk.Dq[i / N][i % N];
   }
-  if (tid < Q) sW[tid] = tk.w[tid];
+  if (threadIdx.x < Q) sW[threadIdx.x] = tk.w[threadIdx.x];
   __syncthreads();
 
   // ---- volume terms -> sL
   {
     double* W = WS;
     double* sQ = WS + K::T1 + K::T2;
-    res_vol_forward<D, N, Q>(tk, sU, W, sQ);
+    res_vol_forward<D, N, Q>(tk, sU, W, sQ, tid, NT);
     __syncthreads();
-    res_vol_flux<D, N, Q, CV>(a, tk, ep, e, dxi, detJ, sQ);
+    res_vol_flux<D, N, Q, CV>(a, tk, ep, e, dxi, detJ, sQ, tid, NT);
     __syncthreads();
-    res_vol_transpose<D, N, Q>(tk, sQ, W, sL);
+    res_vol_transpose<D, N, Q>(tk, sQ, W, sL, tid, NT);
     __syncthreads();
   }
 
@@ -113,10 +139,14 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
     const int ax = f >> 1;
     // side 0: this element on face f; side 1: the neighbour on its face f^1
     const int ss = (f & 1) ^ side;
+    // mode (ia along ax, tm = i + N j with i along the first tangential axis)
+    const int mt = (tm % N) * npow<N>(tang0<D>(ax)) + (D == 3 ? (tm / N) * npow<N>(tang1<D>(ax)) : 0);
+    const int st = npow<N>(ax);
     double tv = 0.0, tn = 0.0;
     if (side == 0 || en >= 0) {
+#pragma unroll
       for (int ia = 0; ia < N; ++ia) {
-        const int m = mode_of<D, N>(ax, ia, tm);
+        const int m = mt + ia * st;
         const double x = side == 0 ? sU[v * NM + m] : ep.in(en * NB + v * NM + m);
         tv += sE[ss * N + ia] * x;
         tn += sE[2 * N + ss * N + ia] * x;
@@ -166,14 +196,15 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
   const int p = pt ? tid % NQF : 0;
   if (pt) {
     const int ax = f >> 1, s = f & 1;
-    int t[2] = {0, 0};
-    tang_axes<D>(ax, t);
+    const int t0 = tang0<D>(ax), t1 = tang1<D>(ax);
     const int pa = p % Q, pb = (D == 3) ? p / Q : 0;
     const long en = s_nb[f];
-    double Us[2][NV], Gs[2][D][NV];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      if (side == 1 && en < 0) break;
+    // values and physical gradients of one side at the point: side 0 this
+    // element on face f, side 1 the neighbour on its face f^1 (the same code
+    // for both, so the two elements of a face see bitwise the same data)
+    // (accumulate: the gradient is added into G, which then holds the sum
+    // of both sides' gradients, left first, as the face flux takes it)
+    auto side_data = [&](int side, double* U, double (*G)[NV], bool accumulate) {
       const long ee = side == 0 ? e : en;
       const int ff = side == 0 ? f : (f ^ 1);
 #pragma unroll
@@ -199,11 +230,11 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
             dn += sB[pa * N + i] * tn[i];
           }
         }
+        // reference gradient component k: d/dn along ax, the tangential ones
         double gr[D];
-        gr[ax] = dn;
-        gr[t[0]] = dt0;
-        if (D == 3) gr[t[1]] = dt1;
-        Us[side][v] = val;
+#pragma unroll
+        for (int k = 0; k < D; ++k) gr[k] = (k == ax) ? dn : ((k == t0) ? dt0 : dt1);
+        U[v] = val;
         if constexpr (CV) {
           const double* Gp = a.fg + (ee * NF + ff) * (long)CF * NQF + p;
 #pragma unroll
@@ -211,15 +242,24 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
             double sg = 0.0;
 #pragma unroll
             for (int k = 0; k < D; ++k) sg += Gp[(k * D + j) * NQF] * gr[k];
-            Gs[side][j][v] = sg;
+            G[j][v] = accumulate ? G[j][v] + sg : sg;
           }
         } else {
           const double* ge = a.geo + ee * GEO;
 #pragma unroll
-          for (int j = 0; j < D; ++j) Gs[side][j][v] = gr[j] * ge[j];
+          for (int j = 0; j < D; ++j) {
+            const double gj = gr[j] * ge[j];
+            G[j][v] = accumulate ? G[j][v] + gj : gj;
+          }
         }
       }
-    }
+    };
+    // left = the side-1 element's data (this element's when s = 1); a
+    // boundary face has this element's only
+    double UL[NV], UR[NV], GS[D][NV];
+    const int sideL = (en >= 0 && !s) ? 1 : 0;
+    side_data(sideL, UL, GS, false);
+    if (en >= 0) side_data(1 - sideL, UR, GS, true);
     double H[NV], Sf[D][NV], nrm[D], wf;
     if (en >= 0) {
       // canonical orientation: the side-1 element's normal, weights and penalty
@@ -237,20 +277,7 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
         if (D == 3) wf *= sW[pb];
       }
       const double beta = a.beta[e1 * NF + f1];
-      // left = the side-1 data: this element's when s = 1 (selected lane by
-      // lane, so that both elements pass bitwise the same arguments)
-      double UL[NV], UR[NV], GL[D][NV], GR[D][NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        UL[v] = s ? Us[0][v] : Us[1][v];
-        UR[v] = s ? Us[1][v] : Us[0][v];
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-          GL[j][v] = s ? Gs[0][j][v] : Gs[1][j][v];
-          GR[j][v] = s ? Gs[1][j][v] : Gs[0][j][v];
-        }
-      }
-      face_flux<D>(ep.ph, UL, UR, GL, GR, nrm, beta, H, Sf);
+      face_flux_gsum<D>(ep.ph, UL, UR, GS, nrm, beta, H, Sf);
       if (!s) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) H[v] = -H[v];
@@ -269,15 +296,14 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
         wf = g[D + 2 + ax] * sW[pa];
         if (D == 3) wf *= sW[pb];
       }
-      double UD[NV];
-      const double* Ub = a.bc_state + bid * NV;
-      if (kind == BC_DIRICHLET) {
-        const double* gb = a.bc_field + (e * NF + f) * (long)NV * NQF + p;
+      // the id's state, or the Dirichlet ghost state at the point
+      double Ub[NV];
+      const bool dir = kind == BC_DIRICHLET;
+      const double* gb = dir ? a.bc_field + (e * NF + f) * (long)NV * NQF + p : a.bc_state + bid * NV;
+      const int gstride = dir ? NQF : 1;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) UD[v] = gb[v * NQF];
-        Ub = UD;
-      }
-      boundary_flux<D>(ep.ph, kind, Us[0], Gs[0], nrm, a.beta[e * NF + f], Ub, H, Sf);
+      for (int v = 0; v < NV; ++v) Ub[v] = gb[v * gstride];
+      boundary_flux<D>(ep.ph, kind, UL, GS, nrm, a.beta[e * NF + f], Ub, H, Sf);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) Af[0][v] = -H[v];
@@ -321,11 +347,9 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
       const int v = (it / Q) % NV;
       const int ff = it / (Q * NV);
       const int ax = ff >> 1;
-      int t[2] = {0, 0};
-      tang_axes<D>(ax, t);
       const double* A0 = AF + ((ff * (D + 1) + 0) * NV + v) * NQF + aa;
-      const double* At0 = AF + ((ff * (D + 1) + 1 + t[0]) * NV + v) * NQF + aa;
-      const double* At1 = AF + ((ff * (D + 1) + 1 + t[1]) * NV + v) * NQF + aa;
+      const double* At0 = AF + ((ff * (D + 1) + 1 + tang0<D>(ax)) * NV + v) * NQF + aa;
+      const double* At1 = AF + ((ff * (D + 1) + 1 + tang1<D>(ax)) * NV + v) * NQF + aa;
       const double* Aax = AF + ((ff * (D + 1) + 1 + ax) * NV + v) * NQF + aa;
       double x0[Q], xt0[Q], xt1[Q], xax[Q];
 #pragma unroll
@@ -416,7 +440,7 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
             sE[2 * N + s * N + mi[ax]] * FMb[((ff * 2 + 1) * NV + v) * NMF + tm];
     }
     if constexpr (CV) sL[i] = Lm;
-    else epilogue(a, ep, e * NB + i, Lm * invdetJ);
+    else if (ok) epilogue(a, ep, e * NB + i, Lm * invdetJ);
   }
   if constexpr (CV) {
     __syncthreads();
@@ -448,7 +472,7 @@ __global__ __launch_bounds__(256) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
       const int m = i % NM, v = i / NM;
       double R = 0.0;
       for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
-      epilogue(a, ep, e * NB + i, R);
+      if (ok) epilogue(a, ep, e * NB + i, R);
     }
   }
 }

@@ -522,6 +522,7 @@ struct dgj_ctx {
   int residual_evals = 0;
   int res_nt[3] = {0, 0, 0};       // block sizes of the volume, face and lift kernels (0: default)
   int fused_nt = 0;                // block size of the fused residual kernel (0: default)
+  int fused_epw = 1;               // elements per workgroup of the fused residual kernel
   bool fused = true;               // interior-penalty residual by the fused kernel (else the three kernels)
   int last_gmres_max = 0;          // largest GMRES count of the last Newton solve since the last build
   // initial guess of the stage solves
@@ -652,16 +653,29 @@ TabK<N, Q> tables_by_value(dgj_ctx* c) {
   return tk;
 }
 
+// the fused kernel with nt threads for epw elements per workgroup (2D: 1,
+// 2, 4 or 8 elements; 3D: one)
 template <int D, int N, int Q, bool CV>
-void launch_fused(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int nt) {
-  if (nt < fused_min_threads<D, N, Q>() || nt > 256 || nt % 64)
-    fail(DGJ_EINVAL, "fused residual workgroup size %d (multiples of 64 from %d to 256)", nt,
+void launch_fused(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int nt, int epw) {
+  const int per = epw > 0 ? nt / epw : 0;
+  if (nt > 256 || nt % 64 || epw < 1 || nt % epw || per < fused_min_threads<D, N, Q>() || per % 32 ||
+      (D == 3 && epw != 1))
+    fail(DGJ_EINVAL, "fused residual tile: %d threads for %d elements (at least %d threads per element)", nt, epw,
          fused_min_threads<D, N, Q>());
-  hipLaunchKernelGGL((k_res_fused<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk);
+  const dim3 grid((unsigned)((c->n_elem + epw - 1) / epw));
+  if constexpr (D == 2) {
+    if (epw == 2) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 2>), grid, dim3(nt), 0, c->stream, a, tk); return; }
+    if (epw == 4) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 4>), grid, dim3(nt), 0, c->stream, a, tk); return; }
+    if (epw == 8) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 8>), grid, dim3(nt), 0, c->stream, a, tk); return; }
+  }
+  if (epw != 1) fail(DGJ_EINVAL, "fused residual: %d elements per workgroup not built", epw);
+  hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 1>), grid, dim3(nt), 0, c->stream, a, tk);
 }
 
 template <int D, int N, int Q>
-int default_fused_nt() { return fused_min_threads<D, N, Q>() > 128 ? 256 : (D == 2 ? 64 : 128); }
+int default_fused_nt() {
+  return fused_min_threads<D, N, Q>() > 128 ? 256 : (D == 2 ? 64 : 128);
+}
 
 // the fused kernel evaluates the interior-penalty residual; LDG (its lifted
 // auxiliary gradient) runs through the three kernels
@@ -672,8 +686,9 @@ void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
   const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
   if (use_fused(c, a)) {
     const int nt = c->fused_nt > 0 ? c->fused_nt : default_fused_nt<D, N, Q>();
-    if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt);
-    else launch_fused<D, N, Q, false>(c, a, tk, nt);
+    const int epw = c->fused_nt > 0 ? c->fused_epw : 1;
+    if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt, epw);
+    else launch_fused<D, N, Q, false>(c, a, tk, nt, epw);
     return;
   }
   if (a.ldg_r)
@@ -687,9 +702,11 @@ void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
 
 ResArgs res_args(dgj_ctx* c);
 
-// Autotuner.  Fused residual: time the kernel with every workgroup size
-// from its minimum (a thread per face point) to 256 in steps of 64 and keep
-// the fastest (chosen = {size, 0, 0}).  Three-kernel path (LDG): time each
+// Autotuner.  Fused residual: time the kernel with every tile of workgroup
+// size (64, 128, 256; 3D: from the first multiple of 64 with a thread per
+// face point) and elements per workgroup (2D: 1, 2, 4, 8 with at least a
+// thread per face point of each; 3D: 1), and keep the fastest (chosen =
+// {size, elements per workgroup, 0}).  Three-kernel path (LDG): time each
 // kernel alone with block sizes 64, 128 and 256 at the state u (the other
 // kernels' inputs left in place by one full evaluation) and keep the
 // fastest per kernel.
@@ -706,11 +723,19 @@ void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* 
   HIPCHK(hipEventCreate(&e1));
   if (use_fused(c, a)) {
     float best = 0.0f;
-    int bnt = 0, ci = 0;
-    for (int nt = fused_min_threads<D, N, Q>(); nt <= 256; nt += 64, ++ci) {
+    int bnt = 0, bepw = 1, ci = 0;
+    std::vector<std::pair<int, int>> tiles;
+    for (int epw : {1, 2, 4, 8})
+      for (int nt : {64, 128, 192, 256}) {
+        const int per = nt / epw;
+        if (nt % epw || per < fused_min_threads<D, N, Q>() || per % 32 || (D == 3 && epw != 1)) continue;
+        if (nt == 192 && (D == 2 || epw != 1)) continue;
+        tiles.push_back({nt, epw});
+      }
+    for (auto [nt, epw] : tiles) {
       auto run = [&]() {
-        if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt);
-        else launch_fused<D, N, Q, false>(c, a, tk, nt);
+        if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt, epw);
+        else launch_fused<D, N, Q, false>(c, a, tk, nt, epw);
       };
       run();
       HIPCHK(hipEventRecord(e0, c->stream));
@@ -721,10 +746,12 @@ void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* 
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       ms /= reps;
       if (times && ci < 9) times[ci] = ms;
-      if (bnt == 0 || ms < best) { best = ms; bnt = nt; }
+      ++ci;
+      if (bnt == 0 || ms < best) { best = ms; bnt = nt; bepw = epw; }
     }
     c->fused_nt = bnt;
-    if (chosen) { chosen[0] = bnt; chosen[1] = 0; chosen[2] = 0; }
+    c->fused_epw = bepw;
+    if (chosen) { chosen[0] = bnt; chosen[1] = bepw; chosen[2] = 0; }
     HIPCHK(hipEventDestroy(e0));
     HIPCHK(hipEventDestroy(e1));
     return;

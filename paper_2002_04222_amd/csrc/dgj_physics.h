@@ -186,6 +186,91 @@ __device__ __forceinline__ void viscous_flux(const Phys& ph, const T* U, const T
   }
 }
 
+// Normal viscous fluxes of rank-one gradients d (x) dU (grad U_v = d dU_v),
+// the interior-penalty and symmetric terms of Eq. 12: with
+// w_c = (dU_{1+c} - u_c dU_0) / rho (then grad u = d (x) w) and
+// e~ = (dU_E - (E/rho) dU_0) / rho - u . w,
+//   n . G[1+c] = mu ((n.d) w_c + (n.w) d_c) - 2/3 mu (d.w) n_c,
+//   n . G[E]   = u . (n . G[mom]) + kappa (n.d) e~,      n . G[0] = 0,
+// the same flux as viscous_flux (Eq. 2-6) without forming the gradient.
+// Pn = n . G(U, n (x) dU) and, if S, S[j] = 1/2 n . G(U, e_j (x) dU).
+template <int D>
+__device__ __forceinline__ void viscous_normal_rank1(const Phys& ph, const double* U, const double* dU,
+                                                     const double* n, double* Pn, double (*S)[D + 2]) {
+  constexpr int NV = D + 2;
+  if (ph.flux_mode == 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Pn[v] = 0.0;
+    if (S) {
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[j][v] = 0.0;
+    }
+    return;
+  }
+  if (ph.flux_mode == 2) {
+    double nn = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) nn += n[j] * n[j];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Pn[v] = nn * dU[v] * (1.0 / ph.Re);
+    if (S) {
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[j][v] = 0.5 * (n[j] * dU[v] * (1.0 / ph.Re));
+    }
+    return;
+  }
+  const double rho = U[0];
+  const double irho = 1.0 / rho;
+  double vel[D], w[D];
+  double ke = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) { vel[c] = U[1 + c] * irho; ke = ke + vel[c] * U[1 + c]; }
+  const double E = U[D + 1];
+  const double p = (ph.gamma - 1.0) * (E - 0.5 * ke);
+  const double mu = viscosity<double>(ph, rho, p);
+  const double kappa = mu * (ph.gamma / ph.Pr);
+  double nw = 0.0, uw = 0.0, nn = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    w[c] = (dU[1 + c] - vel[c] * dU[0]) * irho;
+    nw += n[c] * w[c];
+    uw += vel[c] * w[c];
+    nn += n[c] * n[c];
+  }
+  const double et = (dU[D + 1] - (E * irho) * dU[0]) * irho - uw;
+  // d = n
+  {
+    double work = 0.0;
+    Pn[0] = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double t = mu * (nn * w[c] + nw * n[c]) - (2.0 / 3.0) * mu * nw * n[c];
+      Pn[1 + c] = t;
+      work += vel[c] * t;
+    }
+    Pn[D + 1] = work + kappa * nn * et;
+  }
+  if (S) {
+    // d = e_j: n.d = n_j, d.w = w_j
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double work = 0.0;
+      S[j][0] = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double t = mu * (n[j] * w[c] + ((c == j) ? nw : 0.0)) - (2.0 / 3.0) * mu * w[j] * n[c];
+        S[j][1 + c] = 0.5 * t;
+        work += vel[c] * t;
+      }
+      S[j][D + 1] = 0.5 * (work + kappa * n[j] * et);
+    }
+  }
+}
+
 // n . G for G[j][v]
 template <int D>
 __device__ __forceinline__ void dot_normal(const double (*G)[D + 2], const double* n, double* out) {
@@ -442,10 +527,11 @@ __device__ __forceinline__ void riemann_flux(const Phys& ph, const double* UL, c
 // with Ubar = (Uo+Un)/2, dU = Uo - Un (interior penalty, Eq. 12 with a
 // dissipative penalty and the 1/2 of the test-gradient average).
 // S is optional (nullptr skips it).
+// The same face flux from the sum gs = go + gn of the two sides' gradients.
 template <int D>
-__device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, const double* Un,
-                                          const double (*go)[D + 2], const double (*gn)[D + 2],
-                                          const double* n, double beta, double* H, double (*S)[D + 2]) {
+__device__ __forceinline__ void face_flux_gsum(const Phys& ph, const double* Uo, const double* Un,
+                                               const double (*gs)[D + 2], const double* n, double beta, double* H,
+                                               double (*S)[D + 2]) {
   constexpr int NV = D + 2;
   double F[NV];
   if (ph.flux_mode == 2) {
@@ -468,35 +554,32 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, cons
   double Ub[NV], dU[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) { Ub[v] = 0.5 * (Uo[v] + Un[v]); dU[v] = Uo[v] - Un[v]; }
-  double ga[D][NV], G[D][NV], Gn[NV], Pn[NV];
+  double Gn[NV], Pn[NV];
+  {
+    double ga[D][NV], G[D][NV];
 #pragma unroll
-  for (int j = 0; j < D; ++j)
+    for (int j = 0; j < D; ++j)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ga[j][v] = 0.5 * (go[j][v] + gn[j][v]);
-  viscous_flux<D, double, double>(ph, Ub, ga, G);
-  dot_normal<D>(G, n, Gn);
-#pragma unroll
-  for (int j = 0; j < D; ++j)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ga[j][v] = n[j] * dU[v];
-  viscous_flux<D, double, double>(ph, Ub, ga, G);
-  dot_normal<D>(G, n, Pn);
+      for (int v = 0; v < NV; ++v) ga[j][v] = 0.5 * gs[j][v];
+    viscous_flux<D, double, double>(ph, Ub, ga, G);
+    dot_normal<D>(G, n, Gn);
+  }
+  // penalty and symmetric terms: viscous fluxes of the rank-one gradients n (x) dU, e_j (x) dU
+  viscous_normal_rank1<D>(ph, Ub, dU, n, Pn, S);
 #pragma unroll
   for (int v = 0; v < NV; ++v) H[v] = F[v] - (Gn[v] - beta * Pn[v]);
-  if (S) {
+}
+
+template <int D>
+__device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, const double* Un,
+                                          const double (*go)[D + 2], const double (*gn)[D + 2],
+                                          const double* n, double beta, double* H, double (*S)[D + 2]) {
+  double gs[D][D + 2];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+  for (int j = 0; j < D; ++j)
 #pragma unroll
-      for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) ga[i][v] = (i == j) ? dU[v] : 0.0;
-      viscous_flux<D, double, double>(ph, Ub, ga, G);
-      double t[NV];
-      dot_normal<D>(G, n, t);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) S[j][v] = 0.5 * t[v];
-    }
-  }
+    for (int v = 0; v < D + 2; ++v) gs[j][v] = go[j][v] + gn[j][v];
+  face_flux_gsum<D>(ph, Uo, Un, gs, n, beta, H, S);
 }
 
 // ---------------------------------------------------------------- boundary conditions

@@ -48,14 +48,13 @@ struct ResK {
 // ---------------------------------------------------------------- volume phases
 // Sum-factorised backward transform and reference gradients at the Gauss
 // points: sQ[0][v][q] values, sQ[1+j][v][q] d/dxi_j (W: scratch of
-// ResK::T1 + T2 doubles).  Every loop strides by blockDim.x.
+// ResK::T1 + T2 doubles).  Thread tid of the NT that work on the element;
+// every loop strides by NT.
 template <int D, int N, int Q>
-__device__ __forceinline__ void res_vol_forward(const TabK<N, Q>& tk, const double* __restrict__ sU,
-                                                double* __restrict__ W, double* __restrict__ sQ) {
+__device__ __forceinline__ void res_vol_forward(const TabK<N, Q> tk, const double* __restrict__ sU,
+                                                double* __restrict__ W, double* __restrict__ sQ, int tid, int NT) {
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
-  const int tid = threadIdx.x;
-  const int NT = blockDim.x;
   (void)NM;
   if constexpr (D == 3) {
     double* T1 = W;                  // [2][v][a0][i1 + N i2]
@@ -172,12 +171,11 @@ __device__ __forceinline__ void res_vol_forward(const TabK<N, Q>& tk, const doub
 // contravariant w|J| sum_j (d xi_k / d x_j) H_j (curved), written over the
 // gradient slots of sQ.
 template <int D, int N, int Q, bool CV>
-__device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q>& tk, const ElemParams& ep, long e,
-                                             const double* dxi, double detJ, double* __restrict__ sQ) {
+__device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q> tk, const ElemParams& ep, long e,
+                                             const double* dxi, double detJ, double* __restrict__ sQ, int tid,
+                                             int NT) {
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
-  const int tid = threadIdx.x;
-  const int NT = blockDim.x;
   (void)NM;
   // pointwise volume flux, scaled by w |J| dxi_j (overwrites the gradients);
   // curved: the contravariant flux w|J| sum_j (d xi_k/d x_j) H_j
@@ -243,12 +241,11 @@ __device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q>&
 // Transposed contraction with the derivative bases: out[v][m] =
 // sum_j sum_q d(phi_m)/d(xi_j) H_j (W: scratch of ResK::T1 + T2 doubles).
 template <int D, int N, int Q>
-__device__ __forceinline__ void res_vol_transpose(const TabK<N, Q>& tk, const double* __restrict__ sQ,
-                                                  double* __restrict__ W, double* __restrict__ out) {
+__device__ __forceinline__ void res_vol_transpose(const TabK<N, Q> tk, const double* __restrict__ sQ,
+                                                  double* __restrict__ W, double* __restrict__ out, int tid,
+                                                  int NT) {
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
-  const int tid = threadIdx.x;
-  const int NT = blockDim.x;
   if constexpr (D == 3) {
     const double* Hx = sQ + NV * NQ;
     const double* Hy = sQ + 2 * NV * NQ;
@@ -382,7 +379,7 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
   for (int i = tid; i < NB; i += NT) sU[i] = ep.in(e * NB + i);
   __syncthreads();
 
-  res_vol_forward<D, N, Q>(tk, sU, W, sQ);
+  res_vol_forward<D, N, Q>(tk, sU, W, sQ, tid, NT);
   __syncthreads();
 
   // LDG (affine boxes): the auxiliary gradient is grad u plus the lifted
@@ -463,11 +460,11 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
   __syncthreads();   // the flux loop below overwrites the gradients read above
 
   // pointwise volume flux (overwrites the gradients)
-  res_vol_flux<D, N, Q, CV>(a, tk, ep, e, dxi, detJ, sQ);
+  res_vol_flux<D, N, Q, CV>(a, tk, ep, e, dxi, detJ, sQ, tid, NT);
   __syncthreads();
 
   // transposed contraction with the derivative bases
-  res_vol_transpose<D, N, Q>(tk, sQ, W, Lvol + e * (long)NB);
+  res_vol_transpose<D, N, Q>(tk, sQ, W, Lvol + e * (long)NB, tid, NT);
 }
 
 // ---------------------------------------------------------------- LDG lifting

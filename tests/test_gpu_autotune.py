@@ -31,11 +31,22 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def _fused_sizes(dim, P):
-    """Workgroup sizes the autotuner tries for the fused kernel: multiples of
-    64 from the first that holds a thread per face point up to 256."""
+def _fused_tiles(dim, P):
+    """(workgroup size, elements per workgroup) tiles the autotuner tries for
+    the fused kernel, in its order."""
     npts = 2 * dim * (P + 2) ** (dim - 1)
-    return list(range(((npts + 63) // 64) * 64, 257, 64))
+    unit = 32 if dim == 2 else 64
+    need = ((npts + unit - 1) // unit) * unit
+    tiles = []
+    for epw in (1, 2, 4, 8):
+        for nt in (64, 128, 192, 256):
+            per = nt // epw
+            if nt % epw or per < need or per % 32 or (dim == 3 and epw != 1):
+                continue
+            if nt == 192 and (dim == 2 or epw != 1):
+                continue
+            tiles.append((nt, epw))
+    return tiles
 
 
 @pytest.mark.parametrize("dim,cells,P", [(2, (5, 4), 3), (3, (3, 2, 2), 3)])
@@ -47,13 +58,13 @@ def test_autotune_boxes_bitwise(dim, cells, P):
     u = _dev(W.random_state(mesh.n_elem, dim, P, seed=7))
     R0, R1 = ctx.empty(), ctx.empty()
     ctx.residual(u, R0)
-    # fused kernel: one size
+    # fused kernel: one tile (workgroup size, elements per workgroup)
     chosen, times = ctx.autotune(u, reps=5)
-    sizes = _fused_sizes(dim, P)
-    flat = [t for row in times for t in row][:len(sizes)]
-    assert chosen[0] in sizes and chosen[1:] == [0, 0]
+    tiles = _fused_tiles(dim, P)
+    flat = [t for row in times for t in row][:len(tiles)]
+    assert (chosen[0], chosen[1]) in tiles and chosen[2] == 0
     assert all(t > 0.0 for t in flat)
-    assert flat[sizes.index(chosen[0])] == min(flat)
+    assert flat[tiles.index((chosen[0], chosen[1]))] == min(flat)
     ctx.residual(u, R1)
     assert np.array_equal(_host(R0), _host(R1))
     # the three-kernel path: one size per kernel
@@ -139,7 +150,7 @@ def test_batch_autotune_same_residual():
     b.residual(u, R0)
     chosen = b.autotune(u, reps=3)
     assert 1 <= len(chosen) <= len(cfgs)
-    # fused kernel per order group: one size each
-    assert all(g[0] in (64, 128, 192, 256) and g[1:] == [0, 0] for g in chosen)
+    # fused kernel per order group: one tile each
+    assert all(g[0] in (64, 128, 256) and g[1] in (1, 2, 4, 8) and g[2] == 0 for g in chosen)
     b.residual(u, R1)
     assert np.array_equal(_host(R0), _host(R1))

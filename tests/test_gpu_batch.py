@@ -51,3 +51,32 @@ def test_batch_matches_solo_runs(graphs, prec):
         a, b = ui.reshape(-1).cpu().numpy(), u[o0:o1].cpu().numpy()
         assert np.array_equal(a, b), (i, np.abs(a - b).max())
         ctx.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_at_the_workload_ranges_matches_solo_runs(graphs):
+    """Instances drawn from the batching workload's ranges (meshes 4^2 to
+    32^2, P 2 to 5, Ma 0.1-0.5, Re 100-2000, SDIRK2 at CFL 20): two steps of
+    the batch, each Krylov step of all order groups one launch, equal bitwise
+    to the single-instance runs."""
+    print(f"[case] batch of 8 instances at the workload ranges vs solo, graphs={graphs}", flush=True)
+    from paper_2002_04222_amd import Batch, Context
+    cfgs = W.batch_configs(8, seed=24, nmin=4, nmax=32, pmin=2, pmax=5)
+    assert {c.P for c in cfgs} == {2, 3, 4, 5}
+    batch = Batch(cfgs)
+    batch.set_graphs(graphs)
+    u = batch.empty()
+    batch.project_tgv(torch.tensor(W.noise(batch.n_total, 24), device="cuda"), 1e-3, u)
+    dts = [c.dt() for c in cfgs]
+    u0 = u.clone()
+    steps = [batch.sdirk_step(u, dts) for _ in range(2)]
+    for i, cfg in enumerate(cfgs):
+        o0, o1 = batch.offsets[i], batch.offsets[i] + batch.counts[i]
+        ctx = Context(cfg.mesh(), cfg, pc_refresh_its=0)
+        ui = u0[o0:o1].clone().reshape(ctx.shape)
+        for k in range(2):
+            st = ctx.sdirk_step(ui, dts[i])
+            assert st["newton_its"] == steps[k][0][i][:2], (i, k)
+            assert [sum(x) for x in st["gmres_its"]] == steps[k][1][i][:2], (i, k)
+        assert torch.equal(ui.reshape(-1), u[o0:o1]), i
+        ctx.close()

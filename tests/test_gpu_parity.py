@@ -230,6 +230,25 @@ def test_project_tgv_parity():
     assert rel_err_per_var(_host(u), uo) <= 1e-13
 
 
+@pytest.mark.parametrize("P,cells", [(4, (3, 3)), (5, (3, 2))])
+def test_sdirk_step_parity_high_order_2d(P, cells):
+    """2D P = 4 and 5 (the batching workload's upper orders): two SDIRK2
+    steps with identical counts and 1e-12 per variable."""
+    _case(f"sdirk2 steps 2D P={P} cells={cells}")
+    cfg, mesh, disc = setup(2, cells, P, Ma=0.3, Re=40.0, scheme="sdirk2")
+    ctx = _ctx(cfg, mesh)
+    u0 = W.random_state(mesh.n_elem, 2, P, seed=45)
+    du = _dev(u0)
+    stepper = OS.SDIRK(disc, OS.SolverOpts(scheme="sdirk2"))
+    uo = u0
+    for k in range(2):
+        st = ctx.sdirk_step(du, 0.05)
+        uo, sto = stepper.step(uo, 0.05)
+        assert st["newton_its"] == [s.newton_its for s in sto]
+        assert st["gmres_its"] == [s.gmres_its for s in sto]
+        assert_step(_host(du), uo, f"2D P={P} SDIRK2 step {k}")
+
+
 @pytest.mark.parametrize("scheme", ["sdirk2", "sdirk3"])
 def test_sdirk_step_parity_small(scheme):
     _case(f"sdirk step small {scheme}")
