@@ -127,33 +127,66 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
     __syncthreads();
   }
 
-  // ---- modal face traces of both sides: TR[side][f][kind][v][tm]
+  // ---- modal face traces of both sides: TR[side][f][kind][v][tm] (side 0:
+  // this element on face f; side 1: the neighbour on its face f^1, zero on
+  // boundary faces); item it = (f, v, tm), tm = i + N j with i along the
+  // first tangential axis
   double* TR = WS;
   double* SA = WS + F::TR;
-  for (int it = tid; it < 2 * NF * NV * NMF; it += NT) {
-    const int tm = it % NMF;
-    const int v = (it / NMF) % NV;
-    const int f = (it / (NMF * NV)) % NF;
-    const int side = it / (NMF * NV * NF);
-    const long en = s_nb[f];
+  constexpr int NI = NF * NV * NMF;
+  auto tr_item = [&](int it, int& f, int& v, int& tm, int& mt, int& st) {
+    tm = it % NMF;
+    v = (it / NMF) % NV;
+    f = it / (NMF * NV);
     const int ax = f >> 1;
-    // side 0: this element on face f; side 1: the neighbour on its face f^1
-    const int ss = (f & 1) ^ side;
-    // mode (ia along ax, tm = i + N j with i along the first tangential axis)
-    const int mt = (tm % N) * npow<N>(tang0<D>(ax)) + (D == 3 ? (tm / N) * npow<N>(tang1<D>(ax)) : 0);
-    const int st = npow<N>(ax);
-    double tv = 0.0, tn = 0.0;
-    if (side == 0 || en >= 0) {
+    mt = (tm % N) * npow<N>(tang0<D>(ax)) + (D == 3 ? (tm / N) * npow<N>(tang1<D>(ax)) : 0);
+    st = npow<N>(ax);
+  };
+  // the neighbours' modes come from memory: a thread's loads for up to 4
+  // items are issued together, then contracted
+  for (int i0 = tid; i0 < NI; i0 += 4 * NT) {
+    double x[4][N];
 #pragma unroll
-      for (int ia = 0; ia < N; ++ia) {
-        const int m = mt + ia * st;
-        const double x = side == 0 ? sU[v * NM + m] : ep.in(en * NB + v * NM + m);
-        tv += sE[ss * N + ia] * x;
-        tn += sE[2 * N + ss * N + ia] * x;
+    for (int k = 0; k < 4; ++k) {
+      const int it = i0 + k * NT;
+      int f, v, tm, mt, st;
+      tr_item(it < NI ? it : 0, f, v, tm, mt, st);
+      const long en = s_nb[f];
+      const bool ld = it < NI && en >= 0;
+#pragma unroll
+      for (int ia = 0; ia < N; ++ia) x[k][ia] = ld ? ep.in(en * NB + v * NM + mt + ia * st) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int it = i0 + k * NT;
+      if (it < NI) {
+        int f, v, tm, mt, st;
+        tr_item(it, f, v, tm, mt, st);
+        const int ss = (f & 1) ^ 1;
+        double tv = 0.0, tn = 0.0;
+#pragma unroll
+        for (int ia = 0; ia < N; ++ia) {
+          tv += sE[ss * N + ia] * x[k][ia];
+          tn += sE[2 * N + ss * N + ia] * x[k][ia];
+        }
+        TR[((NF + f) * 2 + 0) * NV * NMF + v * NMF + tm] = tv;
+        TR[((NF + f) * 2 + 1) * NV * NMF + v * NMF + tm] = tn;
       }
     }
-    TR[((side * NF + f) * 2 + 0) * NV * NMF + v * NMF + tm] = tv;
-    TR[((side * NF + f) * 2 + 1) * NV * NMF + v * NMF + tm] = tn;
+  }
+  for (int it = tid; it < NI; it += NT) {
+    int f, v, tm, mt, st;
+    tr_item(it, f, v, tm, mt, st);
+    const int ss = f & 1;
+    double tv = 0.0, tn = 0.0;
+#pragma unroll
+    for (int ia = 0; ia < N; ++ia) {
+      const double x = sU[v * NM + mt + ia * st];
+      tv += sE[ss * N + ia] * x;
+      tn += sE[2 * N + ss * N + ia] * x;
+    }
+    TR[(f * 2 + 0) * NV * NMF + v * NMF + tm] = tv;
+    TR[(f * 2 + 1) * NV * NMF + v * NMF + tm] = tn;
   }
   __syncthreads();
   if constexpr (D == 3) {
@@ -199,6 +232,23 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
     const int t0 = tang0<D>(ax), t1 = tang1<D>(ax);
     const int pa = p % Q, pb = (D == 3) ? p / Q : 0;
     const long en = s_nb[f];
+    // curved elements: the metric d xi_k / d x_j at the point of both sides
+    // (Mo: this element on face f, Mn: the neighbour on its face f^1) and the
+    // normal and face weight of the canonical side (the side-1 element on
+    // interior faces), all loads issued before any use
+    double Mo[CV ? D * D : 1], Mn[CV ? D * D : 1], nrm[D], wf;
+    if constexpr (CV) {
+      const double* Go = a.fg + (e * NF + f) * (long)CF * NQF + p;
+#pragma unroll
+      for (int c = 0; c < D * D; ++c) Mo[c] = Go[c * NQF];
+      const double* Gn = a.fg + ((en >= 0 ? en : e) * NF + (en >= 0 ? (f ^ 1) : f)) * (long)CF * NQF + p;
+#pragma unroll
+      for (int c = 0; c < D * D; ++c) Mn[c] = Gn[c * NQF];
+      const double* G1 = (en >= 0 && !s) ? Gn : Go;
+#pragma unroll
+      for (int j = 0; j < D; ++j) nrm[j] = G1[(D * D + j) * NQF];
+      wf = G1[(D * D + D) * NQF];
+    }
     // values and physical gradients of one side at the point: side 0 this
     // element on face f, side 1 the neighbour on its face f^1 (the same code
     // for both, so the two elements of a face see bitwise the same data)
@@ -206,7 +256,7 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
     // of both sides' gradients, left first, as the face flux takes it)
     auto side_data = [&](int side, double* U, double (*G)[NV], bool accumulate) {
       const long ee = side == 0 ? e : en;
-      const int ff = side == 0 ? f : (f ^ 1);
+      const double* Ms = side == 0 ? Mo : Mn;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double val = 0.0, dt0 = 0.0, dt1 = 0.0, dn = 0.0;
@@ -236,12 +286,11 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
         for (int k = 0; k < D; ++k) gr[k] = (k == ax) ? dn : ((k == t0) ? dt0 : dt1);
         U[v] = val;
         if constexpr (CV) {
-          const double* Gp = a.fg + (ee * NF + ff) * (long)CF * NQF + p;
 #pragma unroll
           for (int j = 0; j < D; ++j) {
             double sg = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) sg += Gp[(k * D + j) * NQF] * gr[k];
+            for (int k = 0; k < D; ++k) sg += Ms[k * D + j] * gr[k];
             G[j][v] = accumulate ? G[j][v] + sg : sg;
           }
         } else {
@@ -260,17 +309,12 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
     const int sideL = (en >= 0 && !s) ? 1 : 0;
     side_data(sideL, UL, GS, false);
     if (en >= 0) side_data(1 - sideL, UR, GS, true);
-    double H[NV], Sf[D][NV], nrm[D], wf;
+    double H[NV], Sf[D][NV];
     if (en >= 0) {
       // canonical orientation: the side-1 element's normal, weights and penalty
       const long e1 = s ? e : en;
       const int f1 = s ? f : (f ^ 1);
-      if constexpr (CV) {
-        const double* Gp = a.fg + (e1 * NF + f1) * (long)CF * NQF + p;
-#pragma unroll
-        for (int j = 0; j < D; ++j) nrm[j] = Gp[(D * D + j) * NQF];
-        wf = Gp[(D * D + D) * NQF];
-      } else {
+      if constexpr (!CV) {
 #pragma unroll
         for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? 1.0 : 0.0;
         wf = a.geo[e1 * GEO + D + 2 + ax] * sW[pa];
@@ -285,12 +329,7 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
     } else {
       const int bid = -(int)en - 1;
       const int kind = a.bc_kind[bid];
-      if constexpr (CV) {
-        const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
-#pragma unroll
-        for (int j = 0; j < D; ++j) nrm[j] = Gp[(D * D + j) * NQF];
-        wf = Gp[(D * D + D) * NQF];
-      } else {
+      if constexpr (!CV) {
 #pragma unroll
         for (int j = 0; j < D; ++j) nrm[j] = (j == ax) ? (s == 1 ? 1.0 : -1.0) : 0.0;
         wf = g[D + 2 + ax] * sW[pa];
@@ -312,10 +351,9 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if constexpr (CV) {
-          const double* Gp = a.fg + (e * NF + f) * (long)CF * NQF + p;
           double sg = 0.0;
 #pragma unroll
-          for (int j = 0; j < D; ++j) sg += Gp[(k * D + j) * NQF] * Sf[j][v];
+          for (int j = 0; j < D; ++j) sg += Mo[k * D + j] * Sf[j][v];
           Af[1 + k][v] = sg;
         } else {
           Af[1 + k][v] = Sf[k][v] * dxi[k];
@@ -444,36 +482,11 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResA
   }
   if constexpr (CV) {
     __syncthreads();
-    // R[v][m] = sum_n M^-1[m][n] L[v][n], M^-1 streamed once per element by
-    // NS groups of MP threads (coalesced over m), partial sums in LDS
-    constexpr int MP = ((NM + 63) / 64) * 64;
-    constexpr int NSC = F::U / NB;
-    static_assert(NSC >= 1, "LDS staging of the mass-matrix product");
-    const int NS = NT / MP < 1 ? 1 : (NT / MP > NSC ? NSC : NT / MP);
-    double* part = WS;
-    const double* Mi = a.minv + e * (long)NM * NM;
-    for (int t = tid; t < NS * MP; t += NT) {
-      const int m = t % MP, h = t / MP;
-      if (m >= NM) continue;
-      double R[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R[v] = 0.0;
-#pragma unroll 4
-      for (int n = h; n < NM; n += NS) {
-        const double w = Mi[(long)n * NM + m];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[v] += w * sL[v * NM + n];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) part[(h * NV + v) * NM + m] = R[v];
-    }
-    __syncthreads();
-    for (int i = tid; i < NB; i += NT) {
-      const int m = i % NM, v = i / NM;
-      double R = 0.0;
-      for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
-      if (ok) epilogue(a, ep, e * NB + i, R);
-    }
+    static_assert(F::U / NB >= 1, "LDS staging of the mass-matrix product");
+    mass_inv_dense<NM, NV>(a.minv + e * (long)NM * mass_ld(NM), sL, WS, tid, NT, F::U / NB,
+                           [&](int i, double R) {
+                             if (ok) epilogue(a, ep, e * NB + i, R);
+                           });
   }
 }
 

@@ -12,7 +12,8 @@
 //           phiE[2][N] = phi_n(-1), phi_n(+1), dphiE[2][N] the derivatives.
 //   curved elements (instead of geo): vg[e][c][q] (c < D*D: d xi_k/d x_j at
 //           c = k*D + j; c = D*D: w_q |J_q|), fg[e][f][c][p] (c < D*D: d xi/d x;
-//           D*D + j: outward unit normal; D*D + D: w^G_p |J^G_p|), minv[e][NM][NM].
+//           D*D + j: outward unit normal; D*D + D: w^G_p |J^G_p|), minv[e][n][m]
+//           (column-major, columns mass_ld(NM) apart).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
@@ -126,7 +127,7 @@ struct ResArgs {
   double* ldg_r;
   // curved elements (all null for affine boxes): per-point metrics
   // vg[e][D*D+1][NQ], fg[e][NF][D*D+D+1][NQF] and the dense inverse mass
-  // matrix minv[e][NM][NM]
+  // matrix minv[e][NM][mass_ld(NM)] (column-major, padding rows zero)
   const double* vg;
   const double* fg;
   const double* minv;
@@ -272,6 +273,71 @@ __device__ __forceinline__ void vol_forward(const Tab& tb, const double* sU, dou
       sQ[2 * NV * NQ + it] = sy;
       sQ[3 * NV * NQ + it] = sz;
     }
+  }
+}
+
+// ---------------------------------------------------------------- curved mass inverse
+// Column stride of the stored inverse mass matrices of curved elements: NM
+// rounded up to even, so that every column starts on a 16-byte boundary
+// (padding rows zero).
+__host__ __device__ constexpr int mass_ld(int nm) { return (nm + 1) & ~1; }
+
+typedef double dgj_d2 __attribute__((ext_vector_type(2)));
+
+// R[v][m] = sum_n Minv[m][n] L[v][n] on one curved element (the M^-1 of
+// Eq. 13), Minv column-major with columns mass_ld(NM) apart.  The NT threads
+// form NS <= NSmax groups of whole wavefronts; a thread of group h owns the
+// row pair (2p, 2p+1) and reads it from the columns n = h, h + NS, ... with
+// 16-byte nontemporal loads, 16 in flight (the matrix is streamed once per
+// evaluation with no reuse), and the groups' partial sums meet in
+// part[NS][NV][NM] (LDS).  Every thread of the element calls it once L[v][n]
+// (LDS) is complete; out(i, R) receives result i = v NM + m once.
+template <int NM, int NV, class Out>
+__device__ __forceinline__ void mass_inv_dense(const double* __restrict__ Mi, const double* sL, double* part,
+                                               int tid, int NT, int NSmax, Out out) {
+  constexpr int NP = mass_ld(NM) / 2;
+  constexpr int GP = ((NP + 63) / 64) * 64;
+  const int NS = NT / GP < 1 ? 1 : (NT / GP > NSmax ? NSmax : NT / GP);
+  const dgj_d2* M2 = reinterpret_cast<const dgj_d2*>(Mi);
+  for (int t = tid; t < NS * GP; t += NT) {
+    const int p = t % GP, h = t / GP;
+    if (p >= NP) continue;
+    double r0[NV], r1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r0[v] = r1[v] = 0.0;
+    constexpr int BK = 16;
+    for (int n0 = h; n0 < NM; n0 += BK * NS) {
+      dgj_d2 w[BK];
+#pragma unroll
+      for (int k = 0; k < BK; ++k) {
+        const int n = n0 + k * NS;
+        w[k] = n < NM ? __builtin_nontemporal_load(M2 + (long)n * NP + p) : dgj_d2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int k = 0; k < BK; ++k) {
+        const int n = n0 + k * NS;
+        if (n < NM) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const double x = sL[v * NM + n];
+            r0[v] += w[k][0] * x;
+            r1[v] += w[k][1] * x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      part[(h * NV + v) * NM + 2 * p] = r0[v];
+      if (2 * p + 1 < NM) part[(h * NV + v) * NM + 2 * p + 1] = r1[v];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < NV * NM; i += NT) {
+    const int m = i % NM, v = i / NM;
+    double R = 0.0;
+    for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
+    out(i, R);
   }
 }
 

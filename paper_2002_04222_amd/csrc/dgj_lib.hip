@@ -315,20 +315,21 @@ __global__ void k_mass_build(const double* __restrict__ tables, const double* __
   }
 }
 
-// out[e][v][m] = sum_n M[e][m][n] q[e][v][n] (M symmetric), one workgroup per element
-__global__ void k_mass_apply(const double* __restrict__ M, const double* __restrict__ q, double* __restrict__ out,
-                             int NM, int NV, long n_elem) {
+// out[e][v][m] = sum_n M[e][m][n] q[e][v][n], M[e] column-major with columns
+// ld apart, one workgroup per element
+__global__ void k_mass_apply(const double* __restrict__ M, int ld, const double* __restrict__ q,
+                             double* __restrict__ out, int NM, int NV, long n_elem) {
   __shared__ double sq[1024];
   const long e = blockIdx.x;
   if (e >= n_elem) return;
   const int NB = NV * NM;
   for (int i = threadIdx.x; i < NB; i += blockDim.x) sq[i] = q[e * NB + i];
   __syncthreads();
-  const double* Me = M + e * (long)NM * NM;
+  const double* Me = M + e * (long)NM * ld;
   for (int i = threadIdx.x; i < NB; i += blockDim.x) {
     const int m = i % NM, v = i / NM;
     double s = 0.0;
-    for (int n = 0; n < NM; ++n) s += Me[(long)n * NM + m] * sq[v * NM + n];
+    for (int n = 0; n < NM; ++n) s += Me[(long)n * ld + m] * sq[v * NM + n];
     out[e * NB + i] = s;
   }
 }
@@ -901,7 +902,7 @@ void precond_apply_bufs(dgj_ctx* c, const double* q, double* out, double* pa, do
   const int J = std::max(1, c->sv.brj_sweeps);
   if (c->curved) {
     // curved elements store (M_e - dt a A_e)^-1: the sweeps take M q
-    hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_M, q, mq, c->NM, c->NV,
+    hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_M, c->NM, q, mq, c->NM, c->NV,
                        c->n_elem);
     q = mq;
   }
@@ -1591,10 +1592,13 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       HIPCHK(hipMalloc(&c->d_rq, (size_t)E * c->dim * c->NV * nqv * sizeof(double)));
     }
     if (curved) {
-      // dense mass matrices and their inverses (Gauss-Jordan on the device)
+      // dense mass matrices and their inverses (Gauss-Jordan on the device;
+      // the inverses with columns mass_ld(NM) apart for 16-byte loads)
       const size_t mm = (size_t)E * c->NM * c->NM;
+      const int ldm = mass_ld(c->NM);
       HIPCHK(hipMalloc(&c->d_M, mm * sizeof(double)));
-      HIPCHK(hipMalloc(&c->d_Minv, mm * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_Minv, (size_t)E * c->NM * ldm * sizeof(double)));
+      HIPCHK(hipMemsetAsync(c->d_Minv, 0, (size_t)E * c->NM * ldm * sizeof(double), c->stream));
       HIPCHK(hipMalloc(&c->d_Mq, vb));
       bool launched = false;
 #define X(d, n, q)                                                                                         \
@@ -1606,8 +1610,9 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       DGJ_FOR_SHAPES(X)
 #undef X
       if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
-      HIPCHK(hipMemcpyAsync(c->d_Minv, c->d_M, mm * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      invert_blocks(c, c->d_Minv, c->d_status, E, c->NM, c->NM);
+      HIPCHK(hipMemcpy2DAsync(c->d_Minv, ldm * sizeof(double), c->d_M, c->NM * sizeof(double),
+                              c->NM * sizeof(double), (size_t)E * c->NM, hipMemcpyDeviceToDevice, c->stream));
+      invert_blocks(c, c->d_Minv, c->d_status, E, c->NM, ldm);
       std::vector<int> st(E);
       HIPCHK(hipMemcpyAsync(st.data(), c->d_status, E * sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1703,7 +1708,8 @@ int dgj_project(dgj_ctx* c, const double* f, double* u) {
 #undef X
     if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
     if (c->curved)
-      hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_Minv, rhs, u, c->NM, c->NV,
+      hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_Minv, mass_ld(c->NM), rhs, u,
+                         c->NM, c->NV,
                          c->n_elem);
     HIPCHK(hipGetLastError());
     return DGJ_OK;
@@ -1833,8 +1839,9 @@ int dgj_mass_inverse(dgj_ctx* c, double* out) {
   if (!c || !out) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     if (!c->curved) fail(DGJ_EINVAL, "mass_inverse: boxes use 1/|J| (no stored inverse)");
-    HIPCHK(hipMemcpyAsync(out, c->d_Minv, (size_t)c->n_elem * c->NM * c->NM * sizeof(double),
-                          hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpy2DAsync(out, c->NM * sizeof(double), c->d_Minv, mass_ld(c->NM) * sizeof(double),
+                            c->NM * sizeof(double), (size_t)c->n_elem * c->NM, hipMemcpyDeviceToDevice,
+                            c->stream));
     return DGJ_OK;
   });
 }

@@ -193,15 +193,15 @@ __device__ __forceinline__ void viscous_flux(const Phys& ph, const T* U, const T
 //   n . G[1+c] = mu ((n.d) w_c + (n.w) d_c) - 2/3 mu (d.w) n_c,
 //   n . G[E]   = u . (n . G[mom]) + kappa (n.d) e~,      n . G[0] = 0,
 // the same flux as viscous_flux (Eq. 2-6) without forming the gradient.
-// Pn = n . G(U, n (x) dU) and, if S, S[j] = 1/2 n . G(U, e_j (x) dU).
-template <int D>
+// Pn = n . G(U, n (x) dU) and, if WS, S[j] = 1/2 n . G(U, e_j (x) dU).
+template <int D, bool WS = true>
 __device__ __forceinline__ void viscous_normal_rank1(const Phys& ph, const double* U, const double* dU,
-                                                     const double* n, double* Pn, double (*S)[D + 2]) {
+                                                     const double* n, double* Pn, double (&S)[D][D + 2]) {
   constexpr int NV = D + 2;
   if (ph.flux_mode == 1) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Pn[v] = 0.0;
-    if (S) {
+    if constexpr (WS) {
 #pragma unroll
       for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -215,7 +215,7 @@ __device__ __forceinline__ void viscous_normal_rank1(const Phys& ph, const doubl
     for (int j = 0; j < D; ++j) nn += n[j] * n[j];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Pn[v] = nn * dU[v] * (1.0 / ph.Re);
-    if (S) {
+    if constexpr (WS) {
 #pragma unroll
       for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -254,7 +254,7 @@ __device__ __forceinline__ void viscous_normal_rank1(const Phys& ph, const doubl
     }
     Pn[D + 1] = work + kappa * nn * et;
   }
-  if (S) {
+  if constexpr (WS) {
     // d = e_j: n.d = n_j, d.w = w_j
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -526,12 +526,12 @@ __device__ __forceinline__ void riemann_flux(const Phys& ph, const double* UL, c
 //   S[j] = 1/2 n.G(Ubar, dU (x) e_j)
 // with Ubar = (Uo+Un)/2, dU = Uo - Un (interior penalty, Eq. 12 with a
 // dissipative penalty and the 1/2 of the test-gradient average).
-// S is optional (nullptr skips it).
+// S is written only when WS (a non-null array reference keeps it in registers).
 // The same face flux from the sum gs = go + gn of the two sides' gradients.
-template <int D>
+template <int D, bool WS = true>
 __device__ __forceinline__ void face_flux_gsum(const Phys& ph, const double* Uo, const double* Un,
                                                const double (*gs)[D + 2], const double* n, double beta, double* H,
-                                               double (*S)[D + 2]) {
+                                               double (&S)[D][D + 2]) {
   constexpr int NV = D + 2;
   double F[NV];
   if (ph.flux_mode == 2) {
@@ -543,7 +543,7 @@ __device__ __forceinline__ void face_flux_gsum(const Phys& ph, const double* Uo,
   if (ph.flux_mode == 1) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) H[v] = F[v];
-    if (S) {
+    if constexpr (WS) {
 #pragma unroll
       for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -565,21 +565,21 @@ __device__ __forceinline__ void face_flux_gsum(const Phys& ph, const double* Uo,
     dot_normal<D>(G, n, Gn);
   }
   // penalty and symmetric terms: viscous fluxes of the rank-one gradients n (x) dU, e_j (x) dU
-  viscous_normal_rank1<D>(ph, Ub, dU, n, Pn, S);
+  viscous_normal_rank1<D, WS>(ph, Ub, dU, n, Pn, S);
 #pragma unroll
   for (int v = 0; v < NV; ++v) H[v] = F[v] - (Gn[v] - beta * Pn[v]);
 }
 
-template <int D>
+template <int D, bool WS = true>
 __device__ __forceinline__ void face_flux(const Phys& ph, const double* Uo, const double* Un,
                                           const double (*go)[D + 2], const double (*gn)[D + 2],
-                                          const double* n, double beta, double* H, double (*S)[D + 2]) {
+                                          const double* n, double beta, double* H, double (&S)[D][D + 2]) {
   double gs[D][D + 2];
 #pragma unroll
   for (int j = 0; j < D; ++j)
 #pragma unroll
     for (int v = 0; v < D + 2; ++v) gs[j][v] = go[j][v] + gn[j][v];
-  face_flux_gsum<D>(ph, Uo, Un, gs, n, beta, H, S);
+  face_flux_gsum<D, WS>(ph, Uo, Un, gs, n, beta, H, S);
 }
 
 // ---------------------------------------------------------------- boundary conditions
@@ -719,14 +719,14 @@ __device__ __forceinline__ void ghost_state(const Phys& ph, int kind, const doub
 }
 
 // boundary face flux seen from the interior (outward normal n)
-template <int D>
+template <int D, bool WS = true>
 __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const double* Uo, const double (*go)[D + 2],
                                               const double* n, double beta, const double* Uinf, double* H,
-                                              double (*S)[D + 2]) {
+                                              double (&S)[D][D + 2]) {
   constexpr int NV = D + 2;
   double Un[NV];
   ghost_state<D>(ph, kind, Uo, n, Uinf, Un);
-  face_flux<D>(ph, Uo, Un, go, go, n, beta, H, S);
+  face_flux<D, WS>(ph, Uo, Un, go, go, n, beta, H, S);
   if (kind == BC_WALL || kind == BC_SLIP) {
     // no heat flux (and no work) through the wall: the energy components
     // keep only the Riemann flux; a slip wall also takes no tangential
@@ -739,7 +739,7 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
       riemann_flux<D>(ph, Uo, Un, n, F);
     }
     H[D + 1] = F[D + 1];
-    if (S) {
+    if constexpr (WS) {
 #pragma unroll
       for (int j = 0; j < D; ++j) S[j][D + 1] = 0.0;
     }
@@ -750,7 +750,7 @@ __device__ __forceinline__ void boundary_flux(const Phys& ph, int kind, const do
       for (int c = 0; c < D; ++c) gn += (F[1 + c] - H[1 + c]) * n[c];
 #pragma unroll
       for (int c = 0; c < D; ++c) H[1 + c] = F[1 + c] - gn * n[c];
-      if (S) {
+      if constexpr (WS) {
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           double sn = 0.0;

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
   const long base = ((e * NF + f) * NQF + p) * NV * NV;
   const long lbase = gid * (long)(NV * NV);   // JmW holds the launch's elements
   double H0[NV], H1[NV];
+  double Sd[D][NV];   // not written (the Jacobian needs no test-gradient terms)
   if (en < 0) {
     // boundary face: the condition is inside the differenced flux (Eq. 31);
     // no neighbour, so no off-diagonal Jacobian
@@ -248,12 +249,12 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
       for (int v = 0; v < NV; ++v) UD[v] = g[v * NQF];
       Uinf = UD;
     }
-    boundary_flux<D>(ph, kind, Uo, go, nrm, b, Uinf, H0, nullptr);
+    boundary_flux<D, false>(ph, kind, Uo, go, nrm, b, Uinf, H0, Sd);
     for (int l = 0; l < NV; ++l) {
       const double chi = chi_dev[l];
       const double save = Uo[l];
       Uo[l] = save + chi;
-      boundary_flux<D>(ph, kind, Uo, go, nrm, b, Uinf, H1, nullptr);
+      boundary_flux<D, false>(ph, kind, Uo, go, nrm, b, Uinf, H1, Sd);
       Uo[l] = save;
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
@@ -265,18 +266,18 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
   }
   trace_point<D, N, Q>(tb, in, en, geo + en * S::GEO, f ^ 1, p, Un, gn,
                        fg ? fg + (en * NF + (f ^ 1)) * (long)CF * NQF : nullptr);
-  face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H0, nullptr);
+  face_flux<D, false>(ph, Uo, Un, go, gn, nrm, b, H0, Sd);
   for (int l = 0; l < NV; ++l) {
     const double chi = chi_dev[l];
     double save = Uo[l];
     Uo[l] = save + chi;
-    face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H1, nullptr);
+    face_flux<D, false>(ph, Uo, Un, go, gn, nrm, b, H1, Sd);
     Uo[l] = save;
 #pragma unroll
     for (int k = 0; k < NV; ++k) JmW[lbase + k * NV + l] = wf * ((H1[k] - H0[k]) / chi);
     save = Un[l];
     Un[l] = save + chi;
-    face_flux<D>(ph, Uo, Un, go, gn, nrm, b, H1, nullptr);
+    face_flux<D, false>(ph, Uo, Un, go, gn, nrm, b, H1, Sd);
     Un[l] = save;
 #pragma unroll
     for (int k = 0; k < NV; ++k) Jp[base + k * NV + l] = (TJ)((H1[k] - H0[k]) / chi);
@@ -709,7 +710,6 @@ template <typename T> __host__ __device__ constexpr int stored_ld(int nb) {
 // widened to the accumulation type.  The block inverses are streamed once
 // per sweep with no reuse, so the loads carry the nontemporal hint (FP64
 // sweep on 16^3 P = 3: 0.58 -> 0.51 ms).
-typedef double dgj_d2 __attribute__((ext_vector_type(2)));
 typedef float dgj_f4 __attribute__((ext_vector_type(4)));
 typedef unsigned dgj_u4 __attribute__((ext_vector_type(4)));
 template <typename T>

@@ -858,39 +858,10 @@ __global__ __launch_bounds__(256) void k_res_lift(ResArgs a, TabK<N, Q> tk, cons
   }
   if constexpr (curved) {
     __syncthreads();
-    // R[v][m] = sum_n M^-1[m][n] L[v][n]: the NT threads split into NS
-    // groups of MP (>= NM) that each own one m for all variables and take
-    // every NS-th n, so M^-1 is streamed once per element, coalesced over m
-    // (the stored M^-1 is symmetric up to rounding and is read by columns);
-    // the group partial sums meet in LDS.
-    constexpr int MP = ((NM + 63) / 64) * 64;
     constexpr int NSC = (NF * (D + 1) * NV * NQF - NB) / NB;   // groups whose partial sums fit in sA
     static_assert(NSC >= 1, "LDS staging of the mass-matrix product");
-    const int NS = NT / MP < 1 ? 1 : (NT / MP > NSC ? NSC : NT / MP);
-    double* part = sA + NB;
-    const double* Mi = a.minv + e * (long)NM * NM;
-    for (int t = tid; t < NS * MP; t += NT) {
-      const int m = t % MP, h = t / MP;
-      if (m >= NM) continue;
-      double R[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R[v] = 0.0;
-#pragma unroll 4
-      for (int n = h; n < NM; n += NS) {
-        const double w = Mi[(long)n * NM + m];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[v] += w * sL[v * NM + n];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) part[(h * NV + v) * NM + m] = R[v];
-    }
-    __syncthreads();
-    for (int i = tid; i < NB; i += NT) {
-      const int m = i % NM, v = i / NM;
-      double R = 0.0;
-      for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
-      epilogue(a, ep, e * NB + i, R);
-    }
+    mass_inv_dense<NM, NV>(a.minv + e * (long)NM * mass_ld(NM), sL, sA + NB, tid, NT, NSC,
+                           [&](int i, double R) { epilogue(a, ep, e * NB + i, R); });
   }
 }
 
