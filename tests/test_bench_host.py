@@ -43,6 +43,9 @@ def test_traffic_record_matches_the_sweep_source():
     changed source voids it."""
     t = bench.measured_traffic("f64")
     assert t is not None and 3.4e9 < t < 3.6e9
+    # the cylinder workload's record: 16,384 blocks of 625 x 625 doubles per launch
+    t4 = bench.measured_traffic("f64", "cylinder-annulus-64x32x8-p4")
+    assert t4 is not None and 5.2e10 < t4 < 6.0e10
     src = os.path.join(ROOT, "paper_2002_04222_amd", "csrc", "dgj_precond.h")
     text = open(src).read()
     orig = bench.open if hasattr(bench, "open") else None
@@ -56,8 +59,33 @@ def test_traffic_record_matches_the_sweep_source():
     bench.open = fake_open
     try:
         assert bench.measured_traffic("f64") is None
+        assert bench.measured_traffic("f64", "cylinder-annulus-64x32x8-p4") is None
     finally:
         if orig is None:
             del bench.open
         else:
             bench.open = orig
+
+
+def test_residual_counter_records_match_the_kernel_sources():
+    """The committed residual counter records of both workloads belong to the
+    current residual sources (fused kernel, physics, shared helpers); a
+    changed source voids them."""
+    for name, lo, hi in (("tgv3d-16c-p3", 2.0e7, 1.0e8), ("cylinder-annulus-64x32x8-p4", 2.8e9, 4.0e9)):
+        rec = bench.residual_counters(name)
+        assert rec is not None, name
+        assert lo < rec["traffic_bytes"] < hi and rec["fp64_flops"] > 0
+    src = os.path.join(ROOT, bench.RESIDUAL_SOURCES[0])
+    text = open(src).read()
+
+    def fake_open(path, *a, **k):
+        if os.path.abspath(path) == os.path.abspath(src):
+            import io
+            return io.StringIO(text + "\n// changed\n")
+        return open(path, *a, **k)
+
+    bench.open = fake_open
+    try:
+        assert bench.residual_counters("tgv3d-16c-p3") is None
+    finally:
+        del bench.open
