@@ -875,7 +875,9 @@ def bench_batch(steps):
 
 def bench_learned(cfg, make, n_train, held, epochs=150):
     """The learned-guess form: record n_train plain steps, fit the per-element
-    MLP on the recorded stages (in the library), then from one saved state
+    MLP (its outputs averaged over the elements blend the increments'
+    differences into the extrapolated guess) on the recorded stages (in the
+    library), then from one saved state
     time `held` steps with each Newton initial guess (the paper's S_m, the
     extrapolated one, the learned one with its fallback), all stopping at the
     same absolute Newton tolerance."""
@@ -903,7 +905,7 @@ def bench_learned(cfg, make, n_train, held, epochs=150):
     torch.cuda.synchronize()
     rec_s = time.perf_counter() - t
     nb = ctx.shape[1] * ctx.shape[2]
-    ctx.mlp_create(256, W.mlp_init(2 * nb, 256, nb, seed=8))
+    ctx.mlp_create(256, W.mlp_init(2 * nb, 256, 2, seed=8))
     t = time.perf_counter()
     # in chunks of passes (the optimiser's state carries over between calls)
     done = 0
@@ -917,7 +919,7 @@ def bench_learned(cfg, make, n_train, held, epochs=150):
     del S_rec, I_rec
     log(f"learned: recorded {n_train} steps in {rec_s:.1f} s, fit loss {loss:.3e} in {fit_s:.1f} s")
     u_save = u.clone()
-    inc_save = torch.empty((2, stages, n), dtype=torch.float64, device="cuda")
+    inc_save = torch.empty((3, stages, n), dtype=torch.float64, device="cuda")
     ctx.guess_state(inc_out=inc_save)
     res = {}
     for mode in ("paper", "extrapolated", "learned"):
@@ -927,15 +929,16 @@ def bench_learned(cfg, make, n_train, held, epochs=150):
         ctx.precond_build(uu, dt * _lam(cfg.scheme))
         torch.cuda.synchronize()
         t = time.perf_counter()
-        its, used, norms = [], [], []
+        its, used, norms, blend = [], [], [], []
         for _ in range(held):
             st = ctx.sdirk_step(uu, dt)
             its.append(st["newton_its"])
             used.append(st["guess_used"])
             norms.append(st["guess_norm"])
+            blend.append(st["guess_blend"])
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / held
-        res[mode] = {"ms_per_step": ms, "newton_its": its, "u": uu, "used": used, "norms": norms}
+        res[mode] = {"ms_per_step": ms, "newton_its": its, "u": uu, "used": used, "norms": norms, "blend": blend}
         log(f"guess {mode}: {ms:.1f} ms/step, newton {its}")
     ctx.set_guess("paper")
     base = res["paper"]["u"]
@@ -945,6 +948,7 @@ def bench_learned(cfg, make, n_train, held, epochs=150):
         out[mode] = {"ms_per_step": r["ms_per_step"], "newton_its": r["newton_its"],
                      "guess_used": r["used"],
                      "guess_norm_N_S_extrap_learned": r["norms"] if mode != "paper" else None,
+                     "learned_blend_c0_c1": r["blend"] if mode == "learned" else None,
                      "speedup_vs_paper_guess": res["paper"]["ms_per_step"] / r["ms_per_step"],
                      "rel_diff_vs_paper_guess": float(torch.linalg.norm(r["u"] - base) / torch.linalg.norm(base))}
     ctx.close()

@@ -186,6 +186,7 @@ typedef struct {
   int32_t guess_used[DGJ_MAX_STAGES];      /* per stage: 0 S_m, 1 extrapolated, 2 learned */
   double guess_norm[DGJ_MAX_STAGES][3];    /* ||N|| of the S_m, extrapolated and learned guesses
                                               (0 if not evaluated) */
+  double guess_blend[DGJ_MAX_STAGES][2];   /* the learned blend weights (c0, c1) (0 if not evaluated) */
 } dgj_step_stats;
 
 /* Create a context on the current device for the discretisation of Sec. 3.1
@@ -341,12 +342,15 @@ int dgj_reset_history(dgj_ctx *ctx);
 
 /* ---- Newton initial guess (not in the paper, which starts from S_m,
  * Eq. 21).  With inc_n = u^m - S_m the converged increment of stage m at
- * step n: the extrapolated guess is S_m + inc_{n-1} after one step and
- * S_m + 2 inc_{n-1} - inc_{n-2} after two; a learned per-element MLP
- * predicts inc_n - inc_{n-1} from the element's inc_{n-1} and
- * inc_{n-1} - inc_{n-2} (guess S_m + inc_{n-1} + prediction).  Whichever
- * candidate has the smallest ||N|| starts Newton, which then stops at the
- * same absolute tolerance alpha ||N(S_m)|| for all.
+ * step n and i_k = inc_{n-k}: the extrapolated guess is S_m + i_1 after one
+ * step and S_m + 2 i_1 - i_2 after two; the learned guess, after three,
+ *   S_m + 2 i_1 - i_2 + c0 (i_1 - i_2) + c1 (i_1 - 2 i_2 + i_3),
+ * c = (c0, c1) the mean over the elements of a per-element MLP's two
+ * outputs (c = 0: the extrapolated guess; c = (0, 1): third-order
+ * extrapolation).  The blend is global because ||N|| punishes corrections
+ * that differ between elements or variables far more than it rewards their
+ * fit.  Whichever candidate has the smallest ||N|| starts Newton, which then
+ * stops at the same absolute tolerance alpha ||N(S_m)|| for all.
  * mode: 0 S_m (the paper), 1 extrapolated, 2 learned with the extrapolated
  * guess as fallback. */
 int dgj_set_guess(dgj_ctx *ctx, int32_t mode);
@@ -356,7 +360,7 @@ int dgj_set_guess(dgj_ctx *ctx, int32_t mode);
  * (training data).  NULL stops recording. */
 int dgj_set_record(dgj_ctx *ctx, double *S_rec, double *inc_rec);
 
-/* MLP of `hidden` units per layer, n_in = 2 nb, n_out = nb (nb = (d+2)(P+1)^d):
+/* MLP of `hidden` units per layer, n_in = 2 nb, n_out = 2 (nb = (d+2)(P+1)^d):
  * z1 = x W1 + b1, h1 = tanh z1, z2 = h1 W2 + b2, h2 = tanh z2, y = h2 W3 + b3.
  * Parameters packed W1[n_in][H], b1[H], W2[H][H], b2[H], W3[H][n_out], b3[n_out]
  * (FP32 master copy, BF16 copy for the matrix-core products).  params_host:
@@ -367,25 +371,30 @@ int dgj_mlp_sizes(const dgj_ctx *ctx, int64_t *n_params, int32_t *n_in, int32_t 
 /* device FP32 parameter vectors of n_params values */
 int dgj_mlp_get_params(dgj_ctx *ctx, float *out);
 int dgj_mlp_set_params(dgj_ctx *ctx, const float *params);
-/* Per-variable scales (host, d+2 values each): features
- * x = [inc_prev/s_inc, (inc_prev - inc_prev2)/s_out]; the network predicts
- * y = (inc - inc_prev)/s_out and the learned guess is S + inc_prev + s_out y. */
-int dgj_mlp_set_scales(dgj_ctx *ctx, const double *s_inc_host, const double *s_out_host);
-/* X[e][2 nb] (FP32) from the two previous increments (FP64 states) */
-int dgj_mlp_features(dgj_ctx *ctx, const double *inc_prev, const double *inc_prev2, float *X);
-/* T[e][nb] = (inc - inc_prev) / s_out (FP32) */
-int dgj_mlp_targets(dgj_ctx *ctx, const double *inc, const double *inc_prev, float *T);
-/* Train on records written through dgj_set_record over n_steps >= 3
+/* Features X[e][2 nb] (FP32, device) of the learned guess from the three
+ * previous increments i1, i2, i3 (FP64 states, device):
+ * [(i1 - i2) / s_v, (i2 - i3) / s_v], s_v the RMS of i1 - i2 over the
+ * context's elements per variable (1 where that is zero). */
+int dgj_mlp_features(dgj_ctx *ctx, const double *i1, const double *i2, const double *i3, float *X);
+/* Pooled forward pass: cbar[k] = mean over the rows of MLP(X)[r][k] (host,
+ * n_out values; FP64 sums); keeps the activations for dgj_mlp_pool_backward. */
+int dgj_mlp_pool(dgj_ctx *ctx, const float *X, int64_t rows, double *cbar);
+/* Gradient of a loss L(cbar) of the last pooled forward pass with respect
+ * to the parameters, given dL/dcbar (host, n_out values): into grad (device
+ * FP32, n_params, may be NULL) and the context's gradient buffer. */
+int dgj_mlp_pool_backward(dgj_ctx *ctx, const double *dLdc, float *grad);
+/* Train on records written through dgj_set_record over n_steps >= 4
  * consecutive steps (S_rec, inc_rec: [n_steps][stages][n_unknowns]; S_rec
- * is not used by the current features): sets the scales to the
- * per-variable RMS of the increments and of their step-to-step change,
- * then runs `epochs` passes of Adam steps, one per (step >= 2, stage) pair
- * with all elements as the batch.  *last_loss: mean loss of the last pass. */
+ * is not used by the features).  Each (step k >= 3, stage) pair is one
+ * sample with loss ||F c - r||^2 / ||r||^2, r = inc_k - 2 i_1 + i_2 the
+ * extrapolated guess's error and F c = c0 (i_1 - i_2) + c1 (i_1 - 2 i_2 + i_3)
+ * the learned correction; `epochs` passes of Adam steps, one per sample.
+ * *last_loss: mean loss of the last pass. */
 int dgj_mlp_fit(dgj_ctx *ctx, const double *S_rec, const double *inc_rec, int32_t n_steps, int32_t epochs, double lr,
                 double *last_loss);
-/* Copy the stored stage increments of the two previous steps out
- * ([2][stages][n_unknowns], stages of the context's scheme; may be NULL) and/or in (may be NULL), to restart a
- * run from a saved point. */
+/* Copy the stored stage increments of the three previous steps out
+ * ([3][stages][n_unknowns]: i_1, i_2, i_3, stages of the context's scheme;
+ * may be NULL) and/or in (may be NULL), to restart a run from a saved point. */
 int dgj_guess_state(dgj_ctx *ctx, double *inc_out, const double *inc_in);
 /* Y[rows][n_out] = MLP(X[rows][n_in]) */
 int dgj_mlp_forward(dgj_ctx *ctx, const float *X, int64_t rows, float *Y);

@@ -53,7 +53,7 @@ class StepStats(C.Structure):
                 ("gmres_its", (C.c_int32 * 64) * MAX_STAGES), ("nres", (C.c_double * 65) * MAX_STAGES),
                 ("pc_built", C.c_int32), ("residual_evals", C.c_int32), ("status", C.c_int32),
                 ("t_total_ms", C.c_double), ("t_pc_build_ms", C.c_double), ("guess_used", C.c_int32 * MAX_STAGES),
-                ("guess_norm", (C.c_double * 3) * MAX_STAGES)]
+                ("guess_norm", (C.c_double * 3) * MAX_STAGES), ("guess_blend", (C.c_double * 2) * MAX_STAGES)]
 
     def to_dict(self):
         s = self.stages
@@ -66,6 +66,7 @@ class StepStats(C.Structure):
             "t_total_ms": self.t_total_ms, "t_pc_build_ms": self.t_pc_build_ms,
             "guess_used": [self.guess_used[m] for m in range(s)],
             "guess_norm": [[self.guess_norm[m][k] for k in range(3)] for m in range(s)],
+            "guess_blend": [[self.guess_blend[m][k] for k in range(2)] for m in range(s)],
         }
 
 
@@ -110,11 +111,11 @@ def load_library(path: str = LIB_PATH):
         "dgj_mlp_sizes": ([vp, i64p, i32p, i32p], C.c_int),
         "dgj_mlp_get_params": ([vp, vp], C.c_int),
         "dgj_mlp_set_params": ([vp, vp], C.c_int),
-        "dgj_mlp_set_scales": ([vp, vp, vp], C.c_int),
         "dgj_mlp_fit": ([vp, vp, vp, C.c_int32, C.c_int32, dp, C.POINTER(C.c_double)], C.c_int),
         "dgj_guess_state": ([vp, vp, vp], C.c_int),
-        "dgj_mlp_features": ([vp, vp, vp, vp], C.c_int),
-        "dgj_mlp_targets": ([vp, vp, vp, vp], C.c_int),
+        "dgj_mlp_features": ([vp, vp, vp, vp, vp], C.c_int),
+        "dgj_mlp_pool": ([vp, vp, C.c_int64, vp], C.c_int),
+        "dgj_mlp_pool_backward": ([vp, vp, vp], C.c_int),
         "dgj_mlp_forward": ([vp, vp, C.c_int64, vp], C.c_int),
         "dgj_mlp_grad": ([vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double)], C.c_int),
         "dgj_mlp_train_step": ([vp, vp, vp, C.c_int64, dp, C.POINTER(C.c_double)], C.c_int),
@@ -418,11 +419,6 @@ class Context:
     def mlp_set_params(self, params):
         self._check(self.lib.dgj_mlp_set_params(self.h, _fptr(params)))
 
-    def mlp_set_scales(self, s_inc, s_out):
-        b = np.ascontiguousarray(s_inc, dtype=np.float64)
-        c = np.ascontiguousarray(s_out, dtype=np.float64)
-        self._check(self.lib.dgj_mlp_set_scales(self.h, b.ctypes.data, c.ctypes.data))
-
     def mlp_fit(self, S_rec, inc_rec, n_steps, epochs, lr):
         loss = C.c_double()
         self._check(self.lib.dgj_mlp_fit(self.h, _ptr(S_rec), _ptr(inc_rec), int(n_steps), int(epochs), float(lr),
@@ -432,11 +428,18 @@ class Context:
     def guess_state(self, inc_out=None, inc_in=None):
         self._check(self.lib.dgj_guess_state(self.h, _ptr(inc_out), _ptr(inc_in)))
 
-    def mlp_features(self, inc_prev, inc_prev2, X):
-        self._check(self.lib.dgj_mlp_features(self.h, _ptr(inc_prev), _ptr(inc_prev2), _fptr(X)))
+    def mlp_features(self, i1, i2, i3, X):
+        self._check(self.lib.dgj_mlp_features(self.h, _ptr(i1), _ptr(i2), _ptr(i3), _fptr(X)))
 
-    def mlp_targets(self, inc, inc_prev, T):
-        self._check(self.lib.dgj_mlp_targets(self.h, _ptr(inc), _ptr(inc_prev), _fptr(T)))
+    def mlp_pool(self, X):
+        """Pooled forward pass: the mean over the rows of MLP(X) (numpy, n_out values)."""
+        out = np.zeros(self.mlp_n_out)
+        self._check(self.lib.dgj_mlp_pool(self.h, _fptr(X), X.shape[0], out.ctypes.data))
+        return out
+
+    def mlp_pool_backward(self, dLdc, grad=None):
+        d = np.ascontiguousarray(dLdc, dtype=np.float64)
+        self._check(self.lib.dgj_mlp_pool_backward(self.h, d.ctypes.data, _fptr(grad)))
 
     def mlp_forward(self, X, Y):
         self._check(self.lib.dgj_mlp_forward(self.h, _fptr(X), X.shape[0], _fptr(Y)))

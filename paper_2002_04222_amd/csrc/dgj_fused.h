@@ -55,10 +55,12 @@ struct FusedK {
   static constexpr int U1 = VOL > FACE ? VOL : FACE;
   static constexpr int U = U1 > LIFT ? U1 : LIFT;
   static constexpr int NPTS = NF * NQF;   // face points: one thread each in the flux phase
-  // workgroups of 256 threads per CU the register budget is set for: as many
-  // as the LDS holds (at most 3)
-  static constexpr int LDS_BYTES = 8 * (2 * NB + U) + 8 * (4 * N + 2 * Q * N + Q) + 8 * NF;
-  static constexpr int MINB = (160 * 1024 / LDS_BYTES) >= 3 ? 3 : ((160 * 1024 / LDS_BYTES) >= 2 ? 2 : 1);
+  // LDS of a workgroup of EPW elements, and the workgroups of 256 threads
+  // per CU the register budget is set for: as many as the LDS holds (at most 3)
+  static constexpr int lds_bytes(int epw) { return epw * 8 * (2 * NB + U + NF) + 8 * (4 * N + 2 * Q * N + Q); }
+  static constexpr int minb(int epw) {
+    return (160 * 1024 / lds_bytes(epw)) >= 3 ? 3 : ((160 * 1024 / lds_bytes(epw)) >= 2 ? 2 : 1);
+  }
 };
 
 // smallest number of threads per element: a thread per face point, in
@@ -72,7 +74,7 @@ constexpr int fused_min_threads() {
 // workgroup-size and elements-per-workgroup tile the autotuner chooses; the
 // arithmetic of each element does not depend on it)
 template <int D, int N, int Q, bool CV, int EPW>
-__global__ __launch_bounds__(256, (FusedK<D, N, Q>::MINB)) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
+__global__ __launch_bounds__(256, (FusedK<D, N, Q>::minb(EPW))) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
   using F = FusedK<D, N, Q>;
   using K = ResK<D, N, Q>;
   constexpr int NV = F::NV, NM = F::NM, NQF = F::NQF, NMF = F::NMF, NF = F::NF, NB = F::NB;

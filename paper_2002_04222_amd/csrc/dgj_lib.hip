@@ -541,9 +541,10 @@ struct dgj_ctx {
   double* d_hs = nullptr;          // per instance scalar slots [n_inst][64]
   double* d_part2 = nullptr;       // per instance reduction partials [n_inst][RED_BLOCKS]
   int* d_kused = nullptr;          // per instance Krylov vectors in use
-  int have_inc = 0;                // number of previous steps whose increments are held (0, 1, 2)
+  int have_inc = 0;                // number of previous steps whose increments are held (0 to 3)
   double* d_inc[DGJ_MAX_STAGES] = {};    // previous step's stage increments
   double* d_inc2[DGJ_MAX_STAGES] = {};   // the step before
+  double* d_inc3[DGJ_MAX_STAGES] = {};   // and the one before that
   int n_stages = 0;                // stages of the scheme
   double* d_uprev = nullptr;       // BDF2: u^{n-1}
   bool have_prev = false;          // BDF2: d_uprev holds the previous step's u^n
@@ -552,16 +553,18 @@ struct dgj_ctx {
   double* rec_S = nullptr;         // optional caller buffers [stages][n]
   double* rec_inc = nullptr;
   struct Mlp {
-    bool ready = false, scales = false;
+    bool ready = false;
     int n_in = 0, H = 0, n_out = 0;
     long np = 0, t = 0, cap = 0;
+    long pool_rows = 0;        // rows of the last pooled forward pass
     long off[6] = {0, 0, 0, 0, 0, 0};
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     uint16_t* wb = nullptr;
     uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dYb = nullptr, *dZb = nullptr;
     float *H1 = nullptr, *H2 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ = nullptr;
-    double *s_inc = nullptr, *s_out = nullptr, *loss_part = nullptr;
-    float *feat = nullptr, *pred = nullptr, *tgt = nullptr;
+    double *scale = nullptr, *loss_part = nullptr;   // per-variable feature scale; MSE partial sums
+    double *pool = nullptr;                          // pooled outputs / upstream gradient [n_out]
+    float* feat = nullptr;
     float* splitk = nullptr;   // split-K partial sums of the weight-gradient products
     long splitk_n = 0;
   } mlp;
@@ -1102,7 +1105,7 @@ void mlp_free_acts(dgj_ctx::Mlp& M) {
 
 void mlp_free(dgj_ctx::Mlp& M) {
   mlp_free_acts(M);
-  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.s_inc, M.s_out, M.loss_part, M.feat, M.pred, M.tgt, M.splitk};
+  void* ps[] = {M.w, M.g, M.m, M.v, M.wb, M.scale, M.loss_part, M.pool, M.feat, M.splitk};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   M = dgj_ctx::Mlp();
@@ -1162,13 +1165,11 @@ void mlp_forward(dgj_ctx* c, const float* X, long R) {
   gemm(c, M.H2b, H, 1, M.wb + M.off[4], M.n_out, 1, (int)R, M.n_out, H, M.w + M.off[5], 0, M.Y, nullptr, M.n_out);
 }
 
-// gradient of the mean squared error into M.g; returns the loss
-double mlp_backward(dgj_ctx* c, const float* T, long R) {
+// gradient into M.g from the upstream gradient dY of the last forward pass
+// (M.dY, M.dYb filled)
+void mlp_backward_dy(dgj_ctx* c, long R) {
   auto& M = c->mlp;
   const int H = M.H;
-  const long ny = R * M.n_out;
-  hipLaunchKernelGGL(k_mse_grad, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, M.Y, T, M.dY, M.dYb, ny,
-                     M.loss_part);
   // W3, b3
   gemm(c, M.H2b, 1, H, M.dYb, M.n_out, 1, H, M.n_out, (int)R, nullptr, 0, M.g + M.off[4], nullptr, M.n_out);
   hipLaunchKernelGGL(k_colsum, dim3((M.n_out + 127) / 128), dim3(128), 0, c->stream, M.dY, R, M.n_out, M.g + M.off[5]);
@@ -1184,12 +1185,68 @@ double mlp_backward(dgj_ctx* c, const float* T, long R) {
   // W1, b1
   gemm(c, M.Xb, 1, M.n_in, M.dZb, H, 1, M.n_in, H, (int)R, nullptr, 0, M.g + M.off[0], nullptr, H);
   hipLaunchKernelGGL(k_colsum, dim3((H + 127) / 128), dim3(128), 0, c->stream, M.dZ, R, H, M.g + M.off[1]);
+}
+
+// gradient of the mean squared error against targets T into M.g; returns the loss
+double mlp_backward(dgj_ctx* c, const float* T, long R) {
+  auto& M = c->mlp;
+  const long ny = R * M.n_out;
+  hipLaunchKernelGGL(k_mse_grad, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, M.Y, T, M.dY, M.dYb, ny,
+                     M.loss_part);
+  mlp_backward_dy(c, R);
   std::vector<double> part(RED_BLOCKS);
   HIPCHK(hipMemcpyAsync(part.data(), M.loss_part, RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   double s = 0.0;
   for (double p : part) s += p;
   return s / (double)ny;
+}
+
+// pooled outputs: cbar[k] = mean over the R rows of the last forward pass's Y[r][k] (host)
+void mlp_pool(dgj_ctx* c, long R, double* cbar) {
+  auto& M = c->mlp;
+  hipLaunchKernelGGL(k_colmean, dim3(M.n_out), dim3(256), 0, c->stream, M.Y, R, M.n_out, M.pool);
+  HIPCHK(hipMemcpyAsync(cbar, M.pool, M.n_out * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// gradient into M.g of a loss of the pooled outputs, given dL/dcbar (host):
+// every row's upstream gradient is dL/dcbar / R
+void mlp_pool_backward(dgj_ctx* c, long R, const double* dLdc) {
+  auto& M = c->mlp;
+  double dv[8];
+  for (int k = 0; k < M.n_out; ++k) dv[k] = dLdc[k] / (double)R;
+  HIPCHK(hipMemcpyAsync(M.pool, dv, M.n_out * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_fill_rows, dim3(grid_for(R * M.n_out)), dim3(256), 0, c->stream, M.dY, M.dYb, R, M.n_out,
+                     M.pool);
+  mlp_backward_dy(c, R);
+}
+
+// per-variable RMS of (a - b) over the elements of the context (host, nv values;
+// a zero RMS is replaced by 1)
+void var_rms_diff(dgj_ctx* c, const double* a, const double* b, double* out) {
+  std::vector<double> part((size_t)RED_BLOCKS * c->NV);
+  hipLaunchKernelGGL(k_varsq_diff, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, a, b, c->n_elem, c->NV, c->NM,
+                     c->d_part);
+  HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int v = 0; v < c->NV; ++v) {
+    double t = 0.0;
+    for (int k = 0; k < RED_BLOCKS; ++k) t += part[(size_t)k * c->NV + v];
+    out[v] = std::sqrt(t / (double)(c->n_elem * c->NM));
+    if (!(out[v] > 0.0)) out[v] = 1.0;
+  }
+}
+
+// features of the learned guess from the increments i1, i2, i3 into M.feat
+// (scales: the RMS of i1 - i2 per variable)
+void mlp_features(dgj_ctx* c, const double* i1, const double* i2, const double* i3, float* X) {
+  auto& M = c->mlp;
+  double sc[8];
+  var_rms_diff(c, i1, i2, sc);
+  HIPCHK(hipMemcpyAsync(M.scale, sc, c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, i1, i2, i3, c->n_elem, c->NV,
+                     c->NM, M.scale, X);
 }
 
 void mlp_require(dgj_ctx* c) {
@@ -1581,9 +1638,11 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       HIPCHK(hipMalloc(&c->d_E[m], vb));
       HIPCHK(hipMalloc(&c->d_inc[m], vb));
       HIPCHK(hipMalloc(&c->d_inc2[m], vb));
+      HIPCHK(hipMalloc(&c->d_inc3[m], vb));
       // explicit stages never write their increments
       HIPCHK(hipMemsetAsync(c->d_inc[m], 0, vb, c->stream));
       HIPCHK(hipMemsetAsync(c->d_inc2[m], 0, vb, c->stream));
+      HIPCHK(hipMemsetAsync(c->d_inc3[m], 0, vb, c->stream));
     }
     if (c->sv.scheme == DGJ_BDF2) HIPCHK(hipMalloc(&c->d_uprev, vb));
     if (c->ldg) {
@@ -1643,7 +1702,7 @@ void dgj_destroy(dgj_ctx* c) {
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   for (int m = 0; m < DGJ_MAX_STAGES; ++m)
-    for (double* p : {c->d_E[m], c->d_inc[m], c->d_inc2[m]})
+    for (double* p : {c->d_E[m], c->d_inc[m], c->d_inc2[m], c->d_inc3[m]})
       if (p) (void)hipFree(p);
   if (c->d_nbr) (void)hipFree(c->d_nbr);
   if (c->d_bc_kind) (void)hipFree(c->d_bc_kind);
@@ -1954,13 +2013,19 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
         const double nE = norm(c, c->d_N);
         st->guess_norm[m][1] = nE;
         if (nE < best) { best = nE; copy(c, c->d_ubar, c->d_g2); st->guess_used[m] = 1; }
-        if (c->guess_mode == 2 && c->mlp.ready && c->mlp.scales && c->have_inc >= 2) {
+        if (c->guess_mode == 2 && c->mlp.ready && c->have_inc >= 3) {
+          // learned: the network's outputs over the elements, averaged, blend
+          // the first and second differences of the increments into the
+          // extrapolated guess
           auto& M = c->mlp;
-          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_inc[m],
-                             c->d_inc2[m], c->n_elem, c->NV, c->NM, M.s_inc, M.s_out, M.feat);
+          mlp_features(c, c->d_inc[m], c->d_inc2[m], c->d_inc3[m], M.feat);
           mlp_forward(c, M.feat, c->n_elem);
-          hipLaunchKernelGGL(k_mlp_guess, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_S, c->d_inc[m], M.Y,
-                             c->n, c->NV, c->NM, M.s_out, c->d_g2);
+          double cb[8];
+          mlp_pool(c, c->n_elem, cb);
+          st->guess_blend[m][0] = cb[0];
+          st->guess_blend[m][1] = cb[1];
+          hipLaunchKernelGGL(k_blend_guess, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_g2, c->d_S,
+                             c->d_inc[m], c->d_inc2[m], c->d_inc3[m], cb[0], cb[1], c->n);
           stage_residual(c, c->d_g2, c->d_S, dta_m, c->d_N);
           const double nM = norm(c, c->d_N);
           st->guess_norm[m][2] = nM;
@@ -1997,14 +2062,15 @@ int dgj_sdirk_step(dgj_ctx* c, double* u, double dt, dgj_step_stats* stats) {
       if (!bdf2)
         hipLaunchKernelGGL(k_sub_div, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_E[m], c->d_ubar, c->d_S,
                            A[m][m], c->n);
-      // stage increment u^m - S_m, kept (with the previous one) for the next steps' guesses
+      // stage increment u^m - S_m, kept (with the two previous ones) for the next steps' guesses
+      copy(c, c->d_inc3[m], c->d_inc2[m]);
       copy(c, c->d_inc2[m], c->d_inc[m]);
       hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_inc[m], c->d_ubar, -1.0,
                          c->d_S, c->n);
       if (c->rec_S) copy(c, c->rec_S + (long)m * c->n, c->d_S);
       if (c->rec_inc) copy(c, c->rec_inc + (long)m * c->n, c->d_inc[m]);
     }
-    c->have_inc = std::min(2, c->have_inc + 1);
+    c->have_inc = std::min(3, c->have_inc + 1);
     if (bdf2) {
       copy(c, u, c->d_ubar);
     } else {
@@ -2055,7 +2121,7 @@ int dgj_mlp_create(dgj_ctx* c, int32_t hidden, const float* params_host) {
     mlp_free(c->mlp);
     auto& M = c->mlp;
     M.n_in = 2 * c->NB;
-    M.n_out = c->NB;
+    M.n_out = 2;
     M.H = hidden;
     const long sz[6] = {(long)M.n_in * M.H, M.H, (long)M.H * M.H, M.H, (long)M.H * M.n_out, M.n_out};
     long o = 0;
@@ -2066,9 +2132,8 @@ int dgj_mlp_create(dgj_ctx* c, int32_t hidden, const float* params_host) {
     HIPCHK(hipMalloc(&M.m, M.np * 4));
     HIPCHK(hipMalloc(&M.v, M.np * 4));
     HIPCHK(hipMalloc(&M.wb, M.np * 2));
-    HIPCHK(hipMalloc(&M.s_inc, 8 * sizeof(double)));
-    HIPCHK(hipMalloc(&M.s_out, 8 * sizeof(double)));
-    HIPCHK(hipMalloc(&M.tgt, (size_t)c->n_elem * M.n_out * 4));
+    HIPCHK(hipMalloc(&M.scale, 8 * sizeof(double)));
+    HIPCHK(hipMalloc(&M.pool, 8 * sizeof(double)));
     HIPCHK(hipMalloc(&M.loss_part, RED_BLOCKS * sizeof(double)));
     HIPCHK(hipMalloc(&M.feat, (size_t)c->n_elem * M.n_in * 4));
     // split-K partial sums of the weight-gradient products (at most 16
@@ -2116,44 +2181,41 @@ int dgj_mlp_set_params(dgj_ctx* c, const float* params) {
   });
 }
 
-int dgj_mlp_set_scales(dgj_ctx* c, const double* s_inc_host, const double* s_out_host) {
-  if (!c || !s_inc_host || !s_out_host) return DGJ_EINVAL;
+int dgj_mlp_features(dgj_ctx* c, const double* i1, const double* i2, const double* i3, float* X) {
+  if (!c || !i1 || !i2 || !i3 || !X) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     mlp_require(c);
-    for (int v = 0; v < c->NV; ++v)
-      if (!(s_inc_host[v] > 0.0) || !(s_out_host[v] > 0.0)) fail(DGJ_EINVAL, "scales must be positive");
-    HIPCHK(hipMemcpy(c->mlp.s_inc, s_inc_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->mlp.s_out, s_out_host, c->NV * sizeof(double), hipMemcpyHostToDevice));
-    c->mlp.scales = true;
+    mlp_features(c, i1, i2, i3, X);
     return DGJ_OK;
   });
 }
 
-int dgj_mlp_features(dgj_ctx* c, const double* inc_prev, const double* inc_prev2, float* X) {
-  if (!c || !inc_prev || !inc_prev2 || !X) return DGJ_EINVAL;
+int dgj_mlp_pool(dgj_ctx* c, const float* X, int64_t rows, double* cbar) {
+  if (!c || !X || !cbar || rows <= 0) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     mlp_require(c);
-    if (!c->mlp.scales) fail(DGJ_EINVAL, "scales not set");
-    hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(c->n)), dim3(256), 0, c->stream, inc_prev, inc_prev2, c->n_elem,
-                       c->NV, c->NM, c->mlp.s_inc, c->mlp.s_out, X);
+    mlp_forward(c, X, rows);
+    mlp_pool(c, rows, cbar);
+    c->mlp.pool_rows = rows;
     return DGJ_OK;
   });
 }
 
-int dgj_mlp_targets(dgj_ctx* c, const double* inc, const double* inc_prev, float* T) {
-  if (!c || !inc || !inc_prev || !T) return DGJ_EINVAL;
+int dgj_mlp_pool_backward(dgj_ctx* c, const double* dLdc, float* grad) {
+  if (!c || !dLdc) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     mlp_require(c);
-    if (!c->mlp.scales) fail(DGJ_EINVAL, "scales not set");
-    hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(c->n)), dim3(256), 0, c->stream, inc, inc_prev, c->n, c->NV,
-                       c->NM, c->mlp.s_out, T);
+    if (c->mlp.pool_rows <= 0) fail(DGJ_EINVAL, "pool_backward: no pooled forward pass to differentiate");
+    mlp_pool_backward(c, c->mlp.pool_rows, dLdc);
+    if (grad) HIPCHK(hipMemcpyAsync(grad, c->mlp.g, c->mlp.np * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return DGJ_OK;
   });
 }
 
 int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t n_steps, int32_t epochs, double lr,
                 double* last_loss) {
-  if (!c || !S_rec || !inc_rec || n_steps < 2 || epochs < 1 || !(lr > 0.0)) return DGJ_EINVAL;
+  if (!c || !S_rec || !inc_rec || n_steps < 4 || epochs < 1 || !(lr > 0.0)) return DGJ_EINVAL;
   return guarded(c, [&]() -> int {
     mlp_require(c);
     auto& M = c->mlp;
@@ -2162,57 +2224,52 @@ int dgj_mlp_fit(dgj_ctx* c, const double* S_rec, const double* inc_rec, int32_t 
     tableau(c->sv.scheme, A, b, s);
     const long n = c->n;
     auto rec = [&](const double* base, int step, int st) { return base + ((long)step * s + st) * n; };
-    if (n_steps < 3) fail(DGJ_EINVAL, "mlp_fit needs at least 3 recorded steps");
-    // per-variable RMS scales of the increments and of their step-to-step change
-    double acc[3][8] = {{0}};
-    long cnt[3] = {0, 0, 0};
-    std::vector<double> part((size_t)RED_BLOCKS * c->NV);
-    auto sumsq = [&](const double* a, const double* bb, int which) {
-      hipLaunchKernelGGL(k_varsq_diff, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, a, bb, c->n_elem, c->NV,
-                         c->NM, c->d_part);
-      HIPCHK(hipMemcpyAsync(part.data(), c->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      for (int v = 0; v < c->NV; ++v)
-        for (int k = 0; k < RED_BLOCKS; ++k) acc[which][v] += part[(size_t)k * c->NV + v];
-      cnt[which] += c->n_elem * c->NM;
-    };
-    for (int st = 0; st < n_steps; ++st)
+    // per sample (step k >= 3, stage m): the loss is quadratic in the pooled
+    // blend c, ||F c - r||^2 / ||r||^2 = (c^T G c - 2 h^T c + e2) / e2 with
+    // G = F^T F, h = F^T r, e2 = r^T r (FP64 reductions, taken once)
+    struct Sample { int k, m; double G[3], h[2], e2; };
+    std::vector<Sample> smp;
+    for (int k = 3; k < n_steps; ++k)
       for (int m = 0; m < s; ++m) {
-        sumsq(rec(inc_rec, st, m), nullptr, 1);
-        if (st > 0) sumsq(rec(inc_rec, st, m), rec(inc_rec, st - 1, m), 2);
+        Sample q{k, m, {0, 0, 0}, {0, 0}, 0};
+        hipLaunchKernelGGL(k_blend_terms, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(inc_rec, k, m),
+                           rec(inc_rec, k - 1, m), rec(inc_rec, k - 2, m), rec(inc_rec, k - 3, m), c->d_t1, c->d_t2,
+                           c->d_w, n);
+        const double* v[6][2] = {{c->d_t1, c->d_t1}, {c->d_t1, c->d_t2}, {c->d_t2, c->d_t2},
+                                 {c->d_t1, c->d_w},  {c->d_t2, c->d_w},  {c->d_w, c->d_w}};
+        for (int i = 0; i < 6; ++i) dot_dev(c, v[i][0], v[i][1], c->d_scal + 40 + i, 0);
+        HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal + 40, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < 3; ++i) q.G[i] = c->h_scal[i];
+        q.h[0] = c->h_scal[3];
+        q.h[1] = c->h_scal[4];
+        q.e2 = c->h_scal[5];
+        if (q.e2 > 0.0) smp.push_back(q);   // explicit stages have no increment
       }
-    double sc[3][8];
-    for (int w = 0; w < 3; ++w)
-      for (int v = 0; v < c->NV; ++v) {
-        sc[w][v] = std::sqrt(acc[w][v] / (double)cnt[w]);
-        if (!(sc[w][v] > 0.0)) sc[w][v] = 1.0;
-      }
-    HIPCHK(hipMemcpy(M.s_inc, sc[1], c->NV * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(M.s_out, sc[2], c->NV * sizeof(double), hipMemcpyHostToDevice));
-    M.scales = true;
+    if (smp.empty()) fail(DGJ_EINVAL, "mlp_fit: no implicit stage with a nonzero extrapolation error");
     double ep_loss = 0.0;
     const float b1 = 0.9f, b2 = 0.999f;
     for (int ep = 0; ep < epochs; ++ep) {
       ep_loss = 0.0;
-      int nb = 0;
-      for (int st = 2; st < n_steps; ++st)
-        for (int m = 0; m < s; ++m) {
-          hipLaunchKernelGGL(k_mlp_features, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(inc_rec, st - 1, m),
-                             rec(inc_rec, st - 2, m), c->n_elem, c->NV, c->NM, M.s_inc, M.s_out, M.feat);
-          hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(n)), dim3(256), 0, c->stream, rec(inc_rec, st, m),
-                             rec(inc_rec, st - 1, m), n, c->NV, c->NM, M.s_out, M.tgt);
-          mlp_forward(c, M.feat, c->n_elem);
-          const double l = mlp_backward(c, M.tgt, c->n_elem);
-          if (!std::isfinite(l)) fail(DGJ_ENAN, "mlp_fit: non-finite loss");
-          M.t += 1;
-          const float c1 = 1.0f - std::pow(b1, (float)M.t), c2 = 1.0f - std::pow(b2, (float)M.t);
-          hipLaunchKernelGGL(k_adam, dim3(grid_for(M.np)), dim3(256), 0, c->stream, M.w, M.wb, M.g, M.m, M.v, M.np,
-                             (float)lr, b1, b2, 1e-8f, c1, c2);
-          ep_loss += l;
-          ++nb;
-        }
-      ep_loss /= nb;
+      for (const Sample& q : smp) {
+        mlp_features(c, rec(inc_rec, q.k - 1, q.m), rec(inc_rec, q.k - 2, q.m), rec(inc_rec, q.k - 3, q.m), M.feat);
+        mlp_forward(c, M.feat, c->n_elem);
+        double cb[8];
+        mlp_pool(c, c->n_elem, cb);
+        const double Gc0 = q.G[0] * cb[0] + q.G[1] * cb[1], Gc1 = q.G[1] * cb[0] + q.G[2] * cb[1];
+        const double l = (cb[0] * Gc0 + cb[1] * Gc1 - 2.0 * (q.h[0] * cb[0] + q.h[1] * cb[1]) + q.e2) / q.e2;
+        if (!std::isfinite(l)) fail(DGJ_ENAN, "mlp_fit: non-finite loss");
+        const double dLdc[2] = {2.0 * (Gc0 - q.h[0]) / q.e2, 2.0 * (Gc1 - q.h[1]) / q.e2};
+        mlp_pool_backward(c, c->n_elem, dLdc);
+        M.t += 1;
+        const float c1 = 1.0f - std::pow(b1, (float)M.t), c2 = 1.0f - std::pow(b2, (float)M.t);
+        hipLaunchKernelGGL(k_adam, dim3(grid_for(M.np)), dim3(256), 0, c->stream, M.w, M.wb, M.g, M.m, M.v, M.np,
+                           (float)lr, b1, b2, 1e-8f, c1, c2);
+        ep_loss += l;
+      }
+      ep_loss /= (double)smp.size();
     }
+    HIPCHK(hipStreamSynchronize(c->stream));
     if (last_loss) *last_loss = ep_loss;
     return DGJ_OK;
   });
@@ -2226,13 +2283,15 @@ int dgj_guess_state(dgj_ctx* c, double* inc_out, const double* inc_in) {
       if (inc_out) {
         copy(c, inc_out + (long)m * c->n, c->d_inc[m]);
         copy(c, inc_out + (long)(S + m) * c->n, c->d_inc2[m]);
+        copy(c, inc_out + (long)(2 * S + m) * c->n, c->d_inc3[m]);
       }
       if (inc_in) {
         copy(c, c->d_inc[m], inc_in + (long)m * c->n);
         copy(c, c->d_inc2[m], inc_in + (long)(S + m) * c->n);
+        copy(c, c->d_inc3[m], inc_in + (long)(2 * S + m) * c->n);
       }
     }
-    if (inc_in) c->have_inc = 2;
+    if (inc_in) c->have_inc = 3;
     HIPCHK(hipStreamSynchronize(c->stream));
     return DGJ_OK;
   });

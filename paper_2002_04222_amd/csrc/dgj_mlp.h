@@ -1,8 +1,10 @@
-// Per-element MLP predicting the Newton initial guess of an implicit stage:
-// y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3, with x the element's two
-// previous converged stage increments (scaled) and y the scaled change of the
-// increment from the previous step.  Weights are held as an FP32 master copy and a BF16 copy; the
-// products run on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// Per-element MLP behind the learned Newton initial guess of an implicit
+// stage (not in the paper, which starts Newton from S_m, Eq. 21):
+// y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3 per element, x the
+// element's last two step-to-step changes of the converged stage increment
+// (scaled per variable), y two blend weights; the guess takes the mean of y
+// over the elements.  Weights are held as an FP32 master copy and a BF16
+// copy; the products run on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32
 // accumulate) in one strided GEMM kernel used for the forward pass and for
 // the transposed products of the backward pass.
 #pragma once
@@ -169,36 +171,68 @@ __global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ wb, const f
   }
 }
 
-// x rows: [inc_prev/s_inc | (inc_prev - inc_prev2)/s_out], per-variable scales, layout [e][v][m]
-__global__ void k_mlp_features(const double* __restrict__ inc1, const double* __restrict__ inc2, long n_elem, int nv,
-                               int nm, const double* __restrict__ s_inc, const double* __restrict__ s_out,
-                               float* __restrict__ X) {
+// x rows [(i1 - i2)/s | (i2 - i3)/s] from the three previous stage
+// increments i1, i2, i3 ([e][v][m]), s the per-variable scale
+__global__ void k_mlp_features(const double* __restrict__ i1, const double* __restrict__ i2,
+                               const double* __restrict__ i3, long n_elem, int nv, int nm,
+                               const double* __restrict__ s, float* __restrict__ X) {
   const long nb = (long)nv * nm;
   const long total = n_elem * nb;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
     const long e = i / nb, r = i % nb;
     const int v = (int)(r / nm);
-    X[e * 2 * nb + r] = (float)(inc1[i] / s_inc[v]);
-    X[e * 2 * nb + nb + r] = (float)((inc1[i] - inc2[i]) / s_out[v]);
+    X[e * 2 * nb + r] = (float)((i1[i] - i2[i]) / s[v]);
+    X[e * 2 * nb + nb + r] = (float)((i2[i] - i3[i]) / s[v]);
   }
 }
 
-// T = (inc - inc_prev) / s_out: the correction of the extrapolated increment
-__global__ void k_mlp_targets(const double* __restrict__ inc, const double* __restrict__ inc_prev, long n, int nv,
-                              int nm, const double* __restrict__ s_out, float* __restrict__ T) {
+// g = S + 2 i1 - i2 + c0 (i1 - i2) + c1 (i1 - 2 i2 + i3): the extrapolated
+// guess plus the learned blend of the first and second differences
+__global__ void k_blend_guess(double* __restrict__ g, const double* __restrict__ S, const double* __restrict__ i1,
+                              const double* __restrict__ i2, const double* __restrict__ i3, double c0, double c1,
+                              long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int v = (int)((i / nm) % nv);
-    T[i] = (float)((inc[i] - inc_prev[i]) / s_out[v]);
+    const double d1 = i1[i] - i2[i], d2 = i2[i] - i3[i];
+    g[i] = S[i] + (2.0 * i1[i] - i2[i]) + c0 * d1 + c1 * (d1 - d2);
   }
 }
 
-// guess = S + inc_prev + s_out * y
-__global__ void k_mlp_guess(const double* __restrict__ S, const double* __restrict__ inc_prev,
-                            const float* __restrict__ Y, long n, int nv, int nm, const double* __restrict__ s_out,
-                            double* __restrict__ g) {
+// training terms of one recorded stage: F0 = i1 - i2, F1 = i1 - 2 i2 + i3
+// (the blend directions) and r = inc - 2 i1 + i2 (the extrapolated guess's error)
+__global__ void k_blend_terms(const double* __restrict__ inc, const double* __restrict__ i1,
+                              const double* __restrict__ i2, const double* __restrict__ i3, double* __restrict__ F0,
+                              double* __restrict__ F1, double* __restrict__ r, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int v = (int)((i / nm) % nv);
-    g[i] = S[i] + inc_prev[i] + s_out[v] * (double)Y[i];
+    const double d1 = i1[i] - i2[i], d2 = i2[i] - i3[i];
+    F0[i] = d1;
+    F1[i] = d1 - d2;
+    r[i] = inc[i] - (2.0 * i1[i] - i2[i]);
+  }
+}
+
+// out[j] = mean over the R rows of Y[r][j]: one workgroup of 256 threads per
+// column, FP64 partial sums over rows t, t + 256, ..., then a fixed-order tree
+__global__ __launch_bounds__(256) void k_colmean(const float* __restrict__ Y, long R, int N, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (long r = threadIdx.x; r < R; r += 256) s += (double)Y[r * N + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0] / (double)R;
+}
+
+// every row of the upstream gradient dY[R][N] = dv[0..N) (FP32 and BF16 copies)
+__global__ void k_fill_rows(float* __restrict__ dY, uint16_t* __restrict__ dYb, long R, int N,
+                            const double* __restrict__ dv) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < R * N; i += (long)gridDim.x * blockDim.x) {
+    const float x = (float)dv[i % N];
+    dY[i] = x;
+    dYb[i] = f2bf(x);
   }
 }
 
