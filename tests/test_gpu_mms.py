@@ -161,8 +161,8 @@ def test_pseudo_time_steps_against_oracle_newton_bound():
     amplified by 1/sqrt(eps_hat) into every Newton correction, so the states
     cannot agree to rounding; they agree within the Newton tolerance's own
     bound ||u_d - u_o|| <= ||J^-1|| (||N(u_d)|| + ||N(u_o)||), J the exact
-    Jacobian of the stage equation (complex step) at the oracle's state --
-    the O8 fallback kappa alpha ||N^0|| made concrete -- and the device state
+    Jacobian of the stage equation (complex step) at the oracle's state (a
+    concrete form of the bound kappa alpha ||N^0||), and the device state
     meets the oracle's Newton tolerance."""
     _case("MMS pseudo-time steps vs the oracle's Newton bound, P=2 4x4")
     cfg, d, inp = mms_disc(2, 4)
