@@ -651,22 +651,37 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int*
         okD[v] = jj < ncol;
         colD[v] = Ae + (long)(okD[v] ? (jj < k0 ? jj : jj + kb) : 0) * ld;
       }
-      for (int rt = 0; rt < nrt; ++rt) {
-        const int n = rt * 16 + li;
-        const bool rowok = n < nb;
-        const bool piv_row = n >= k0 && n < k0 + kb;
-        dgj_d4 acc;
+      // RB row tiles at a time: all their loads in flight together, then
+      // RB independent MFMA chains, then the stores
+      constexpr int RB = 4;
+      for (int rt0 = 0; rt0 < nrt; rt0 += RB) {
+        dgj_d4 acc[RB];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = (okD[v] && rowok && !piv_row) ? colD[v][n] : 0.0;
+        for (int b = 0; b < RB; ++b) {
+          const int n = (rt0 + b) * 16 + li;
+          const bool rowok = n < nb;
+          const bool piv_row = n >= k0 && n < k0 + kb;
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk) {
-          const int t = 4 * kk + lq;
-          const double bv = (rowok && t < kb) ? Pan[n * (KB + 1) + t] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bv, acc, 0, 0, 0);
+          for (int v = 0; v < 4; ++v) acc[b][v] = (okD[v] && rowok && !piv_row) ? colD[v][n] : 0.0;
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (okD[v] && rowok) colD[v][n] = acc[v];
+        for (int b = 0; b < RB; ++b) {
+          const int n = (rt0 + b) * 16 + li;
+          const bool rowok = n < nb;
+#pragma unroll
+          for (int kk = 0; kk < NK; ++kk) {
+            const int t = 4 * kk + lq;
+            const double bv = (rowok && t < kb) ? Pan[n * (KB + 1) + t] : 0.0;
+            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bv, acc[b], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const int n = (rt0 + b) * 16 + li;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (okD[v] && n < nb) colD[v][n] = acc[b][v];
+        }
       }
     }
     __syncthreads();
@@ -698,12 +713,15 @@ __device__ __forceinline__ double ld_acc<double>(const double* p) { return *p; }
 
 template <typename T> __device__ __forceinline__ double jp_ld(const T* p) { return (double)(*p); }
 
-// Column stride of the stored block inverses: nb rounded up to a whole
-// number of 16-byte groups, so that every column starts on a 16-byte boundary
-// and the sweep reads them with 16-byte loads (padding rows are zero or
-// unused; e.g. 3D P = 4: nb = 625 -> 626 FP64, 628 FP32, 632 BF16).
+// Column stride of the stored block inverses, so that the sweep reads them
+// with 16-byte loads: columns of at least 1 KB start on a 128-byte boundary
+// (whole cache lines, none shared by two columns: the sweep streams the
+// blocks with the nontemporal hint, and a shared line was fetched twice),
+// smaller ones on a 16-byte boundary (padding rows are zero or unused; e.g.
+// 3D P = 4: nb = 625 -> 640 in every precision; 3D P = 3: 320 unchanged).
 template <typename T> __host__ __device__ constexpr int stored_ld(int nb) {
-  return (nb + (16 / (int)sizeof(T)) - 1) / (16 / (int)sizeof(T)) * (16 / (int)sizeof(T));
+  const int g = nb * (int)sizeof(T) >= 1024 ? 128 / (int)sizeof(T) : 16 / (int)sizeof(T);
+  return (nb + g - 1) / g * g;
 }
 
 // 16-byte load of 16/sizeof(T) consecutive entries (p 16-byte aligned),

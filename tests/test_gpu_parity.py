@@ -147,8 +147,8 @@ def test_stage_residual_and_matvec_parity():
     assert np.linalg.norm(_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
 
 
-# 3D P = 2 and 4 have odd block sizes (135, 625): FP64 blocks stored with a
-# padding row per column
+# 3D P = 2 and 4 have odd block sizes (135, 625): FP64 blocks stored with
+# padding rows (columns of whole cache lines: 144, 640 rows)
 @pytest.mark.parametrize("dim,cells,P", [(2, (3, 3), 2), (3, (2, 2, 3), 1), (3, (2, 2, 2), 3), (3, (2, 1, 1), 4),
                                          (2, (2, 2), 1), (3, (3, 2, 2), 2)])
 def test_precond_parity(dim, cells, P):
@@ -171,8 +171,8 @@ def test_precond_parity(dim, cells, P):
     assert np.abs(_host(o) - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
-# block sizes 320 (3D P = 3), 135 (3D P = 2: padded to 136 / 136 rows) and
-# 36 (2D P = 2: padded to 40 rows in BF16)
+# block sizes 320 (3D P = 3), 135 (3D P = 2: padded to 136 rows in FP32
+# and BF16) and 36 (2D P = 2: padded to 40 rows in BF16)
 @pytest.mark.parametrize("dim,cells,P", [(3, (2, 2, 2), 3), (3, (2, 2, 3), 2), (2, (3, 3), 2)])
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("bf16", 3e-2)])
 def test_precond_reduced_precision(prec, tol, dim, cells, P):
