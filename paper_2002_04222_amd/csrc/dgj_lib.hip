@@ -950,8 +950,8 @@ void build_shape(dgj_ctx* c, const double* up, double dt_a, double* Wt, double* 
 
 template <typename T, int KB>
 void invert(dgj_ctx* c, T* A, int* status, long ne, int nb, int ld, int threads) {
-  size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 32 * sizeof(T) + 32 * sizeof(int) +
-               (2 * KB + 1) * sizeof(int);
+  size_t lds = (size_t)nb * (KB + 1) * sizeof(T) + 2 * nb * sizeof(int) + 64 * sizeof(T) + 64 * sizeof(int) +
+               (3 * KB + 1) * sizeof(int);
   if (nb > 1024) fail(DGJ_EUNSUPPORTED, "block size %d above 1024", nb);
   HIPCHK(hipFuncSetAttribute((const void*)k_gj_invert<T, KB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_gj_invert<T, KB>), dim3(ne), dim3(threads), lds, c->stream, A, nb, ld, ne, status);
@@ -969,7 +969,7 @@ void invert_blocks(dgj_ctx* c, double* A, int* status, long ne, int nb, int ld) 
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   const size_t L = (size_t)lim;
-  auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 32 * 8 + 32 * 4 + (2 * kb + 1) * 4; };
+  auto lds = [nb](int kb) { return (size_t)nb * (kb + 1) * 8 + 2 * nb * 4 + 64 * 8 + 64 * 4 + (3 * kb + 1) * 4; };
   const int threads = nb <= 256 ? ((nb + 63) / 64) * 64 : (nb <= 512 ? 512 : 1024);
   const int want = nb <= 256 ? 16 : (nb <= 512 ? 24 : 32);
   if (want >= 32 && lds(32) <= L) invert<double, 32>(c, A, status, ne, nb, ld, threads);

@@ -492,11 +492,13 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
 // In-place inversion of each nb x nb block (column-major, columns ld apart,
 // blocks nb ld apart) by Gauss-Jordan elimination with partial pivoting,
 // processed in column panels of width KB held in LDS: the panel is eliminated
-// on all rows (row swaps applied to the panel only, one thread per row), then
-// the other columns take the panel's row swaps and the rank-KB update
-// x <- x(non-pivot rows) + Panel * x(pivot rows) on FP64 MFMA; finally the
-// columns are unscrambled in reverse order of the swaps.  status[e] = 1 if a
-// zero pivot was met.
+// on all rows (one thread per row, one workgroup barrier per pivot: a row
+// stays where it is inside the panel, the pivot row is scaled by its own
+// thread at the next step, and the row swaps of the panel are derived from
+// the pivots chosen afterwards), then the other columns take the panel's row
+// swaps and the rank-KB update x <- x(non-pivot rows) + Panel * x(pivot rows)
+// on FP64 MFMA; finally the columns are unscrambled in reverse order of the
+// swaps.  status[e] = 1 if a zero pivot was met.
 template <typename T, int KB>
 __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int* __restrict__ status) {
   static_assert(sizeof(T) == 8, "the trailing update runs on FP64 MFMA");
@@ -504,10 +506,11 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int*
   T* Pan = reinterpret_cast<T*>(smraw);                       // [nb][KB+1]
   int* piv = reinterpret_cast<int*>(Pan + (size_t)nb * (KB + 1));
   int* perm = piv + nb;
-  T* redv = reinterpret_cast<T*>(perm + nb);                   // [32]
-  int* redi = reinterpret_cast<int*>(redv + 32);               // [32]
-  int* srow = redi + 32;                                       // [2 KB] rows the panel's swaps touch
+  T* redv = reinterpret_cast<T*>(perm + nb);                   // [2][32] per-wave pivot candidates (by step parity)
+  int* redi = reinterpret_cast<int*>(redv + 64);               // [2][32]
+  int* srow = redi + 64;                                       // [2 KB] rows the panel's swaps touch
   int* nsrow = srow + 2 * KB;                                  // [1] their number
+  int* pphys = nsrow + 1;                                      // [KB] the panel's pivot rows (rows as loaded)
   const long e = blockIdx.x;
   if (e >= n_elem) return;
   T* Ae = A + e * (long)nb * ld;
@@ -519,69 +522,71 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int*
     const int kb = (nb - k0) < KB ? (nb - k0) : KB;
     if (r < nb)
       for (int c = 0; c < kb; ++c) Pan[r * (KB + 1) + c] = Ae[(long)(k0 + c) * ld + r];
-    __syncthreads();
+    // candidates: the rows from k0 on that are not yet pivots of this panel
+    bool elig = r < nb && r >= k0;
+    int prev = -1;        // the previous step's pivot row, scaled at this step by its thread
+    T prev_inv = (T)0;
     for (int t = 0; t < kb; ++t) {
-      const int k = k0 + t;
-      // pivot: largest |Pan[r][t]| over rows r >= k (smallest row on ties)
+      // pivot candidate of this thread's own row (rows are only ever written
+      // by their own thread), reduced over the wave
       T best = (T)-1;
       int bi = nb;
-      if (r < nb && r >= k) { T x = Pan[r * (KB + 1) + t]; best = x < (T)0 ? -x : x; bi = r; }
+      if (elig) { T x = Pan[r * (KB + 1) + t]; best = x < (T)0 ? -x : x; bi = r; }
       for (int off = 32; off > 0; off >>= 1) {
         T ob = __shfl_down(best, off, 64);
         int oi = __shfl_down(bi, off, 64);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      if (lane == 0) { redv[wid] = best; redi[wid] = bi; }
-      __syncthreads();
-      if (r == 0) {
-        T b = redv[0];
-        int i = redi[0];
-        for (int w = 1; w < nw; ++w)
-          if (redv[w] > b || (redv[w] == b && redi[w] < i)) { b = redv[w]; i = redi[w]; }
-        piv[k] = i;
-        redi[0] = i;
-        redv[0] = b;
+      T* rv = redv + (t & 1) * 32;
+      int* ri = redi + (t & 1) * 32;
+      if (lane == 0) { rv[wid] = best; ri[wid] = bi; }
+      __syncthreads();   // the wave candidates, and every row's update of the previous step
+      if (r == prev) {
+        // the previous pivot row, which no other thread reads at this step
+        for (int c = 0; c < kb; ++c)
+          Pan[r * (KB + 1) + c] = (c == t - 1) ? prev_inv : Pan[r * (KB + 1) + c] * prev_inv;
       }
-      __syncthreads();
-      const int p = redi[0];
-      if (!(redv[0] > (T)0)) bad = 1;
-      // swap rows k and p of the panel
-      if (p != k && r < kb) {
-        T a0 = Pan[k * (KB + 1) + r], a1 = Pan[p * (KB + 1) + r];
-        Pan[k * (KB + 1) + r] = a1;
-        Pan[p * (KB + 1) + r] = a0;
-      }
-      __syncthreads();
-      const T pv = Pan[k * (KB + 1) + t];
-      const T pinv = bad ? (T)0 : (T)1 / pv;
-      __syncthreads();   // every wave has read the pivot before the pivot row is scaled in place
-      // scale the pivot row
-      if (r < kb) {
-        T x = Pan[k * (KB + 1) + r];
-        Pan[k * (KB + 1) + r] = (r == t) ? pinv : x * pinv;
-      }
-      __syncthreads();
-      // eliminate column t from every other row
-      if (r < nb && r != k) {
-        T fct = Pan[r * (KB + 1) + t];
+      // the pivot: largest |value| (smallest row on ties), the same in every thread
+      T b = rv[0];
+      int p = ri[0];
+      for (int w = 1; w < nw; ++w)
+        if (rv[w] > b || (rv[w] == b && ri[w] < p)) { b = rv[w]; p = ri[w]; }
+      if (!(b > (T)0)) bad = 1;
+      const T pinv = bad ? (T)0 : (T)1 / Pan[p * (KB + 1) + t];
+      if (r == 0) pphys[t] = p;
+      // eliminate column t from every other row with the scaled pivot row
+      // (its entries scaled here; the row itself is scaled at the next step)
+      if (r < nb && r != p) {
+        const T fct = Pan[r * (KB + 1) + t];
         for (int c = 0; c < kb; ++c) {
           if (c == t) continue;
-          Pan[r * (KB + 1) + c] -= fct * Pan[k * (KB + 1) + c];
+          Pan[r * (KB + 1) + c] -= fct * (Pan[p * (KB + 1) + c] * pinv);
         }
         Pan[r * (KB + 1) + t] = -fct * pinv;
       }
-      __syncthreads();
+      if (r == p) { elig = false; prev_inv = pinv; }
+      prev = p;
     }
-    // write the panel back; composed row permutation of this panel
-    if (r < nb) {
-      for (int c = 0; c < kb; ++c) Ae[(long)(k0 + c) * ld + r] = Pan[r * (KB + 1) + c];
-      perm[r] = r;
-    }
+    __syncthreads();   // every read of the last pivot row
+    if (r == prev)
+      for (int c = 0; c < kb; ++c)
+        Pan[r * (KB + 1) + c] = (c == kb - 1) ? prev_inv : Pan[r * (KB + 1) + c] * prev_inv;
+    if (r < nb) perm[r] = r;
     __syncthreads();
     if (r == 0) {
+      // the equivalent row swaps: step t moves its pivot row (at the position
+      // the earlier swaps left it) to position k0 + t; perm[pos] = the row
+      // (as loaded) that ends at pos
       for (int t = 0; t < kb; ++t) {
-        int k = k0 + t, p = piv[k];
-        int tmp = perm[k]; perm[k] = perm[p]; perm[p] = tmp;
+        int q = pphys[t];
+        for (int u = 0; u < t; ++u) {
+          const int a0 = k0 + u, a1 = piv[k0 + u];
+          if (q == a0) q = a1;
+          else if (q == a1) q = a0;
+        }
+        piv[k0 + t] = q;
+        const int k = k0 + t;
+        int tmp = perm[k]; perm[k] = perm[q]; perm[q] = tmp;
       }
       // every row a swap moved: the pivot range and the rows below it that
       // were exchanged with it (rows below only ever receive pivot-range rows)
@@ -598,6 +603,11 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int*
       *nsrow = ns;
     }
     __syncthreads();
+    // write the panel back in the swapped row order
+    if (r < nb) {
+      const int src = perm[r];
+      for (int c = 0; c < kb; ++c) Ae[(long)(k0 + c) * ld + r] = Pan[src * (KB + 1) + c];
+    }
     // FP64 MFMA trailing update over tiles of 16 columns, one tile per wave
     // at a time: (a) the panel's row swaps are applied to the tile's
     // columns in memory (each touched row's source read before any write),
@@ -668,10 +678,11 @@ __global__ void k_gj_invert(T* __restrict__ A, int nb, int ld, long n_elem, int*
         for (int b = 0; b < RB; ++b) {
           const int n = (rt0 + b) * 16 + li;
           const bool rowok = n < nb;
+          const int pn = rowok ? perm[n] : 0;   // the panel row (as loaded) at position n
 #pragma unroll
           for (int kk = 0; kk < NK; ++kk) {
             const int t = 4 * kk + lq;
-            const double bv = (rowok && t < kb) ? Pan[n * (KB + 1) + t] : 0.0;
+            const double bv = (rowok && t < kb) ? Pan[pn * (KB + 1) + t] : 0.0;
             acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bv, acc[b], 0, 0, 0);
           }
         }
