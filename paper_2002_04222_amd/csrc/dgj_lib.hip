@@ -285,12 +285,13 @@ __global__ void k_dinv_export<double>(const double* __restrict__ Dinv, int nb, i
   }
 }
 
-// Mass matrix of curved elements, M[e][m][n] = sum_q phi_m(xi_q) w_q|J_q| phi_n(xi_q)
+// Mass matrix of curved elements, M[e][m][n] = sum_q phi_m(xi_q) w_q|J_q| phi_n(xi_q),
+// stored column-major with columns mass_ld(NM) apart (padding rows zero)
 template <int D, int N, int Q>
 __global__ void k_mass_build(const double* __restrict__ tables, const double* __restrict__ vg, long n_elem,
                              double* __restrict__ M) {
   using S = Shape<D, N, Q>;
-  constexpr int NM = S::NM, NQ = S::NQ;
+  constexpr int NM = S::NM, NQ = S::NQ, LDM = mass_ld(S::NM);
   const long total = n_elem * NM * NM;
   for (long gid = (long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += (long)gridDim.x * blockDim.x) {
     const long e = gid / (NM * NM);
@@ -311,8 +312,26 @@ __global__ void k_mass_build(const double* __restrict__ tables, const double* __
       }
       s += b * wJ[q];
     }
-    M[gid] = s;
+    M[e * NM * (long)LDM + (long)m * LDM + n] = s;
   }
+}
+
+// out[e][v][m] = sum_n M[e][m][n] q[e][v][n] for dense per-element matrices
+// stored column-major with columns mass_ld(NM) apart (the curved mass
+// matrices, for the apply of the M-scaled blocks): one workgroup per element,
+// the matrix streamed once with the residual's 16-byte-load product
+template <int NM, int NV>
+__global__ __launch_bounds__(256) void k_mass_apply_dense(const double* __restrict__ M, const double* __restrict__ q,
+                                                          double* __restrict__ out, long n_elem) {
+  constexpr int NB = NV * NM, NSC = 4;
+  __shared__ double sq[NB];
+  __shared__ double part[NSC * NB];
+  const long e = blockIdx.x;
+  if (e >= n_elem) return;
+  for (int i = threadIdx.x; i < NB; i += blockDim.x) sq[i] = q[e * NB + i];
+  __syncthreads();
+  mass_inv_dense<NM, NV>(M + e * (long)NM * mass_ld(NM), sq, part, threadIdx.x, blockDim.x, NSC,
+                         [&](int i, double R) { out[e * NB + i] = R; });
 }
 
 // out[e][v][m] = sum_n M[e][m][n] q[e][v][n], M[e] column-major with columns
@@ -899,14 +918,25 @@ void sweep_shape(dgj_ctx* c, const double* q, const double* qold, double* out, d
   else sweep_t<D, N, Q, __hip_bfloat16, float>(c, q, qold, out, dt_a, first);
 }
 
+void mass_apply_dense(dgj_ctx* c, const double* M, const double* q, double* out) {
+#define X(d, n_, q_)                                                                                           \
+  if (c->dim == d && c->N == n_ && c->nq == q_) {                                                             \
+    hipLaunchKernelGGL((k_mass_apply_dense<Shape<d, n_, q_>::NM, d + 2>), dim3(c->n_elem), dim3(256), 0, c->stream, \
+                       M, q, out, c->n_elem);                                                                 \
+    return;                                                                                                   \
+  }
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "unsupported shape");
+}
+
 // P^-1 q through the iterate buffers pa, pb and (curved meshes) the mass
 // product buffer mq, each of n unknowns
 void precond_apply_bufs(dgj_ctx* c, const double* q, double* out, double* pa, double* pb, double* mq) {
   const int J = std::max(1, c->sv.brj_sweeps);
   if (c->curved) {
     // curved elements store (M_e - dt a A_e)^-1: the sweeps take M q
-    hipLaunchKernelGGL(k_mass_apply, dim3(c->n_elem), dim3(256), 0, c->stream, c->d_M, c->NM, q, mq, c->NM, c->NV,
-                       c->n_elem);
+    mass_apply_dense(c, c->d_M, q, mq);
     q = mq;
   }
   // ping-pong so the last sweep lands in out
@@ -1655,7 +1685,8 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       // the inverses with columns mass_ld(NM) apart for 16-byte loads)
       const size_t mm = (size_t)E * c->NM * c->NM;
       const int ldm = mass_ld(c->NM);
-      HIPCHK(hipMalloc(&c->d_M, mm * sizeof(double)));
+      HIPCHK(hipMalloc(&c->d_M, (size_t)E * c->NM * ldm * sizeof(double)));
+      HIPCHK(hipMemsetAsync(c->d_M, 0, (size_t)E * c->NM * ldm * sizeof(double), c->stream));
       HIPCHK(hipMalloc(&c->d_Minv, (size_t)E * c->NM * ldm * sizeof(double)));
       HIPCHK(hipMemsetAsync(c->d_Minv, 0, (size_t)E * c->NM * ldm * sizeof(double), c->stream));
       HIPCHK(hipMalloc(&c->d_Mq, vb));
@@ -1669,8 +1700,8 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       DGJ_FOR_SHAPES(X)
 #undef X
       if (!launched) fail(DGJ_EUNSUPPORTED, "unsupported shape");
-      HIPCHK(hipMemcpy2DAsync(c->d_Minv, ldm * sizeof(double), c->d_M, c->NM * sizeof(double),
-                              c->NM * sizeof(double), (size_t)E * c->NM, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(c->d_Minv, c->d_M, (size_t)E * c->NM * ldm * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
       invert_blocks(c, c->d_Minv, c->d_status, E, c->NM, ldm);
       std::vector<int> st(E);
       HIPCHK(hipMemcpyAsync(st.data(), c->d_status, E * sizeof(int), hipMemcpyDeviceToHost, c->stream));

@@ -483,7 +483,8 @@ __global__ __launch_bounds__((AssembleSF<D, N, Q>::NT)) void k_pc_assemble_sf(
       fsum += nf * ff[f * FB + fi];
     }
     double* o = out + (long)n * ld + m;
-    const double dg = mass ? ((k == l) ? mass[(e * NM + m) * (long)NM + n] : 0.0) : ((k == l && m == n) ? 1.0 : 0.0);
+    const double dg = mass ? ((k == l) ? mass[(e * NM + m) * (long)mass_ld(NM) + n] : 0.0)
+                           : ((k == l && m == n) ? 1.0 : 0.0);
     *o = dg - sc * (*o - fsum);
   }
 }
