@@ -219,7 +219,8 @@ def _profile_record(name, tag):
 
 SWEEP_MARKER = "// ---------------------------------------------------------------- apply"
 RESIDUAL_SOURCES = ("paper_2002_04222_amd/csrc/dgj_fused.h", "paper_2002_04222_amd/csrc/dgj_residual.h",
-                    "paper_2002_04222_amd/csrc/dgj_physics.h", "paper_2002_04222_amd/csrc/dgj_kernels.h")
+                    "paper_2002_04222_amd/csrc/dgj_physics.h", "paper_2002_04222_amd/csrc/dgj_kernels.h",
+                    "paper_2002_04222_amd/csrc/dgj_tables.h")
 
 
 def measured_traffic(prec, workload="tgv3d-16c-p3"):

@@ -74,7 +74,8 @@ constexpr int fused_min_threads() {
 // workgroup-size and elements-per-workgroup tile the autotuner chooses; the
 // arithmetic of each element does not depend on it)
 template <int D, int N, int Q, bool CV, int EPW>
-__global__ __launch_bounds__(256, (FusedK<D, N, Q>::minb(EPW))) void k_res_fused(ResArgs a, TabK<N, Q> tk) {
+__global__ __launch_bounds__(256, (FusedK<D, N, Q>::minb(EPW))) void k_res_fused(ResArgs a) {
+  static constexpr TabK<N, Q> tk = make_tabk<N, Q>();
   using F = FusedK<D, N, Q>;
   using K = ResK<D, N, Q>;
   constexpr int NV = F::NV, NM = F::NM, NQF = F::NQF, NMF = F::NMF, NF = F::NF, NB = F::NB;

@@ -43,94 +43,6 @@ constexpr int RED_THREADS = 256;
 constexpr long PC_CHUNK = 4096;
 const double EPS_HAT = std::ldexp(1.0, -52);
 
-// ---------------------------------------------------------------- basis tables (host)
-// Gauss-Legendre nodes/weights by Newton iteration on P_n, and the
-// orthonormal Legendre functions phi_i = sqrt((2i+1)/2) P_i with their
-// derivatives from the three-term recurrence.
-void legendre_all(int P, double x, std::vector<double>& v, std::vector<double>& d) {
-  // P_0 = 1, P_1 = x, i P_i = (2i-1) x P_{i-1} - (i-1) P_{i-2};
-  // P_i' = P_{i-2}' + (2i-1) P_{i-1}
-  std::vector<double> p(P + 1), dp(P + 1);
-  p[0] = 1.0;
-  dp[0] = 0.0;
-  if (P >= 1) { p[1] = x; dp[1] = 1.0; }
-  for (int i = 2; i <= P; ++i) {
-    p[i] = ((2.0 * i - 1.0) * x * p[i - 1] - (i - 1.0) * p[i - 2]) / i;
-    dp[i] = dp[i - 2] + (2.0 * i - 1.0) * p[i - 1];
-  }
-  v.assign(P + 1, 0.0);
-  d.assign(P + 1, 0.0);
-  for (int i = 0; i <= P; ++i) {
-    const double c = std::sqrt((2.0 * i + 1.0) / 2.0);
-    v[i] = c * p[i];
-    d[i] = c * dp[i];
-  }
-}
-
-// P_n(z) and P_{n-1}(z)
-static void leg_pair(int n, double z, double& pn, double& pm) {
-  double p0 = 1.0, p1 = z;
-  if (n == 0) { pn = 1.0; pm = 0.0; return; }
-  for (int j = 2; j <= n; ++j) {
-    double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
-    p0 = p1;
-    p1 = p2;
-  }
-  pn = p1;
-  pm = p0;
-}
-
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
-  x.resize(n);
-  w.resize(n);
-  const double pi = 3.14159265358979323846;
-  for (int k = 0; k < n; ++k) {
-    double z = std::cos(pi * (k + 0.75) / (n + 0.5));
-    double pn, pm, dp;
-    for (int it = 0; it < 100; ++it) {
-      leg_pair(n, z, pn, pm);
-      dp = n * (z * pn - pm) / (z * z - 1.0);
-      double dz = pn / dp;
-      z -= dz;
-      if (std::fabs(dz) <= 1e-16) break;
-    }
-    leg_pair(n, z, pn, pm);
-    dp = n * (z * pn - pm) / (z * z - 1.0);
-    x[n - 1 - k] = z;
-    w[n - 1 - k] = 2.0 / ((1.0 - z * z) * dp * dp);
-  }
-}
-
-std::vector<double> build_tables(int P, int Q) {
-  const int N = P + 1;
-  std::vector<double> x, w, v, d;
-  gauss_legendre(Q, x, w);
-  std::vector<double> t(2 * Q * N + Q + 4 * N);
-  for (int q = 0; q < Q; ++q) {
-    legendre_all(P, x[q], v, d);
-    for (int n = 0; n < N; ++n) { t[q * N + n] = v[n]; t[Q * N + q * N + n] = d[n]; }
-    t[2 * Q * N + q] = w[q];
-  }
-  for (int s = 0; s < 2; ++s) {
-    legendre_all(P, s == 0 ? -1.0 : 1.0, v, d);
-    for (int n = 0; n < N; ++n) {
-      t[2 * Q * N + Q + s * N + n] = v[n];
-      t[2 * Q * N + Q + 2 * N + s * N + n] = d[n];
-    }
-  }
-  // Lagrange basis of the Gauss points evaluated at xi = -1 and +1
-  for (int s = 0; s < 2; ++s) {
-    const double xe = s == 0 ? -1.0 : 1.0;
-    for (int a = 0; a < Q; ++a) {
-      double l = 1.0;
-      for (int b = 0; b < Q; ++b)
-        if (b != a) l *= (xe - x[b]) / (x[a] - x[b]);
-      t.push_back(l);
-    }
-  }
-  return t;
-}
-
 // ---------------------------------------------------------------- vector kernels
 __device__ __forceinline__ double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -512,7 +424,6 @@ struct dgj_ctx {
   double* d_rq = nullptr;         // LDG lifted jump gradients at the volume points [E][D][NV][NQ]
   double* d_origin = nullptr;
   double* d_tab = nullptr;
-  std::vector<double> h_tab;   // tables + Lagrange weights, passed by value to the residual kernels
   double *d_trace = nullptr, *d_X = nullptr, *d_Lvol = nullptr;   // residual scratch
   // reductions
   double* d_part = nullptr;    // [RED_BLOCKS * 8]
@@ -646,40 +557,64 @@ bool shape_supported(int D, int N, int Q) {
   return false;
 }
 
+// ---------------------------------------------------------------- basis tables (host)
+// The host's copies of the constexpr tables of every built shape: the flat
+// table array (the member order of TabK) that the preconditioner and mass
+// kernels read, and the Gauss rule of the curved-element metrics.
+template <int N, int Q>
+std::vector<double> tables_of() {
+  static_assert(sizeof(TabK<N, Q>) == sizeof(double) * (2 * Q * N + Q + 4 * N + 2 * Q), "TabK layout");
+  std::vector<double> t(sizeof(TabK<N, Q>) / sizeof(double));
+  std::memcpy(t.data(), &kTab<N, Q>, sizeof(TabK<N, Q>));
+  return t;
+}
+
+std::vector<double> build_tables(int P, int Q) {
+#define X(d, n, q) if (P + 1 == n && Q == q) return tables_of<n, q>();
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "no basis tables for P %d with %d Gauss points", P, Q);
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+#define X(d, n_, q)                                 \
+  if (n == q) {                                    \
+    constexpr GaussRule<q> g = gauss_rule<q>();    \
+    x.assign(g.x, g.x + q);                        \
+    w.assign(g.w, g.w + q);                        \
+    return;                                        \
+  }
+  DGJ_FOR_SHAPES(X)
+#undef X
+  fail(DGJ_EUNSUPPORTED, "no Gauss rule with %d points", n);
+}
+
 // The three residual kernels with the context's block sizes (0: the defaults)
 template <int D, int N, int Q>
 int default_nt(int k) { return k == 1 ? 128 : (D == 2 ? 64 : (k == 0 ? 128 : 256)); }
 
 template <int D, int N, int Q, bool CV>
-void launch_res_kernel(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int k, int nt) {
+void launch_res_kernel(dgj_ctx* c, const ResArgs& a, int k, int nt) {
   using K = ResK<D, N, Q>;
   // the kernels stride by blockDim; the lift's per-thread register arrays assume at least one wavefront
   if (nt < 64 || nt > 256 || nt % 64) fail(DGJ_EINVAL, "residual workgroup size %d (64, 128, 192 or 256)", nt);
   if (k == 0) {
-    hipLaunchKernelGGL((k_res_vol<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk, c->d_trace,
+    hipLaunchKernelGGL((k_res_vol<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, c->d_trace,
                        c->d_Lvol);
   } else if (k == 1) {
     const long nf = c->n_elem * D * K::NQF;
-    hipLaunchKernelGGL((k_res_face<D, N, Q, CV>), dim3((nf + nt - 1) / nt), dim3(nt), 0, c->stream, a, tk,
+    hipLaunchKernelGGL((k_res_face<D, N, Q, CV>), dim3((nf + nt - 1) / nt), dim3(nt), 0, c->stream, a,
                        c->d_trace, c->d_X);
   } else {
-    hipLaunchKernelGGL((k_res_lift<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, tk, c->d_Lvol,
+    hipLaunchKernelGGL((k_res_lift<D, N, Q, CV>), dim3(c->n_elem), dim3(nt), 0, c->stream, a, c->d_Lvol,
                        c->d_X);
   }
-}
-
-template <int D, int N, int Q>
-TabK<N, Q> tables_by_value(dgj_ctx* c) {
-  TabK<N, Q> tk;
-  static_assert(sizeof(TabK<N, Q>) == sizeof(double) * (2 * Q * N + Q + 4 * N + 2 * Q), "TabK layout");
-  std::memcpy(&tk, c->h_tab.data(), sizeof(tk));
-  return tk;
 }
 
 // the fused kernel with nt threads for epw elements per workgroup (2D: 1,
 // 2, 4 or 8 elements; 3D: one)
 template <int D, int N, int Q, bool CV>
-void launch_fused(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int nt, int epw) {
+void launch_fused(dgj_ctx* c, const ResArgs& a, int nt, int epw) {
   const int per = epw > 0 ? nt / epw : 0;
   if (nt > 256 || nt % 64 || epw < 1 || nt % epw || per < fused_min_threads<D, N, Q>() || per % 32 ||
       (D == 3 && epw != 1))
@@ -687,12 +622,12 @@ void launch_fused(dgj_ctx* c, const ResArgs& a, const TabK<N, Q>& tk, int nt, in
          fused_min_threads<D, N, Q>());
   const dim3 grid((unsigned)((c->n_elem + epw - 1) / epw));
   if constexpr (D == 2) {
-    if (epw == 2) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 2>), grid, dim3(nt), 0, c->stream, a, tk); return; }
-    if (epw == 4) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 4>), grid, dim3(nt), 0, c->stream, a, tk); return; }
-    if (epw == 8) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 8>), grid, dim3(nt), 0, c->stream, a, tk); return; }
+    if (epw == 2) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 2>), grid, dim3(nt), 0, c->stream, a); return; }
+    if (epw == 4) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 4>), grid, dim3(nt), 0, c->stream, a); return; }
+    if (epw == 8) { hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 8>), grid, dim3(nt), 0, c->stream, a); return; }
   }
   if (epw != 1) fail(DGJ_EINVAL, "fused residual: %d elements per workgroup not built", epw);
-  hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 1>), grid, dim3(nt), 0, c->stream, a, tk);
+  hipLaunchKernelGGL((k_res_fused<D, N, Q, CV, 1>), grid, dim3(nt), 0, c->stream, a);
 }
 
 template <int D, int N, int Q>
@@ -706,20 +641,19 @@ bool use_fused(const dgj_ctx* c, const ResArgs& a) { return c->fused && !a.ldg_r
 
 template <int D, int N, int Q>
 void launch_residual_t(dgj_ctx* c, const ResArgs& a) {
-  const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
   if (use_fused(c, a)) {
     const int nt = c->fused_nt > 0 ? c->fused_nt : default_fused_nt<D, N, Q>();
     const int epw = c->fused_nt > 0 ? c->fused_epw : 1;
-    if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt, epw);
-    else launch_fused<D, N, Q, false>(c, a, tk, nt, epw);
+    if (c->curved) launch_fused<D, N, Q, true>(c, a, nt, epw);
+    else launch_fused<D, N, Q, false>(c, a, nt, epw);
     return;
   }
   if (a.ldg_r)
-    hipLaunchKernelGGL((k_ldg_lift<D, N, Q>), dim3(c->n_elem), dim3(128), 0, c->stream, a, tk, a.ldg_r);
+    hipLaunchKernelGGL((k_ldg_lift<D, N, Q>), dim3(c->n_elem), dim3(128), 0, c->stream, a, a.ldg_r);
   for (int k = 0; k < 3; ++k) {
     const int nt = c->res_nt[k] > 0 ? c->res_nt[k] : default_nt<D, N, Q>(k);
-    if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, tk, k, nt);
-    else launch_res_kernel<D, N, Q, false>(c, a, tk, k, nt);
+    if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, k, nt);
+    else launch_res_kernel<D, N, Q, false>(c, a, k, nt);
   }
 }
 
@@ -740,7 +674,6 @@ void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* 
   a.out = c->d_t1;
   a.mode = RES_R;
   launch_residual_t<D, N, Q>(c, a);
-  const TabK<N, Q> tk = tables_by_value<D, N, Q>(c);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -757,8 +690,8 @@ void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* 
       }
     for (auto [nt, epw] : tiles) {
       auto run = [&]() {
-        if (c->curved) launch_fused<D, N, Q, true>(c, a, tk, nt, epw);
-        else launch_fused<D, N, Q, false>(c, a, tk, nt, epw);
+        if (c->curved) launch_fused<D, N, Q, true>(c, a, nt, epw);
+        else launch_fused<D, N, Q, false>(c, a, nt, epw);
       };
       run();
       HIPCHK(hipEventRecord(e0, c->stream));
@@ -785,8 +718,8 @@ void autotune_t(dgj_ctx* c, const double* u, int reps, int32_t* chosen, double* 
     int bnt = 0;
     for (int ci = 0; ci < 3; ++ci) {
       auto run = [&]() {
-        if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, tk, k, cand[ci]);
-        else launch_res_kernel<D, N, Q, false>(c, a, tk, k, cand[ci]);
+        if (c->curved) launch_res_kernel<D, N, Q, true>(c, a, k, cand[ci]);
+        else launch_res_kernel<D, N, Q, false>(c, a, k, cand[ci]);
       };
       run();
       HIPCHK(hipEventRecord(e0, c->stream));
@@ -1618,7 +1551,6 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       HIPCHK(hipMemcpy(c->d_bc_state, mesh->bc_state, mesh->n_bc * NVh * sizeof(double), hipMemcpyHostToDevice));
     }
     std::vector<double> tab = build_tables(c->P, c->nq);
-    c->h_tab = tab;
     {
       const long nqf = (long)std::pow(c->nq, D - 1);
       HIPCHK(hipMalloc(&c->d_trace, (size_t)E * NF * (D + 1) * c->NV * nqf * sizeof(double)));

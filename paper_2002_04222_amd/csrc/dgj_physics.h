@@ -92,6 +92,17 @@ template <int M> __device__ __forceinline__ Dual<M> dsqrt(const Dual<M>& a) {
 }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
 
+// 1/x for the positive, normal quantities of the pointwise fluxes (densities,
+// c^2, sums of square roots): the hardware reciprocal estimate refined by two
+// Newton steps, within about an ulp of the quotient, in place of the full
+// IEEE division sequence.  Dual numbers keep their quotient rule.
+__device__ __forceinline__ double rcp_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+template <int M> __device__ __forceinline__ Dual<M> rcp_pos(const Dual<M>& x) { return 1.0 / x; }
+
 // ---------------------------------------------------------------- fluxes
 template <typename T>
 __device__ __forceinline__ T viscosity(const Phys& ph, const T& rho, const T& p) {
@@ -113,7 +124,7 @@ __device__ __forceinline__ void euler_flux(const Phys& ph, const T* U, T (*F)[D 
     return;
   }
   T rho = U[0];
-  T irho = 1.0 / rho;
+  T irho = rcp_pos(rho);
   T vel[D];
   T ke = T(0.0);
 #pragma unroll
@@ -148,7 +159,7 @@ __device__ __forceinline__ void viscous_flux(const Phys& ph, const T* U, const T
     return;
   }
   T rho = U[0];
-  T irho = 1.0 / rho;
+  T irho = rcp_pos(rho);
   T vel[D];
   T ke = T(0.0);
 #pragma unroll
@@ -224,7 +235,7 @@ __device__ __forceinline__ void viscous_normal_rank1(const Phys& ph, const doubl
     return;
   }
   const double rho = U[0];
-  const double irho = 1.0 / rho;
+  const double irho = rcp_pos(rho);
   double vel[D], w[D];
   double ke = 0.0;
 #pragma unroll
@@ -291,19 +302,21 @@ __device__ __forceinline__ void roe_flux(const Phys& ph, const double* UL, const
                                          double* Fn) {
   constexpr int NV = D + 2;
   const double g = ph.gamma;
+  // one division per reciprocal (1/rho of each side, 1/c^2) instead of per quotient
   double rL = UL[0], rR = UR[0];
+  const double irL = rcp_pos(rL), irR = rcp_pos(rR);
   double vL[D], vR[D], kL = 0.0, kR = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
-    vL[c] = UL[1 + c] / rL; vR[c] = UR[1 + c] / rR;
+    vL[c] = UL[1 + c] * irL; vR[c] = UR[1 + c] * irR;
     kL += vL[c] * UL[1 + c]; kR += vR[c] * UR[1 + c];
   }
   double pL = (g - 1.0) * (UL[D + 1] - 0.5 * kL);
   double pR = (g - 1.0) * (UR[D + 1] - 0.5 * kR);
-  double HL = (UL[D + 1] + pL) / rL, HR = (UR[D + 1] + pR) / rR;
+  double HL = (UL[D + 1] + pL) * irL, HR = (UR[D + 1] + pR) * irR;
   double sL = sqrt(rL), sR = sqrt(rR);
   double rt = sL * sR;
-  double isum = 1.0 / (sL + sR);
+  double isum = rcp_pos(sL + sR);
   double vt[D], q2 = 0.0, unt = 0.0, dun = 0.0, dv[D], unL = 0.0, unR = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
@@ -319,9 +332,10 @@ __device__ __forceinline__ void roe_flux(const Phys& ph, const double* UL, const
   double c2 = (g - 1.0) * (Ht - 0.5 * q2);
   double ct = sqrt(c2);
   double dr = rR - rL, dp = pR - pL;
-  double a1 = (dp - rt * ct * dun) / (2.0 * c2);
-  double a5 = (dp + rt * ct * dun) / (2.0 * c2);
-  double a2 = dr - dp / c2;
+  const double ic2 = rcp_pos(c2);
+  double a1 = (dp - rt * ct * dun) * (0.5 * ic2);
+  double a5 = (dp + rt * ct * dun) * (0.5 * ic2);
+  double a2 = dr - dp * ic2;
   double l1 = fabs_(unt - ct), l2 = fabs_(unt), l5 = fabs_(unt + ct);
   double diss[NV];
   double c1 = l1 * a1, c5 = l5 * a5;

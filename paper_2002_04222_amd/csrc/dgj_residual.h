@@ -15,23 +15,14 @@
 //               over the 2D faces, times 1/|J| (M^-1 of the orthonormal basis on
 //               affine elements), then the R / N / Jv epilogue.
 // Each face flux is computed once, so the element sums of the residual
-// cancel exactly across interior faces.  The 1D tables are passed by value
-// as kernel arguments: with the fully unrolled contractions their entries
-// are uniform across the wavefront and sit in scalar registers.
+// cancel exactly across interior faces.  The 1D tables are compile-time
+// constants of each kernel (make_tabk): the fully unrolled contractions take
+// their entries as immediate operands.
 #pragma once
 #include "dgj_kernels.h"
+#include "dgj_tables.h"
 
 namespace dgj {
-
-template <int N, int Q>
-struct TabK {
-  double B[Q][N];
-  double Dq[Q][N];
-  double w[Q];
-  double phiE[2][N];
-  double dphiE[2][N];
-  double lag[2][Q];   // Lagrange basis of the Gauss points at xi = -1, +1
-};
 
 template <int D, int N, int Q>
 struct ResK {
@@ -51,7 +42,7 @@ struct ResK {
 // ResK::T1 + T2 doubles).  Thread tid of the NT that work on the element;
 // every loop strides by NT.
 template <int D, int N, int Q>
-__device__ __forceinline__ void res_vol_forward(const TabK<N, Q> tk, const double* __restrict__ sU,
+__device__ __forceinline__ void res_vol_forward(const TabK<N, Q>& tk, const double* __restrict__ sU,
                                                 double* __restrict__ W, double* __restrict__ sQ, int tid, int NT) {
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ;
@@ -171,7 +162,7 @@ __device__ __forceinline__ void res_vol_forward(const TabK<N, Q> tk, const doubl
 // contravariant w|J| sum_j (d xi_k / d x_j) H_j (curved), written over the
 // gradient slots of sQ.
 template <int D, int N, int Q, bool CV>
-__device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q> tk, const ElemParams& ep, long e,
+__device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q>& tk, const ElemParams& ep, long e,
                                              const double* dxi, double detJ, double* __restrict__ sQ, int tid,
                                              int NT) {
   using K = ResK<D, N, Q>;
@@ -241,7 +232,7 @@ __device__ __forceinline__ void res_vol_flux(const ResArgs& a, const TabK<N, Q> 
 // Transposed contraction with the derivative bases: out[v][m] =
 // sum_j sum_q d(phi_m)/d(xi_j) H_j (W: scratch of ResK::T1 + T2 doubles).
 template <int D, int N, int Q>
-__device__ __forceinline__ void res_vol_transpose(const TabK<N, Q> tk, const double* __restrict__ sQ,
+__device__ __forceinline__ void res_vol_transpose(const TabK<N, Q>& tk, const double* __restrict__ sQ,
                                                   double* __restrict__ W, double* __restrict__ out, int tid,
                                                   int NT) {
   using K = ResK<D, N, Q>;
@@ -358,8 +349,9 @@ __device__ __forceinline__ void res_vol_transpose(const TabK<N, Q> tk, const dou
 // Block size (runtime, a multiple of 64, at most 256) is chosen per shape by
 // the autotuner; every loop strides by blockDim.x.
 template <int D, int N, int Q, bool CV>
-__global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, double* __restrict__ trace,
+__global__ __launch_bounds__(256) void k_res_vol(ResArgs a, double* __restrict__ trace,
                                                 double* __restrict__ Lvol) {
+  static constexpr TabK<N, Q> tk = make_tabk<N, Q>();
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
   __shared__ double sU[NB];
@@ -480,7 +472,8 @@ __global__ __launch_bounds__(256) void k_res_vol(ResArgs a, TabK<N, Q> tk, doubl
 // with the 1D kernels k1[a][b] = sum_i B[a][i] B[b][i] (Gauss points) and
 // kE[a][s] = sum_i B[a][i] phi_i(+-1).
 template <int D, int N, int Q>
-__global__ __launch_bounds__(256) void k_ldg_lift(ResArgs a, TabK<N, Q> tk, double* __restrict__ rq) {
+__global__ __launch_bounds__(256) void k_ldg_lift(ResArgs a, double* __restrict__ rq) {
+  static constexpr TabK<N, Q> tk = make_tabk<N, Q>();
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQ = K::NQ, NQF = K::NQF, NF = K::NF, NB = K::NB;
   __shared__ double sU[NB], sN[NB];
@@ -692,8 +685,9 @@ __device__ __forceinline__ void face_point_flux(const ResArgs& a, const TabK<N, 
 // boundary face by its element, in its own orientation, so the thread of
 // axis a also computes its element's side-0 face when that is a boundary.
 template <int D, int N, int Q, bool CV>
-__global__ __launch_bounds__(256) void k_res_face(ResArgs a, TabK<N, Q> tk, const double* __restrict__ trace,
+__global__ __launch_bounds__(256) void k_res_face(ResArgs a, const double* __restrict__ trace,
                                                   double* __restrict__ X) {
+  static constexpr TabK<N, Q> tk = make_tabk<N, Q>();
   using K = ResK<D, N, Q>;
   constexpr int NQF = K::NQF, NF = K::NF;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -723,8 +717,9 @@ __device__ __forceinline__ void epilogue(const ResArgs& a, const ElemParams& ep,
 
 // ---------------------------------------------------------------- lift + epilogue
 template <int D, int N, int Q, bool CV>
-__global__ __launch_bounds__(256) void k_res_lift(ResArgs a, TabK<N, Q> tk, const double* __restrict__ Lvol,
+__global__ __launch_bounds__(256) void k_res_lift(ResArgs a, const double* __restrict__ Lvol,
                                                  const double* __restrict__ X) {
+  static constexpr TabK<N, Q> tk = make_tabk<N, Q>();
   using K = ResK<D, N, Q>;
   constexpr int NV = K::NV, NM = K::NM, NQF = K::NQF, NMF = K::NMF, NF = K::NF, NB = K::NB;
   __shared__ double sA[NF * (D + 1) * NV * NQF];
