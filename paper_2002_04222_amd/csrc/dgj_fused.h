@@ -465,8 +465,19 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::minb(EPW))) void k_res_fused
   __syncthreads();
 
   // ---- expansion along the normal index, mass inverse, epilogue
+  // The epilogue's operands of this thread's first MINV_OUTK unknowns
+  // (i = tid + k NT) are loaded here, ahead of their results (the stage
+  // residual and the matvec; R alone needs none); the state is the
+  // element's copy in LDS.
+  EpiIn pre[MINV_OUTK];
+  const bool need = ok && a.mode != RES_R;
+#pragma unroll
+  for (int k = 0; k < MINV_OUTK; ++k) {
+    const int i = tid + k * NT;
+    pre[k] = (need && i < NB) ? epi_load(a, e * NB + i, sU[i]) : EpiIn{0.0, 0.0, 0.0};
+  }
   const double invdetJ = g[D + 1];
-  for (int i = tid; i < NB; i += NT) {
+  auto expand = [&](int i) {
     const int m = i % NM, v = i / NM;
     int mi[3] = {0, 0, 0};
     split<D, N>(m, mi);
@@ -480,16 +491,26 @@ __global__ __launch_bounds__(256, (FusedK<D, N, Q>::minb(EPW))) void k_res_fused
       Lm += sE[s * N + mi[ax]] * FMb[((ff * 2 + 0) * NV + v) * NMF + tm] +
             sE[2 * N + s * N + mi[ax]] * FMb[((ff * 2 + 1) * NV + v) * NMF + tm];
     }
-    if constexpr (CV) sL[i] = Lm;
-    else if (ok) epilogue(a, ep, e * NB + i, Lm * invdetJ);
-  }
+    return Lm;
+  };
   if constexpr (CV) {
+    for (int i = tid; i < NB; i += NT) sL[i] = expand(i);
     __syncthreads();
     static_assert(F::U / NB >= 1, "LDS staging of the mass-matrix product");
     mass_inv_dense<NM, NV>(a.minv + e * (long)NM * mass_ld(NM), sL, WS, tid, NT, F::U / NB,
-                           [&](int i, double R) {
-                             if (ok) epilogue(a, ep, e * NB + i, R);
+                           [&](int i, double R, int k) {
+                             if (!ok) return;
+                             const long gi = e * NB + i;
+                             epilogue_pre(a, ep, gi, R, k >= 0 ? pre[k] : epi_load(a, gi, sU[i]));
                            });
+  } else {
+#pragma unroll
+    for (int k = 0; k < MINV_OUTK; ++k) {
+      const int i = tid + k * NT;
+      if (i < NB && ok) epilogue_pre(a, ep, e * NB + i, expand(i) * invdetJ, pre[k]);
+    }
+    for (int i = tid + MINV_OUTK * NT; i < NB; i += NT)
+      if (ok) epilogue_pre(a, ep, e * NB + i, expand(i) * invdetJ, epi_load(a, e * NB + i, sU[i]));
   }
 }
 

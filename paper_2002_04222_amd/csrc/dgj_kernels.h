@@ -291,7 +291,12 @@ typedef double dgj_d2 __attribute__((ext_vector_type(2)));
 // 16-byte nontemporal loads, 16 in flight (the matrix is streamed once per
 // evaluation with no reuse), and the groups' partial sums meet in
 // part[NS][NV][NM] (LDS).  Every thread of the element calls it once L[v][n]
-// (LDS) is complete; out(i, R) receives result i = v NM + m once.
+// (LDS) is complete; out(i, R, k) receives result i = v NM + m once, with k
+// the ordinal of i among the thread's results (i = tid + k NT) for the first
+// MINV_OUTK of them and -1 for the rest, so that a caller can use values it
+// loaded ahead for them.
+constexpr int MINV_OUTK = 4;
+
 template <int NM, int NV, class Out>
 __device__ __forceinline__ void mass_inv_dense(const double* __restrict__ Mi, const double* sL, double* part,
                                                int tid, int NT, int NSmax, Out out) {
@@ -333,12 +338,16 @@ __device__ __forceinline__ void mass_inv_dense(const double* __restrict__ Mi, co
     }
   }
   __syncthreads();
-  for (int i = tid; i < NV * NM; i += NT) {
+  auto result = [&](int i, int k) {
     const int m = i % NM, v = i / NM;
     double R = 0.0;
     for (int h = 0; h < NS; ++h) R += part[(h * NV + v) * NM + m];
-    out(i, R);
-  }
+    out(i, R, k);
+  };
+#pragma unroll
+  for (int k = 0; k < MINV_OUTK; ++k)
+    if (tid + k * NT < NV * NM) result(tid + k * NT, k);
+  for (int i = tid + MINV_OUTK * NT; i < NV * NM; i += NT) result(i, -1);
 }
 
 }  // namespace dgj

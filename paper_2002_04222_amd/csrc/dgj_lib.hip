@@ -148,6 +148,16 @@ __global__ void k_add_scaled(double* __restrict__ y, const double* __restrict__ 
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = z ? x[i] + a * z[i] : x[i];
 }
+// w = u + eps v with the rounding of StateIn (the product, then the sum),
+// eps per instance in batches (epsv[inst[i / nb]])
+__global__ void k_perturb(double* __restrict__ w, const double* __restrict__ u, const double* __restrict__ v,
+                          double eps, const double* __restrict__ epsv, const int* __restrict__ inst, int nb,
+                          long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double ep = epsv ? epsv[inst[i / nb]] : eps;
+    w[i] = __dadd_rn(u[i], __dmul_rn(ep, v[i]));
+  }
+}
 // g = S + inc1 (inc2 null) or S + 2 inc1 - inc2
 __global__ void k_extrap(double* __restrict__ g, const double* __restrict__ S, const double* __restrict__ inc1,
                          const double* __restrict__ inc2, long n) {
@@ -243,7 +253,7 @@ __global__ __launch_bounds__(256) void k_mass_apply_dense(const double* __restri
   for (int i = threadIdx.x; i < NB; i += blockDim.x) sq[i] = q[e * NB + i];
   __syncthreads();
   mass_inv_dense<NM, NV>(M + e * (long)NM * mass_ld(NM), sq, part, threadIdx.x, blockDim.x, NSC,
-                         [&](int i, double R) { out[e * NB + i] = R; });
+                         [&](int i, double R, int) { out[e * NB + i] = R; });
 }
 
 // out[e][v][m] = sum_n M[e][m][n] q[e][v][n], M[e] column-major with columns
@@ -480,6 +490,7 @@ struct dgj_ctx {
   bool have_prev = false;          // BDF2: d_uprev holds the previous step's u^n
   double dt_prev = 0.0;            // BDF2: that step's dt
   double* d_g2 = nullptr;          // candidate guess
+  double* d_upe = nullptr;         // u + eps v of the current matvec
   double* rec_S = nullptr;         // optional caller buffers [stages][n]
   double* rec_inc = nullptr;
   struct Mlp {
@@ -800,10 +811,16 @@ void stage_residual(dgj_ctx* c, const double* u, const double* S, double dt_a, d
   launch_residual(c, a);
   c->residual_evals++;
 }
+// The perturbed state u + eps v is formed once, by an elementwise pass into
+// the context's buffer, and the residual kernels read it as a plain state:
+// formed inside them it doubled every state load, the neighbours' included
+// (bitwise the same values either way).
 void matvec(dgj_ctx* c, const double* u, const double* Nu, const double* S, double dt_a, const double* v, double eps,
             double* Jv) {
   ResArgs a = res_args(c);
-  a.in = StateIn{u, v, eps};
+  hipLaunchKernelGGL(k_perturb, dim3(grid_for(c->n)), dim3(256), 0, c->stream, c->d_upe, u, v, eps, a.epsv, a.inst,
+                     c->NB, c->n);
+  a.in = StateIn{c->d_upe, nullptr, eps};
   a.S = S;
   a.Nu = Nu;
   a.dt_a = dt_a;
@@ -1590,7 +1607,7 @@ int dgj_create(const dgj_mesh* mesh, const dgj_phys* phys, const dgj_solver* sol
       HIPCHK(hipMalloc(&c->d_h2, 64 * sizeof(double)));
     }
     double** bufs[] = {&c->d_z, &c->d_w, &c->d_t1, &c->d_t2, &c->d_ubar, &c->d_N, &c->d_S, &c->d_b, &c->d_x,
-                       &c->d_un, &c->d_pa, &c->d_pb, &c->d_g2};
+                       &c->d_un, &c->d_pa, &c->d_pb, &c->d_g2, &c->d_upe};
     for (auto pp : bufs) HIPCHK(hipMalloc(pp, vb));
     {
       double At[DGJ_MAX_STAGES][DGJ_MAX_STAGES], bt[DGJ_MAX_STAGES];
@@ -1661,7 +1678,7 @@ void dgj_destroy(dgj_ctx* c) {
   double* ptrs[] = {c->d_vg, c->d_fg, c->d_M, c->d_Minv, c->d_Mq, c->d_trace, c->d_X, c->d_Lvol, c->d_geo,
                     c->d_beta, c->d_origin, c->d_tab, c->d_part, c->d_scal, c->d_chi, c->d_z, c->d_w,
                     c->d_t1, c->d_t2, c->d_ubar, c->d_N, c->d_S, c->d_b, c->d_x, c->d_un, c->d_pa, c->d_pb,
-                    c->d_g2, c->d_uprev};
+                    c->d_g2, c->d_upe, c->d_uprev};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   for (int m = 0; m < DGJ_MAX_STAGES; ++m)

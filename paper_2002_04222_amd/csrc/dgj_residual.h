@@ -702,6 +702,31 @@ __global__ __launch_bounds__(256) void k_res_face(ResArgs a, const double* __res
   if (e0 < 0) face_point_flux<D, N, Q, CV>(a, tk, ep.ph, trace, X, e, 2 * ax, e0, p);
 }
 
+// the operands of the epilogue of unknown gi other than R: the state w
+// (the caller's copy), and S and N_u as the mode needs them, so that a
+// kernel can load them ahead of the result
+struct EpiIn {
+  double w, S, Nu;
+};
+__device__ __forceinline__ EpiIn epi_load(const ResArgs& a, long gi, double w) {
+  EpiIn x{w, 0.0, 0.0};
+  if (a.mode != RES_R) x.S = a.S[gi];
+  if (a.mode == RES_JV) x.Nu = a.Nu[gi];
+  return x;
+}
+// the epilogue below with its operands given (the same arithmetic)
+__device__ __forceinline__ void epilogue_pre(const ResArgs& a, const ElemParams& ep, long gi, double R,
+                                             const EpiIn& x) {
+  if (a.src) R += a.src[gi];
+  if (a.mode == RES_R) {
+    a.out[gi] = R;
+  } else {
+    const double Nw = (x.w - x.S) - ep.dt_a * R;
+    if (a.mode == RES_N) a.out[gi] = Nw;
+    else a.out[gi] = (Nw - x.Nu) / ep.in.eps;
+  }
+}
+
 // output of the residual kernels for unknown gi with R = (M^-1 L)_gi
 __device__ __forceinline__ void epilogue(const ResArgs& a, const ElemParams& ep, long gi, double R) {
   if (a.src) R += a.src[gi];
@@ -856,7 +881,7 @@ __global__ __launch_bounds__(256) void k_res_lift(ResArgs a, const double* __res
     constexpr int NSC = (NF * (D + 1) * NV * NQF - NB) / NB;   // groups whose partial sums fit in sA
     static_assert(NSC >= 1, "LDS staging of the mass-matrix product");
     mass_inv_dense<NM, NV>(a.minv + e * (long)NM * mass_ld(NM), sL, sA + NB, tid, NT, NSC,
-                           [&](int i, double R) { epilogue(a, ep, e * NB + i, R); });
+                           [&](int i, double R, int) { epilogue(a, ep, e * NB + i, R); });
   }
 }
 
