@@ -245,7 +245,9 @@ int dgj_stage_residual(dgj_ctx *ctx, const double *u, const double *S, double dt
 
 /* Jv = (N(u + eps v) - N_u) / eps  (Eq. 25) with N_u = N(u) stored by the
  * caller.  eps <= 0 selects eps = ||u||_2 sqrt(2^-52) (Eq. 26; synchronises
- * to read the norm).  u + eps v is formed on the fly, not stored. */
+ * to read the norm).  u + eps v is formed once per call into a buffer the
+ * context owns (the rounding of the product, then the sum) and read by the
+ * residual kernels as the state. */
 int dgj_jfnk_matvec(dgj_ctx *ctx, const double *u, const double *N_u, const double *S, double dt_a,
                     const double *v, double eps, double *Jv);
 
