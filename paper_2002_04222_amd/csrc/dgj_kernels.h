@@ -88,14 +88,9 @@ __device__ __forceinline__ int mode_of(int a, int ia, int tm) {
 
 // ---------------------------------------------------------------- state access
 struct StateIn {
-  const double* u;    // base state
-  const double* v;    // perturbation direction (matvec) or nullptr
-  double eps;
-  __device__ __forceinline__ double operator()(long i) const {
-    if (v == nullptr) return u[i];
-    // u + eps v rounded as two separate operations (no contraction)
-    return __dadd_rn(u[i], __dmul_rn(eps, v[i]));
-  }
+  const double* u;    // the state the residual is evaluated at (the matvec's u + eps v)
+  double eps;         // the matvec's eps (mode RES_JV)
+  __device__ __forceinline__ double operator()(long i) const { return u[i]; }
 };
 
 enum ResMode { RES_R = 0, RES_N = 1, RES_JV = 2 };

@@ -214,7 +214,7 @@ __global__ __launch_bounds__(128) void k_pc_face(const double* __restrict__ u, c
   const long e = e0 + gid / (NQF * NF);
   const long en = nbr[e * NF + f];
   const int ax = f >> 1, s = f & 1;
-  StateIn in{u, nullptr, 0.0};
+  StateIn in{u, 0.0};
   double Uo[NV], Un[NV], go[D][NV], gn[D][NV];
   constexpr int CF = D * D + D + 1;
   const double* fgo = fg ? fg + (e * NF + f) * (long)CF * NQF : nullptr;
