@@ -2,7 +2,8 @@
 of a curved mesh and the BRJ block inverses come out bitwise identical from
 two separate contexts (a missing barrier in the Gauss-Jordan pivot step once
 made a few blocks per launch differ), and sampled inverse mass matrices
-equal numpy's inverse of the oracle's mass matrices."""
+equal numpy's inverse of the oracle's mass matrices.  The residual, stage
+residual and matvec repeat bitwise on the cylinder's element shape."""
 import dataclasses
 import gc
 import sys
@@ -73,3 +74,32 @@ def test_brj_block_inverses_repeatable():
         del ctx, dinv
         gc.collect()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_residuals_repeatable_on_the_annulus(fused):
+    """R, N and the matvec evaluated twice on a 3D P=4 annulus (wall and far
+    field, the cylinder's element shape) come out bitwise equal: every sum in
+    the residual kernels has a fixed order (no atomics, no races between the
+    phases of a workgroup)."""
+    _case(f"residual repeatability, annulus 3D P=4, fused={fused}")
+    from paper_2002_04222_amd import Context
+    cfg = dataclasses.replace(W.config(4), ncells=(2, 8, 2), lengths=(1.0, 2 * np.pi, 1.0), r1=3.0, Re=200.0)
+    mesh = cfg.mesh()
+    k, st = cfg.boundary()
+    ctx = Context(mesh, cfg, bc_kind=k, bc_state=st)
+    ctx.set_residual_kernels(fused)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda").reshape(ctx.shape)
+    u = dev(W.freestream_state(cfg, mesh.n_elem)) * (1.0 + 1e-3 * dev(W.random_vector(mesh.n_elem, 3, cfg.P, seed=3)))
+    S = 0.999 * u
+    v = dev(W.random_vector(mesh.n_elem, 3, cfg.P, seed=4))
+    outs = []
+    for _ in range(2):
+        R, N, J = ctx.empty(), ctx.empty(), ctx.empty()
+        ctx.residual(u, R)
+        ctx.stage_residual(u, S, 0.05, N)
+        ctx.jfnk_matvec(u, N, S, 0.05, v, 1e-7, J)
+        outs.append((_host(R), _host(N), _host(J)))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    ctx.close()
